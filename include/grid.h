@@ -1,0 +1,154 @@
+/*
+ * grid.h -- C ABI of the MI355X batched gradient-of-forward-dynamics library.
+ *
+ * The calls follow the problem statement of GRiD (arXiv 2109.06976): a robot model
+ * plus arrays of joint positions q, velocities qd and torques tau go in; the joint
+ * accelerations qdd, the inverse mass matrix M^-1 and the gradients dqdd/dq and
+ * dqdd/dqd come out (Sec. IV-B, the last item of the feature list:
+ * dqdd/du = -M^-1 dRNEA(q, qd, qdd)/du, and dqdd/dtau = M^-1).
+ *
+ * Conventions shared by every call
+ *   - Bodies are numbered 0..n-1 with parent[i] < i; parent -1 is the fixed base
+ *     (Sec. III-B). Outputs use the caller's numbering.
+ *   - Every joint is revolute about its own z axis (S_i = e_3); the joint transform is
+ *     iX_lambda(q_i) = rot(E_z(q_i)) * X_T,i, with X_T,i given by tree_rot (rotation from
+ *     the parent frame to the joint frame) and tree_pos (the joint origin in parent
+ *     coordinates) (Sec. III-B).
+ *   - Spatial vectors are ordered [angular; linear] (Eq. 2). SI units, radians.
+ *   - Fixed base, fully actuated (B = I in Eq. 1), no external forces (F = 0).
+ *   - Batched arrays are knot-major and row-major float32:
+ *       q, qd, tau, qdd       [N][n]
+ *       Minv, dqdd_dq, dqdd_dqd  [N][n][n],  dqdd_dq[k][i][j] = d qdd_i / d q_j at knot k.
+ *     M^-1 is returned exactly symmetric.
+ *   - Arithmetic: the derivative sweeps and the final product run in float32; the
+ *     transforms, RNEA, M, M^-1 and qdd run in float64 unless the model was created
+ *     with GRID_FLAG_FP32_DYNAMICS.
+ *
+ * Errors: every call returns a grid_status. Arguments are validated on the host
+ * before any device work, so on error nothing has been enqueued. N = 0 is a no-op that
+ * returns GRID_OK. NaN or Inf inputs are not checked and propagate to the outputs. A
+ * fault of an asynchronous launch surfaces as GRID_EDEVICE at the next call that
+ * synchronises. grid_last_error() returns a thread-local description of the last
+ * failure on the calling thread. No C++ exception crosses this interface.
+ *
+ * Ownership: a grid_model owns its device constants and compiled kernels and is not
+ * modified by launches, so several threads may launch with one model. A
+ * grid_workspace belongs to one stream (or one thread) at a time. The caller owns all
+ * input and output buffers.
+ */
+#ifndef GRID_H
+#define GRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t grid_status;
+#define GRID_OK 0
+#define GRID_EINVAL (-1)        /* bad argument or model description */
+#define GRID_ENOMEM (-2)        /* device or host allocation failed */
+#define GRID_EDEVICE (-3)       /* HIP runtime error, no device, or a kernel fault */
+#define GRID_EUNSUPPORTED (-4)  /* valid request this build does not implement */
+#define GRID_ECOMPILE (-5)      /* generating or compiling the robot's kernel failed */
+
+#define GRID_JOINT_REVOLUTE 0
+
+/* Model creation flags */
+#define GRID_FLAG_FP32_DYNAMICS 1   /* transforms, RNEA, M, M^-1, qdd in float32 too */
+
+typedef struct grid_model_desc {
+    int32_t n;                   /* number of joints/bodies, 1..32 */
+    const int32_t* parent;       /* [n], -1 <= parent[i] < i */
+    const int32_t* joint_type;   /* [n] GRID_JOINT_REVOLUTE, or NULL for all revolute */
+    const double* axis;          /* [n][3] joint axis in the joint frame: must be (0,0,1); NULL = z */
+    const double* tree_rot;      /* [n][3][3] E_T, row-major, parent frame -> joint frame */
+    const double* tree_pos;      /* [n][3] joint origin in parent coordinates (m) */
+    const double* mass;          /* [n] link mass (kg), > 0 */
+    const double* com;           /* [n][3] centre of mass in the body frame (m) */
+    const double* inertia_com;   /* [n][6] xx yy zz xy xz yz about the centre of mass (kg m^2) */
+    double gravity[3];           /* gravity in base coordinates (m/s^2) */
+} grid_model_desc;
+
+typedef struct grid_model_s* grid_model;
+typedef struct grid_workspace_s* grid_workspace;
+
+typedef struct grid_timing {
+    float h2d_ms;      /* host -> device copy of q, qd, tau */
+    float kernel_ms;   /* device compute */
+    float d2h_ms;      /* device -> host copy of the four outputs */
+    float total_ms;    /* first copy start to last copy end */
+} grid_timing;
+
+/* Name of a status code (static string). */
+const char* grid_status_string(grid_status s);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* grid_last_error(void);
+
+/*
+ * Validate a model description, upload its constants to `device` and obtain the
+ * robot's kernel: the library writes the topology out as compile-time tables
+ * (Sec. IV-C code generation) and compiles it for gfx950, or loads the code object
+ * from the kernel cache (directory GRID_KERNEL_CACHE, else the package's _kcache).
+ * flags: 0 or GRID_FLAG_FP32_DYNAMICS. On success *out owns device memory until
+ * grid_model_destroy. Errors: EINVAL (bad description), EUNSUPPORTED (non-z axis,
+ * non-revolute joint, n > 32), ECOMPILE, EDEVICE, ENOMEM.
+ */
+grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint32_t flags,
+                              grid_model* out);
+
+/* Release a model (NULL is accepted). Waits for nothing: the caller must not destroy a
+ * model that still has launches in flight. */
+grid_status grid_model_destroy(grid_model m);
+
+/* n, bytes moved per knot by the host-pointer call (inputs + outputs), and the number
+ * of lanes of a 64-lane wavefront one knot occupies. Any pointer may be NULL. */
+grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
+                            int32_t* lanes_per_knot);
+
+/*
+ * The batched path, one fused kernel launch (steps: transforms, RNEA, CRBA, M^-1,
+ * qdd, RNEA at qdd, dRNEA forward/backward, -M^-1 dtau). All pointers are device
+ * pointers in the layouts above; `stream` is a hipStream_t (NULL = default stream).
+ * Asynchronous: returns after the launch is enqueued. Errors: EINVAL (N < 0, a NULL
+ * pointer with N > 0, N > 2^31/64), EDEVICE (launch failure).
+ */
+grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* qd,
+                         const float* tau, float* qdd, float* Minv, float* dqdd_dq,
+                         float* dqdd_dqd, void* stream);
+
+/*
+ * Workspace for the host-pointer call: device buffers and pinned host staging for up
+ * to max_knots knots, plus a private stream and events.
+ */
+grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspace* out);
+grid_status grid_workspace_destroy(grid_workspace ws);
+
+/*
+ * Host-pointer variant (the paper's CPU-side call, Sec. IV-A): copies q, qd, tau to
+ * the device, runs grid_fd_grad, copies the outputs back and waits. Host buffers are
+ * ordinary (pageable) memory in the layouts above; they are staged through the
+ * workspace's pinned buffers. `timing` (may be NULL) receives HIP-event times of the
+ * three phases. Errors: EINVAL (N > max_knots of the workspace, NULL pointers, a
+ * workspace made for another model), EDEVICE.
+ */
+grid_status grid_fd_grad_host(grid_model m, grid_workspace ws, int32_t N, const float* q,
+                              const float* qd, const float* tau, float* qdd, float* Minv,
+                              float* dqdd_dq, float* dqdd_dqd, grid_timing* timing);
+
+/*
+ * Code generation without a device: write the generated HIP source for a topology
+ * into buf (len in: capacity, out: bytes needed including the terminating NUL), or
+ * compile it into the kernel cache. Used by the build step and by tests.
+ */
+grid_status grid_codegen_source(const int32_t* parent, int32_t n, uint32_t flags, char* buf,
+                                size_t* len);
+grid_status grid_codegen_precompile(const int32_t* parent, int32_t n, uint32_t flags);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRID_H */

@@ -1,0 +1,128 @@
+"""Build libgrid.so (hipcc, gfx950) in-tree and fill its kernel cache.
+
+Steps:
+  1. embed csrc/grid_device.hip into a generated include (_build/grid_device_src.inc);
+  2. compile the host runtime (csrc/*.cpp) with hipcc into libgrid.so;
+  3. compile the device source with hipcc for gfx950 behind a generated chain prelude
+     (a full offline compile check; -save-temps keeps the ISA under _build/);
+  4. run the library's own code generator + hiprtc for every topology the tests,
+     benchmark and smoke check use, so no kernel is compiled inside a GPU run.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libgrid.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# no packed FP32 instructions in any HIP code of this project
+NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"command failed ({r.returncode}): {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return r
+
+
+def embed_device_source() -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    src = open(os.path.join(CSRC, "grid_device.hip"), "rb").read()
+    body = ",".join(str(b) for b in src)
+    inc = os.path.join(BUILD, "grid_device_src.inc")
+    text = ("// generated from csrc/grid_device.hip by build.py\n"
+            f"static const char grid_device_src[] = {{{body},0}};\n")
+    if not os.path.exists(inc) or open(inc).read() != text:
+        with open(inc, "w") as f:
+            f.write(text)
+    return inc
+
+
+def build_library(verbose=False) -> str:
+    embed_device_source()
+    cmd = [HIPCC, "-std=c++17", "-O2", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "--offload-arch=gfx950", *NO_PACKED_FP32,
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", BUILD,
+           os.path.join(CSRC, "grid_runtime.cpp"), os.path.join(CSRC, "grid_codegen.cpp"),
+           "-lhiprtc", "-o", LIB + ".tmp"]
+    _run(cmd, verbose)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def _codegen_source(lib, parent, flags=0) -> str:
+    import numpy as np
+    p = np.ascontiguousarray(parent, dtype=np.int32)
+    ln = C.c_size_t(0)
+    pp = p.ctypes.data_as(C.POINTER(C.c_int32))
+    lib.grid_codegen_source(pp, C.c_int32(len(p)), C.c_uint32(flags), None, C.byref(ln))
+    buf = C.create_string_buffer(ln.value)
+    st = lib.grid_codegen_source(pp, C.c_int32(len(p)), C.c_uint32(flags), buf, C.byref(ln))
+    if st != 0:
+        raise RuntimeError(f"grid_codegen_source failed: {st}")
+    return buf.value.decode()
+
+
+def offline_compile_check(lib, verbose=False):
+    """hipcc --genco of the generated source for the 7-dof chain (both precisions)."""
+    from paper_2109_06976_amd import synth
+    for flags, tag in ((0, "f64dyn"), (1, "f32dyn")):
+        src = "#include <hip/hip_runtime.h>\n" + _codegen_source(lib, synth.chain_parent(7), flags)
+        path = os.path.join(BUILD, f"chain7_{tag}.hip")
+        with open(path, "w") as f:
+            f.write(src)
+        out = os.path.join(BUILD, f"chain7_{tag}.hsaco")
+        _run([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", *NO_PACKED_FP32, "--genco",
+              "-save-temps=obj", "-o", out, path], verbose)
+
+
+def standard_topologies():
+    """Every topology the tests, the benchmark and the smoke check instantiate."""
+    import numpy as np
+    from paper_2109_06976_amd import synth
+    tops = [synth.chain_parent(n) for n in (1, 2, 3, 7)]
+    tops += [synth.quadruped_parent(), synth.humanoid_parent("anatomical"),
+             synth.humanoid_parent("literal"),
+             np.array([-1, 0, 0], np.int32), np.array([-1, -1, 1], np.int32),
+             np.array([-1, 0, 0, 1, 1, 2, 2], np.int32)]
+    bfs_quad = [-1, -1, -1, -1, 0, 1, 2, 3, 4, 5, 6, 7]
+    tops.append(np.array(bfs_quad, np.int32))
+    return tops
+
+
+def precompile(lib, verbose=False):
+    import numpy as np
+    for parent in standard_topologies():
+        for flags in (0, 1):
+            p = np.ascontiguousarray(parent, dtype=np.int32)
+            st = lib.grid_codegen_precompile(p.ctypes.data_as(C.POINTER(C.c_int32)),
+                                             C.c_int32(len(p)), C.c_uint32(flags))
+            if st != 0:
+                msg = C.cast(lib.grid_last_error(), C.c_char_p).value
+                raise RuntimeError(f"precompile {list(parent)} flags={flags}: {st} {msg}")
+            if verbose:
+                print(f"cached kernel for parent={list(parent)} flags={flags}", flush=True)
+
+
+def build(verbose=False):
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    build_library(verbose)
+    lib = C.CDLL(LIB)
+    lib.grid_last_error.restype = C.c_void_p
+    offline_compile_check(lib, verbose)
+    precompile(lib, verbose)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

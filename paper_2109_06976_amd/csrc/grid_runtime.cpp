@@ -1,0 +1,409 @@
+// libgrid host runtime: the C ABI declared in include/grid.h.
+#include "grid_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+using namespace grid_impl;
+
+namespace grid_impl {
+
+static thread_local std::string t_last_error;
+
+void set_error(const std::string& msg) { t_last_error = msg; }
+
+}  // namespace grid_impl
+
+namespace {
+
+grid_status fail(grid_status s, const std::string& msg)
+{
+    set_error(msg);
+    return s;
+}
+
+grid_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(GRID_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess)                          \
+            return hip_fail(e_, #expr);                \
+    } while (0)
+
+bool finite_all(const double* p, size_t k)
+{
+    for (size_t i = 0; i < k; ++i)
+        if (!std::isfinite(p[i]))
+            return false;
+    return true;
+}
+
+grid_status validate_desc(const grid_model_desc* d)
+{
+    if (!d)
+        return fail(GRID_EINVAL, "model description is NULL");
+    if (d->n < 1)
+        return fail(GRID_EINVAL, "n must be >= 1");
+    if (d->n > kMaxBodies)
+        return fail(GRID_EUNSUPPORTED, "n > " + std::to_string(kMaxBodies) + " is not supported");
+    if (!d->parent || !d->tree_rot || !d->tree_pos || !d->mass || !d->com || !d->inertia_com)
+        return fail(GRID_EINVAL, "a required model array is NULL");
+    const int n = d->n;
+    for (int i = 0; i < n; ++i) {
+        if (d->joint_type && d->joint_type[i] != GRID_JOINT_REVOLUTE)
+            return fail(GRID_EUNSUPPORTED, "only revolute joints are supported");
+        if (d->axis) {
+            const double* a = d->axis + 3 * i;
+            if (a[0] != 0.0 || a[1] != 0.0 || a[2] != 1.0)
+                return fail(GRID_EUNSUPPORTED, "joint axes other than +z are not supported");
+        }
+    }
+    if (!finite_all(d->tree_rot, 9 * n) || !finite_all(d->tree_pos, 3 * n) ||
+        !finite_all(d->mass, n) || !finite_all(d->com, 3 * n) ||
+        !finite_all(d->inertia_com, 6 * n) || !finite_all(d->gravity, 3))
+        return fail(GRID_EINVAL, "model description holds a non-finite value");
+    for (int i = 0; i < n; ++i) {
+        if (!(d->mass[i] > 0))
+            return fail(GRID_EINVAL, "mass[" + std::to_string(i) + "] must be > 0");
+        const double* R = d->tree_rot + 9 * i;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0;
+                for (int k = 0; k < 3; ++k)
+                    s += R[a * 3 + k] * R[b * 3 + k];
+                if (std::fabs(s - (a == b ? 1.0 : 0.0)) > 1e-5)
+                    return fail(GRID_EINVAL, "tree_rot[" + std::to_string(i) + "] is not a rotation");
+            }
+        // inertia about the centre of mass must be positive definite (Sylvester)
+        const double* J = d->inertia_com + 6 * i;
+        const double xx = J[0], yy = J[1], zz = J[2], xy = J[3], xz = J[4], yz = J[5];
+        const double m2 = xx * yy - xy * xy;
+        const double m3 = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+        if (!(xx > 0 && m2 > 0 && m3 > 0))
+            return fail(GRID_EINVAL, "inertia_com[" + std::to_string(i) + "] is not positive definite");
+    }
+    return GRID_OK;
+}
+
+// device constants per body: E_T, r, Ibar = Ic + m (|c|^2 1 - c c^T) about the body origin,
+// h = m c, m
+std::vector<double> pack_constants(const grid_model_desc* d)
+{
+    std::vector<double> out((size_t)d->n * kBodyStride, 0.0);
+    for (int i = 0; i < d->n; ++i) {
+        double* b = out.data() + (size_t)i * kBodyStride;
+        std::memcpy(b, d->tree_rot + 9 * i, 9 * sizeof(double));
+        std::memcpy(b + 9, d->tree_pos + 3 * i, 3 * sizeof(double));
+        const double m = d->mass[i];
+        const double* c = d->com + 3 * i;
+        const double* J = d->inertia_com + 6 * i;
+        b[12] = J[0] + m * (c[1] * c[1] + c[2] * c[2]);
+        b[13] = J[1] + m * (c[0] * c[0] + c[2] * c[2]);
+        b[14] = J[2] + m * (c[0] * c[0] + c[1] * c[1]);
+        b[15] = J[3] - m * c[0] * c[1];
+        b[16] = J[4] - m * c[0] * c[2];
+        b[17] = J[5] - m * c[1] * c[2];
+        b[18] = m * c[0];
+        b[19] = m * c[1];
+        b[20] = m * c[2];
+        b[21] = m;
+    }
+    return out;
+}
+
+grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
+                         const float* tau, float* qdd, float* Minv, float* dq, float* dqd,
+                         hipStream_t stream)
+{
+    KernelArgs a;
+    a.model = m->d_model;
+    a.a0[0] = m->a0[0];
+    a.a0[1] = m->a0[1];
+    a.a0[2] = m->a0[2];
+    a.nknots = N;
+    a.q = q;
+    a.qd = qd;
+    a.tau = tau;
+    a.qdd = qdd;
+    a.Minv = Minv;
+    a.dqdd_dq = dq;
+    a.dqdd_dqd = dqd;
+    const int K = 64 / m->topo.lanes;
+    const unsigned blocks = (unsigned)((N + K - 1) / K);
+    size_t size = sizeof(a);
+    void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
+                      HIP_LAUNCH_PARAM_END};
+    HIP_TRY(hipModuleLaunchKernel(m->fused, blocks, 1, 1, 64, 1, 1, 0, stream, nullptr, config));
+    return GRID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* grid_status_string(grid_status s)
+{
+    switch (s) {
+    case GRID_OK: return "GRID_OK";
+    case GRID_EINVAL: return "GRID_EINVAL";
+    case GRID_ENOMEM: return "GRID_ENOMEM";
+    case GRID_EDEVICE: return "GRID_EDEVICE";
+    case GRID_EUNSUPPORTED: return "GRID_EUNSUPPORTED";
+    case GRID_ECOMPILE: return "GRID_ECOMPILE";
+    default: return "GRID_UNKNOWN";
+    }
+}
+
+const char* grid_last_error(void) { return t_last_error.c_str(); }
+
+grid_status grid_codegen_source(const int32_t* parent, int32_t n, uint32_t flags, char* buf,
+                                size_t* len)
+{
+    if (!parent || !len)
+        return fail(GRID_EINVAL, "parent and len must not be NULL");
+    Topology t;
+    std::string err;
+    if (!analyse_topology(parent, n, &t, &err))
+        return fail(GRID_EINVAL, err);
+    const std::string src = generate_source(t, flags);
+    const size_t need = src.size() + 1;
+    if (buf && *len >= need)
+        std::memcpy(buf, src.c_str(), need);
+    const bool fits = buf && *len >= need;
+    *len = need;
+    if (buf && !fits)
+        return fail(GRID_EINVAL, "buffer too small");
+    return GRID_OK;
+}
+
+grid_status grid_codegen_precompile(const int32_t* parent, int32_t n, uint32_t flags)
+{
+    if (!parent)
+        return fail(GRID_EINVAL, "parent must not be NULL");
+    Topology t;
+    std::string err;
+    if (!analyse_topology(parent, n, &t, &err))
+        return fail(GRID_EINVAL, err);
+    std::vector<char> code;
+    grid_status s = compile_cached(generate_source(t, flags), &code, &err);
+    if (s != GRID_OK)
+        return fail(s, err);
+    return GRID_OK;
+}
+
+grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint32_t flags,
+                              grid_model* out)
+{
+    if (!out)
+        return fail(GRID_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (flags & ~(uint32_t)GRID_FLAG_FP32_DYNAMICS)
+        return fail(GRID_EINVAL, "unknown flag bits");
+    grid_status s = validate_desc(desc);
+    if (s != GRID_OK)
+        return s;
+    Topology topo;
+    std::string err;
+    if (!analyse_topology(desc->parent, desc->n, &topo, &err))
+        return fail(GRID_EINVAL, err);
+    std::vector<char> code;
+    s = compile_cached(generate_source(topo, flags), &code, &err);
+    if (s != GRID_OK)
+        return fail(s, err);
+
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(GRID_EINVAL, "device index out of range");
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GRID_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName +
+                                           ", kernels are built for gfx950");
+
+    grid_model m = new (std::nothrow) grid_model_s;
+    if (!m)
+        return fail(GRID_ENOMEM, "host allocation failed");
+    m->device = device;
+    m->flags = flags;
+    m->topo = std::move(topo);
+    for (int k = 0; k < 3; ++k)
+        m->a0[k] = -desc->gravity[k];
+    const std::vector<double> consts = pack_constants(desc);
+    hipError_t e = hipMalloc(&m->d_model, consts.size() * sizeof(double));
+    if (e != hipSuccess) {
+        delete m;
+        return fail(GRID_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    e = hipMemcpy(m->d_model, consts.data(), consts.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipModuleLoadData(&m->module, code.data());
+    if (e == hipSuccess)
+        e = hipModuleGetFunction(&m->fused, m->module, "grid_fdgrad_fused");
+    if (e != hipSuccess) {
+        grid_model_destroy(m);
+        return hip_fail(e, "model upload / module load");
+    }
+    *out = m;
+    return GRID_OK;
+}
+
+grid_status grid_model_destroy(grid_model m)
+{
+    if (!m)
+        return GRID_OK;
+    hipSetDevice(m->device);
+    if (m->module)
+        hipModuleUnload(m->module);
+    if (m->d_model)
+        hipFree(m->d_model);
+    delete m;
+    return GRID_OK;
+}
+
+grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
+                            int32_t* lanes_per_knot)
+{
+    if (!m)
+        return fail(GRID_EINVAL, "model is NULL");
+    const size_t nn = (size_t)m->topo.n;
+    if (n)
+        *n = m->topo.n;
+    if (io_bytes_per_knot)
+        *io_bytes_per_knot = sizeof(float) * (3 * nn + nn + 3 * nn * nn);
+    if (lanes_per_knot)
+        *lanes_per_knot = m->topo.lanes;
+    return GRID_OK;
+}
+
+grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* qd,
+                         const float* tau, float* qdd, float* Minv, float* dqdd_dq,
+                         float* dqdd_dqd, void* stream)
+{
+    if (!m)
+        return fail(GRID_EINVAL, "model is NULL");
+    if (N < 0)
+        return fail(GRID_EINVAL, "N must be >= 0");
+    if (N == 0)
+        return GRID_OK;
+    if (N > (1 << 30) / 64)
+        return fail(GRID_EINVAL, "N too large");
+    if (!q || !qd || !tau || !qdd || !Minv || !dqdd_dq || !dqdd_dqd)
+        return fail(GRID_EINVAL, "a data pointer is NULL");
+    HIP_TRY(hipSetDevice(m->device));
+    return launch_fused(m, N, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, (hipStream_t)stream);
+}
+
+grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspace* out)
+{
+    if (!m || !out)
+        return fail(GRID_EINVAL, "model and out must not be NULL");
+    *out = nullptr;
+    if (max_knots < 1 || max_knots > (1 << 30) / 64)
+        return fail(GRID_EINVAL, "max_knots out of range");
+    HIP_TRY(hipSetDevice(m->device));
+    grid_workspace w = new (std::nothrow) grid_workspace_s;
+    if (!w)
+        return fail(GRID_ENOMEM, "host allocation failed");
+    w->model = m;
+    w->max_knots = max_knots;
+    const size_t n = (size_t)m->topo.n;
+    const size_t in_f = (size_t)max_knots * 3 * n;
+    const size_t out_f = (size_t)max_knots * (n + 3 * n * n);
+    hipError_t e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        e = hipEventCreate(&w->ev[k]);
+    if (e == hipSuccess)
+        e = hipMalloc(&w->d_in, in_f * sizeof(float));
+    if (e == hipSuccess)
+        e = hipMalloc(&w->d_out, out_f * sizeof(float));
+    if (e == hipSuccess)
+        e = hipHostMalloc(&w->h_in, in_f * sizeof(float), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(&w->h_out, out_f * sizeof(float), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        grid_workspace_destroy(w);
+        return fail(GRID_ENOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
+    }
+    *out = w;
+    return GRID_OK;
+}
+
+grid_status grid_workspace_destroy(grid_workspace w)
+{
+    if (!w)
+        return GRID_OK;
+    hipSetDevice(w->model->device);
+    if (w->stream)
+        hipStreamSynchronize(w->stream);
+    for (auto& ev : w->ev)
+        if (ev)
+            hipEventDestroy(ev);
+    if (w->stream)
+        hipStreamDestroy(w->stream);
+    hipFree(w->d_in);
+    hipFree(w->d_out);
+    if (w->h_in)
+        hipHostFree(w->h_in);
+    if (w->h_out)
+        hipHostFree(w->h_out);
+    delete w;
+    return GRID_OK;
+}
+
+grid_status grid_fd_grad_host(grid_model m, grid_workspace w, int32_t N, const float* q,
+                              const float* qd, const float* tau, float* qdd, float* Minv,
+                              float* dqdd_dq, float* dqdd_dqd, grid_timing* timing)
+{
+    if (!m || !w)
+        return fail(GRID_EINVAL, "model and workspace must not be NULL");
+    if (w->model != m)
+        return fail(GRID_EINVAL, "workspace was created for another model");
+    if (N < 0 || N > w->max_knots)
+        return fail(GRID_EINVAL, "N must be in 0..max_knots of the workspace");
+    if (timing)
+        *timing = grid_timing{0, 0, 0, 0};
+    if (N == 0)
+        return GRID_OK;
+    if (!q || !qd || !tau || !qdd || !Minv || !dqdd_dq || !dqdd_dqd)
+        return fail(GRID_EINVAL, "a data pointer is NULL");
+    HIP_TRY(hipSetDevice(m->device));
+    const size_t n = (size_t)m->topo.n;
+    const size_t vec = (size_t)N * n, mat = (size_t)N * n * n;
+    std::memcpy(w->h_in, q, vec * sizeof(float));
+    std::memcpy(w->h_in + vec, qd, vec * sizeof(float));
+    std::memcpy(w->h_in + 2 * vec, tau, vec * sizeof(float));
+    float* d_q = w->d_in;
+    float* d_qdd = w->d_out;
+    HIP_TRY(hipEventRecord(w->ev[0], w->stream));
+    HIP_TRY(hipMemcpyAsync(d_q, w->h_in, 3 * vec * sizeof(float), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipEventRecord(w->ev[1], w->stream));
+    grid_status s = launch_fused(m, N, d_q, d_q + vec, d_q + 2 * vec, d_qdd, d_qdd + vec,
+                                 d_qdd + vec + mat, d_qdd + vec + 2 * mat, w->stream);
+    if (s != GRID_OK)
+        return s;
+    HIP_TRY(hipEventRecord(w->ev[2], w->stream));
+    HIP_TRY(hipMemcpyAsync(w->h_out, d_qdd, (vec + 3 * mat) * sizeof(float),
+                           hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipEventRecord(w->ev[3], w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    std::memcpy(qdd, w->h_out, vec * sizeof(float));
+    std::memcpy(Minv, w->h_out + vec, mat * sizeof(float));
+    std::memcpy(dqdd_dq, w->h_out + vec + mat, mat * sizeof(float));
+    std::memcpy(dqdd_dqd, w->h_out + vec + 2 * mat, mat * sizeof(float));
+    if (timing) {
+        HIP_TRY(hipEventElapsedTime(&timing->h2d_ms, w->ev[0], w->ev[1]));
+        HIP_TRY(hipEventElapsedTime(&timing->kernel_ms, w->ev[1], w->ev[2]));
+        HIP_TRY(hipEventElapsedTime(&timing->d2h_ms, w->ev[2], w->ev[3]));
+        HIP_TRY(hipEventElapsedTime(&timing->total_ms, w->ev[0], w->ev[3]));
+    }
+    return GRID_OK;
+}
+
+}  // extern "C"

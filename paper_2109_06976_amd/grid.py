@@ -1,0 +1,242 @@
+"""Python binding of libgrid (include/grid.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; this module converts Python objects
+to the C types of the interface and raises GridError on a non-zero status. It loads
+the in-tree libgrid.so and fails loudly when it has not been built. Device arrays are
+passed as torch tensors (or raw integer device addresses); PyTorch only provides the
+memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrid.so")
+
+GRID_OK = 0
+GRID_EINVAL = -1
+GRID_ENOMEM = -2
+GRID_EDEVICE = -3
+GRID_EUNSUPPORTED = -4
+GRID_ECOMPILE = -5
+GRID_FLAG_FP32_DYNAMICS = 1
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+_f32p = C.POINTER(C.c_float)
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("parent", _i32p), ("joint_type", _i32p), ("axis", _f64p),
+                ("tree_rot", _f64p), ("tree_pos", _f64p), ("mass", _f64p), ("com", _f64p),
+                ("inertia_com", _f64p), ("gravity", C.c_double * 3)]
+
+
+class GridTiming(C.Structure):
+    _fields_ = [("h2d_ms", C.c_float), ("kernel_ms", C.c_float), ("d2h_ms", C.c_float),
+                ("total_ms", C.c_float)]
+
+
+class GridError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "grid_status_string": (C.c_char_p, [C.c_int32]),
+    "grid_last_error": (C.c_char_p, []),
+    "grid_model_create": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_uint32,
+                                      C.POINTER(C.c_void_p)]),
+    "grid_model_destroy": (C.c_int32, [C.c_void_p]),
+    "grid_model_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_size_t),
+                                    C.POINTER(C.c_int32)]),
+    "grid_fd_grad": (C.c_int32, [C.c_void_p, C.c_int32] + [C.c_void_p] * 7 + [C.c_void_p]),
+    "grid_workspace_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "grid_workspace_destroy": (C.c_int32, [C.c_void_p]),
+    "grid_fd_grad_host": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32] + [C.c_void_p] * 7 +
+                          [C.POINTER(GridTiming)]),
+    "grid_codegen_source": (C.c_int32, [_i32p, C.c_int32, C.c_uint32, C.c_char_p,
+                                        C.POINTER(C.c_size_t)]),
+    "grid_codegen_precompile": (C.c_int32, [_i32p, C.c_int32, C.c_uint32]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load the in-tree libgrid.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GridError(GRID_EDEVICE, f"{LIB_PATH} is missing: run __graft_entry__.build()")
+        handle = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().grid_status_string(status).decode()
+
+
+def last_error() -> str:
+    return lib().grid_last_error().decode()
+
+
+def _check(status: int):
+    if status != GRID_OK:
+        raise GridError(status, last_error())
+
+
+def _addr(x) -> int | None:
+    """Device address of a torch tensor (or an int address)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class _Desc:
+    """C view of a robot model (keeps the numpy buffers alive)."""
+
+    def __init__(self, robot):
+        self.parent = np.ascontiguousarray(robot.parent, dtype=np.int32)
+        n = int(self.parent.shape[0])
+        self.arrays = [np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n, -1))
+                       for a in (robot.E_T, robot.r, robot.mass, robot.com, robot.Ic)]
+        E_T, r, mass, com, Ic = self.arrays
+        g = np.asarray(robot.gravity, dtype=np.float64).reshape(3)
+        p = lambda a: a.ctypes.data_as(_f64p)
+        self.c = GridDesc(n, self.parent.ctypes.data_as(_i32p), None, None, p(E_T), p(r),
+                          p(mass), p(com), p(Ic), (C.c_double * 3)(*g))
+
+
+class Model:
+    """A robot model on one device (grid_model)."""
+
+    def __init__(self, robot, device: int = 0, flags: int = 0):
+        self._h = None
+        desc = _Desc(robot)
+        h = C.c_void_p()
+        _check(lib().grid_model_create(C.byref(desc.c), int(device), int(flags), C.byref(h)))
+        self._h = h
+        n = C.c_int32()
+        io = C.c_size_t()
+        lanes = C.c_int32()
+        _check(lib().grid_model_info(h, C.byref(n), C.byref(io), C.byref(lanes)))
+        self.n, self.io_bytes_per_knot, self.lanes_per_knot = n.value, io.value, lanes.value
+        self.device = device
+        self.flags = flags
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().grid_model_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fd_grad(self, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, N=None, stream=None):
+        """grid_fd_grad on device buffers (torch tensors or addresses), asynchronous."""
+        if N is None:
+            N = int(q.shape[0])
+        _check(lib().grid_fd_grad(self._h, int(N), _addr(q), _addr(qd), _addr(tau), _addr(qdd),
+                                  _addr(Minv), _addr(dqdd_dq), _addr(dqdd_dqd),
+                                  _stream_handle(stream)))
+
+
+class Workspace:
+    """grid_workspace: pinned staging + device buffers for the host-pointer call."""
+
+    def __init__(self, model: Model, max_knots: int):
+        self._h = None
+        h = C.c_void_p()
+        _check(lib().grid_workspace_create(model.handle, int(max_knots), C.byref(h)))
+        self._h = h
+        self.model = model
+        self.max_knots = max_knots
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().grid_workspace_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fd_grad_host(self, q, qd, tau):
+        """grid_fd_grad_host on numpy arrays; returns (outputs dict, timing dict)."""
+        n = self.model.n
+        q = np.ascontiguousarray(q, dtype=np.float32).reshape(-1, n)
+        N = q.shape[0]
+        qd = np.ascontiguousarray(qd, dtype=np.float32).reshape(N, n)
+        tau = np.ascontiguousarray(tau, dtype=np.float32).reshape(N, n)
+        out = {"qdd": np.empty((N, n), np.float32), "Minv": np.empty((N, n, n), np.float32),
+               "dqdd_dq": np.empty((N, n, n), np.float32),
+               "dqdd_dqd": np.empty((N, n, n), np.float32)}
+        t = GridTiming()
+        ptr = lambda a: a.ctypes.data
+        _check(lib().grid_fd_grad_host(self.model.handle, self._h, N, ptr(q), ptr(qd), ptr(tau),
+                                       ptr(out["qdd"]), ptr(out["Minv"]), ptr(out["dqdd_dq"]),
+                                       ptr(out["dqdd_dqd"]), C.byref(t)))
+        timing = {k: float(getattr(t, k)) for k in ("h2d_ms", "kernel_ms", "d2h_ms", "total_ms")}
+        return out, timing
+
+
+def codegen_source(parent, flags: int = 0) -> str:
+    p = np.ascontiguousarray(parent, dtype=np.int32)
+    ln = C.c_size_t(0)
+    _check(lib().grid_codegen_source(p.ctypes.data_as(_i32p), len(p), flags, None, C.byref(ln)))
+    buf = C.create_string_buffer(ln.value)
+    _check(lib().grid_codegen_source(p.ctypes.data_as(_i32p), len(p), flags, buf, C.byref(ln)))
+    return buf.value.decode()
+
+
+def codegen_precompile(parent, flags: int = 0):
+    p = np.ascontiguousarray(parent, dtype=np.int32)
+    _check(lib().grid_codegen_precompile(p.ctypes.data_as(_i32p), len(p), flags))
+
+
+def fd_grad_torch(model: Model, q, qd, tau, stream=None):
+    """Allocate outputs with torch on q's device and launch on the current stream."""
+    import torch
+    N, n = q.shape
+    dev = q.device
+    out = {"qdd": torch.empty((N, n), device=dev, dtype=torch.float32),
+           "Minv": torch.empty((N, n, n), device=dev, dtype=torch.float32),
+           "dqdd_dq": torch.empty((N, n, n), device=dev, dtype=torch.float32),
+           "dqdd_dqd": torch.empty((N, n, n), device=dev, dtype=torch.float32)}
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    model.fd_grad(q, qd, tau, out["qdd"], out["Minv"], out["dqdd_dq"], out["dqdd_dqd"], N=N,
+                  stream=stream)
+    return out
