@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: gradient of forward dynamics, knot-evals/s, 7-DoF chain, N = 128 knots.
+
+One step = one batched call of the whole path (transforms, RNEA, CRBA, M^-1, qdd, RNEA
+at qdd, dRNEA forward and backward, -M^-1 dtau) over 128 knot points, with inputs and
+outputs resident in device memory. Prints one JSON line.
+
+Also reported (extra fields of the same line):
+  roofline      the fused kernel's algorithmic FLOP rate against the FP32 vector peak,
+                from HIP-event kernel durations measured here;
+  io_inclusive  the host-pointer call (pinned staging, H2D + kernel + D2H);
+  cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (published)
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused.json")
+
+
+def kernel_source_hash() -> str:
+    path = os.path.join(ROOT, "paper_2109_06976_amd", "csrc", "grid_device.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
+    taken on the current kernel source for this workload."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(workload)
+    if not entry or entry.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--robot", default="chain7")
+    ap.add_argument("--knots", type=int, default=128)
+    ap.add_argument("--seed", type=int, default=102)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="bounded CPU sample for the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-io", action="store_true")
+    ap.add_argument("--sweep", default="", help="comma-separated extra knot counts to time")
+    ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
+                    help="also run a plain device copy of this size (for counter scaling)")
+    return ap.parse_args()
+
+
+def time_steps(torch, launch, steps, warmup):
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        launch()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_durations(torch, launch, count):
+    """Average per-launch duration from HIP events on the launch stream (torch's current)."""
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(count)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(count)]
+    torch.cuda.synchronize()
+    for s, e in zip(starts, ends):
+        s.record()
+        launch()
+        e.record()
+    torch.cuda.synchronize()
+    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms.sort()
+    return sum(ms) / len(ms), ms[len(ms) // 2]
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the batched gradient of forward dynamics shards "
+              "knots across GPUs with no exchange, and this build runs on a single MI355X "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2109_06976_amd import flops, grid, synth
+
+    robot = synth.model_by_name(args.robot)
+    n, N = robot.n, args.knots
+    kn = synth.random_knots(n, N, args.seed)
+    dev = torch.device("cuda:0")
+    model = grid.Model(robot, device=0)
+    stream = torch.cuda.current_stream(dev)
+
+    def buffers(NK, seed):
+        k = synth.random_knots(n, NK, seed)
+        ins = [torch.from_numpy(a).to(dev) for a in (k.q, k.qd, k.tau)]
+        outs = [torch.empty((NK, n), device=dev), torch.empty((NK, n, n), device=dev),
+                torch.empty((NK, n, n), device=dev), torch.empty((NK, n, n), device=dev)]
+        return ins, outs
+
+    ins, outs = buffers(N, args.seed)
+
+    def launch_for(ins_, outs_, NK):
+        return lambda: model.fd_grad(*ins_, *outs_, N=NK, stream=stream)
+
+    launch = launch_for(ins, outs, N)
+    sec_per_step = time_steps(torch, launch, args.steps, args.warmup)
+    avg_ms, med_ms = kernel_durations(torch, launch, min(args.steps, 2000))
+
+    fl = flops.fdgrad_flops(robot.parent)
+    flop_launch = fl["total"] * N
+    achieved_tflops = flop_launch / (avg_ms * 1e-3) / 1e12
+    workload = f"{args.robot}-N{N}"
+    traffic = measured_traffic(workload)
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 4), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
+                "traffic": traffic,
+                "kernel": "grid_fdgrad_fused", "kernel_avg_us": round(avg_ms * 1e3, 3),
+                "kernel_median_us": round(med_ms * 1e3, 3),
+                "flop_per_knot": fl["total"],
+                "hbm_bytes_per_launch": flops.io_bytes_per_knot(n) * N,
+                "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+
+    result = {
+        "metric": "dFD knot-evals/sec (7-DoF chain, N=128)",
+        "value": N / sec_per_step,
+        "unit": "knot-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.robot}: {n}-joint fixed-base robot, N={N} knots, "
+                               "fused kernel, device-resident inputs",
+                   "robot": args.robot, "knots": N, "lanes_per_knot": model.lanes_per_knot},
+        "roofline": roofline,
+    }
+
+    if not args.no_io:
+        ws = grid.Workspace(model, N)
+        for _ in range(20):
+            ws.fd_grad_host(kn.q, kn.qd, kn.tau)
+        reps = 200
+        tot = {"h2d_ms": 0.0, "kernel_ms": 0.0, "d2h_ms": 0.0, "total_ms": 0.0}
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, t = ws.fd_grad_host(kn.q, kn.qd, kn.tau)
+            for k in tot:
+                tot[k] += t[k]
+        wall = (time.perf_counter() - t0) / reps
+        ws.close()
+        result["io_inclusive"] = {
+            "value": N / wall, "unit": "knot-evals/s", "wall_ms_per_call": wall * 1e3,
+            **{k: v / reps for k, v in tot.items()},
+            "note": "host-pointer call: pageable->pinned staging, H2D, kernel, D2H, sync"}
+
+    if args.sweep:
+        sweep = {}
+        for NK in [int(x) for x in args.sweep.split(",") if x]:
+            i2, o2 = buffers(NK, args.seed + NK)
+            l2 = launch_for(i2, o2, NK)
+            s = time_steps(torch, l2, max(200, args.steps // 5), 50)
+            a, m = kernel_durations(torch, l2, 500)
+            sweep[str(NK)] = {"knot_evals_per_s": NK / s, "ms_per_step": s * 1e3,
+                              "kernel_avg_us": a * 1e3,
+                              "alu_frac": fl["total"] * NK / (a * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+        result["sweep"] = sweep
+
+    if args.copy_calibration_mb > 0:
+        nbytes = int(args.copy_calibration_mb * 2**20)
+        src = torch.ones(nbytes // 4, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        om = orc.OracleModel(robot)
+        q, qd, tau = (a.astype(np.float64) for a in (kn.q, kn.qd, kn.tau))
+        orc.fd_grad_batch(om, q, qd, tau)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            orc.fd_grad_batch(om, q, qd, tau)
+            reps += 1
+        el = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": reps * N / el, "unit": "knot-evals/s", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} repetitions of the same {N}-knot {args.robot} batch "
+                      f"({el:.1f} s), FP64 C oracle, OpenMP over knots"}
+
+    model.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,9 +20,7 @@
  *       q, qd, tau, qdd       [N][n]
  *       Minv, dqdd_dq, dqdd_dqd  [N][n][n],  dqdd_dq[k][i][j] = d qdd_i / d q_j at knot k.
  *     M^-1 is returned exactly symmetric.
- *   - Arithmetic: the derivative sweeps and the final product run in float32; the
- *     transforms, RNEA, M, M^-1 and qdd run in float64 unless the model was created
- *     with GRID_FLAG_FP32_DYNAMICS.
+ *   - Arithmetic is float32 throughout.
  *
  * Errors: every call returns a grid_status. Arguments are validated on the host
  * before any device work, so on error nothing has been enqueued. N = 0 is a no-op that
@@ -55,9 +53,6 @@ typedef int32_t grid_status;
 #define GRID_ECOMPILE (-5)      /* generating or compiling the robot's kernel failed */
 
 #define GRID_JOINT_REVOLUTE 0
-
-/* Model creation flags */
-#define GRID_FLAG_FP32_DYNAMICS 1   /* transforms, RNEA, M, M^-1, qdd in float32 too */
 
 typedef struct grid_model_desc {
     int32_t n;                   /* number of joints/bodies, 1..32 */
@@ -93,7 +88,7 @@ const char* grid_last_error(void);
  * robot's kernel: the library writes the topology out as compile-time tables
  * (Sec. IV-C code generation) and compiles it for gfx950, or loads the code object
  * from the kernel cache (directory GRID_KERNEL_CACHE, else the package's _kcache).
- * flags: 0 or GRID_FLAG_FP32_DYNAMICS. On success *out owns device memory until
+ * flags: reserved, must be 0. On success *out owns device memory until
  * grid_model_destroy. Errors: EINVAL (bad description), EUNSUPPORTED (non-z axis,
  * non-revolute joint, n > 32), ECOMPILE, EDEVICE, ENOMEM.
  */
@@ -105,13 +100,15 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
 grid_status grid_model_destroy(grid_model m);
 
 /* n, bytes moved per knot by the host-pointer call (inputs + outputs), and the number
- * of lanes of a 64-lane wavefront one knot occupies. Any pointer may be NULL. */
+ * of wavefront lanes one knot occupies (summed over its base branches). Any pointer
+ * may be NULL. */
 grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
-                            int32_t* lanes_per_knot);
+                            int32_t* lanes);
 
 /*
- * The batched path, one fused kernel launch (steps: transforms, RNEA, CRBA, M^-1,
- * qdd, RNEA at qdd, dRNEA forward/backward, -M^-1 dtau). All pointers are device
+ * The batched path, one fused kernel launch (per knot and per branch of the tree at
+ * the fixed base: transforms, RNEA, M, its sparse factorisation, qdd, RNEA at qdd,
+ * dRNEA forward/backward, -M^-1 dtau and M^-1). All pointers are device
  * pointers in the layouts above; `stream` is a hipStream_t (NULL = default stream).
  * Asynchronous: returns after the launch is enqueued. Errors: EINVAL (N < 0, a NULL
  * pointer with N > 0, N > 2^31/64), EDEVICE (launch failure).

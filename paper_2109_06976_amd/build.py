@@ -73,14 +73,15 @@ def _codegen_source(lib, parent, flags=0) -> str:
 
 
 def offline_compile_check(lib, verbose=False):
-    """hipcc --genco of the generated source for the 7-dof chain (both precisions)."""
+    """hipcc --genco of the generated source for the three workload robots."""
     from paper_2109_06976_amd import synth
-    for flags, tag in ((0, "f64dyn"), (1, "f32dyn")):
-        src = "#include <hip/hip_runtime.h>\n" + _codegen_source(lib, synth.chain_parent(7), flags)
-        path = os.path.join(BUILD, f"chain7_{tag}.hip")
+    for name, parent in (("chain7", synth.chain_parent(7)), ("quad12", synth.quadruped_parent()),
+                         ("humanoid30", synth.humanoid_parent("anatomical"))):
+        src = "#include <hip/hip_runtime.h>\n" + _codegen_source(lib, parent, 0)
+        path = os.path.join(BUILD, f"{name}.hip")
         with open(path, "w") as f:
             f.write(src)
-        out = os.path.join(BUILD, f"chain7_{tag}.hsaco")
+        out = os.path.join(BUILD, f"{name}.hsaco")
         _run([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", *NO_PACKED_FP32, "--genco",
               "-save-temps=obj", "-o", out, path], verbose)
 
@@ -102,7 +103,7 @@ def standard_topologies():
 def precompile(lib, verbose=False):
     import numpy as np
     for parent in standard_topologies():
-        for flags in (0, 1):
+        for flags in (0,):
             p = np.ascontiguousarray(parent, dtype=np.int32)
             st = lib.grid_codegen_precompile(p.ctypes.data_as(C.POINTER(C.c_int32)),
                                              C.c_int32(len(p)), C.c_uint32(flags))

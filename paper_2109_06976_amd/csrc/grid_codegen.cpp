@@ -34,8 +34,7 @@ bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::stri
     Topology t;
     t.n = n;
     t.parent.assign(parent, parent + n);
-    t.level.assign(n, 0);
-    t.branch.assign(n, 0);
+    std::vector<int> root(n, -1);
     for (int i = 0; i < n; ++i) {
         const int p = parent[i];
         if (p < -1 || p >= i) {
@@ -43,92 +42,124 @@ bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::stri
                    " must satisfy -1 <= parent[i] < i";
             return false;
         }
-        t.level[i] = p < 0 ? 0 : t.level[p] + 1;
-        t.branch[i] = p < 0 ? i : t.branch[p];
+        root[i] = p < 0 ? i : root[p];
     }
-    t.nlev = 0;
-    for (int i = 0; i < n; ++i)
-        t.nlev = std::max(t.nlev, t.level[i] + 1);
-    t.level_mask.assign(t.nlev, 0);
-    for (int i = 0; i < n; ++i)
-        t.level_mask[t.level[i]] |= 1ull << i;
-    // inward rounds, deepest level first: round k of a level holds the k-th child of every
-    // parent, so no two bodies of a round add into the same parent
-    t.round_mask.clear();
-    for (int l = t.nlev - 1; l >= 1; --l) {
-        std::vector<std::vector<int>> kids(n);
-        size_t rounds = 0;
+    // one branch per body attached to the fixed base: that body and all its descendants,
+    // in increasing robot index (so every local parent precedes its child)
+    int coff = 0;
+    for (int r = 0; r < n; ++r) {
+        if (parent[r] >= 0)
+            continue;
+        BranchInst inst;
+        std::vector<int> local(n, -1);
         for (int i = 0; i < n; ++i)
-            if (t.level[i] == l) {
-                kids[parent[i]].push_back(i);
-                rounds = std::max(rounds, kids[parent[i]].size());
+            if (root[i] == r) {
+                local[i] = (int)inst.body.size();
+                inst.body.push_back(i);
+                inst.mask |= 1ull << i;
             }
-        for (size_t k = 0; k < rounds; ++k) {
-            uint64_t m = 0;
-            for (int p = 0; p < n; ++p)
-                if (k < kids[p].size())
-                    m |= 1ull << kids[p][k];
-            t.round_mask.push_back(m);
+        BranchShape shape;
+        shape.B = (int)inst.body.size();
+        for (int k = 0; k < shape.B; ++k) {
+            const int p = parent[inst.body[k]];
+            shape.parent.push_back(p < 0 ? -1 : local[p]);
+            uint64_t anc = 0;
+            for (int a = shape.parent[k]; a >= 0; a = shape.parent[a])
+                anc |= 1ull << a;
+            shape.anc.push_back(anc);
         }
-    }
-    // related[i]: bodies on the same root path as i (ancestors, descendants, itself);
-    // M_ik is structurally zero for every other k
-    t.related.assign(n, 0);
-    for (int i = 0; i < n; ++i) {
-        t.related[i] |= 1ull << i;
-        for (int a = parent[i]; a >= 0; a = parent[a]) {
-            t.related[i] |= 1ull << a;
-            t.related[a] |= 1ull << i;
+        shape.L = 2;
+        while (shape.L < 2 * shape.B)
+            shape.L *= 2;
+        int sid = -1;
+        for (size_t s = 0; s < t.shapes.size(); ++s)
+            if (t.shapes[s].parent == shape.parent)
+                sid = (int)s;
+        if (sid < 0) {
+            sid = (int)t.shapes.size();
+            t.shapes.push_back(shape);
         }
+        inst.shape = sid;
+        inst.coff = coff;
+        coff += shape.B * kConstStride;
+        t.insts.push_back(inst);
     }
-    t.max_anc = t.nlev - 1;
-    int lanes = 2;
-    while (lanes < 2 * n)
-        lanes *= 2;
-    t.lanes = lanes;
     *out = std::move(t);
     return true;
 }
 
-static void emit_int_array(std::ostringstream& os, const char* name, const std::vector<int>& v)
+int64_t workgroups_for(const Topology& t, int64_t nknots)
 {
-    os << "__device__ constexpr int " << name << "[" << std::max<size_t>(1, v.size()) << "] = {";
-    if (v.empty())
-        os << "0";
-    for (size_t i = 0; i < v.size(); ++i)
-        os << (i ? ", " : "") << v[i];
-    os << "};\n";
+    int64_t total = 0;
+    for (const BranchInst& inst : t.insts) {
+        const int K = 64 / t.shapes[inst.shape].L;
+        total += (nknots + K - 1) / K;
+    }
+    return total;
 }
 
-static void emit_mask_array(std::ostringstream& os, const char* name,
-                            const std::vector<uint64_t>& v)
+int lanes_per_knot(const Topology& t)
 {
-    os << "__device__ constexpr unsigned long long " << name << "["
-       << std::max<size_t>(1, v.size()) << "] = {";
-    if (v.empty())
-        os << "0ull";
+    int lanes = 0;
+    for (const BranchInst& inst : t.insts)
+        lanes += t.shapes[inst.shape].L;
+    return lanes;
+}
+
+template <class T>
+static void emit_list(std::ostringstream& os, const std::vector<T>& v, const char* suffix = "")
+{
+    os << "{";
     for (size_t i = 0; i < v.size(); ++i)
-        os << (i ? ", " : "") << "0x" << std::hex << v[i] << std::dec << "ull";
-    os << "};\n";
+        os << (i ? ", " : "") << v[i] << suffix;
+    os << "}";
 }
 
 std::string generate_source(const Topology& t, uint32_t flags)
 {
+    (void)flags;
     std::ostringstream os;
-    os << "// generated: one robot topology as compile-time tables\n";
+    os << "// generated: one robot topology as compile-time structures\n";
     os << "#define GRID_N " << t.n << "\n";
-    os << "#define GRID_L " << t.lanes << "\n";
-    os << "#define GRID_NLEV " << t.nlev << "\n";
-    os << "#define GRID_NROUND " << t.round_mask.size() << "\n";
-    os << "#define GRID_MAXANC " << t.max_anc << "\n";
-    os << "#define GRID_DYN_DOUBLE " << ((flags & GRID_FLAG_FP32_DYNAMICS) ? 0 : 1) << "\n";
-    emit_int_array(os, "kParent", t.parent);
-    emit_int_array(os, "kBranch", t.branch);
-    emit_mask_array(os, "kRelated", t.related);
-    emit_mask_array(os, "kLevelMask", t.level_mask);
-    emit_mask_array(os, "kRoundMask", t.round_mask);
+    os << "template <int s> struct Shape;\ntemplate <int k> struct Inst;\n";
+    for (size_t s = 0; s < t.shapes.size(); ++s) {
+        const BranchShape& sh = t.shapes[s];
+        os << "template <> struct Shape<" << s << "> {\n";
+        os << "    static constexpr int B = " << sh.B << ";\n";
+        os << "    static constexpr int L = " << sh.L << ";\n";
+        os << "    static constexpr int parent[B] = ";
+        emit_list(os, sh.parent);
+        os << ";\n    static constexpr unsigned long long anc[B] = ";
+        emit_list(os, sh.anc, "ull");
+        os << ";\n};\n";
+    }
+    for (size_t k = 0; k < t.insts.size(); ++k) {
+        const BranchInst& in = t.insts[k];
+        os << "template <> struct Inst<" << k << "> {\n";
+        os << "    using S = Shape<" << in.shape << ">;\n";
+        os << "    static constexpr int body[S::B] = ";
+        emit_list(os, in.body);
+        os << ";\n    static constexpr int coff = " << in.coff << ";\n";
+        os << "    static constexpr unsigned long long mask = " << in.mask << "ull;\n";
+        os << "    __device__ static int body_of(int i) {\n"
+              "        int r = body[0];\n"
+              "#pragma unroll\n"
+              "        for (int k = 1; k < S::B; ++k) r = (i == k) ? body[k] : r;\n"
+              "        return r;\n    }\n";
+        os << "    __device__ static bool contains(int g) { return (mask >> g) & 1ull; }\n";
+        os << "};\n";
+    }
     os << "#line 1 \"grid_device.hip\"\n";
     os << grid_device_src;
+    os << "\n// generated: workgroup -> (branch, knot group)\n";
+    os << "__device__ void grid_dispatch(const grid::Args& a, int block)\n{\n    int b = block;\n";
+    for (size_t k = 0; k < t.insts.size(); ++k) {
+        os << "    {\n        constexpr int K = 64 / Inst<" << k << ">::S::L;\n"
+           << "        const int nb = (a.nknots + K - 1) / K;\n"
+           << "        if (b < nb) {\n            grid::run_branch<Inst<" << k
+           << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
+    }
+    os << "}\n";
     return os.str();
 }
 

@@ -1,30 +1,35 @@
 // Batched gradient of forward dynamics, CDNA4 (gfx950) device code.
 //
-// This file is compiled at model-creation time (hiprtc) behind a generated prelude that
-// fixes one robot's topology as compile-time tables (see grid_codegen.cpp):
-//   GRID_N, GRID_L, GRID_NLEV, GRID_NROUND, GRID_MAXANC, GRID_DYN_DOUBLE,
-//   kParent[n], kBranch[n], kLevelMask[NLEV], kRoundMask[NROUND].
-// Every loop over bodies is unrolled against those tables, so a kernel is one robot's
-// kinematic tree written out (the paper's code generation, Sec. IV-C).
+// Compiled at model-creation time (hiprtc) behind a generated prelude that writes one
+// robot's topology out as compile-time structures (grid_codegen.cpp):
+//   GRID_N                      joints of the robot
+//   Shape<s>  { B, L, parent[B], anc[B] }   a base branch shape: B bodies in local
+//                               numbering, lanes per knot L, parents, strict-ancestor masks
+//   Inst<k>   { using S; body[B]; coff }    one base branch of the robot: its shape,
+//                               the robot index of each local body, and the offset of its
+//                               constants
+//   grid_dispatch(args, block)  maps a workgroup to (branch, knot group) and runs it
 //
-// One workgroup is one wavefront (64 lanes) and holds K = 64 / GRID_L knots; each knot
-// owns GRID_L lanes and a private LDS slice. Because a workgroup is a single wavefront,
-// the level-by-level sweeps synchronise with a wave barrier only.
+// Branches hanging off the fixed base are dynamically independent: M is block diagonal
+// over them, so M^-1, qdd and dqdd/du are computed branch by branch, each by its own lane
+// group, and rows of other branches are zero.
 //
-// Per knot (paper Sec. IV-B):
-//   1. X_i(q_i) = (E_i, r_i) with E_i = E_z(q_i) E_T,i                  [lanes = bodies]
-//   2. RNEA(q, qd, 0) outward by tree level, f_i, inward by rounds -> c  [lanes = bodies]
-//      composite inertias (CRBA) ride along the same inward rounds
-//   3. M from the composite inertias, each lane walking its ancestors    [lanes = columns]
-//   4. M^-1 by in-place Gauss-Jordan (M is SPD: no pivoting)             [lanes = entries]
-//   5. qdd = M^-1 (tau - c)                                              [lanes = rows]
-//   6. RNEA at qdd: a_i, f_i and the column-independent temporaries of Algorithm 2
-//      (alpha_i = v_i x S, beta_i = (X_i a_lambda) x S, gamma_i = I_i v_i, and the
-//      backward source zeta_i = X_i^T (S x* f_i))                        [lanes = bodies]
-//   7. dRNEA forward and backward pass, one derivative column per lane   [lanes = 2n columns]
-//   8. dqdd/du = -M^-1 dtau/du for the lane's column; stores             [lanes = columns]
-// Steps 1-6 run in DT (double when GRID_DYN_DOUBLE: M can be ill-conditioned); the
-// derivative sweeps 7-8, the bulk of the arithmetic, run in float.
+// One workgroup is one wavefront. A branch of B bodies occupies L lanes (a power of two
+// >= 2B), so a wavefront holds K = 64 / L (knot, branch) problems. Every lane keeps the
+// branch's body quantities in registers and runs the shared recursions itself, so the
+// tree sweeps need no cross-lane traffic; lanes differ only in the derivative column
+// they own. The single exchange is the mass matrix, passed through LDS once.
+//
+// Per (knot, branch), all float32 (Sec. IV-B):
+//   1. X_i = (E_i, r_i), E_i = E_z(q_i) E_T,i
+//   2. RNEA(q, qd, 0): v_i, a_i, f_i outward, accumulated f inward; c_i = S^T f_i
+//   3. column t of M as ID(q, 0, e_t) without gravity (one column per lane), LDS exchange
+//   4. M = L^T L, sparse factorization along ancestor paths (no fill-in on a tree)
+//   5. qdd = M^-1 (tau - c) by the two triangular solves
+//   6. RNEA at qdd: a_i, f_i; the lane captures the source terms of its own column j:
+//      (X_j v_lambda) x S = v_j x S, (X_j a_lambda) x S, and X_j^T (S x* f_j)
+//   7. dRNEA forward (Algorithm 1) and backward pass for the lane's column (u, j)
+//   8. dqdd/du_j = -M^-1 dtau/du_j and column t of M^-1 by the same solves; stores
 //
 // Spatial vectors are [angular; linear]; S = e_3 (revolute about the joint z axis).
 
@@ -34,23 +39,13 @@
 
 namespace grid {
 
-constexpr int N = GRID_N;
-constexpr int L = GRID_L;              // lanes per knot
-constexpr int K = 64 / GRID_L;         // knots per wavefront
-constexpr int NN = N * N;
-constexpr int kBodyStride = 24;        // doubles of model constants per body
-// body constant layout: [0..8] E_T (row-major), [9..11] r, [12..17] Ibar (xx yy zz xy xz yz
-// about the body origin), [18..20] h = m c, [21] m
-
-#if GRID_DYN_DOUBLE
-typedef double DT;
-#else
-typedef float DT;
-#endif
+constexpr int kConstStride = 24;   // floats of model constants per body
+// body constants: [0..8] E_T (row-major), [9..11] r, [12..17] Ibar (xx yy zz xy xz yz about
+// the body origin), [18..20] h = m c, [21] m
 
 struct Args {
-    const double* model;   // N * kBodyStride
-    double a0[3];          // linear part of the base acceleration, -g
+    const float* cf;      // constants, branch by branch in local order
+    float a0[3];          // linear part of the base acceleration, -g
     int nknots;
     const float* q;
     const float* qd;
@@ -61,40 +56,18 @@ struct Args {
     float* dqdd_dqd;
 };
 
-struct KnotLds {
-    DT E[N][9];
-    DT r[N][3];
-    DT v[N][6];
-    DT a[N][6];
-    DT F[N][6];
-    DT IC[N][10];          // composite inertia: m, h[3], Ibar[6]
-    DT M[N][N];            // M, then M^-1 in place
-    DT qd[N];
-    DT tmc[N];             // tau - c
-    DT qdd[N];
-    float Ef[N][12];       // E (9) and r (3) in float
-    float vf[N][6];
-    float gam[N][6];       // gamma_i = I_i v_i
-    float alpha[N][6];     // alpha_i = v_i x S
-    float beta[N][6];      // beta_i = (X_i a_lambda) x S
-    float zeta[N][6];      // X_i^T (S x* f_i)
-    float qdf[N];
-    float minvf[N][N];
-};
-
 __device__ __forceinline__ void wave_sync()
 {
-    // the workgroup is exactly one wavefront: this orders LDS traffic within it
+    // a workgroup is exactly one wavefront: this only orders its LDS traffic
     __syncthreads();
 }
 
-template <class T>
-__device__ __forceinline__ void x_mv(const T* E, const T* r, const T* m, T* y)
+// X m = [E w; E (v - r x w)]
+__device__ __forceinline__ void x_mv(const float* E, const float* r, const float* m, float* y)
 {
-    // X m = [E w; E (v - r x w)]
-    const T t0 = m[3] - (r[1] * m[2] - r[2] * m[1]);
-    const T t1 = m[4] - (r[2] * m[0] - r[0] * m[2]);
-    const T t2 = m[5] - (r[0] * m[1] - r[1] * m[0]);
+    const float t0 = m[3] - (r[1] * m[2] - r[2] * m[1]);
+    const float t1 = m[4] - (r[2] * m[0] - r[0] * m[2]);
+    const float t2 = m[5] - (r[0] * m[1] - r[1] * m[0]);
     y[0] = E[0] * m[0] + E[1] * m[1] + E[2] * m[2];
     y[1] = E[3] * m[0] + E[4] * m[1] + E[5] * m[2];
     y[2] = E[6] * m[0] + E[7] * m[1] + E[8] * m[2];
@@ -103,28 +76,26 @@ __device__ __forceinline__ void x_mv(const T* E, const T* r, const T* m, T* y)
     y[5] = E[6] * t0 + E[7] * t1 + E[8] * t2;
 }
 
-template <class T>
-__device__ __forceinline__ void xt_fv(const T* E, const T* r, const T* f, T* y)
+// X^T f = [E^T n + r x (E^T f_l); E^T f_l]
+__device__ __forceinline__ void xt_fv(const float* E, const float* r, const float* f, float* y)
 {
-    // X^T f = [E^T n + r x (E^T f_l); E^T f_l]
-    const T l0 = E[0] * f[3] + E[3] * f[4] + E[6] * f[5];
-    const T l1 = E[1] * f[3] + E[4] * f[4] + E[7] * f[5];
-    const T l2 = E[2] * f[3] + E[5] * f[4] + E[8] * f[5];
-    const T n0 = E[0] * f[0] + E[3] * f[1] + E[6] * f[2];
-    const T n1 = E[1] * f[0] + E[4] * f[1] + E[7] * f[2];
-    const T n2 = E[2] * f[0] + E[5] * f[1] + E[8] * f[2];
-    y[0] = n0 + (r[1] * l2 - r[2] * l1);
-    y[1] = n1 + (r[2] * l0 - r[0] * l2);
-    y[2] = n2 + (r[0] * l1 - r[1] * l0);
+    const float l0 = E[0] * f[3] + E[3] * f[4] + E[6] * f[5];
+    const float l1 = E[1] * f[3] + E[4] * f[4] + E[7] * f[5];
+    const float l2 = E[2] * f[3] + E[5] * f[4] + E[8] * f[5];
+    y[0] = E[0] * f[0] + E[3] * f[1] + E[6] * f[2] + (r[1] * l2 - r[2] * l1);
+    y[1] = E[1] * f[0] + E[4] * f[1] + E[7] * f[2] + (r[2] * l0 - r[0] * l2);
+    y[2] = E[2] * f[0] + E[5] * f[1] + E[8] * f[2] + (r[0] * l1 - r[1] * l0);
     y[3] = l0;
     y[4] = l1;
     y[5] = l2;
 }
 
-template <class T>
-__device__ __forceinline__ void inertia_mv(const T* Ib, const T* h, T m, const T* x, T* y)
+// rigid-body inertia about the body origin: I x = [Ibar w + h x v; m v - h x w]
+__device__ __forceinline__ void inertia_mv(const float* c, const float* x, float* y)
 {
-    // I x = [Ibar w + h x v; m v - h x w]
+    const float* Ib = c + 12;
+    const float* h = c + 18;
+    const float m = c[21];
     y[0] = Ib[0] * x[0] + Ib[3] * x[1] + Ib[4] * x[2] + (h[1] * x[5] - h[2] * x[4]);
     y[1] = Ib[3] * x[0] + Ib[1] * x[1] + Ib[5] * x[2] + (h[2] * x[3] - h[0] * x[5]);
     y[2] = Ib[4] * x[0] + Ib[5] * x[1] + Ib[2] * x[2] + (h[0] * x[4] - h[1] * x[3]);
@@ -133,10 +104,9 @@ __device__ __forceinline__ void inertia_mv(const T* Ib, const T* h, T m, const T
     y[5] = m * x[5] - (h[0] * x[1] - h[1] * x[0]);
 }
 
-template <class T>
-__device__ __forceinline__ void crf_mv(const T* v, const T* f, T* y)
+// v x* f = [w x n + v_l x f_l; w x f_l]
+__device__ __forceinline__ void crf_mv(const float* v, const float* f, float* y)
 {
-    // v x* f = [w x n + v_l x f_l; w x f_l]
     y[0] = v[1] * f[2] - v[2] * f[1] + v[4] * f[5] - v[5] * f[4];
     y[1] = v[2] * f[0] - v[0] * f[2] + v[5] * f[3] - v[3] * f[5];
     y[2] = v[0] * f[1] - v[1] * f[0] + v[3] * f[4] - v[4] * f[3];
@@ -146,463 +116,392 @@ __device__ __forceinline__ void crf_mv(const T* v, const T* f, T* y)
 }
 
 // (m x) S for S = e_3
-template <class T>
-__device__ __forceinline__ void cross_S(const T* m, T* y)
+__device__ __forceinline__ void cross_S(const float* m, float* y)
 {
     y[0] = m[1];
     y[1] = -m[0];
-    y[2] = 0;
+    y[2] = 0.0f;
     y[3] = m[4];
     y[4] = -m[3];
-    y[5] = 0;
+    y[5] = 0.0f;
 }
 
-// Composite inertia update IC_p += X^T IC_i X for rigid-body inertias kept as
-// (m, h, Ibar): h' = E^T h + m r,
-// Ibar' = E^T Ibar E + (m|r|^2 + 2 r.y) 1 - m r r^T - y r^T - r y^T, y = E^T h.
-__device__ __forceinline__ void inertia_to_parent(const DT* E, const DT* r, const DT* ic, DT* out)
+template <class S>
+__device__ __forceinline__ constexpr bool is_anc(int a, int i)   // a strict ancestor of i
 {
-    const DT m = ic[0];
-    const DT* h = ic + 1;
-    const DT* I = ic + 4;   // xx yy zz xy xz yz
-    const DT Ib[9] = {I[0], I[3], I[4], I[3], I[1], I[5], I[4], I[5], I[2]};
-    DT y[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-        y[a] = E[0 * 3 + a] * h[0] + E[1 * 3 + a] * h[1] + E[2 * 3 + a] * h[2];
-    DT B[9];   // Ibar E
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            B[a * 3 + b] = Ib[a * 3 + 0] * E[0 * 3 + b] + Ib[a * 3 + 1] * E[1 * 3 + b] +
-                           Ib[a * 3 + 2] * E[2 * 3 + b];
-    DT C[9];   // E^T B (symmetric)
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = a; b < 3; ++b)
-            C[a * 3 + b] = E[0 * 3 + a] * B[0 * 3 + b] + E[1 * 3 + a] * B[1 * 3 + b] +
-                           E[2 * 3 + a] * B[2 * 3 + b];
-    const DT ry = r[0] * y[0] + r[1] * y[1] + r[2] * y[2];
-    const DT rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    const DT d = m * rr + 2 * ry;
-    out[0] += m;
-    out[1] += y[0] + m * r[0];
-    out[2] += y[1] + m * r[1];
-    out[3] += y[2] + m * r[2];
-    out[4] += C[0] + d - m * r[0] * r[0] - 2 * y[0] * r[0];
-    out[5] += C[4] + d - m * r[1] * r[1] - 2 * y[1] * r[1];
-    out[6] += C[8] + d - m * r[2] * r[2] - 2 * y[2] * r[2];
-    out[7] += C[1] - m * r[0] * r[1] - y[0] * r[1] - r[0] * y[1];
-    out[8] += C[2] - m * r[0] * r[2] - y[0] * r[2] - r[0] * y[2];
-    out[9] += C[5] - m * r[1] * r[2] - y[1] * r[2] - r[1] * y[2];
+    return (S::anc[i] >> a) & 1ull;
 }
 
-__device__ __forceinline__ void sincos_dt(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ void sincos_dt(float x, float* s, float* c) { sincosf(x, s, c); }
-
-__device__ __forceinline__ bool in_mask(unsigned long long mask, int t)
+// In place x <- (L^T L)^-1 x for the factor produced by ltl_factor (L lower triangular,
+// nonzero only on ancestor paths; dinv[k] = 1 / L_kk).
+template <class S>
+__device__ __forceinline__ void ltl_solve(const float (&Lf)[S::B][S::B], const float (&dinv)[S::B],
+                                          float (&x)[S::B])
 {
-    return t < 64 && ((mask >> t) & 1ull);
+    constexpr int B = S::B;
+#pragma unroll
+    for (int k = B - 1; k >= 0; --k) {       // x <- L^-T x
+        x[k] *= dinv[k];
+#pragma unroll
+        for (int a = 0; a < B; ++a)
+            if (is_anc<S>(a, k))
+                x[a] -= Lf[k][a] * x[k];
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) {            // x <- L^-1 x
+#pragma unroll
+        for (int a = 0; a < B; ++a)
+            if (is_anc<S>(a, k))
+                x[k] -= Lf[k][a] * x[a];
+        x[k] *= dinv[k];
+    }
 }
 
-}  // namespace grid
-
-using namespace grid;
-
-extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_fused(Args args)
+template <class I>
+__device__ __forceinline__ void run_branch(const Args& A, int kg)
 {
-    __shared__ double s_model[N * kBodyStride];
-    __shared__ KnotLds s_knot[K];
+    using S = typename I::S;
+    constexpr int B = S::B;
+    constexpr int L = S::L;
+    constexpr int K = 64 / L;
+    constexpr int N = GRID_N;
+    __shared__ float s_M[K][B][B];
 
     const int lane = threadIdx.x;
-    const int g = lane / L;            // knot slot in this wavefront
-    const int t = lane % L;            // lane within the knot
-    const int knot_raw = blockIdx.x * K + g;
-    const bool valid = knot_raw < args.nknots;
-    const int knot = valid ? knot_raw : args.nknots - 1;   // tail slots recompute the last knot
-    KnotLds& S = s_knot[g];
+    const int g = lane / L;                 // problem slot in the wavefront
+    const int t = lane % L;                 // lane within the problem
+    const int kraw = kg * K + g;
+    const bool valid = kraw < A.nknots;
+    const int knot = valid ? kraw : A.nknots - 1;   // tail slots recompute the last knot
+    const float* C = A.cf + I::coff;        // uniform: scalar loads
 
-    for (int e = lane; e < N * kBodyStride; e += 64)
-        s_model[e] = args.model[e];
+    // lane roles: M column jm; derivative column (u, j): u = 0 -> d/dq, u = 1 -> d/dqd
+    const int jm = t % B;
+    const int col = t % (2 * B);
+    const int u = col / B;
+    const int j = col % B;
+    const bool owns_col = t < 2 * B;
 
-    // ---------------------------------------------------------------- 1. transforms
-    DT my_tau = 0;
-    if (t < N) {
-        const DT qi = (DT)args.q[(long)knot * N + t];
-        const DT qdi = (DT)args.qd[(long)knot * N + t];
-        my_tau = (DT)args.tau[(long)knot * N + t];
-        DT s, c;
-        sincos_dt(qi, &s, &c);
-        const double* b = args.model + t * kBodyStride;   // read once from global
-        DT ET[9], rT[3];
+    // ------------------------------------------------------------ 1. transforms
+    float q[B], qd[B], tau[B];
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
-            ET[k] = (DT)b[k];
+    for (int i = 0; i < B; ++i) {
+        const long o = (long)knot * N + I::body[i];
+        q[i] = A.q[o];
+        qd[i] = A.qd[o];
+        tau[i] = A.tau[o];
+    }
+    float E[B][9];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            rT[k] = (DT)b[9 + k];
-        // E = E_z(q) E_T, E_z = [[c, s, 0], [-s, c, 0], [0, 0, 1]]
+    for (int i = 0; i < B; ++i) {
+        const float* c = C + i * kConstStride;
+        float s, co;
+        sincosf(q[i], &s, &co);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            S.E[t][k] = c * ET[k] + s * ET[3 + k];
-            S.E[t][3 + k] = -s * ET[k] + c * ET[3 + k];
-            S.E[t][6 + k] = ET[6 + k];
-            S.r[t][k] = rT[k];
+            E[i][k] = co * c[k] + s * c[3 + k];
+            E[i][3 + k] = co * c[3 + k] - s * c[k];
+            E[i][6 + k] = c[6 + k];
         }
-        S.qd[t] = qdi;
-        S.qdf[t] = (float)qdi;
-        S.IC[t][0] = (DT)b[21];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            S.IC[t][1 + k] = (DT)b[18 + k];
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            S.IC[t][4 + k] = (DT)b[12 + k];
     }
-    wave_sync();
+    const float a0[6] = {0.0f, 0.0f, 0.0f, A.a0[0], A.a0[1], A.a0[2]};
+    const float zero6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 
-    // ---------------------------------------------------------------- 2. RNEA(q, qd, 0)
-    // outward by tree level: v_i = X_i v_p + S qd_i, a_i = X_i a_p + (v_i x S) qd_i
+    // ------------------------------------------------------------ 2. RNEA(q, qd, 0)
+    float v[B][6], a[B][6], F[B][6];
 #pragma unroll
-    for (int l = 0; l < GRID_NLEV; ++l) {
-        if (in_mask(kLevelMask[l], t)) {
-            const int p = kParent[t];
-            DT vp[6], ap[6];
+    for (int i = 0; i < B; ++i) {
+        const int p = S::parent[i];
+        const float* c = C + i * kConstStride;
+        float xv[6], xa[6], vxs[6], Iv[6], Ia[6], w[6];
+        x_mv(E[i], c + 9, p < 0 ? zero6 : v[p < 0 ? 0 : p], xv);
+        x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa);
+        xv[2] += qd[i];
+        cross_S(xv, vxs);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                vp[k] = p < 0 ? (DT)0 : S.v[p][k];
-                ap[k] = p < 0 ? (k < 3 ? (DT)0 : (DT)args.a0[k - 3]) : S.a[p][k];
-            }
-            DT v[6], xa[6], vxs[6];
-            x_mv(S.E[t], S.r[t], vp, v);
-            v[2] += S.qd[t];
-            x_mv(S.E[t], S.r[t], ap, xa);
-            cross_S(v, vxs);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                S.v[t][k] = v[k];
-                S.a[t][k] = xa[k] + vxs[k] * S.qd[t];
-            }
+        for (int k = 0; k < 6; ++k) {
+            v[i][k] = xv[k];
+            a[i][k] = xa[k] + vxs[k] * qd[i];
         }
-        wave_sync();
-    }
-    // f_i = I_i a_i + v_i x* (I_i v_i)
-    if (t < N) {
-        const double* b = s_model + t * kBodyStride;
-        DT Ib[6], h[3];
+        inertia_mv(c, v[i], Iv);
+        inertia_mv(c, a[i], Ia);
+        crf_mv(v[i], Iv, w);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            Ib[k] = (DT)b[12 + k];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            h[k] = (DT)b[18 + k];
-        const DT m = (DT)b[21];
-        DT v[6], a[6], Iv[6], Ia[6], w[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            v[k] = S.v[t][k];
-            a[k] = S.a[t][k];
-        }
-        inertia_mv(Ib, h, m, v, Iv);
-        inertia_mv(Ib, h, m, a, Ia);
-        crf_mv(v, Iv, w);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            S.F[t][k] = Ia[k] + w[k];
-            S.vf[t][k] = (float)v[k];
-            S.gam[t][k] = (float)Iv[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 9; ++k)
-            S.Ef[t][k] = (float)S.E[t][k];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            S.Ef[t][9 + k] = (float)S.r[t][k];
+            F[i][k] = Ia[k] + w[k];
     }
-    wave_sync();
-    // inward: f_p += X_i^T f_i and IC_p += X_i^T IC_i X_i, in rounds whose bodies have
-    // distinct parents, deepest level first
 #pragma unroll
-    for (int rd = 0; rd < GRID_NROUND; ++rd) {
-        if (in_mask(kRoundMask[rd], t)) {
-            const int p = kParent[t];
-            DT y[6];
-            xt_fv(S.E[t], S.r[t], S.F[t], y);
+    for (int i = B - 1; i >= 0; --i) {
+        const int p = S::parent[i];
+        if (p >= 0) {
+            float y[6];
+            xt_fv(E[i], C + i * kConstStride + 9, F[i], y);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                S.F[p][k] += y[k];
-            inertia_to_parent(S.E[t], S.r[t], S.IC[t], S.IC[p]);
+                F[p][k] += y[k];
         }
-        wave_sync();
     }
-    if (t < N)
-        S.tmc[t] = my_tau - S.F[t][2];   // c_i = S^T f_i
-
-    // ---------------------------------------------------------------- 3. M from IC
-    // lane t owns column t: F = IC_t S, M_tt = S^T F; walk up j -> parent(j):
-    // F = X_j^T F, M_{parent(j), t} = S^T F
-    if (t < N) {
-        DT f[6];
-        f[0] = S.IC[t][8];     // Ibar_xz
-        f[1] = S.IC[t][9];     // Ibar_yz
-        f[2] = S.IC[t][6];     // Ibar_zz
-        f[3] = -S.IC[t][2];    // -h_y
-        f[4] = S.IC[t][1];     //  h_x
-        f[5] = 0;
-        S.M[t][t] = f[2];
-        int j = t;
+    float x[B];                                   // becomes qdd
 #pragma unroll
-        for (int step = 0; step < GRID_MAXANC; ++step) {
-            const int p = j < 0 ? -1 : kParent[j];
-            if (p >= 0) {
-                DT y[6];
-                xt_fv(S.E[j], S.r[j], f, y);
+    for (int i = 0; i < B; ++i)
+        x[i] = tau[i] - F[i][2];                  // tau - c
+
+    // ------------------------------------------------------------ 3. column jm of M
+    {
+        float am[B][6], fm[B][6];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int p = S::parent[i];
+            const float* c = C + i * kConstStride;
+            if (p >= 0)
+                x_mv(E[i], c + 9, am[p < 0 ? 0 : p], am[i]);
+            else
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
-                    f[k] = y[k];
-                S.M[p][t] = f[2];
-                S.M[t][p] = f[2];
-            }
-            j = p;
+                    am[i][k] = 0.0f;
+            am[i][2] += (i == jm) ? 1.0f : 0.0f;
+            inertia_mv(c, am[i], fm[i]);
         }
-    }
-    wave_sync();
-    // zero the entries no walk touched: (i, k) with neither an ancestor of the other
-    for (int e = t; e < NN; e += L) {
-        const int i = e / N, k = e % N;
-        if (!(kRelated[i] >> k & 1ull))
-            S.M[i][k] = 0;
-    }
-    wave_sync();
-
-    // ---------------------------------------------------------------- 4. Gauss-Jordan
-    constexpr int EPL = (NN + L - 1) / L;   // entries per lane
-#pragma unroll 1
-    for (int p = 0; p < N; ++p) {
-        DT nv[EPL];
-        const DT piv = (DT)1 / S.M[p][p];
 #pragma unroll
-        for (int s = 0; s < EPL; ++s) {
-            const int e = t + s * L;
-            if (e < NN) {
-                const int i = e / N, k = e % N;
-                const DT aik = S.M[i][k], aip = S.M[i][p], apk = S.M[p][k];
-                DT r;
-                if (i == p && k == p)
-                    r = piv;
-                else if (i == p)
-                    r = apk * piv;
-                else if (k == p)
-                    r = -aip * piv;
-                else
-                    r = aik - aip * apk * piv;
-                nv[s] = r;
+        for (int i = B - 1; i >= 0; --i) {
+            const int p = S::parent[i];
+            if (p >= 0) {
+                float y[6];
+                xt_fv(E[i], C + i * kConstStride + 9, fm[i], y);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    fm[p][k] += y[k];
             }
         }
-        wave_sync();
+        if (t < B) {
 #pragma unroll
-        for (int s = 0; s < EPL; ++s) {
-            const int e = t + s * L;
-            if (e < NN)
-                S.M[e / N][e % N] = nv[s];
+            for (int i = 0; i < B; ++i)
+                s_M[g][i][t] = fm[i][2];
         }
-        wave_sync();
-    }
-    // mirror the upper triangle: M^-1 is returned exactly symmetric
-    for (int e = t; e < NN; e += L) {
-        const int i = e / N, k = e % N;
-        const DT val = i <= k ? S.M[i][k] : S.M[k][i];
-        S.minvf[i][k] = (float)val;
-    }
-
-    // ---------------------------------------------------------------- 5. qdd
-    if (t < N) {
-        DT acc = 0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const DT mik = t <= k ? S.M[t][k] : S.M[k][t];
-            acc += mik * S.tmc[k];
-        }
-        S.qdd[t] = acc;
-        if (valid)
-            args.qdd[(long)knot * N + t] = (float)acc;
     }
     wave_sync();
 
-    // ---------------------------------------------------------------- 6. RNEA at qdd
+    // ------------------------------------------------------------ 4. M = L^T L
+    float Lf[B][B], dinv[B];
 #pragma unroll
-    for (int l = 0; l < GRID_NLEV; ++l) {
-        if (in_mask(kLevelMask[l], t)) {
-            const int p = kParent[t];
-            DT ap[6];
+    for (int i = 0; i < B; ++i)
 #pragma unroll
-            for (int k = 0; k < 6; ++k)
-                ap[k] = p < 0 ? (k < 3 ? (DT)0 : (DT)args.a0[k - 3]) : S.a[p][k];
-            DT xa[6], vxs[6], v[6], bxs[6];
+        for (int b = 0; b <= i; ++b)
+            if (b == i || is_anc<S>(b, i))
+                Lf[i][b] = s_M[g][i][b];
 #pragma unroll
-            for (int k = 0; k < 6; ++k)
-                v[k] = S.v[t][k];
-            x_mv(S.E[t], S.r[t], ap, xa);
-            cross_S(v, vxs);
-            cross_S(xa, bxs);
+    for (int k = B - 1; k >= 0; --k) {
+        const float d = sqrtf(Lf[k][k]);
+        const float di = 1.0f / d;
+        dinv[k] = di;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                S.a[t][k] = xa[k] + vxs[k] * S.qd[t];
-                S.beta[t][k] = (float)bxs[k];
-                S.alpha[t][k] = (float)vxs[k];
-            }
-            S.a[t][2] += S.qdd[t];
-        }
-        wave_sync();
+        for (int b = 0; b < B; ++b)
+            if (is_anc<S>(b, k))
+                Lf[k][b] *= di;
+#pragma unroll
+        for (int a2 = 0; a2 < B; ++a2)
+            if (is_anc<S>(a2, k))
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    if (b == a2 || is_anc<S>(b, a2))
+                        Lf[a2][b] -= Lf[k][a2] * Lf[k][b];
     }
-    if (t < N) {
-        const double* b = s_model + t * kBodyStride;
-        DT Ib[6], h[3];
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            Ib[k] = (DT)b[12 + k];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            h[k] = (DT)b[18 + k];
-        const DT m = (DT)b[21];
-        DT a[6], v[6], Ia[6], w[6], Iv[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            a[k] = S.a[t][k];
-            v[k] = S.v[t][k];
-        }
-        inertia_mv(Ib, h, m, a, Ia);
-        inertia_mv(Ib, h, m, v, Iv);
-        crf_mv(v, Iv, w);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            S.F[t][k] = Ia[k] + w[k];
-    }
-    wave_sync();
-#pragma unroll
-    for (int rd = 0; rd < GRID_NROUND; ++rd) {
-        if (in_mask(kRoundMask[rd], t)) {
-            const int p = kParent[t];
-            DT y[6];
-            xt_fv(S.E[t], S.r[t], S.F[t], y);
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                S.F[p][k] += y[k];
-        }
-        wave_sync();
-    }
-    if (t < N) {
-        // zeta_i = X_i^T (S x* f_i), S x* f = [-f1, f0, 0, -f4, f3, 0]
-        DT sf[6], y[6];
-        sf[0] = -S.F[t][1];
-        sf[1] = S.F[t][0];
-        sf[2] = 0;
-        sf[3] = -S.F[t][4];
-        sf[4] = S.F[t][3];
-        sf[5] = 0;
-        xt_fv(S.E[t], S.r[t], sf, y);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            S.zeta[t][k] = (float)y[k];
-    }
-    wave_sync();
 
-    // ---------------------------------------------------------------- 7. dRNEA columns
-    // lane t < 2N: u = t / N (0: d/dq, 1: d/dqd), column j = t % N
-    const bool col_lane = t < 2 * N;
-    const int u = t < N ? 0 : 1;
-    const int j = col_lane ? (t % N) : 0;
-    float src_v[6], src_a[6], src_f[6];
+    // ------------------------------------------------------------ 5. qdd
+    ltl_solve<S>(Lf, dinv, x);
+
+    // ------------------------------------------------------------ 6. RNEA at qdd
+    float gam[B][6];                              // gamma_i = I_i v_i
+    float av[6], ab[6];                           // v_j and X_j a_lambda of the lane's j
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        // u = q : dv += (X_j v_p) x S = alpha_j,  da += beta_j,  backward += zeta_j
-        // u = qd: dv += S,                         da += alpha_j (= v_j x S)
-        src_v[k] = u == 0 ? S.alpha[j][k] : (k == 2 ? 1.0f : 0.0f);
-        src_a[k] = u == 0 ? S.beta[j][k] : S.alpha[j][k];
-        src_f[k] = u == 0 ? S.zeta[j][k] : 0.0f;
+        av[k] = 0.0f;
+        ab[k] = 0.0f;
     }
-    float dv[N][6], da[N][6], df[N][6];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const int p = kParent[i];
-        const float* E = S.Ef[i];
-        const float* r = S.Ef[i] + 9;
-        const float sel = (i == j) ? 1.0f : 0.0f;
-        float xdv[6], xda[6];
-        if (p >= 0) {
-            x_mv(E, r, dv[p], xdv);
-            x_mv(E, r, da[p], xda);
-        } else {
+    for (int i = 0; i < B; ++i) {
+        const int p = S::parent[i];
+        const float* c = C + i * kConstStride;
+        float xa[6], vxs[6], Ia[6], w[6];
+        x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa);
+        cross_S(v[i], vxs);
+        const bool mine = i == j;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                xdv[k] = 0.0f;
-                xda[k] = 0.0f;
-            }
+        for (int k = 0; k < 6; ++k) {
+            a[i][k] = xa[k] + vxs[k] * qd[i];
+            av[k] = mine ? v[i][k] : av[k];
+            ab[k] = mine ? xa[k] : ab[k];
         }
+        a[i][2] += x[i];
+        inertia_mv(c, v[i], gam[i]);
+        inertia_mv(c, a[i], Ia);
+        crf_mv(v[i], gam[i], w);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            dv[i][k] = xdv[k] + sel * src_v[k];
-        float dvxs[6];
-        cross_S(dv[i], dvxs);
-        const float qdi = S.qdf[i];
+            F[i][k] = Ia[k] + w[k];
+    }
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        const int p = S::parent[i];
+        if (p >= 0) {
+            float y[6];
+            xt_fv(E[i], C + i * kConstStride + 9, F[i], y);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                F[p][k] += y[k];
+        }
+    }
+    // source terms of column (u, j):
+    //   u = q : dv += (X_j v_lambda) x S = v_j x S,  da += (X_j a_lambda) x S,
+    //           backward += X_j^T (S x* f_j)
+    //   u = qd: dv += S,                             da += v_j x S
+    float src_v[6], src_a[6], src_f[6];
+    {
+        float vxs[6], axs[6];
+        cross_S(av, vxs);
+        cross_S(ab, axs);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            src_v[k] = u == 0 ? vxs[k] : (k == 2 ? 1.0f : 0.0f);
+            src_a[k] = u == 0 ? axs[k] : vxs[k];
+        }
+        float Fj[6], Ej[9], rj[3];
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            da[i][k] = xda[k] + dvxs[k] * qdi + sel * src_a[k];
-        // df_i = I_i da_i + dv_i x* gamma_i + v_i x* (I_i dv_i)
-        const double* b = s_model + i * kBodyStride;
-        float Ib[6], h[3];
+            Fj[k] = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-            Ib[k] = (float)b[12 + k];
+        for (int k = 0; k < 9; ++k)
+            Ej[k] = 0.0f;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            h[k] = (float)b[18 + k];
-        const float m = (float)b[21];
-        float t1[6], t2[6], t3[6], Idv[6];
-        inertia_mv(Ib, h, m, da[i], t1);
-        crf_mv(dv[i], S.gam[i], t2);
-        inertia_mv(Ib, h, m, dv[i], Idv);
-        crf_mv(S.vf[i], Idv, t3);
+            rj[k] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const bool mine = i == j;
+            const float* c = C + i * kConstStride;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                Fj[k] = mine ? F[i][k] : Fj[k];
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                Ej[k] = mine ? E[i][k] : Ej[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                rj[k] = mine ? c[9 + k] : rj[k];
+        }
+        float sf[6] = {-Fj[1], Fj[0], 0.0f, -Fj[4], Fj[3], 0.0f};   // S x* f
+        xt_fv(Ej, rj, sf, src_f);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            df[i][k] = t1[k] + t2[k] + t3[k];
+            src_f[k] = u == 0 ? src_f[k] : 0.0f;
     }
-    float dtau[N];
+
+    // ------------------------------------------------------------ 7. dRNEA column (u, j)
+    float df[B][6];
+    {
+        float dv[B][6], da[B][6];
 #pragma unroll
-    for (int i = N - 1; i >= 0; --i) {
-        dtau[i] = df[i][2];
-        const int p = kParent[i];
+        for (int i = 0; i < B; ++i) {
+            const int p = S::parent[i];
+            const float* c = C + i * kConstStride;
+            const float sel = (i == j) ? 1.0f : 0.0f;
+            float xdv[6], xda[6];
+            if (p >= 0) {
+                x_mv(E[i], c + 9, dv[p < 0 ? 0 : p], xdv);
+                x_mv(E[i], c + 9, da[p < 0 ? 0 : p], xda);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    xdv[k] = 0.0f;
+                    xda[k] = 0.0f;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                dv[i][k] = xdv[k] + sel * src_v[k];
+            float dvxs[6];
+            cross_S(dv[i], dvxs);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                da[i][k] = xda[k] + dvxs[k] * qd[i] + sel * src_a[k];
+            // df_i = I_i da_i + dv_i x* gamma_i + v_i x* (I_i dv_i)
+            float t1[6], t2[6], t3[6], Idv[6];
+            inertia_mv(c, da[i], t1);
+            crf_mv(dv[i], gam[i], t2);
+            inertia_mv(c, dv[i], Idv);
+            crf_mv(v[i], Idv, t3);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                df[i][k] = t1[k] + t2[k] + t3[k];
+        }
+    }
+    float dx[B];
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        dx[i] = df[i][2];
+        const int p = S::parent[i];
         if (p >= 0) {
-            const float* E = S.Ef[i];
-            const float* r = S.Ef[i] + 9;
             const float sel = (i == j) ? 1.0f : 0.0f;
             float y[6];
-            xt_fv(E, r, df[i], y);
+            xt_fv(E[i], C + i * kConstStride + 9, df[i], y);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
                 df[p][k] += y[k] + sel * src_f[k];
         }
     }
 
-    // ---------------------------------------------------------------- 8. -M^-1 dtau
-    if (col_lane && valid) {
-        float* out = (u == 0 ? args.dqdd_dq : args.dqdd_dqd) + (long)knot * NN;
+    // ------------------------------------------------------------ 8. solves and stores
+    ltl_solve<S>(Lf, dinv, dx);                   // M^-1 dtau/du_j
+    float mc[B];                                  // column jm of M^-1
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            float acc = 0.0f;
+    for (int i = 0; i < B; ++i)
+        mc[i] = (i == jm) ? 1.0f : 0.0f;
+    ltl_solve<S>(Lf, dinv, mc);
+
+    if (!valid)
+        return;
+    const long vbase = (long)knot * N;
+    const long mbase = (long)knot * N * N;
+    // this branch's rows: values in its own columns, zeros elsewhere
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                if (kBranch[i] == kBranch[k])      // M^-1 couples bodies of one base branch only
-                    acc += S.minvf[i][k] * dtau[k];
-            }
-            out[i * N + j] = -acc;
+    for (int i = 0; i < B; ++i) {
+        const int gi = I::body[i];
+        if (t == i)
+            A.qdd[vbase + gi] = x[i];
+        if (owns_col) {
+            float* out = u == 0 ? A.dqdd_dq : A.dqdd_dqd;
+            out[mbase + (long)gi * N + I::body_of(j)] = -dx[i];
+        }
+        // entry (i, jm) with i <= jm is written to both mirrored positions by the lane
+        // owning column jm, so M^-1 comes out exactly symmetric
+        if (t < B && i <= jm) {
+            const int gj = I::body_of(jm);
+            A.Minv[mbase + (long)gi * N + gj] = mc[i];
+            A.Minv[mbase + (long)gj * N + gi] = mc[i];
         }
     }
-    if (valid) {
-        float* out = args.Minv + (long)knot * NN;
-        for (int e = t; e < NN; e += L)
-            out[e] = S.minvf[e / N][e % N];
+    if (N > B) {
+        // zero the columns of other branches in this branch's rows
+        for (int e = t; e < B * N; e += L) {
+            const int i = e / N, col2 = e % N;
+            if (!I::contains(col2)) {
+                const long o = mbase + (long)I::body_of(i) * N + col2;
+                A.Minv[o] = 0.0f;
+                A.dqdd_dq[o] = 0.0f;
+                A.dqdd_dqd[o] = 0.0f;
+            }
+        }
     }
+}
+
+}  // namespace grid
+
+using namespace grid;
+
+// defined by the generated epilogue: workgroup -> (branch, knot group)
+__device__ void grid_dispatch(const Args& args, int block);
+
+extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_fused(Args args)
+{
+    grid_dispatch(args, (int)blockIdx.x);
 }

@@ -12,24 +12,36 @@
 
 namespace grid_impl {
 
-constexpr int kMaxBodies = 32;      // 2n derivative columns fit one wavefront
-constexpr int kBodyStride = 24;     // doubles of device constants per body
+constexpr int kMaxBodies = 32;      // the 2B derivative columns of a branch fit one wavefront
+constexpr int kConstStride = 24;    // floats of device constants per body
+
+// A branch hanging off the fixed base, in local numbering (parent before child).
+struct BranchShape {
+    int B = 0;                       // bodies
+    int L = 0;                       // lanes per knot: power of two >= 2B
+    std::vector<int> parent;         // local parent, -1 = the fixed base
+    std::vector<uint64_t> anc;       // strict ancestors (local bit masks)
+};
+
+// One base branch of a robot: its shape and where its bodies sit in the robot.
+struct BranchInst {
+    int shape = 0;
+    std::vector<int> body;           // robot index of each local body
+    int coff = 0;                    // float offset of the branch's constants
+    uint64_t mask = 0;               // robot bodies in this branch
+};
 
 struct Topology {
     int n = 0;
-    int nlev = 0;
-    int max_anc = 0;
-    int lanes = 0;                       // lanes per knot (power of two >= 2n)
-    std::vector<int> parent, level, branch;
-    std::vector<uint64_t> level_mask;    // bodies per tree level
-    std::vector<uint64_t> round_mask;    // inward accumulation rounds, deepest first
-    std::vector<uint64_t> related;       // per body: ancestors, descendants and itself
+    std::vector<int> parent;
+    std::vector<BranchShape> shapes;
+    std::vector<BranchInst> insts;
 };
 
 // Kernel argument block; must match grid::Args in grid_device.hip.
 struct KernelArgs {
-    const double* model;
-    double a0[3];
+    const float* cf;
+    float a0[3];
     int nknots;
     const float* q;
     const float* qd;
@@ -42,6 +54,8 @@ struct KernelArgs {
 
 bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::string* err);
 std::string generate_source(const Topology& t, uint32_t flags);
+int64_t workgroups_for(const Topology& t, int64_t nknots);
+int lanes_per_knot(const Topology& t);
 grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err);
 std::string cache_dir();
 
@@ -53,8 +67,8 @@ struct grid_model_s {
     int device = 0;
     uint32_t flags = 0;
     grid_impl::Topology topo;
-    double a0[3] = {0, 0, 0};
-    double* d_model = nullptr;          // n * kBodyStride doubles
+    float a0[3] = {0, 0, 0};
+    float* d_model = nullptr;           // constants, branch by branch
     hipModule_t module = nullptr;
     hipFunction_t fused = nullptr;
 };

@@ -90,29 +90,33 @@ grid_status validate_desc(const grid_model_desc* d)
     return GRID_OK;
 }
 
-// device constants per body: E_T, r, Ibar = Ic + m (|c|^2 1 - c c^T) about the body origin,
-// h = m c, m
-std::vector<double> pack_constants(const grid_model_desc* d)
+// device constants, branch by branch in local order, kConstStride floats per body:
+// E_T, r, Ibar = Ic + m (|c|^2 1 - c c^T) about the body origin, h = m c, m
+std::vector<float> pack_constants(const grid_model_desc* d, const Topology& t)
 {
-    std::vector<double> out((size_t)d->n * kBodyStride, 0.0);
-    for (int i = 0; i < d->n; ++i) {
-        double* b = out.data() + (size_t)i * kBodyStride;
-        std::memcpy(b, d->tree_rot + 9 * i, 9 * sizeof(double));
-        std::memcpy(b + 9, d->tree_pos + 3 * i, 3 * sizeof(double));
-        const double m = d->mass[i];
-        const double* c = d->com + 3 * i;
-        const double* J = d->inertia_com + 6 * i;
-        b[12] = J[0] + m * (c[1] * c[1] + c[2] * c[2]);
-        b[13] = J[1] + m * (c[0] * c[0] + c[2] * c[2]);
-        b[14] = J[2] + m * (c[0] * c[0] + c[1] * c[1]);
-        b[15] = J[3] - m * c[0] * c[1];
-        b[16] = J[4] - m * c[0] * c[2];
-        b[17] = J[5] - m * c[1] * c[2];
-        b[18] = m * c[0];
-        b[19] = m * c[1];
-        b[20] = m * c[2];
-        b[21] = m;
-    }
+    std::vector<float> out((size_t)d->n * kConstStride, 0.0f);
+    for (const BranchInst& inst : t.insts)
+        for (size_t k = 0; k < inst.body.size(); ++k) {
+            const int i = inst.body[k];
+            float* b = out.data() + inst.coff + k * kConstStride;
+            for (int e = 0; e < 9; ++e)
+                b[e] = (float)d->tree_rot[9 * i + e];
+            for (int e = 0; e < 3; ++e)
+                b[9 + e] = (float)d->tree_pos[3 * i + e];
+            const double m = d->mass[i];
+            const double* c = d->com + 3 * i;
+            const double* J = d->inertia_com + 6 * i;
+            b[12] = (float)(J[0] + m * (c[1] * c[1] + c[2] * c[2]));
+            b[13] = (float)(J[1] + m * (c[0] * c[0] + c[2] * c[2]));
+            b[14] = (float)(J[2] + m * (c[0] * c[0] + c[1] * c[1]));
+            b[15] = (float)(J[3] - m * c[0] * c[1]);
+            b[16] = (float)(J[4] - m * c[0] * c[2]);
+            b[17] = (float)(J[5] - m * c[1] * c[2]);
+            b[18] = (float)(m * c[0]);
+            b[19] = (float)(m * c[1]);
+            b[20] = (float)(m * c[2]);
+            b[21] = (float)m;
+        }
     return out;
 }
 
@@ -121,7 +125,7 @@ grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* q
                          hipStream_t stream)
 {
     KernelArgs a;
-    a.model = m->d_model;
+    a.cf = m->d_model;
     a.a0[0] = m->a0[0];
     a.a0[1] = m->a0[1];
     a.a0[2] = m->a0[2];
@@ -133,8 +137,7 @@ grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* q
     a.Minv = Minv;
     a.dqdd_dq = dq;
     a.dqdd_dqd = dqd;
-    const int K = 64 / m->topo.lanes;
-    const unsigned blocks = (unsigned)((N + K - 1) / K);
+    const unsigned blocks = (unsigned)workgroups_for(m->topo, N);
     size_t size = sizeof(a);
     void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
                       HIP_LAUNCH_PARAM_END};
@@ -202,7 +205,7 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     if (!out)
         return fail(GRID_EINVAL, "out must not be NULL");
     *out = nullptr;
-    if (flags & ~(uint32_t)GRID_FLAG_FP32_DYNAMICS)
+    if (flags != 0)
         return fail(GRID_EINVAL, "unknown flag bits");
     grid_status s = validate_desc(desc);
     if (s != GRID_OK)
@@ -234,14 +237,14 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     m->flags = flags;
     m->topo = std::move(topo);
     for (int k = 0; k < 3; ++k)
-        m->a0[k] = -desc->gravity[k];
-    const std::vector<double> consts = pack_constants(desc);
-    hipError_t e = hipMalloc(&m->d_model, consts.size() * sizeof(double));
+        m->a0[k] = (float)-desc->gravity[k];
+    const std::vector<float> consts = pack_constants(desc, m->topo);
+    hipError_t e = hipMalloc(&m->d_model, consts.size() * sizeof(float));
     if (e != hipSuccess) {
         delete m;
         return fail(GRID_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
-    e = hipMemcpy(m->d_model, consts.data(), consts.size() * sizeof(double), hipMemcpyHostToDevice);
+    e = hipMemcpy(m->d_model, consts.data(), consts.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipModuleLoadData(&m->module, code.data());
     if (e == hipSuccess)
@@ -268,7 +271,7 @@ grid_status grid_model_destroy(grid_model m)
 }
 
 grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
-                            int32_t* lanes_per_knot)
+                            int32_t* lanes)
 {
     if (!m)
         return fail(GRID_EINVAL, "model is NULL");
@@ -277,8 +280,8 @@ grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
         *n = m->topo.n;
     if (io_bytes_per_knot)
         *io_bytes_per_knot = sizeof(float) * (3 * nn + nn + 3 * nn * nn);
-    if (lanes_per_knot)
-        *lanes_per_knot = m->topo.lanes;
+    if (lanes)
+        *lanes = lanes_per_knot(m->topo);
     return GRID_OK;
 }
 

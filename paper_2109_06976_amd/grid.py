@@ -22,7 +22,6 @@ GRID_ENOMEM = -2
 GRID_EDEVICE = -3
 GRID_EUNSUPPORTED = -4
 GRID_ECOMPILE = -5
-GRID_FLAG_FP32_DYNAMICS = 1
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)

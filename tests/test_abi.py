@@ -67,53 +67,66 @@ def test_unknown_flags_rejected():
     assert e.value.status == grid.GRID_EINVAL
 
 
-def _table(src, name):
-    m = re.search(name + r"\[\d+\] = \{([^}]*)\}", src)
-    return [int(x.replace("ull", ""), 0) for x in m.group(1).split(",")]
+def _shapes(src):
+    """(B, L, parent list, anc masks) of every generated branch shape."""
+    out = []
+    for m in re.finditer(r"struct Shape<(\d+)> \{\s*static constexpr int B = (\d+);\s*"
+                         r"static constexpr int L = (\d+);\s*static constexpr int parent\[B\] = "
+                         r"\{([^}]*)\};\s*static constexpr unsigned long long anc\[B\] = \{([^}]*)\}",
+                         src):
+        parent = [int(x) for x in m.group(4).split(",")]
+        anc = [int(x.strip().replace("ull", "")) for x in m.group(5).split(",")]
+        out.append((int(m.group(2)), int(m.group(3)), parent, anc))
+    return out
 
 
-def test_codegen_tables_quadruped():
+def _insts(src):
+    out = []
+    for m in re.finditer(r"struct Inst<(\d+)> \{\s*using S = Shape<(\d+)>;\s*"
+                         r"static constexpr int body\[S::B\] = \{([^}]*)\};\s*"
+                         r"static constexpr int coff = (\d+);", src):
+        out.append((int(m.group(2)), [int(x) for x in m.group(3).split(",")], int(m.group(4))))
+    return out
+
+
+def test_codegen_quadruped_has_four_identical_branches():
     src = grid.codegen_source(synth.quadruped_parent())
-    assert "#define GRID_N 12" in src and "#define GRID_NLEV 3" in src
-    assert "#define GRID_L 32" in src
-    levels = _table(src, "kLevelMask")
-    assert levels == [0b001001001001, 0b010010010010, 0b100100100100]
-    # two inward rounds (level 2 -> 1, level 1 -> 0); each leg has one child per level
-    assert _table(src, "kRoundMask") == [0b100100100100, 0b010010010010]
-    assert _table(src, "kBranch") == [0, 0, 0, 3, 3, 3, 6, 6, 6, 9, 9, 9]
+    assert "#define GRID_N 12" in src
+    shapes = _shapes(src)
+    assert shapes == [(3, 8, [-1, 0, 1], [0, 0b1, 0b11])]
+    insts = _insts(src)
+    assert [b for _, b, _ in insts] == [[0, 1, 2], [3, 4, 5], [6, 7, 8], [9, 10, 11]]
+    assert [c for _, _, c in insts] == [0, 72, 144, 216]        # 24 floats per body
 
 
-def test_codegen_rounds_have_distinct_parents():
+def test_codegen_humanoid_branches():
     parent = synth.humanoid_parent("anatomical")
     src = grid.codegen_source(parent)
-    rounds = _table(src, "kRoundMask")
-    seen = 0
-    for mask in rounds:
-        bodies = [i for i in range(30) if mask >> i & 1]
-        parents = [parent[i] for i in bodies]
-        assert len(set(parents)) == len(parents)
-        assert all(p >= 0 for p in parents)
-        assert seen & mask == 0
-        seen |= mask
-    # every non-root body adds into its parent exactly once
-    assert seen == sum(1 << i for i in range(30) if parent[i] >= 0)
-    # body 1 (second torso link) has three children at the same level: three rounds there
-    assert "#define GRID_NLEV 9" in src
+    shapes = _shapes(src)
+    insts = _insts(src)
+    # torso tree (torso, head, arms) and two identical legs
+    assert sorted(len(b) for _, b, _ in insts) == [6, 6, 18]
+    assert len(shapes) == 2
+    covered = sorted(i for _, b, _ in insts for i in b)
+    assert covered == list(range(30))
+    for sid, bodies, _ in insts:
+        B, L, lparent, anc = shapes[sid]
+        assert B == len(bodies) and L >= 2 * B and L & (L - 1) == 0
+        for k, i in enumerate(bodies):
+            p = parent[i]
+            assert lparent[k] == (-1 if p < 0 else bodies.index(p))
+            # strict-ancestor masks follow the local parents
+            expect, a = 0, lparent[k]
+            while a >= 0:
+                expect |= 1 << a
+                a = lparent[a]
+            assert anc[k] == expect
 
 
-def test_codegen_related_masks():
-    parent = synth.humanoid_parent("anatomical")
-    rel = _table(grid.codegen_source(parent), "kRelated")
-    anc = [set() for _ in range(30)]
-    for i in range(30):
-        a = parent[i]
-        while a >= 0:
-            anc[i].add(a)
-            a = parent[a]
-    for i in range(30):
-        for k in range(30):
-            expect = i == k or k in anc[i] or i in anc[k]
-            assert bool(rel[i] >> k & 1) == expect
+def test_codegen_bfs_numbering_branches_are_local_orders():
+    parent = np.array([-1, -1, -1, -1, 0, 1, 2, 3, 4, 5, 6, 7], np.int32)
+    insts = _insts(grid.codegen_source(parent))
+    assert [b for _, b, _ in insts] == [[0, 4, 8], [1, 5, 9], [2, 6, 10], [3, 7, 11]]
 
 
 def test_codegen_rejects_bad_topology():

@@ -158,16 +158,3 @@ def test_invalid_launch_arguments(torch_cuda):
     with pytest.raises(grid.GridError) as e:
         model.fd_grad(t, None, t, t, t, t, t, N=4)
     assert e.value.status == grid.GRID_EINVAL
-
-
-@pytest.mark.parametrize("name,N,seed", [("chain7", 128, 102), ("quad12", 256, 103),
-                                         ("humanoid30", 128, 104)])
-def test_fp32_dynamics_variant(torch_cuda, orc, name, N, seed):
-    """All-float32 variant: the gradients meet 1e-3; qdd is reported (ill-conditioned M)."""
-    robot, model = get_model(name, flags=grid.GRID_FLAG_FP32_DYNAMICS)
-    say(f"[gpu] fp32-dynamics {name} N={N}")
-    kn = synth.random_knots(robot.n, N, seed)
-    got = run_device(torch_cuda, model, kn)
-    tol = dict(TOL)
-    tol["qdd"] = 1e-2
-    check(orc, robot, kn, got, tol=tol, label=f"fp32dyn {name} N={N}")
