@@ -66,29 +66,21 @@ def parse():
 
 
 def time_steps(torch, launch, steps, warmup):
+    """Wall time per step (barrier + synchronize on both sides) and GPU time per launch
+    from a HIP event pair on the launch stream around the same back-to-back launches."""
     for _ in range(warmup):
         launch()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    start.record()
     for _ in range(steps):
         launch()
+    end.record()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
-
-
-def kernel_durations(torch, launch, count):
-    """Average per-launch duration from HIP events on the launch stream (torch's current)."""
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(count)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(count)]
-    torch.cuda.synchronize()
-    for s, e in zip(starts, ends):
-        s.record()
-        launch()
-        e.record()
-    torch.cuda.synchronize()
-    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    ms.sort()
-    return sum(ms) / len(ms), ms[len(ms) // 2]
+    wall = (time.perf_counter() - t0) / steps
+    return wall, start.elapsed_time(end) * 1e-3 / steps
 
 
 def main():
@@ -125,8 +117,8 @@ def main():
         return lambda: model.fd_grad(*ins_, *outs_, N=NK, stream=stream)
 
     launch = launch_for(ins, outs, N)
-    sec_per_step = time_steps(torch, launch, args.steps, args.warmup)
-    avg_ms, med_ms = kernel_durations(torch, launch, min(args.steps, 2000))
+    sec_per_step, kernel_s = time_steps(torch, launch, args.steps, args.warmup)
+    avg_ms = kernel_s * 1e3
 
     fl = flops.fdgrad_flops(robot.parent)
     flop_launch = fl["total"] * N
@@ -137,7 +129,6 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
                 "traffic": traffic,
                 "kernel": "grid_fdgrad_fused", "kernel_avg_us": round(avg_ms * 1e3, 3),
-                "kernel_median_us": round(med_ms * 1e3, 3),
                 "flop_per_knot": fl["total"],
                 "hbm_bytes_per_launch": flops.io_bytes_per_knot(n) * N,
                 "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
@@ -184,11 +175,10 @@ def main():
         for NK in [int(x) for x in args.sweep.split(",") if x]:
             i2, o2 = buffers(NK, args.seed + NK)
             l2 = launch_for(i2, o2, NK)
-            s = time_steps(torch, l2, max(200, args.steps // 5), 50)
-            a, m = kernel_durations(torch, l2, 500)
+            s, a = time_steps(torch, l2, max(200, args.steps // 5), 50)
             sweep[str(NK)] = {"knot_evals_per_s": NK / s, "ms_per_step": s * 1e3,
-                              "kernel_avg_us": a * 1e3,
-                              "alu_frac": fl["total"] * NK / (a * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+                              "kernel_avg_us": a * 1e6,
+                              "alu_frac": fl["total"] * NK / a / 1e12 / PEAK_FP32_TFLOPS}
         result["sweep"] = sweep
 
     if args.copy_calibration_mb > 0:
