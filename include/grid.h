@@ -84,11 +84,12 @@ const char* grid_status_string(grid_status s);
 const char* grid_last_error(void);
 
 /*
- * Validate a model description, upload its constants to `device` and obtain the
- * robot's kernel: the library writes the topology out as compile-time tables
- * (Sec. IV-C code generation) and compiles it for gfx950, or loads the code object
- * from the kernel cache (directory GRID_KERNEL_CACHE, else the package's _kcache).
- * flags: reserved, must be 0. On success *out owns device memory until
+ * Validate a model description and obtain the robot's kernel on `device`: the library
+ * writes the topology out as compile-time structures and the constants as literals
+ * (Sec. IV-C code generation), compiles it for gfx950 or loads the code object from
+ * the kernel cache (directory GRID_KERNEL_CACHE, else the package's _kcache), and
+ * loads it on the device.
+ * flags: reserved, must be 0. On success *out owns the loaded code object until
  * grid_model_destroy. Errors: EINVAL (bad description), EUNSUPPORTED (non-z axis,
  * non-revolute joint, n > 32), ECOMPILE, EDEVICE, ENOMEM.
  */
@@ -137,13 +138,15 @@ grid_status grid_fd_grad_host(grid_model m, grid_workspace ws, int32_t N, const 
                               float* dqdd_dq, float* dqdd_dqd, grid_timing* timing);
 
 /*
- * Code generation without a device: write the generated HIP source for a topology
- * into buf (len in: capacity, out: bytes needed including the terminating NUL), or
- * compile it into the kernel cache. Used by the build step and by tests.
+ * Code generation without a device: write the generated HIP source for a model (its
+ * topology as compile-time structures, its constants as float literals) into buf (len
+ * in: capacity, out: bytes needed including the terminating NUL; buf may be NULL to
+ * query), or compile it into the kernel cache. Used by the build step and by tests.
+ * Errors: as grid_model_create's description checks; EINVAL if buf is too small.
  */
-grid_status grid_codegen_source(const int32_t* parent, int32_t n, uint32_t flags, char* buf,
+grid_status grid_codegen_source(const grid_model_desc* desc, uint32_t flags, char* buf,
                                 size_t* len);
-grid_status grid_codegen_precompile(const int32_t* parent, int32_t n, uint32_t flags);
+grid_status grid_codegen_precompile(const grid_model_desc* desc, uint32_t flags);
 
 #ifdef __cplusplus
 }

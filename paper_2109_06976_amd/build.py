@@ -10,7 +10,6 @@ Steps:
 """
 from __future__ import annotations
 
-import ctypes as C
 import os
 import subprocess
 import sys
@@ -59,25 +58,25 @@ def build_library(verbose=False) -> str:
     return LIB
 
 
-def _codegen_source(lib, parent, flags=0) -> str:
+def standard_models():
+    """Every robot model the tests, the benchmark and the smoke check instantiate."""
     import numpy as np
-    p = np.ascontiguousarray(parent, dtype=np.int32)
-    ln = C.c_size_t(0)
-    pp = p.ctypes.data_as(C.POINTER(C.c_int32))
-    lib.grid_codegen_source(pp, C.c_int32(len(p)), C.c_uint32(flags), None, C.byref(ln))
-    buf = C.create_string_buffer(ln.value)
-    st = lib.grid_codegen_source(pp, C.c_int32(len(p)), C.c_uint32(flags), buf, C.byref(ln))
-    if st != 0:
-        raise RuntimeError(f"grid_codegen_source failed: {st}")
-    return buf.value.decode()
-
-
-def offline_compile_check(lib, verbose=False):
-    """hipcc --genco of the generated source for the three workload robots."""
     from paper_2109_06976_amd import synth
-    for name, parent in (("chain7", synth.chain_parent(7)), ("quad12", synth.quadruped_parent()),
-                         ("humanoid30", synth.humanoid_parent("anatomical"))):
-        src = "#include <hip/hip_runtime.h>\n" + _codegen_source(lib, parent, 0)
+    models = [synth.chain7(), synth.quad12(), synth.humanoid30(),
+              synth.humanoid30(variant="literal")]
+    # small trees of the GPU tests: (parent, seed)
+    for parent, seed in [([-1], 40), ([-1, 0], 41), ([-1, 0, 1], 42), ([-1, 0, 0], 43),
+                         ([-1, -1, 1], 44), ([-1, 0, 0, 1, 1, 2, 2], 45)]:
+        models.append(synth.random_model(np.array(parent, np.int32), seed))
+    return models
+
+
+def offline_compile_check(verbose=False):
+    """hipcc --genco of the generated source for the three workload robots."""
+    from paper_2109_06976_amd import grid, synth
+    for robot in (synth.chain7(), synth.quad12(), synth.humanoid30()):
+        src = "#include <hip/hip_runtime.h>\n" + grid.codegen_source(robot)
+        name = robot.name.split("-")[0]
         path = os.path.join(BUILD, f"{name}.hip")
         with open(path, "w") as f:
             f.write(src)
@@ -86,42 +85,21 @@ def offline_compile_check(lib, verbose=False):
               "-save-temps=obj", "-o", out, path], verbose)
 
 
-def standard_topologies():
-    """Every topology the tests, the benchmark and the smoke check instantiate."""
-    import numpy as np
-    from paper_2109_06976_amd import synth
-    tops = [synth.chain_parent(n) for n in (1, 2, 3, 7)]
-    tops += [synth.quadruped_parent(), synth.humanoid_parent("anatomical"),
-             synth.humanoid_parent("literal"),
-             np.array([-1, 0, 0], np.int32), np.array([-1, -1, 1], np.int32),
-             np.array([-1, 0, 0, 1, 1, 2, 2], np.int32)]
-    bfs_quad = [-1, -1, -1, -1, 0, 1, 2, 3, 4, 5, 6, 7]
-    tops.append(np.array(bfs_quad, np.int32))
-    return tops
-
-
-def precompile(lib, verbose=False):
-    import numpy as np
-    for parent in standard_topologies():
-        for flags in (0,):
-            p = np.ascontiguousarray(parent, dtype=np.int32)
-            st = lib.grid_codegen_precompile(p.ctypes.data_as(C.POINTER(C.c_int32)),
-                                             C.c_int32(len(p)), C.c_uint32(flags))
-            if st != 0:
-                msg = C.cast(lib.grid_last_error(), C.c_char_p).value
-                raise RuntimeError(f"precompile {list(parent)} flags={flags}: {st} {msg}")
-            if verbose:
-                print(f"cached kernel for parent={list(parent)} flags={flags}", flush=True)
+def precompile(verbose=False):
+    from paper_2109_06976_amd import grid
+    for robot in standard_models():
+        grid.codegen_precompile(robot)
+        if verbose:
+            print(f"cached kernel for {robot.name} parent={list(map(int, robot.parent))}",
+                  flush=True)
 
 
 def build(verbose=False):
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
     build_library(verbose)
-    lib = C.CDLL(LIB)
-    lib.grid_last_error.restype = C.c_void_p
-    offline_compile_check(lib, verbose)
-    precompile(lib, verbose)
+    offline_compile_check(verbose)
+    precompile(verbose)
     return LIB
 
 

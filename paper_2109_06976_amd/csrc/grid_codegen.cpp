@@ -115,12 +115,29 @@ static void emit_list(std::ostringstream& os, const std::vector<T>& v, const cha
     os << "}";
 }
 
-std::string generate_source(const Topology& t, uint32_t flags)
+static void emit_floats(std::ostringstream& os, const float* v, size_t k)
+{
+    // hexadecimal float literals: exact
+    char buf[48];
+    os << "{";
+    for (size_t i = 0; i < k; ++i) {
+        std::snprintf(buf, sizeof buf, "%a", (double)v[i]);
+        os << (i ? ", " : "") << buf << "f";
+    }
+    os << "}";
+}
+
+std::string generate_source(const Topology& t, const std::vector<float>& consts,
+                            const double gravity[3], uint32_t flags)
 {
     (void)flags;
     std::ostringstream os;
-    os << "// generated: one robot topology as compile-time structures\n";
+    os << "// generated: one robot as compile-time structures and constants\n";
     os << "#define GRID_N " << t.n << "\n";
+    const float a0[3] = {(float)-gravity[0], (float)-gravity[1], (float)-gravity[2]};
+    os << "__device__ constexpr float grid_a0[3] = ";
+    emit_floats(os, a0, 3);
+    os << ";\n";
     os << "template <int s> struct Shape;\ntemplate <int k> struct Inst;\n";
     for (size_t s = 0; s < t.shapes.size(); ++s) {
         const BranchShape& sh = t.shapes[s];
@@ -135,11 +152,16 @@ std::string generate_source(const Topology& t, uint32_t flags)
     }
     for (size_t k = 0; k < t.insts.size(); ++k) {
         const BranchInst& in = t.insts[k];
+        // E_T (9), r (3), Ibar (6), h (3), m, 2 unused: per body in local order
+        os << "__device__ constexpr float grid_const_" << k << "[" << in.body.size() * kConstStride
+           << "] = ";
+        emit_floats(os, consts.data() + in.coff, in.body.size() * kConstStride);
+        os << ";\n";
         os << "template <> struct Inst<" << k << "> {\n";
         os << "    using S = Shape<" << in.shape << ">;\n";
         os << "    static constexpr int body[S::B] = ";
         emit_list(os, in.body);
-        os << ";\n    static constexpr int coff = " << in.coff << ";\n";
+        os << ";\n";
         os << "    static constexpr unsigned long long mask = " << in.mask << "ull;\n";
         os << "    __device__ static int body_of(int i) {\n"
               "        int r = body[0];\n"
@@ -147,6 +169,7 @@ std::string generate_source(const Topology& t, uint32_t flags)
               "        for (int k = 1; k < S::B; ++k) r = (i == k) ? body[k] : r;\n"
               "        return r;\n    }\n";
         os << "    __device__ static bool contains(int g) { return (mask >> g) & 1ull; }\n";
+        os << "    __device__ static const float* consts() { return grid_const_" << k << "; }\n";
         os << "};\n";
     }
     os << "#line 1 \"grid_device.hip\"\n";

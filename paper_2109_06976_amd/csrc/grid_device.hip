@@ -3,11 +3,12 @@
 // Compiled at model-creation time (hiprtc) behind a generated prelude that writes one
 // robot's topology out as compile-time structures (grid_codegen.cpp):
 //   GRID_N                      joints of the robot
+//   grid_a0[3]                  -g, the base acceleration that carries gravity
 //   Shape<s>  { B, L, parent[B], anc[B] }   a base branch shape: B bodies in local
 //                               numbering, lanes per knot L, parents, strict-ancestor masks
-//   Inst<k>   { using S; body[B]; coff }    one base branch of the robot: its shape,
-//                               the robot index of each local body, and the offset of its
-//                               constants
+//   Inst<k>   { using S; body[B]; consts() } one base branch of the robot: its shape,
+//                               the robot index of each local body, and its constants as
+//                               float literals (folded into the instructions)
 //   grid_dispatch(args, block)  maps a workgroup to (branch, knot group) and runs it
 //
 // Branches hanging off the fixed base are dynamically independent: M is block diagonal
@@ -26,8 +27,9 @@
 //   3. column t of M as ID(q, 0, e_t) without gravity (one column per lane), LDS exchange
 //   4. M = L^T L, sparse factorization along ancestor paths (no fill-in on a tree)
 //   5. qdd = M^-1 (tau - c) by the two triangular solves
-//   6. RNEA at qdd: a_i, f_i; the lane captures the source terms of its own column j:
-//      (X_j v_lambda) x S = v_j x S, (X_j a_lambda) x S, and X_j^T (S x* f_j)
+//   6. RNEA at qdd as the increment over step 2 (RNEA is affine in qdd); the lane keeps
+//      the source terms of its own column j: (X_j v_lambda) x S = v_j x S,
+//      (X_j a_lambda) x S and X_j^T (S x* f_j)
 //   7. dRNEA forward (Algorithm 1) and backward pass for the lane's column (u, j)
 //   8. dqdd/du_j = -M^-1 dtau/du_j and column t of M^-1 by the same solves; stores
 //
@@ -44,8 +46,6 @@ constexpr int kConstStride = 24;   // floats of model constants per body
 // the body origin), [18..20] h = m c, [21] m
 
 struct Args {
-    const float* cf;      // constants, branch by branch in local order
-    float a0[3];          // linear part of the base acceleration, -g
     int nknots;
     const float* q;
     const float* qd;
@@ -173,7 +173,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
     const int kraw = kg * K + g;
     const bool valid = kraw < A.nknots;
     const int knot = valid ? kraw : A.nknots - 1;   // tail slots recompute the last knot
-    const float* C = A.cf + I::coff;        // uniform: scalar loads
+    const float* C = I::consts();           // generated literals: folded into the code
 
     // lane roles: M column jm; derivative column (u, j): u = 0 -> d/dq, u = 1 -> d/dqd
     const int jm = t % B;
@@ -204,28 +204,39 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
             E[i][6 + k] = c[6 + k];
         }
     }
-    const float a0[6] = {0.0f, 0.0f, 0.0f, A.a0[0], A.a0[1], A.a0[2]};
+    const float a0[6] = {0.0f, 0.0f, 0.0f, grid_a0[0], grid_a0[1], grid_a0[2]};   // -g
     const float zero6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 
     // ------------------------------------------------------------ 2. RNEA(q, qd, 0)
-    float v[B][6], a[B][6], F[B][6];
+    // v_i, a_i, f_i outward (f accumulated inward below); gamma_i = I_i v_i is kept for
+    // the derivative sweep, and the lane keeps v_j and X_j a_lambda(j) of its own column
+    float v[B][6], a[B][6], F[B][6], gam[B][6];
+    float av[6], ab[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        av[k] = 0.0f;
+        ab[k] = 0.0f;
+    }
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         const int p = S::parent[i];
         const float* c = C + i * kConstStride;
-        float xv[6], xa[6], vxs[6], Iv[6], Ia[6], w[6];
+        float xv[6], xa[6], vxs[6], Ia[6], w[6];
         x_mv(E[i], c + 9, p < 0 ? zero6 : v[p < 0 ? 0 : p], xv);
         x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa);
         xv[2] += qd[i];
         cross_S(xv, vxs);
+        const bool mine = i == j;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             v[i][k] = xv[k];
             a[i][k] = xa[k] + vxs[k] * qd[i];
+            av[k] = mine ? xv[k] : av[k];
+            ab[k] = mine ? xa[k] : ab[k];
         }
-        inertia_mv(c, v[i], Iv);
+        inertia_mv(c, v[i], gam[i]);
         inertia_mv(c, a[i], Ia);
-        crf_mv(v[i], Iv, w);
+        crf_mv(v[i], gam[i], w);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             F[i][k] = Ia[k] + w[k];
@@ -311,61 +322,42 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
     ltl_solve<S>(Lf, dinv, x);
 
     // ------------------------------------------------------------ 6. RNEA at qdd
-    float gam[B][6];                              // gamma_i = I_i v_i
-    float av[6], ab[6];                           // v_j and X_j a_lambda of the lane's j
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        av[k] = 0.0f;
-        ab[k] = 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-        const int p = S::parent[i];
-        const float* c = C + i * kConstStride;
-        float xa[6], vxs[6], Ia[6], w[6];
-        x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa);
-        cross_S(v[i], vxs);
-        const bool mine = i == j;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            a[i][k] = xa[k] + vxs[k] * qd[i];
-            av[k] = mine ? v[i][k] : av[k];
-            ab[k] = mine ? xa[k] : ab[k];
-        }
-        a[i][2] += x[i];
-        inertia_mv(c, v[i], gam[i]);
-        inertia_mv(c, a[i], Ia);
-        crf_mv(v[i], gam[i], w);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            F[i][k] = Ia[k] + w[k];
-    }
-#pragma unroll
-    for (int i = B - 1; i >= 0; --i) {
-        const int p = S::parent[i];
-        if (p >= 0) {
-            float y[6];
-            xt_fv(E[i], C + i * kConstStride + 9, F[i], y);
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                F[p][k] += y[k];
-        }
-    }
-    // source terms of column (u, j):
-    //   u = q : dv += (X_j v_lambda) x S = v_j x S,  da += (X_j a_lambda) x S,
-    //           backward += X_j^T (S x* f_j)
-    //   u = qd: dv += S,                             da += v_j x S
-    float src_v[6], src_a[6], src_f[6];
+    // RNEA is affine in qdd: a_i(qdd) = a_i(0) + Da_i and f_i(qdd) = f_i(0) + Df_i, with
+    // Da_i = X_i Da_lambda + S qdd_i (Da_0 = 0), Df_i = I_i Da_i accumulated inward
+    float Fj[6], Ej[9], rj[3];
     {
-        float vxs[6], axs[6];
-        cross_S(av, vxs);
-        cross_S(ab, axs);
+        float Da[B][6], Df[B][6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            src_v[k] = u == 0 ? vxs[k] : (k == 2 ? 1.0f : 0.0f);
-            src_a[k] = u == 0 ? axs[k] : vxs[k];
+        for (int i = 0; i < B; ++i) {
+            const int p = S::parent[i];
+            const float* c = C + i * kConstStride;
+            float xd[6];
+            if (p >= 0)
+                x_mv(E[i], c + 9, Da[p < 0 ? 0 : p], xd);
+            else
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    xd[k] = 0.0f;
+            const bool mine = i == j;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                Da[i][k] = xd[k];
+                ab[k] = mine ? ab[k] + xd[k] : ab[k];      // X_j a_lambda(j) at qdd
+            }
+            Da[i][2] += x[i];
+            inertia_mv(c, Da[i], Df[i]);
         }
-        float Fj[6], Ej[9], rj[3];
+#pragma unroll
+        for (int i = B - 1; i >= 0; --i) {
+            const int p = S::parent[i];
+            if (p >= 0) {
+                float y[6];
+                xt_fv(E[i], C + i * kConstStride + 9, Df[i], y);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    Df[p][k] += y[k];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             Fj[k] = 0.0f;
@@ -381,13 +373,28 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
             const float* c = C + i * kConstStride;
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                Fj[k] = mine ? F[i][k] : Fj[k];
+                Fj[k] = mine ? F[i][k] + Df[i][k] : Fj[k];
 #pragma unroll
             for (int k = 0; k < 9; ++k)
                 Ej[k] = mine ? E[i][k] : Ej[k];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
                 rj[k] = mine ? c[9 + k] : rj[k];
+        }
+    }
+    // source terms of column (u, j):
+    //   u = q : dv += (X_j v_lambda) x S = v_j x S,  da += (X_j a_lambda) x S,
+    //           backward += X_j^T (S x* f_j)
+    //   u = qd: dv += S,                             da += v_j x S
+    float src_v[6], src_a[6], src_f[6];
+    {
+        float vxs[6], axs[6];
+        cross_S(av, vxs);
+        cross_S(ab, axs);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            src_v[k] = u == 0 ? vxs[k] : (k == 2 ? 1.0f : 0.0f);
+            src_a[k] = u == 0 ? axs[k] : vxs[k];
         }
         float sf[6] = {-Fj[1], Fj[0], 0.0f, -Fj[4], Fj[3], 0.0f};   // S x* f
         xt_fv(Ej, rj, sf, src_f);

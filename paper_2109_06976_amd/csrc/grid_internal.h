@@ -40,8 +40,6 @@ struct Topology {
 
 // Kernel argument block; must match grid::Args in grid_device.hip.
 struct KernelArgs {
-    const float* cf;
-    float a0[3];
     int nknots;
     const float* q;
     const float* qd;
@@ -53,7 +51,10 @@ struct KernelArgs {
 };
 
 bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::string* err);
-std::string generate_source(const Topology& t, uint32_t flags);
+std::vector<float> pack_constants(const grid_model_desc* d, const Topology& t);
+std::string generate_source(const Topology& t, const std::vector<float>& consts,
+                            const double gravity[3], uint32_t flags);
+grid_status validate_desc(const grid_model_desc* d, std::string* err);
 int64_t workgroups_for(const Topology& t, int64_t nknots);
 int lanes_per_knot(const Topology& t);
 grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err);
@@ -67,8 +68,6 @@ struct grid_model_s {
     int device = 0;
     uint32_t flags = 0;
     grid_impl::Topology topo;
-    float a0[3] = {0, 0, 0};
-    float* d_model = nullptr;           // constants, branch by branch
     hipModule_t module = nullptr;
     hipFunction_t fused = nullptr;
 };

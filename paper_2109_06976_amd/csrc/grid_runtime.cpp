@@ -13,29 +13,13 @@ static thread_local std::string t_last_error;
 
 void set_error(const std::string& msg) { t_last_error = msg; }
 
-}  // namespace grid_impl
-
-namespace {
-
-grid_status fail(grid_status s, const std::string& msg)
+static grid_status fail_to(std::string* err, grid_status s, const std::string& msg)
 {
-    set_error(msg);
+    *err = msg;
     return s;
 }
 
-grid_status hip_fail(hipError_t e, const char* what)
-{
-    return fail(GRID_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define HIP_TRY(expr)                                  \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess)                          \
-            return hip_fail(e_, #expr);                \
-    } while (0)
-
-bool finite_all(const double* p, size_t k)
+static bool finite_all(const double* p, size_t k)
 {
     for (size_t i = 0; i < k; ++i)
         if (!std::isfinite(p[i]))
@@ -43,33 +27,33 @@ bool finite_all(const double* p, size_t k)
     return true;
 }
 
-grid_status validate_desc(const grid_model_desc* d)
+grid_status validate_desc(const grid_model_desc* d, std::string* err)
 {
     if (!d)
-        return fail(GRID_EINVAL, "model description is NULL");
+        return fail_to(err, GRID_EINVAL, "model description is NULL");
     if (d->n < 1)
-        return fail(GRID_EINVAL, "n must be >= 1");
+        return fail_to(err, GRID_EINVAL, "n must be >= 1");
     if (d->n > kMaxBodies)
-        return fail(GRID_EUNSUPPORTED, "n > " + std::to_string(kMaxBodies) + " is not supported");
+        return fail_to(err, GRID_EUNSUPPORTED, "n > " + std::to_string(kMaxBodies) + " is not supported");
     if (!d->parent || !d->tree_rot || !d->tree_pos || !d->mass || !d->com || !d->inertia_com)
-        return fail(GRID_EINVAL, "a required model array is NULL");
+        return fail_to(err, GRID_EINVAL, "a required model array is NULL");
     const int n = d->n;
     for (int i = 0; i < n; ++i) {
         if (d->joint_type && d->joint_type[i] != GRID_JOINT_REVOLUTE)
-            return fail(GRID_EUNSUPPORTED, "only revolute joints are supported");
+            return fail_to(err, GRID_EUNSUPPORTED, "only revolute joints are supported");
         if (d->axis) {
             const double* a = d->axis + 3 * i;
             if (a[0] != 0.0 || a[1] != 0.0 || a[2] != 1.0)
-                return fail(GRID_EUNSUPPORTED, "joint axes other than +z are not supported");
+                return fail_to(err, GRID_EUNSUPPORTED, "joint axes other than +z are not supported");
         }
     }
     if (!finite_all(d->tree_rot, 9 * n) || !finite_all(d->tree_pos, 3 * n) ||
         !finite_all(d->mass, n) || !finite_all(d->com, 3 * n) ||
         !finite_all(d->inertia_com, 6 * n) || !finite_all(d->gravity, 3))
-        return fail(GRID_EINVAL, "model description holds a non-finite value");
+        return fail_to(err, GRID_EINVAL, "model description holds a non-finite value");
     for (int i = 0; i < n; ++i) {
         if (!(d->mass[i] > 0))
-            return fail(GRID_EINVAL, "mass[" + std::to_string(i) + "] must be > 0");
+            return fail_to(err, GRID_EINVAL, "mass[" + std::to_string(i) + "] must be > 0");
         const double* R = d->tree_rot + 9 * i;
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
@@ -77,7 +61,7 @@ grid_status validate_desc(const grid_model_desc* d)
                 for (int k = 0; k < 3; ++k)
                     s += R[a * 3 + k] * R[b * 3 + k];
                 if (std::fabs(s - (a == b ? 1.0 : 0.0)) > 1e-5)
-                    return fail(GRID_EINVAL, "tree_rot[" + std::to_string(i) + "] is not a rotation");
+                    return fail_to(err, GRID_EINVAL, "tree_rot[" + std::to_string(i) + "] is not a rotation");
             }
         // inertia about the centre of mass must be positive definite (Sylvester)
         const double* J = d->inertia_com + 6 * i;
@@ -85,7 +69,7 @@ grid_status validate_desc(const grid_model_desc* d)
         const double m2 = xx * yy - xy * xy;
         const double m3 = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
         if (!(xx > 0 && m2 > 0 && m3 > 0))
-            return fail(GRID_EINVAL, "inertia_com[" + std::to_string(i) + "] is not positive definite");
+            return fail_to(err, GRID_EINVAL, "inertia_com[" + std::to_string(i) + "] is not positive definite");
     }
     return GRID_OK;
 }
@@ -120,15 +104,34 @@ std::vector<float> pack_constants(const grid_model_desc* d, const Topology& t)
     return out;
 }
 
+}  // namespace grid_impl
+
+namespace {
+
+grid_status fail(grid_status s, const std::string& msg)
+{
+    set_error(msg);
+    return s;
+}
+
+grid_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(GRID_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess)                          \
+            return hip_fail(e_, #expr);                \
+    } while (0)
+
+
 grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
                          const float* tau, float* qdd, float* Minv, float* dq, float* dqd,
                          hipStream_t stream)
 {
     KernelArgs a;
-    a.cf = m->d_model;
-    a.a0[0] = m->a0[0];
-    a.a0[1] = m->a0[1];
-    a.a0[2] = m->a0[2];
     a.nknots = N;
     a.q = q;
     a.qd = qd;
@@ -164,36 +167,51 @@ const char* grid_status_string(grid_status s)
 
 const char* grid_last_error(void) { return t_last_error.c_str(); }
 
-grid_status grid_codegen_source(const int32_t* parent, int32_t n, uint32_t flags, char* buf,
+// validated description -> topology, packed constants and generated source
+static grid_status prepare(const grid_model_desc* desc, uint32_t flags, Topology* topo,
+                           std::string* src)
+{
+    std::string err;
+    grid_status s = validate_desc(desc, &err);
+    if (s != GRID_OK)
+        return fail(s, err);
+    if (flags != 0)
+        return fail(GRID_EINVAL, "unknown flag bits");
+    if (!analyse_topology(desc->parent, desc->n, topo, &err))
+        return fail(GRID_EINVAL, err);
+    *src = generate_source(*topo, pack_constants(desc, *topo), desc->gravity, flags);
+    return GRID_OK;
+}
+
+grid_status grid_codegen_source(const grid_model_desc* desc, uint32_t flags, char* buf,
                                 size_t* len)
 {
-    if (!parent || !len)
-        return fail(GRID_EINVAL, "parent and len must not be NULL");
+    if (!len)
+        return fail(GRID_EINVAL, "len must not be NULL");
     Topology t;
-    std::string err;
-    if (!analyse_topology(parent, n, &t, &err))
-        return fail(GRID_EINVAL, err);
-    const std::string src = generate_source(t, flags);
+    std::string src;
+    grid_status s = prepare(desc, flags, &t, &src);
+    if (s != GRID_OK)
+        return s;
     const size_t need = src.size() + 1;
-    if (buf && *len >= need)
-        std::memcpy(buf, src.c_str(), need);
     const bool fits = buf && *len >= need;
+    if (fits)
+        std::memcpy(buf, src.c_str(), need);
     *len = need;
     if (buf && !fits)
         return fail(GRID_EINVAL, "buffer too small");
     return GRID_OK;
 }
 
-grid_status grid_codegen_precompile(const int32_t* parent, int32_t n, uint32_t flags)
+grid_status grid_codegen_precompile(const grid_model_desc* desc, uint32_t flags)
 {
-    if (!parent)
-        return fail(GRID_EINVAL, "parent must not be NULL");
     Topology t;
-    std::string err;
-    if (!analyse_topology(parent, n, &t, &err))
-        return fail(GRID_EINVAL, err);
+    std::string src, err;
+    grid_status s = prepare(desc, flags, &t, &src);
+    if (s != GRID_OK)
+        return s;
     std::vector<char> code;
-    grid_status s = compile_cached(generate_source(t, flags), &code, &err);
+    s = compile_cached(src, &code, &err);
     if (s != GRID_OK)
         return fail(s, err);
     return GRID_OK;
@@ -205,17 +223,13 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     if (!out)
         return fail(GRID_EINVAL, "out must not be NULL");
     *out = nullptr;
-    if (flags != 0)
-        return fail(GRID_EINVAL, "unknown flag bits");
-    grid_status s = validate_desc(desc);
+    Topology topo;
+    std::string src, err;
+    grid_status s = prepare(desc, flags, &topo, &src);
     if (s != GRID_OK)
         return s;
-    Topology topo;
-    std::string err;
-    if (!analyse_topology(desc->parent, desc->n, &topo, &err))
-        return fail(GRID_EINVAL, err);
     std::vector<char> code;
-    s = compile_cached(generate_source(topo, flags), &code, &err);
+    s = compile_cached(src, &code, &err);
     if (s != GRID_OK)
         return fail(s, err);
 
@@ -236,22 +250,12 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     m->device = device;
     m->flags = flags;
     m->topo = std::move(topo);
-    for (int k = 0; k < 3; ++k)
-        m->a0[k] = (float)-desc->gravity[k];
-    const std::vector<float> consts = pack_constants(desc, m->topo);
-    hipError_t e = hipMalloc(&m->d_model, consts.size() * sizeof(float));
-    if (e != hipSuccess) {
-        delete m;
-        return fail(GRID_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    e = hipMemcpy(m->d_model, consts.data(), consts.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipModuleLoadData(&m->module, code.data());
+    hipError_t e = hipModuleLoadData(&m->module, code.data());
     if (e == hipSuccess)
         e = hipModuleGetFunction(&m->fused, m->module, "grid_fdgrad_fused");
     if (e != hipSuccess) {
         grid_model_destroy(m);
-        return hip_fail(e, "model upload / module load");
+        return hip_fail(e, "module load");
     }
     *out = m;
     return GRID_OK;
@@ -261,11 +265,9 @@ grid_status grid_model_destroy(grid_model m)
 {
     if (!m)
         return GRID_OK;
-    hipSetDevice(m->device);
+    (void)hipSetDevice(m->device);
     if (m->module)
-        hipModuleUnload(m->module);
-    if (m->d_model)
-        hipFree(m->d_model);
+        (void)hipModuleUnload(m->module);
     delete m;
     return GRID_OK;
 }
@@ -342,20 +344,20 @@ grid_status grid_workspace_destroy(grid_workspace w)
 {
     if (!w)
         return GRID_OK;
-    hipSetDevice(w->model->device);
+    (void)hipSetDevice(w->model->device);
     if (w->stream)
-        hipStreamSynchronize(w->stream);
+        (void)hipStreamSynchronize(w->stream);
     for (auto& ev : w->ev)
         if (ev)
-            hipEventDestroy(ev);
+            (void)hipEventDestroy(ev);
     if (w->stream)
-        hipStreamDestroy(w->stream);
-    hipFree(w->d_in);
-    hipFree(w->d_out);
+        (void)hipStreamDestroy(w->stream);
+    (void)hipFree(w->d_in);
+    (void)hipFree(w->d_out);
     if (w->h_in)
-        hipHostFree(w->h_in);
+        (void)hipHostFree(w->h_in);
     if (w->h_out)
-        hipHostFree(w->h_out);
+        (void)hipHostFree(w->h_out);
     delete w;
     return GRID_OK;
 }

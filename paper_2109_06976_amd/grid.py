@@ -61,9 +61,9 @@ _SIGS = {
     "grid_workspace_destroy": (C.c_int32, [C.c_void_p]),
     "grid_fd_grad_host": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32] + [C.c_void_p] * 7 +
                           [C.POINTER(GridTiming)]),
-    "grid_codegen_source": (C.c_int32, [_i32p, C.c_int32, C.c_uint32, C.c_char_p,
+    "grid_codegen_source": (C.c_int32, [C.POINTER(GridDesc), C.c_uint32, C.c_char_p,
                                         C.POINTER(C.c_size_t)]),
-    "grid_codegen_precompile": (C.c_int32, [_i32p, C.c_int32, C.c_uint32]),
+    "grid_codegen_precompile": (C.c_int32, [C.POINTER(GridDesc), C.c_uint32]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -211,18 +211,20 @@ class Workspace:
         return out, timing
 
 
-def codegen_source(parent, flags: int = 0) -> str:
-    p = np.ascontiguousarray(parent, dtype=np.int32)
+def codegen_source(robot, flags: int = 0) -> str:
+    """Generated HIP source for a robot model (no device needed)."""
+    desc = _Desc(robot)
     ln = C.c_size_t(0)
-    _check(lib().grid_codegen_source(p.ctypes.data_as(_i32p), len(p), flags, None, C.byref(ln)))
+    _check(lib().grid_codegen_source(C.byref(desc.c), flags, None, C.byref(ln)))
     buf = C.create_string_buffer(ln.value)
-    _check(lib().grid_codegen_source(p.ctypes.data_as(_i32p), len(p), flags, buf, C.byref(ln)))
+    _check(lib().grid_codegen_source(C.byref(desc.c), flags, buf, C.byref(ln)))
     return buf.value.decode()
 
 
-def codegen_precompile(parent, flags: int = 0):
-    p = np.ascontiguousarray(parent, dtype=np.int32)
-    _check(lib().grid_codegen_precompile(p.ctypes.data_as(_i32p), len(p), flags))
+def codegen_precompile(robot, flags: int = 0):
+    """Compile a robot's kernel into the on-disk cache (no device needed)."""
+    desc = _Desc(robot)
+    _check(lib().grid_codegen_precompile(C.byref(desc.c), flags))
 
 
 def fd_grad_torch(model: Model, q, qd, tau, stream=None):

@@ -83,33 +83,42 @@ def _shapes(src):
 def _insts(src):
     out = []
     for m in re.finditer(r"struct Inst<(\d+)> \{\s*using S = Shape<(\d+)>;\s*"
-                         r"static constexpr int body\[S::B\] = \{([^}]*)\};\s*"
-                         r"static constexpr int coff = (\d+);", src):
-        out.append((int(m.group(2)), [int(x) for x in m.group(3).split(",")], int(m.group(4))))
+                         r"static constexpr int body\[S::B\] = \{([^}]*)\};", src):
+        out.append((int(m.group(2)), [int(x) for x in m.group(3).split(",")]))
     return out
 
 
 def test_codegen_quadruped_has_four_identical_branches():
-    src = grid.codegen_source(synth.quadruped_parent())
+    src = grid.codegen_source(synth.quad12())
     assert "#define GRID_N 12" in src
     shapes = _shapes(src)
     assert shapes == [(3, 8, [-1, 0, 1], [0, 0b1, 0b11])]
     insts = _insts(src)
-    assert [b for _, b, _ in insts] == [[0, 1, 2], [3, 4, 5], [6, 7, 8], [9, 10, 11]]
-    assert [c for _, _, c in insts] == [0, 72, 144, 216]        # 24 floats per body
+    assert [b for _, b in insts] == [[0, 1, 2], [3, 4, 5], [6, 7, 8], [9, 10, 11]]
+    # each branch's constants are emitted as exact float literals, 24 per body
+    robot = synth.quad12()
+    for k in range(4):
+        m = re.search(r"grid_const_%d\[(\d+)\] = \{([^}]*)\}" % k, src)
+        vals = [float.fromhex(x.strip().rstrip("f")) for x in m.group(2).split(",")]
+        assert int(m.group(1)) == 72 and len(vals) == 72
+        for b in range(3):
+            i = 3 * k + b
+            np.testing.assert_array_equal(vals[24 * b:24 * b + 9], robot.E_T[i].reshape(9))
+            np.testing.assert_array_equal(vals[24 * b + 9:24 * b + 12], robot.r[i])
+            assert vals[24 * b + 21] == np.float32(robot.mass[i])
 
 
 def test_codegen_humanoid_branches():
     parent = synth.humanoid_parent("anatomical")
-    src = grid.codegen_source(parent)
+    src = grid.codegen_source(synth.humanoid30())
     shapes = _shapes(src)
     insts = _insts(src)
     # torso tree (torso, head, arms) and two identical legs
-    assert sorted(len(b) for _, b, _ in insts) == [6, 6, 18]
+    assert sorted(len(b) for _, b in insts) == [6, 6, 18]
     assert len(shapes) == 2
-    covered = sorted(i for _, b, _ in insts for i in b)
+    covered = sorted(i for _, b in insts for i in b)
     assert covered == list(range(30))
-    for sid, bodies, _ in insts:
+    for sid, bodies in insts:
         B, L, lparent, anc = shapes[sid]
         assert B == len(bodies) and L >= 2 * B and L & (L - 1) == 0
         for k, i in enumerate(bodies):
@@ -125,11 +134,13 @@ def test_codegen_humanoid_branches():
 
 def test_codegen_bfs_numbering_branches_are_local_orders():
     parent = np.array([-1, -1, -1, -1, 0, 1, 2, 3, 4, 5, 6, 7], np.int32)
-    insts = _insts(grid.codegen_source(parent))
-    assert [b for _, b, _ in insts] == [[0, 4, 8], [1, 5, 9], [2, 6, 10], [3, 7, 11]]
+    insts = _insts(grid.codegen_source(synth.random_model(parent, 3)))
+    assert [b for _, b in insts] == [[0, 4, 8], [1, 5, 9], [2, 6, 10], [3, 7, 11]]
 
 
 def test_codegen_rejects_bad_topology():
+    robot = synth.random_model(np.array([-1, 0], np.int32), 1)
+    robot.parent = np.array([-1, 1], np.int32)
     with pytest.raises(grid.GridError) as e:
-        grid.codegen_source(np.array([-1, 1], np.int32))
+        grid.codegen_source(robot)
     assert e.value.status == grid.GRID_EINVAL
