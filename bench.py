@@ -1,11 +1,14 @@
 #!/usr/bin/env python3
 """Benchmark: gradient of forward dynamics, knot-evals/s, 7-DoF chain, N = 128 knots.
 
-One step = one batched call of the whole path (transforms, RNEA, CRBA, M^-1, qdd, RNEA
-at qdd, dRNEA forward and backward, -M^-1 dtau) over 128 knot points, with inputs and
-outputs resident in device memory. Prints one JSON line.
+One step = one batched call of the whole path (transforms, RNEA, M and its factor,
+M^-1, qdd, RNEA at qdd, dRNEA forward and backward, -M^-1 dtau) over 128 knot points, as
+one fused kernel launch, with inputs and outputs resident in device memory. Prints one
+JSON line.
 
 Also reported (extra fields of the same line):
+  plain         the staged pipeline (five launches, intermediates in device memory) on
+                the same batch, and fused_vs_plain = plain step time / fused step time;
   roofline      the fused kernel's algorithmic FLOP rate against the FP32 vector peak,
                 from HIP-event kernel durations measured here;
   io_inclusive  the host-pointer call (pinned staging, H2D + kernel + D2H);
@@ -120,6 +123,12 @@ def main():
     sec_per_step, kernel_s = time_steps(torch, launch, args.steps, args.warmup)
     avg_ms = kernel_s * 1e3
 
+    # the plain staged pipeline (five launches, intermediates in HBM) on the same batch
+    ws_plain = grid.Workspace(model, N)
+    plain = lambda: ws_plain.fd_grad_staged(*ins, *outs, N=N, stream=stream)
+    plain_step, plain_gpu = time_steps(torch, plain, max(200, args.steps // 5), 50)
+    ws_plain.close()
+
     fl = flops.fdgrad_flops(robot.parent)
     flop_launch = fl["total"] * N
     achieved_tflops = flop_launch / (avg_ms * 1e-3) / 1e12
@@ -150,6 +159,11 @@ def main():
                                "fused kernel, device-resident inputs",
                    "robot": args.robot, "knots": N, "lanes_per_knot": model.lanes_per_knot},
         "roofline": roofline,
+        "plain": {"value": N / plain_step, "unit": "knot-evals/s", "ms_per_step": plain_step * 1e3,
+                  "gpu_us_per_step": plain_gpu * 1e6,
+                  "note": "staged pipeline: 5 launches (RNEA, M^-1, qdd, dRNEA, dFD), "
+                          "intermediates through device memory"},
+        "fused_vs_plain": plain_step / sec_per_step,
     }
 
     if not args.no_io:

@@ -51,6 +51,9 @@ typedef int32_t grid_status;
 #define GRID_EDEVICE (-3)       /* HIP runtime error, no device, or a kernel fault */
 #define GRID_EUNSUPPORTED (-4)  /* valid request this build does not implement */
 #define GRID_ECOMPILE (-5)      /* generating or compiling the robot's kernel failed */
+#define GRID_EBUSY (-6)         /* a request larger than the server's admission budget */
+#define GRID_ETIMEDOUT (-7)     /* the wait ended before the request completed */
+#define GRID_ECANCELED (-8)     /* the server was destroyed before the request ran */
 
 #define GRID_JOINT_REVOLUTE 0
 
@@ -119,8 +122,21 @@ grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* q
                          float* dqdd_dqd, void* stream);
 
 /*
- * Workspace for the host-pointer call: device buffers and pinned host staging for up
- * to max_knots knots, plus a private stream and events.
+ * Vector-Jacobian product of forward dynamics, qdd = FD(q, qd, tau), for reverse-mode
+ * differentiation: given the outputs of grid_fd_grad and an output cotangent gbar [N][n],
+ *   qbar = (dqdd/dq)^T gbar,  qdbar = (dqdd/dqd)^T gbar,  taubar = M^-1 gbar
+ * (dqdd/dtau = M^-1 is symmetric; Sec. IV-B). Device pointers, [N][n] vectors and
+ * [N][n][n] matrices as above; asynchronous on `stream`. Errors: EINVAL (N < 0, NULL
+ * pointers), EDEVICE.
+ */
+grid_status grid_fd_vjp(grid_model m, int32_t N, const float* dqdd_dq, const float* dqdd_dqd,
+                        const float* Minv, const float* gbar, float* qbar, float* qdbar,
+                        float* taubar, void* stream);
+
+/*
+ * Workspace for the host-pointer and staged calls: device buffers, pinned host staging
+ * and the staged pipeline's intermediates for up to max_knots knots, plus a private
+ * stream and events.
  */
 grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspace* out);
 grid_status grid_workspace_destroy(grid_workspace ws);
@@ -138,6 +154,18 @@ grid_status grid_fd_grad_host(grid_model m, grid_workspace ws, int32_t N, const 
                               float* dqdd_dq, float* dqdd_dqd, grid_timing* timing);
 
 /*
+ * The plain staged pipeline, for comparison with the fused launch: the same steps in
+ * five launches on `stream` (transforms + RNEA -> c; M and its factor -> M^-1;
+ * qdd; RNEA at qdd + dRNEA -> dtau/du; -M^-1 dtau/du), each intermediate going through
+ * the workspace in device memory. Device pointers as in grid_fd_grad; N <= max_knots of
+ * the workspace. Results equal grid_fd_grad's up to float rounding. Errors: as
+ * grid_fd_grad, plus EINVAL for a workspace of another model or too small.
+ */
+grid_status grid_fd_grad_staged(grid_model m, grid_workspace ws, int32_t N, const float* q,
+                                const float* qd, const float* tau, float* qdd, float* Minv,
+                                float* dqdd_dq, float* dqdd_dqd, void* stream);
+
+/*
  * Code generation without a device: write the generated HIP source for a model (its
  * topology as compile-time structures, its constants as float literals) into buf (len
  * in: capacity, out: bytes needed including the terminating NUL; buf may be NULL to
@@ -147,6 +175,86 @@ grid_status grid_fd_grad_host(grid_model m, grid_workspace ws, int32_t N, const 
 grid_status grid_codegen_source(const grid_model_desc* desc, uint32_t flags, char* buf,
                                 size_t* len);
 grid_status grid_codegen_precompile(const grid_model_desc* desc, uint32_t flags);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A server accepts dFD requests (a model index, N knots, host arrays) from any number of
+ * client threads and runs them with continuous batching: a scheduler thread admits
+ * requests while the device bytes they need fit the budget, packs the admitted requests of
+ * one model into the next free batch context (up to max_batch_knots knots per launch), and
+ * issues H2D copy, one fused launch and D2H copy on that context's stream. Several batch
+ * contexts per model are in flight at once, so requests that arrive while others run are
+ * packed into the next launch and their work overlaps on the device. Model constants live
+ * in the models' code objects on the device. Each knot's arithmetic does not depend on the
+ * other knots of its launch, so a request's results are the same alone and in a mix.
+ */
+typedef struct grid_server_s* grid_server;
+
+#define GRID_SERVER_PER_REQUEST 1   /* baseline: one staged (plain) launch per request */
+
+typedef struct grid_server_config {
+    size_t device_budget_bytes;  /* admission budget of in-flight request bytes (inputs+outputs) */
+    int32_t max_batch_knots;     /* knots per launch, >= the largest request */
+    int32_t contexts_per_model;  /* batch contexts (streams) per model, >= 1 */
+    uint32_t flags;              /* 0 or GRID_SERVER_PER_REQUEST */
+} grid_server_config;
+
+typedef struct grid_server_stats {
+    uint64_t submitted, completed, canceled;
+    uint64_t knots_completed;
+    uint64_t launches;           /* device launches issued (fused, or staged pipelines) */
+    uint64_t max_inflight_bytes;
+} grid_server_stats;
+
+/* Create a server over `count` models (all on one device; the models must outlive the
+ * server). Errors: EINVAL (bad config, NULL models, models on different devices), ENOMEM,
+ * EDEVICE. */
+grid_status grid_server_create(const grid_model* models, int32_t count,
+                               const grid_server_config* config, grid_server* out);
+
+/* Queue a request. Host buffers in the layouts of grid_fd_grad; inputs are read and
+ * outputs written by the server until grid_server_wait reports completion, so they must
+ * stay valid until then. *ticket identifies the request. Errors: EINVAL (bad index, N < 1,
+ * N > max_batch_knots, NULL pointers), EBUSY (the request alone exceeds the admission
+ * budget), ECANCELED (the server is shutting down). */
+grid_status grid_server_submit(grid_server s, int32_t model_index, int32_t N, const float* q,
+                               const float* qd, const float* tau, float* qdd, float* Minv,
+                               float* dqdd_dq, float* dqdd_dqd, uint64_t* ticket);
+
+/* Wait up to timeout_us microseconds (< 0: no limit) for a request. GRID_OK once its outputs
+ * are written (the ticket is then released); ETIMEDOUT if still running (the ticket stays
+ * valid); ECANCELED if the server dropped it; EINVAL for an unknown ticket. */
+grid_status grid_server_wait(grid_server s, uint64_t ticket, int64_t timeout_us);
+
+grid_status grid_server_stats_get(grid_server s, grid_server_stats* out);
+
+/* Stop accepting requests, finish the ones already launched, cancel the queued ones (their
+ * waiters get ECANCELED) and release everything. Waiters must not call into the server
+ * after this returns. */
+grid_status grid_server_destroy(grid_server s);
+
+/* Open-loop load generator for measurement: Poisson arrivals at `rate_per_s` for
+ * `warmup_s + duration_s` seconds; each request picks model k with probability
+ * model_prob[k] and N uniformly in [n_min, n_max]; inputs are drawn once per model
+ * (q ~ U[-pi, pi], qd ~ N(0,1), tau ~ N(0,25)) and requests take windows of them.
+ * Latency = completion (outputs in host memory) - scheduled arrival; requests arriving
+ * in the warm-up are not counted. */
+typedef struct grid_loadgen_config {
+    double rate_per_s, duration_s, warmup_s;
+    const double* model_prob;    /* [count of server models], sums to 1 */
+    int32_t n_min, n_max;
+    uint64_t seed;
+} grid_loadgen_config;
+
+typedef struct grid_loadgen_result {
+    uint64_t requests, knots;    /* completed in the measured window */
+    double seconds;              /* measured window */
+    double p50_us, p90_us, p99_us, max_us, mean_us;
+    double offered_rate_per_s;
+} grid_loadgen_result;
+
+grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
+                                grid_loadgen_result* out);
 
 #ifdef __cplusplus
 }

@@ -52,7 +52,8 @@ def build_library(verbose=False) -> str:
            "--offload-arch=gfx950", *NO_PACKED_FP32,
            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", BUILD,
            os.path.join(CSRC, "grid_runtime.cpp"), os.path.join(CSRC, "grid_codegen.cpp"),
-           "-lhiprtc", "-o", LIB + ".tmp"]
+           os.path.join(CSRC, "grid_vjp.hip"), os.path.join(CSRC, "grid_server.cpp"),
+           "-lhiprtc", "-lpthread", "-o", LIB + ".tmp"]
     _run(cmd, verbose)
     os.replace(LIB + ".tmp", LIB)
     return LIB

@@ -98,6 +98,22 @@ int64_t workgroups_for(const Topology& t, int64_t nknots)
     return total;
 }
 
+WorkspaceLayout workspace_layout(const Topology& t)
+{
+    WorkspaceLayout w;
+    w.c = 0;
+    w.L = t.n;
+    int total = 0;
+    for (const BranchInst& inst : t.insts) {
+        w.loff.push_back(total);
+        total += (int)(inst.body.size() * inst.body.size());
+    }
+    w.dinv = w.L + total;
+    w.dtau = w.dinv + t.n;
+    w.stride = w.dtau + 2 * t.n * t.n;
+    return w;
+}
+
 int lanes_per_knot(const Topology& t)
 {
     int lanes = 0;
@@ -138,6 +154,10 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << "__device__ constexpr float grid_a0[3] = ";
     emit_floats(os, a0, 3);
     os << ";\n";
+    const WorkspaceLayout ws = workspace_layout(t);
+    os << "#define GRID_WS_C " << ws.c << "\n#define GRID_WS_L " << ws.L << "\n#define GRID_WS_DINV "
+       << ws.dinv << "\n#define GRID_WS_DTAU " << ws.dtau << "\n#define GRID_WS_STRIDE "
+       << ws.stride << "\n";
     os << "template <int s> struct Shape;\ntemplate <int k> struct Inst;\n";
     for (size_t s = 0; s < t.shapes.size(); ++s) {
         const BranchShape& sh = t.shapes[s];
@@ -161,7 +181,7 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
         os << "    using S = Shape<" << in.shape << ">;\n";
         os << "    static constexpr int body[S::B] = ";
         emit_list(os, in.body);
-        os << ";\n";
+        os << ";\n    static constexpr int loff = " << ws.loff[k] << ";\n";
         os << "    static constexpr unsigned long long mask = " << in.mask << "ull;\n";
         os << "    __device__ static int body_of(int i) {\n"
               "        int r = body[0];\n"
@@ -175,12 +195,13 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << "#line 1 \"grid_device.hip\"\n";
     os << grid_device_src;
     os << "\n// generated: workgroup -> (branch, knot group)\n";
-    os << "__device__ void grid_dispatch(const grid::Args& a, int block)\n{\n    int b = block;\n";
+    os << "template <int ST>\n__device__ void grid_dispatch(const grid::Args& a, int block)\n{\n"
+          "    int b = block;\n";
     for (size_t k = 0; k < t.insts.size(); ++k) {
         os << "    {\n        constexpr int K = 64 / Inst<" << k << ">::S::L;\n"
            << "        const int nb = (a.nknots + K - 1) / K;\n"
            << "        if (b < nb) {\n            grid::run_branch<Inst<" << k
-           << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
+           << ">, ST>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
     }
     os << "}\n";
     return os.str();

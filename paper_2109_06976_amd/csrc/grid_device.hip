@@ -47,6 +47,7 @@ constexpr int kConstStride = 24;   // floats of model constants per body
 
 struct Args {
     int nknots;
+    float* work;          // staged pipeline workspace, GRID_WS_STRIDE floats per knot
     const float* q;
     const float* qd;
     const float* tau;
@@ -157,7 +158,18 @@ __device__ __forceinline__ void ltl_solve(const float (&Lf)[S::B][S::B], const f
     }
 }
 
-template <class I>
+// Stages: the fused kernel runs everything; the staged pipeline splits the same steps
+// over five launches with their intermediates in a device workspace (HBM).
+enum Stage : int {
+    kFused = 0,
+    kStageRnea = 1,     // transforms, RNEA(q, qd, 0)             -> c
+    kStageMinv = 2,     // transforms, M, M = L^T L               -> L, 1/L_kk, M^-1
+    kStageQdd = 3,      // L, c, tau                              -> qdd
+    kStageDrnea = 4,    // transforms, RNEA, RNEA at qdd, dRNEA   -> dtau/dq, dtau/dqd
+    kStageFdgrad = 5,   // L, dtau                                -> dqdd/dq, dqdd/dqd
+};
+
+template <class I, int ST>
 __device__ __forceinline__ void run_branch(const Args& A, int kg)
 {
     using S = typename I::S;
@@ -165,6 +177,8 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
     constexpr int L = S::L;
     constexpr int K = 64 / L;
     constexpr int N = GRID_N;
+    constexpr bool kFullSweeps = ST == kFused || ST == kStageRnea || ST == kStageDrnea;
+    constexpr bool kNeedsX = kFullSweeps || ST == kStageMinv;
     __shared__ float s_M[K][B][B];
 
     const int lane = threadIdx.x;
@@ -174,6 +188,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
     const bool valid = kraw < A.nknots;
     const int knot = valid ? kraw : A.nknots - 1;   // tail slots recompute the last knot
     const float* C = I::consts();           // generated literals: folded into the code
+    float* W = A.work + (long)knot * GRID_WS_STRIDE;   // staged pipeline only
 
     // lane roles: M column jm; derivative column (u, j): u = 0 -> d/dq, u = 1 -> d/dqd
     const int jm = t % B;
@@ -181,27 +196,26 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
     const int u = col / B;
     const int j = col % B;
     const bool owns_col = t < 2 * B;
+    const long vbase = (long)knot * N;
+    const long mbase = (long)knot * N * N;
 
     // ------------------------------------------------------------ 1. transforms
-    float q[B], qd[B], tau[B];
+    float qd[B], tau[B], E[B][9];
+    if constexpr (kNeedsX) {
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-        const long o = (long)knot * N + I::body[i];
-        q[i] = A.q[o];
-        qd[i] = A.qd[o];
-        tau[i] = A.tau[o];
-    }
-    float E[B][9];
+        for (int i = 0; i < B; ++i) {
+            const long o = vbase + I::body[i];
+            const float* c = C + i * kConstStride;
+            float s, co;
+            sincosf(A.q[o], &s, &co);
+            qd[i] = A.qd[o];
+            tau[i] = A.tau[o];
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-        const float* c = C + i * kConstStride;
-        float s, co;
-        sincosf(q[i], &s, &co);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            E[i][k] = co * c[k] + s * c[3 + k];
-            E[i][3 + k] = co * c[3 + k] - s * c[k];
-            E[i][6 + k] = c[6 + k];
+            for (int k = 0; k < 3; ++k) {
+                E[i][k] = co * c[k] + s * c[3 + k];
+                E[i][3 + k] = co * c[3 + k] - s * c[k];
+                E[i][6 + k] = c[6 + k];
+            }
         }
     }
     const float a0[6] = {0.0f, 0.0f, 0.0f, grid_a0[0], grid_a0[1], grid_a0[2]};   // -g
@@ -210,292 +224,381 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
     // ------------------------------------------------------------ 2. RNEA(q, qd, 0)
     // v_i, a_i, f_i outward (f accumulated inward below); gamma_i = I_i v_i is kept for
     // the derivative sweep, and the lane keeps v_j and X_j a_lambda(j) of its own column
-    float v[B][6], a[B][6], F[B][6], gam[B][6];
+    float v[B][6], F[B][6], gam[B][6];
     float av[6], ab[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        av[k] = 0.0f;
-        ab[k] = 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-        const int p = S::parent[i];
-        const float* c = C + i * kConstStride;
-        float xv[6], xa[6], vxs[6], Ia[6], w[6];
-        x_mv(E[i], c + 9, p < 0 ? zero6 : v[p < 0 ? 0 : p], xv);
-        x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa);
-        xv[2] += qd[i];
-        cross_S(xv, vxs);
-        const bool mine = i == j;
+    float x[B];                                   // tau - c, then qdd
+    if constexpr (kFullSweeps) {
+        float a[B][6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            v[i][k] = xv[k];
-            a[i][k] = xa[k] + vxs[k] * qd[i];
-            av[k] = mine ? xv[k] : av[k];
-            ab[k] = mine ? xa[k] : ab[k];
+            av[k] = 0.0f;
+            ab[k] = 0.0f;
         }
-        inertia_mv(c, v[i], gam[i]);
-        inertia_mv(c, a[i], Ia);
-        crf_mv(v[i], gam[i], w);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            F[i][k] = Ia[k] + w[k];
-    }
-#pragma unroll
-    for (int i = B - 1; i >= 0; --i) {
-        const int p = S::parent[i];
-        if (p >= 0) {
-            float y[6];
-            xt_fv(E[i], C + i * kConstStride + 9, F[i], y);
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                F[p][k] += y[k];
-        }
-    }
-    float x[B];                                   // becomes qdd
-#pragma unroll
-    for (int i = 0; i < B; ++i)
-        x[i] = tau[i] - F[i][2];                  // tau - c
-
-    // ------------------------------------------------------------ 3. column jm of M
-    {
-        float am[B][6], fm[B][6];
 #pragma unroll
         for (int i = 0; i < B; ++i) {
             const int p = S::parent[i];
             const float* c = C + i * kConstStride;
-            if (p >= 0)
-                x_mv(E[i], c + 9, am[p < 0 ? 0 : p], am[i]);
-            else
-#pragma unroll
-                for (int k = 0; k < 6; ++k)
-                    am[i][k] = 0.0f;
-            am[i][2] += (i == jm) ? 1.0f : 0.0f;
-            inertia_mv(c, am[i], fm[i]);
-        }
-#pragma unroll
-        for (int i = B - 1; i >= 0; --i) {
-            const int p = S::parent[i];
-            if (p >= 0) {
-                float y[6];
-                xt_fv(E[i], C + i * kConstStride + 9, fm[i], y);
-#pragma unroll
-                for (int k = 0; k < 6; ++k)
-                    fm[p][k] += y[k];
-            }
-        }
-        if (t < B) {
-#pragma unroll
-            for (int i = 0; i < B; ++i)
-                s_M[g][i][t] = fm[i][2];
-        }
-    }
-    wave_sync();
-
-    // ------------------------------------------------------------ 4. M = L^T L
-    float Lf[B][B], dinv[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i)
-#pragma unroll
-        for (int b = 0; b <= i; ++b)
-            if (b == i || is_anc<S>(b, i))
-                Lf[i][b] = s_M[g][i][b];
-#pragma unroll
-    for (int k = B - 1; k >= 0; --k) {
-        const float d = sqrtf(Lf[k][k]);
-        const float di = 1.0f / d;
-        dinv[k] = di;
-#pragma unroll
-        for (int b = 0; b < B; ++b)
-            if (is_anc<S>(b, k))
-                Lf[k][b] *= di;
-#pragma unroll
-        for (int a2 = 0; a2 < B; ++a2)
-            if (is_anc<S>(a2, k))
-#pragma unroll
-                for (int b = 0; b < B; ++b)
-                    if (b == a2 || is_anc<S>(b, a2))
-                        Lf[a2][b] -= Lf[k][a2] * Lf[k][b];
-    }
-
-    // ------------------------------------------------------------ 5. qdd
-    ltl_solve<S>(Lf, dinv, x);
-
-    // ------------------------------------------------------------ 6. RNEA at qdd
-    // RNEA is affine in qdd: a_i(qdd) = a_i(0) + Da_i and f_i(qdd) = f_i(0) + Df_i, with
-    // Da_i = X_i Da_lambda + S qdd_i (Da_0 = 0), Df_i = I_i Da_i accumulated inward
-    float Fj[6], Ej[9], rj[3];
-    {
-        float Da[B][6], Df[B][6];
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            const int p = S::parent[i];
-            const float* c = C + i * kConstStride;
-            float xd[6];
-            if (p >= 0)
-                x_mv(E[i], c + 9, Da[p < 0 ? 0 : p], xd);
-            else
-#pragma unroll
-                for (int k = 0; k < 6; ++k)
-                    xd[k] = 0.0f;
+            float xv[6], xa[6], vxs[6], Ia[6], w[6];
+            x_mv(E[i], c + 9, p < 0 ? zero6 : v[p < 0 ? 0 : p], xv);
+            x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa);
+            xv[2] += qd[i];
+            cross_S(xv, vxs);
             const bool mine = i == j;
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                Da[i][k] = xd[k];
-                ab[k] = mine ? ab[k] + xd[k] : ab[k];      // X_j a_lambda(j) at qdd
+                v[i][k] = xv[k];
+                a[i][k] = xa[k] + vxs[k] * qd[i];
+                av[k] = mine ? xv[k] : av[k];
+                ab[k] = mine ? xa[k] : ab[k];
             }
-            Da[i][2] += x[i];
-            inertia_mv(c, Da[i], Df[i]);
+            inertia_mv(c, v[i], gam[i]);
+            inertia_mv(c, a[i], Ia);
+            crf_mv(v[i], gam[i], w);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                F[i][k] = Ia[k] + w[k];
         }
 #pragma unroll
         for (int i = B - 1; i >= 0; --i) {
             const int p = S::parent[i];
             if (p >= 0) {
                 float y[6];
-                xt_fv(E[i], C + i * kConstStride + 9, Df[i], y);
+                xt_fv(E[i], C + i * kConstStride + 9, F[i], y);
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
-                    Df[p][k] += y[k];
+                    F[p][k] += y[k];
             }
         }
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-            Fj[k] = 0.0f;
+        for (int i = 0; i < B; ++i)
+            x[i] = tau[i] - F[i][2];              // tau - c
+        if constexpr (ST == kStageRnea) {
+            if (valid && t < B) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
-            Ej[k] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            rj[k] = 0.0f;
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            const bool mine = i == j;
-            const float* c = C + i * kConstStride;
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                Fj[k] = mine ? F[i][k] + Df[i][k] : Fj[k];
-#pragma unroll
-            for (int k = 0; k < 9; ++k)
-                Ej[k] = mine ? E[i][k] : Ej[k];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                rj[k] = mine ? c[9 + k] : rj[k];
+                for (int i = 0; i < B; ++i)
+                    if (t == i)
+                        W[GRID_WS_C + I::body[i]] = F[i][2];
+            }
+            return;
         }
-    }
-    // source terms of column (u, j):
-    //   u = q : dv += (X_j v_lambda) x S = v_j x S,  da += (X_j a_lambda) x S,
-    //           backward += X_j^T (S x* f_j)
-    //   u = qd: dv += S,                             da += v_j x S
-    float src_v[6], src_a[6], src_f[6];
-    {
-        float vxs[6], axs[6];
-        cross_S(av, vxs);
-        cross_S(ab, axs);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            src_v[k] = u == 0 ? vxs[k] : (k == 2 ? 1.0f : 0.0f);
-            src_a[k] = u == 0 ? axs[k] : vxs[k];
-        }
-        float sf[6] = {-Fj[1], Fj[0], 0.0f, -Fj[4], Fj[3], 0.0f};   // S x* f
-        xt_fv(Ej, rj, sf, src_f);
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            src_f[k] = u == 0 ? src_f[k] : 0.0f;
     }
 
-    // ------------------------------------------------------------ 7. dRNEA column (u, j)
-    float df[B][6];
-    {
-        float dv[B][6], da[B][6];
+    // ------------------------------------------------------------ 3-4. M = L^T L
+    float Lf[B][B], dinv[B];
+    if constexpr (ST == kFused || ST == kStageMinv) {
+        // column jm of M as ID(q, 0, e_jm) without gravity, exchanged through LDS
+        {
+            float am[B][6], fm[B][6];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const int p = S::parent[i];
+                const float* c = C + i * kConstStride;
+                if (p >= 0)
+                    x_mv(E[i], c + 9, am[p < 0 ? 0 : p], am[i]);
+                else
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        am[i][k] = 0.0f;
+                am[i][2] += (i == jm) ? 1.0f : 0.0f;
+                inertia_mv(c, am[i], fm[i]);
+            }
+#pragma unroll
+            for (int i = B - 1; i >= 0; --i) {
+                const int p = S::parent[i];
+                if (p >= 0) {
+                    float y[6];
+                    xt_fv(E[i], C + i * kConstStride + 9, fm[i], y);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        fm[p][k] += y[k];
+                }
+            }
+            if (t < B) {
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+                    s_M[g][i][t] = fm[i][2];
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+            for (int b = 0; b <= i; ++b)
+                if (b == i || is_anc<S>(b, i))
+                    Lf[i][b] = s_M[g][i][b];
+        // sparse factorisation along ancestor paths: for k from the leaves,
+        // L_kk = sqrt(M_kk), L_ka = M_ka / L_kk, M_ab -= L_ka L_kb (a, b ancestors of k)
+#pragma unroll
+        for (int k = B - 1; k >= 0; --k) {
+            const float d = sqrtf(Lf[k][k]);
+            const float di = 1.0f / d;
+            dinv[k] = di;
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (is_anc<S>(b, k))
+                    Lf[k][b] *= di;
+#pragma unroll
+            for (int a2 = 0; a2 < B; ++a2)
+                if (is_anc<S>(a2, k))
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+                        if (b == a2 || is_anc<S>(b, a2))
+                            Lf[a2][b] -= Lf[k][a2] * Lf[k][b];
+        }
+    } else if constexpr (ST == kStageQdd || ST == kStageFdgrad) {
+        const float* Wl = W + GRID_WS_L + I::loff;
 #pragma unroll
         for (int i = 0; i < B; ++i) {
-            const int p = S::parent[i];
-            const float* c = C + i * kConstStride;
-            const float sel = (i == j) ? 1.0f : 0.0f;
-            float xdv[6], xda[6];
-            if (p >= 0) {
-                x_mv(E[i], c + 9, dv[p < 0 ? 0 : p], xdv);
-                x_mv(E[i], c + 9, da[p < 0 ? 0 : p], xda);
-            } else {
+            dinv[i] = W[GRID_WS_DINV + I::body[i]];
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (is_anc<S>(b, i))
+                    Lf[i][b] = Wl[i * B + b];
+        }
+    }
+
+    // ------------------------------------------------------------ M^-1 and the factor
+    if constexpr (ST == kFused || ST == kStageMinv) {
+        float mc[B];                              // column jm of M^-1
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            mc[i] = (i == jm) ? 1.0f : 0.0f;
+        ltl_solve<S>(Lf, dinv, mc);
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                // entry (i, jm) with i <= jm is written to both mirrored positions by the
+                // lane owning column jm, so M^-1 comes out exactly symmetric
+                if (t < B && i <= jm) {
+                    const int gi = I::body[i];
+                    const int gj = I::body_of(jm);
+                    A.Minv[mbase + (long)gi * N + gj] = mc[i];
+                    A.Minv[mbase + (long)gj * N + gi] = mc[i];
+                }
+            }
+            if (N > B) {
+                for (int e = t; e < B * N; e += L) {
+                    const int i = e / N, c2 = e % N;
+                    if (!I::contains(c2))
+                        A.Minv[mbase + (long)I::body_of(i) * N + c2] = 0.0f;
+                }
+            }
+        }
+        if constexpr (ST == kStageMinv) {
+            if (valid && t == 0) {
+                float* Wl = W + GRID_WS_L + I::loff;
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    W[GRID_WS_DINV + I::body[i]] = dinv[i];
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+                        if (is_anc<S>(b, i))
+                            Wl[i * B + b] = Lf[i][b];
+                }
+            }
+            return;
+        }
+    }
+
+    // ------------------------------------------------------------ 5. qdd
+    if constexpr (ST == kFused || ST == kStageQdd) {
+        if constexpr (ST == kStageQdd) {
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                x[i] = A.tau[vbase + I::body[i]] - W[GRID_WS_C + I::body[i]];
+        }
+        ltl_solve<S>(Lf, dinv, x);
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                if (t == i)
+                    A.qdd[vbase + I::body[i]] = x[i];
+        }
+        if constexpr (ST == kStageQdd)
+            return;
+    }
+    if constexpr (ST == kStageDrnea) {
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            x[i] = A.qdd[vbase + I::body[i]];
+    }
+
+    float dx[B];                                  // dtau/du_j, then dqdd/du_j
+    if constexpr (kFullSweeps) {
+        // -------------------------------------------------------- 6. RNEA at qdd
+        // RNEA is affine in qdd: a_i(qdd) = a_i(0) + Da_i and f_i(qdd) = f_i(0) + Df_i,
+        // Da_i = X_i Da_lambda + S qdd_i (Da_0 = 0), Df_i = I_i Da_i accumulated inward
+        float Fj[6], Ej[9], rj[3];
+        {
+            float Da[B][6], Df[B][6];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const int p = S::parent[i];
+                const float* c = C + i * kConstStride;
+                float xd[6];
+                if (p >= 0)
+                    x_mv(E[i], c + 9, Da[p < 0 ? 0 : p], xd);
+                else
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        xd[k] = 0.0f;
+                const bool mine = i == j;
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
-                    xdv[k] = 0.0f;
-                    xda[k] = 0.0f;
+                    Da[i][k] = xd[k];
+                    ab[k] = mine ? ab[k] + xd[k] : ab[k];      // X_j a_lambda(j) at qdd
+                }
+                Da[i][2] += x[i];
+                inertia_mv(c, Da[i], Df[i]);
+            }
+#pragma unroll
+            for (int i = B - 1; i >= 0; --i) {
+                const int p = S::parent[i];
+                if (p >= 0) {
+                    float y[6];
+                    xt_fv(E[i], C + i * kConstStride + 9, Df[i], y);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        Df[p][k] += y[k];
                 }
             }
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                dv[i][k] = xdv[k] + sel * src_v[k];
-            float dvxs[6];
-            cross_S(dv[i], dvxs);
+                Fj[k] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                Ej[k] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                rj[k] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const bool mine = i == j;
+                const float* c = C + i * kConstStride;
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    Fj[k] = mine ? F[i][k] + Df[i][k] : Fj[k];
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    Ej[k] = mine ? E[i][k] : Ej[k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    rj[k] = mine ? c[9 + k] : rj[k];
+            }
+        }
+        // source terms of column (u, j):
+        //   u = q : dv += (X_j v_lambda) x S = v_j x S,  da += (X_j a_lambda) x S,
+        //           backward += X_j^T (S x* f_j)
+        //   u = qd: dv += S,                             da += v_j x S
+        float src_v[6], src_a[6], src_f[6];
+        {
+            float vxs[6], axs[6];
+            cross_S(av, vxs);
+            cross_S(ab, axs);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                src_v[k] = u == 0 ? vxs[k] : (k == 2 ? 1.0f : 0.0f);
+                src_a[k] = u == 0 ? axs[k] : vxs[k];
+            }
+            float sf[6] = {-Fj[1], Fj[0], 0.0f, -Fj[4], Fj[3], 0.0f};   // S x* f
+            xt_fv(Ej, rj, sf, src_f);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                da[i][k] = xda[k] + dvxs[k] * qd[i] + sel * src_a[k];
-            // df_i = I_i da_i + dv_i x* gamma_i + v_i x* (I_i dv_i)
-            float t1[6], t2[6], t3[6], Idv[6];
-            inertia_mv(c, da[i], t1);
-            crf_mv(dv[i], gam[i], t2);
-            inertia_mv(c, dv[i], Idv);
-            crf_mv(v[i], Idv, t3);
+                src_f[k] = u == 0 ? src_f[k] : 0.0f;
+        }
+
+        // -------------------------------------------------------- 7. dRNEA column (u, j)
+        float df[B][6];
+        {
+            float dv[B][6], da[B][6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k)
-                df[i][k] = t1[k] + t2[k] + t3[k];
+            for (int i = 0; i < B; ++i) {
+                const int p = S::parent[i];
+                const float* c = C + i * kConstStride;
+                const float sel = (i == j) ? 1.0f : 0.0f;
+                float xdv[6], xda[6];
+                if (p >= 0) {
+                    x_mv(E[i], c + 9, dv[p < 0 ? 0 : p], xdv);
+                    x_mv(E[i], c + 9, da[p < 0 ? 0 : p], xda);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        xdv[k] = 0.0f;
+                        xda[k] = 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    dv[i][k] = xdv[k] + sel * src_v[k];
+                float dvxs[6];
+                cross_S(dv[i], dvxs);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    da[i][k] = xda[k] + dvxs[k] * qd[i] + sel * src_a[k];
+                // df_i = I_i da_i + dv_i x* gamma_i + v_i x* (I_i dv_i)
+                float t1[6], t2[6], t3[6], Idv[6];
+                inertia_mv(c, da[i], t1);
+                crf_mv(dv[i], gam[i], t2);
+                inertia_mv(c, dv[i], Idv);
+                crf_mv(v[i], Idv, t3);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    df[i][k] = t1[k] + t2[k] + t3[k];
+            }
+        }
+#pragma unroll
+        for (int i = B - 1; i >= 0; --i) {
+            dx[i] = df[i][2];
+            const int p = S::parent[i];
+            if (p >= 0) {
+                const float sel = (i == j) ? 1.0f : 0.0f;
+                float y[6];
+                xt_fv(E[i], C + i * kConstStride + 9, df[i], y);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    df[p][k] += y[k] + sel * src_f[k];
+            }
+        }
+        if constexpr (ST == kStageDrnea) {
+            if (valid && owns_col) {
+                float* Wd = W + GRID_WS_DTAU + u * N * N;
+                const int gj = I::body_of(j);
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+                    Wd[I::body[i] * N + gj] = dx[i];
+            }
+            return;
         }
     }
-    float dx[B];
+    if constexpr (ST == kStageFdgrad) {
+        const float* Wd = W + GRID_WS_DTAU + u * N * N;
+        const int gj = I::body_of(j);
 #pragma unroll
-    for (int i = B - 1; i >= 0; --i) {
-        dx[i] = df[i][2];
-        const int p = S::parent[i];
-        if (p >= 0) {
-            const float sel = (i == j) ? 1.0f : 0.0f;
-            float y[6];
-            xt_fv(E[i], C + i * kConstStride + 9, df[i], y);
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                df[p][k] += y[k] + sel * src_f[k];
-        }
+        for (int i = 0; i < B; ++i)
+            dx[i] = Wd[I::body[i] * N + gj];
     }
 
-    // ------------------------------------------------------------ 8. solves and stores
-    ltl_solve<S>(Lf, dinv, dx);                   // M^-1 dtau/du_j
-    float mc[B];                                  // column jm of M^-1
-#pragma unroll
-    for (int i = 0; i < B; ++i)
-        mc[i] = (i == jm) ? 1.0f : 0.0f;
-    ltl_solve<S>(Lf, dinv, mc);
-
-    if (!valid)
-        return;
-    const long vbase = (long)knot * N;
-    const long mbase = (long)knot * N * N;
-    // this branch's rows: values in its own columns, zeros elsewhere
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-        const int gi = I::body[i];
-        if (t == i)
-            A.qdd[vbase + gi] = x[i];
+    // ------------------------------------------------------------ 8. -M^-1 dtau/du_j
+    if constexpr (ST == kFused || ST == kStageFdgrad) {
+        ltl_solve<S>(Lf, dinv, dx);
+        if (!valid)
+            return;
         if (owns_col) {
             float* out = u == 0 ? A.dqdd_dq : A.dqdd_dqd;
-            out[mbase + (long)gi * N + I::body_of(j)] = -dx[i];
+            const int gj = I::body_of(j);
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                out[mbase + (long)I::body[i] * N + gj] = -dx[i];
         }
-        // entry (i, jm) with i <= jm is written to both mirrored positions by the lane
-        // owning column jm, so M^-1 comes out exactly symmetric
-        if (t < B && i <= jm) {
-            const int gj = I::body_of(jm);
-            A.Minv[mbase + (long)gi * N + gj] = mc[i];
-            A.Minv[mbase + (long)gj * N + gi] = mc[i];
-        }
-    }
-    if (N > B) {
-        // zero the columns of other branches in this branch's rows
-        for (int e = t; e < B * N; e += L) {
-            const int i = e / N, col2 = e % N;
-            if (!I::contains(col2)) {
-                const long o = mbase + (long)I::body_of(i) * N + col2;
-                A.Minv[o] = 0.0f;
-                A.dqdd_dq[o] = 0.0f;
-                A.dqdd_dqd[o] = 0.0f;
+        if (N > B) {
+            // this branch's rows hold zeros in the other branches' columns
+            for (int e = t; e < B * N; e += L) {
+                const int i = e / N, c2 = e % N;
+                if (!I::contains(c2)) {
+                    const long o = mbase + (long)I::body_of(i) * N + c2;
+                    A.dqdd_dq[o] = 0.0f;
+                    A.dqdd_dqd[o] = 0.0f;
+                }
             }
         }
     }
@@ -506,9 +609,35 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
 using namespace grid;
 
 // defined by the generated epilogue: workgroup -> (branch, knot group)
+template <int ST>
 __device__ void grid_dispatch(const Args& args, int block);
 
 extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_fused(Args args)
 {
-    grid_dispatch(args, (int)blockIdx.x);
+    grid_dispatch<kFused>(args, (int)blockIdx.x);
+}
+
+extern "C" __global__ void __launch_bounds__(64) grid_stage_rnea(Args args)
+{
+    grid_dispatch<kStageRnea>(args, (int)blockIdx.x);
+}
+
+extern "C" __global__ void __launch_bounds__(64) grid_stage_minv(Args args)
+{
+    grid_dispatch<kStageMinv>(args, (int)blockIdx.x);
+}
+
+extern "C" __global__ void __launch_bounds__(64) grid_stage_qdd(Args args)
+{
+    grid_dispatch<kStageQdd>(args, (int)blockIdx.x);
+}
+
+extern "C" __global__ void __launch_bounds__(64) grid_stage_drnea(Args args)
+{
+    grid_dispatch<kStageDrnea>(args, (int)blockIdx.x);
+}
+
+extern "C" __global__ void __launch_bounds__(64) grid_stage_fdgrad(Args args)
+{
+    grid_dispatch<kStageFdgrad>(args, (int)blockIdx.x);
 }

@@ -38,9 +38,17 @@ struct Topology {
     std::vector<BranchInst> insts;
 };
 
+// Staged pipeline workspace per knot (floats): c [n], the factors L of every branch
+// [sum B^2], 1/L_kk [n], dtau/dq and dtau/dqd [2 n^2].
+struct WorkspaceLayout {
+    int c = 0, L = 0, dinv = 0, dtau = 0, stride = 0;
+    std::vector<int> loff;           // per branch: offset of its B x B factor
+};
+
 // Kernel argument block; must match grid::Args in grid_device.hip.
 struct KernelArgs {
     int nknots;
+    float* work;
     const float* q;
     const float* qd;
     const float* tau;
@@ -57,10 +65,14 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
 grid_status validate_desc(const grid_model_desc* d, std::string* err);
 int64_t workgroups_for(const Topology& t, int64_t nknots);
 int lanes_per_knot(const Topology& t);
+WorkspaceLayout workspace_layout(const Topology& t);
 grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err);
 std::string cache_dir();
 
 void set_error(const std::string& msg);
+
+hipError_t launch_vjp(int nknots, int n, const float* dq, const float* dqd, const float* Minv,
+                      const float* g, float* qbar, float* qdbar, float* taubar, hipStream_t stream);
 
 }  // namespace grid_impl
 
@@ -70,6 +82,7 @@ struct grid_model_s {
     grid_impl::Topology topo;
     hipModule_t module = nullptr;
     hipFunction_t fused = nullptr;
+    hipFunction_t stage[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 struct grid_workspace_s {
@@ -79,6 +92,7 @@ struct grid_workspace_s {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float* d_in = nullptr;              // q | qd | tau
     float* d_out = nullptr;             // qdd | Minv | dqdd_dq | dqdd_dqd
+    float* d_stage = nullptr;           // staged pipeline intermediates
     float* h_in = nullptr;              // pinned staging
     float* h_out = nullptr;
 };

@@ -127,12 +127,13 @@ grid_status hip_fail(hipError_t e, const char* what)
     } while (0)
 
 
-grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
-                         const float* tau, float* qdd, float* Minv, float* dq, float* dqd,
-                         hipStream_t stream)
+grid_status launch(hipFunction_t fn, grid_model m, int32_t N, float* work, const float* q,
+                   const float* qd, const float* tau, float* qdd, float* Minv, float* dq,
+                   float* dqd, hipStream_t stream)
 {
     KernelArgs a;
     a.nknots = N;
+    a.work = work;
     a.q = q;
     a.qd = qd;
     a.tau = tau;
@@ -144,8 +145,15 @@ grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* q
     size_t size = sizeof(a);
     void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
                       HIP_LAUNCH_PARAM_END};
-    HIP_TRY(hipModuleLaunchKernel(m->fused, blocks, 1, 1, 64, 1, 1, 0, stream, nullptr, config));
+    HIP_TRY(hipModuleLaunchKernel(fn, blocks, 1, 1, 64, 1, 1, 0, stream, nullptr, config));
     return GRID_OK;
+}
+
+grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
+                         const float* tau, float* qdd, float* Minv, float* dq, float* dqd,
+                         hipStream_t stream)
+{
+    return launch(m->fused, m, N, nullptr, q, qd, tau, qdd, Minv, dq, dqd, stream);
 }
 
 }  // namespace
@@ -161,6 +169,9 @@ const char* grid_status_string(grid_status s)
     case GRID_EDEVICE: return "GRID_EDEVICE";
     case GRID_EUNSUPPORTED: return "GRID_EUNSUPPORTED";
     case GRID_ECOMPILE: return "GRID_ECOMPILE";
+    case GRID_EBUSY: return "GRID_EBUSY";
+    case GRID_ETIMEDOUT: return "GRID_ETIMEDOUT";
+    case GRID_ECANCELED: return "GRID_ECANCELED";
     default: return "GRID_UNKNOWN";
     }
 }
@@ -250,9 +261,13 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     m->device = device;
     m->flags = flags;
     m->topo = std::move(topo);
+    static const char* const kStages[5] = {"grid_stage_rnea", "grid_stage_minv", "grid_stage_qdd",
+                                           "grid_stage_drnea", "grid_stage_fdgrad"};
     hipError_t e = hipModuleLoadData(&m->module, code.data());
     if (e == hipSuccess)
         e = hipModuleGetFunction(&m->fused, m->module, "grid_fdgrad_fused");
+    for (int k = 0; k < 5 && e == hipSuccess; ++k)
+        e = hipModuleGetFunction(&m->stage[k], m->module, kStages[k]);
     if (e != hipSuccess) {
         grid_model_destroy(m);
         return hip_fail(e, "module load");
@@ -305,6 +320,48 @@ grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* q
     return launch_fused(m, N, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, (hipStream_t)stream);
 }
 
+grid_status grid_fd_grad_staged(grid_model m, grid_workspace w, int32_t N, const float* q,
+                                const float* qd, const float* tau, float* qdd, float* Minv,
+                                float* dqdd_dq, float* dqdd_dqd, void* stream)
+{
+    if (!m || !w)
+        return fail(GRID_EINVAL, "model and workspace must not be NULL");
+    if (w->model != m)
+        return fail(GRID_EINVAL, "workspace was created for another model");
+    if (N < 0 || N > w->max_knots)
+        return fail(GRID_EINVAL, "N must be in 0..max_knots of the workspace");
+    if (N == 0)
+        return GRID_OK;
+    if (!q || !qd || !tau || !qdd || !Minv || !dqdd_dq || !dqdd_dqd)
+        return fail(GRID_EINVAL, "a data pointer is NULL");
+    HIP_TRY(hipSetDevice(m->device));
+    for (int k = 0; k < 5; ++k) {
+        grid_status s = launch(m->stage[k], m, N, w->d_stage, q, qd, tau, qdd, Minv, dqdd_dq,
+                               dqdd_dqd, (hipStream_t)stream);
+        if (s != GRID_OK)
+            return s;
+    }
+    return GRID_OK;
+}
+
+grid_status grid_fd_vjp(grid_model m, int32_t N, const float* dqdd_dq, const float* dqdd_dqd,
+                        const float* Minv, const float* gbar, float* qbar, float* qdbar,
+                        float* taubar, void* stream)
+{
+    if (!m)
+        return fail(GRID_EINVAL, "model is NULL");
+    if (N < 0 || N > (1 << 30) / 64)
+        return fail(GRID_EINVAL, "N out of range");
+    if (N == 0)
+        return GRID_OK;
+    if (!dqdd_dq || !dqdd_dqd || !Minv || !gbar || !qbar || !qdbar || !taubar)
+        return fail(GRID_EINVAL, "a data pointer is NULL");
+    HIP_TRY(hipSetDevice(m->device));
+    HIP_TRY(launch_vjp(N, m->topo.n, dqdd_dq, dqdd_dqd, Minv, gbar, qbar, qdbar, taubar,
+                       (hipStream_t)stream));
+    return GRID_OK;
+}
+
 grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspace* out)
 {
     if (!m || !out)
@@ -328,6 +385,9 @@ grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspac
         e = hipMalloc(&w->d_in, in_f * sizeof(float));
     if (e == hipSuccess)
         e = hipMalloc(&w->d_out, out_f * sizeof(float));
+    if (e == hipSuccess)
+        e = hipMalloc(&w->d_stage, (size_t)max_knots * workspace_layout(m->topo).stride *
+                                       sizeof(float));
     if (e == hipSuccess)
         e = hipHostMalloc(&w->h_in, in_f * sizeof(float), hipHostMallocDefault);
     if (e == hipSuccess)
@@ -354,6 +414,7 @@ grid_status grid_workspace_destroy(grid_workspace w)
         (void)hipStreamDestroy(w->stream);
     (void)hipFree(w->d_in);
     (void)hipFree(w->d_out);
+    (void)hipFree(w->d_stage);
     if (w->h_in)
         (void)hipHostFree(w->h_in);
     if (w->h_out)

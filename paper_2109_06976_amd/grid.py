@@ -22,6 +22,10 @@ GRID_ENOMEM = -2
 GRID_EDEVICE = -3
 GRID_EUNSUPPORTED = -4
 GRID_ECOMPILE = -5
+GRID_EBUSY = -6
+GRID_ETIMEDOUT = -7
+GRID_ECANCELED = -8
+GRID_SERVER_PER_REQUEST = 1
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
@@ -37,6 +41,30 @@ class GridDesc(C.Structure):
 class GridTiming(C.Structure):
     _fields_ = [("h2d_ms", C.c_float), ("kernel_ms", C.c_float), ("d2h_ms", C.c_float),
                 ("total_ms", C.c_float)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("device_budget_bytes", C.c_size_t), ("max_batch_knots", C.c_int32),
+                ("contexts_per_model", C.c_int32), ("flags", C.c_uint32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("canceled", C.c_uint64),
+                ("knots_completed", C.c_uint64), ("launches", C.c_uint64),
+                ("max_inflight_bytes", C.c_uint64)]
+
+
+class LoadgenConfig(C.Structure):
+    _fields_ = [("rate_per_s", C.c_double), ("duration_s", C.c_double), ("warmup_s", C.c_double),
+                ("model_prob", _f64p), ("n_min", C.c_int32), ("n_max", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class LoadgenResult(C.Structure):
+    _fields_ = [("requests", C.c_uint64), ("knots", C.c_uint64), ("seconds", C.c_double),
+                ("p50_us", C.c_double), ("p90_us", C.c_double), ("p99_us", C.c_double),
+                ("max_us", C.c_double), ("mean_us", C.c_double),
+                ("offered_rate_per_s", C.c_double)]
 
 
 class GridError(RuntimeError):
@@ -57,7 +85,19 @@ _SIGS = {
     "grid_model_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_size_t),
                                     C.POINTER(C.c_int32)]),
     "grid_fd_grad": (C.c_int32, [C.c_void_p, C.c_int32] + [C.c_void_p] * 7 + [C.c_void_p]),
+    "grid_fd_vjp": (C.c_int32, [C.c_void_p, C.c_int32] + [C.c_void_p] * 7 + [C.c_void_p]),
+    "grid_fd_grad_staged": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32] + [C.c_void_p] * 7 +
+                            [C.c_void_p]),
     "grid_workspace_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "grid_server_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(ServerConfig),
+                                       C.POINTER(C.c_void_p)]),
+    "grid_server_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 7 +
+                           [C.POINTER(C.c_uint64)]),
+    "grid_server_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64]),
+    "grid_server_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(ServerStats)]),
+    "grid_server_destroy": (C.c_int32, [C.c_void_p]),
+    "grid_server_loadgen": (C.c_int32, [C.c_void_p, C.POINTER(LoadgenConfig),
+                                        C.POINTER(LoadgenResult)]),
     "grid_workspace_destroy": (C.c_int32, [C.c_void_p]),
     "grid_fd_grad_host": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32] + [C.c_void_p] * 7 +
                           [C.POINTER(GridTiming)]),
@@ -170,6 +210,15 @@ class Model:
                                   _stream_handle(stream)))
 
 
+def fd_vjp(model, dqdd_dq, dqdd_dqd, Minv, gbar, qbar, qdbar, taubar, N=None, stream=None):
+    """grid_fd_vjp on device buffers (torch tensors or addresses), asynchronous."""
+    if N is None:
+        N = int(gbar.shape[0])
+    _check(lib().grid_fd_vjp(model.handle, int(N), _addr(dqdd_dq), _addr(dqdd_dqd), _addr(Minv),
+                             _addr(gbar), _addr(qbar), _addr(qdbar), _addr(taubar),
+                             _stream_handle(stream)))
+
+
 class Workspace:
     """grid_workspace: pinned staging + device buffers for the host-pointer call."""
 
@@ -192,6 +241,14 @@ class Workspace:
         except Exception:
             pass
 
+    def fd_grad_staged(self, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, N=None, stream=None):
+        """grid_fd_grad_staged: the five-launch pipeline on device buffers, asynchronous."""
+        if N is None:
+            N = int(q.shape[0])
+        _check(lib().grid_fd_grad_staged(self.model.handle, self._h, int(N), _addr(q), _addr(qd),
+                                         _addr(tau), _addr(qdd), _addr(Minv), _addr(dqdd_dq),
+                                         _addr(dqdd_dqd), _stream_handle(stream)))
+
     def fd_grad_host(self, q, qd, tau):
         """grid_fd_grad_host on numpy arrays; returns (outputs dict, timing dict)."""
         n = self.model.n
@@ -209,6 +266,72 @@ class Workspace:
                                        ptr(out["dqdd_dqd"]), C.byref(t)))
         timing = {k: float(getattr(t, k)) for k in ("h2d_ms", "kernel_ms", "d2h_ms", "total_ms")}
         return out, timing
+
+
+class Server:
+    """grid_server: continuous batching of dFD requests over several models."""
+
+    def __init__(self, models, budget_bytes=1 << 30, max_batch_knots=1024, contexts_per_model=3,
+                 flags=0):
+        self._h = None
+        self.models = list(models)
+        handles = (C.c_void_p * len(self.models))(*[m.handle.value for m in self.models])
+        cfg = ServerConfig(int(budget_bytes), int(max_batch_knots), int(contexts_per_model),
+                           int(flags))
+        h = C.c_void_p()
+        _check(lib().grid_server_create(handles, len(self.models), C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, model_index, q, qd, tau):
+        """Queue one request on host arrays; returns (ticket, outputs dict being filled)."""
+        n = self.models[model_index].n
+        q = np.ascontiguousarray(q, dtype=np.float32).reshape(-1, n)
+        N = q.shape[0]
+        qd = np.ascontiguousarray(qd, dtype=np.float32).reshape(N, n)
+        tau = np.ascontiguousarray(tau, dtype=np.float32).reshape(N, n)
+        out = {"qdd": np.empty((N, n), np.float32), "Minv": np.empty((N, n, n), np.float32),
+               "dqdd_dq": np.empty((N, n, n), np.float32),
+               "dqdd_dqd": np.empty((N, n, n), np.float32)}
+        t = C.c_uint64()
+        ptr = lambda a: a.ctypes.data
+        _check(lib().grid_server_submit(self._h, int(model_index), N, ptr(q), ptr(qd), ptr(tau),
+                                        ptr(out["qdd"]), ptr(out["Minv"]), ptr(out["dqdd_dq"]),
+                                        ptr(out["dqdd_dqd"]), C.byref(t)))
+        self._keep[t.value] = (q, qd, tau, out)      # buffers must live until wait returns
+        return t.value, out
+
+    def wait(self, ticket, timeout_us=-1):
+        st = lib().grid_server_wait(self._h, C.c_uint64(ticket), C.c_int64(int(timeout_us)))
+        if st != GRID_ETIMEDOUT:
+            self._keep.pop(ticket, None)
+        _check(st)
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().grid_server_stats_get(self._h, C.byref(s)))
+        return {k: int(getattr(s, k)) for k, _ in ServerStats._fields_}
+
+    def loadgen(self, rate_per_s, duration_s, model_prob, n_min=16, n_max=256, warmup_s=1.0,
+                seed=7):
+        probs = np.ascontiguousarray(model_prob, dtype=np.float64)
+        cfg = LoadgenConfig(float(rate_per_s), float(duration_s), float(warmup_s),
+                            probs.ctypes.data_as(_f64p), int(n_min), int(n_max), int(seed))
+        r = LoadgenResult()
+        _check(lib().grid_server_loadgen(self._h, C.byref(cfg), C.byref(r)))
+        return {k: (float(getattr(r, k)) if t is C.c_double else int(getattr(r, k)))
+                for k, t in LoadgenResult._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().grid_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def codegen_source(robot, flags: int = 0) -> str:

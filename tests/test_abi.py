@@ -144,3 +144,16 @@ def test_codegen_rejects_bad_topology():
     with pytest.raises(grid.GridError) as e:
         grid.codegen_source(robot)
     assert e.value.status == grid.GRID_EINVAL
+
+
+def test_server_rejects_bad_arguments_without_a_device():
+    import ctypes as C
+    lib = grid.lib()
+    h = C.c_void_p()
+    cfg = grid.ServerConfig(1 << 20, 64, 1, 0)
+    assert lib.grid_server_create(None, 1, C.byref(cfg), C.byref(h)) == grid.GRID_EINVAL
+    t = C.c_uint64()
+    assert lib.grid_server_submit(None, 0, 1, *([None] * 7), C.byref(t)) == grid.GRID_EINVAL
+    assert lib.grid_server_wait(None, 1, 0) == grid.GRID_EINVAL
+    assert lib.grid_server_destroy(None) == grid.GRID_OK
+    assert grid.status_string(grid.GRID_ETIMEDOUT) == "GRID_ETIMEDOUT"

@@ -1,0 +1,167 @@
+"""The continuous-batching server on an MI355X, through the C ABI."""
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+from paper_2109_06976_amd import grid, synth
+
+pytestmark = pytest.mark.gpu
+
+OUTS = ("qdd", "Minv", "dqdd_dq", "dqdd_dqd")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def models():
+    import torch
+    assert torch.cuda.is_available()
+    robots = [synth.chain7(), synth.quad12(), synth.humanoid30()]
+    ms = [grid.Model(r) for r in robots]
+    yield robots, ms
+    for m in ms:
+        m.close()
+
+
+def test_request_alone_equals_request_in_mix(models, orc):
+    robots, ms = models
+    say("[gpu] server identity: alone vs Poisson-like mix")
+    srv = grid.Server(ms, budget_bytes=1 << 28, max_batch_knots=1024, contexts_per_model=3)
+    probe = synth.random_knots(robots[2].n, 100, 55)
+    t, alone = srv.submit(2, probe.q, probe.qd, probe.tau)
+    srv.wait(t)
+    # the same request in the middle of a stream of mixed requests from two client threads
+    rng = np.random.default_rng(3)
+    mixed = {}
+    tickets = []
+
+    def client(seed, count):
+        r = np.random.default_rng(seed)
+        for _ in range(count):
+            k = int(r.choice(3, p=[0.5, 0.3, 0.2]))
+            N = int(r.integers(16, 257))
+            kn = synth.random_knots(robots[k].n, N, int(r.integers(1 << 30)))
+            tickets.append(srv.submit(k, kn.q, kn.qd, kn.tau)[0])
+
+    th = [threading.Thread(target=client, args=(s, 40)) for s in (1, 2)]
+    for x in th:
+        x.start()
+    t2, mixed = srv.submit(2, probe.q, probe.qd, probe.tau)
+    for x in th:
+        x.join()
+    srv.wait(t2)
+    for t in tickets:
+        srv.wait(t)
+    for key in OUTS:
+        np.testing.assert_array_equal(mixed[key], alone[key])
+    st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == st["submitted"] == 82 and st["launches"] < 82
+    ref = orc.fd_grad_batch(robots[2], probe.q, probe.qd, probe.tau)
+    e = np.abs(alone["qdd"] - ref["qdd"]).max(axis=1) / np.abs(ref["qdd"]).max(axis=1)
+    assert e.max() <= 1e-4
+    srv.close()
+
+
+def test_server_matches_direct_launch(models):
+    import torch
+    robots, ms = models
+    say("[gpu] server result = direct fused launch")
+    srv = grid.Server(ms[:1], budget_bytes=1 << 26, max_batch_knots=512)
+    kn = synth.random_knots(7, 77, 9)
+    t, out = srv.submit(0, kn.q, kn.qd, kn.tau)
+    srv.wait(t)
+    d = grid.fd_grad_torch(ms[0], *(torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)))
+    torch.cuda.synchronize()
+    for key in OUTS:
+        np.testing.assert_array_equal(out[key], d[key].cpu().numpy())
+    srv.close()
+
+
+def test_admission_budget(models):
+    robots, ms = models
+    say("[gpu] server admission under a small budget")
+    n = 7
+    per_knot = 4 * (4 * n + 3 * n * n)
+    srv = grid.Server(ms[:1], budget_bytes=per_knot * 300, max_batch_knots=1024,
+                      contexts_per_model=2)
+    kn = synth.random_knots(n, 301, 4)
+    with pytest.raises(grid.GridError) as e:
+        srv.submit(0, kn.q, kn.qd, kn.tau)             # can never fit
+    assert e.value.status == grid.GRID_EBUSY
+    tickets = []
+    for k in range(30):                               # 30 x 100 knots >> budget
+        a = synth.random_knots(n, 100, 100 + k)
+        tickets.append(srv.submit(0, a.q, a.qd, a.tau))
+    for t, out in tickets:
+        srv.wait(t)
+        assert np.all(np.isfinite(out["qdd"]))
+    st = srv.stats()
+    assert st["completed"] == 30 and st["max_inflight_bytes"] <= per_knot * 300
+    srv.close()
+
+
+def test_wait_timeout_and_unknown_ticket(models):
+    robots, ms = models
+    srv = grid.Server(ms[2:], budget_bytes=1 << 28, max_batch_knots=1024)
+    kn = synth.random_knots(30, 1024, 5)
+    t, _ = srv.submit(0, kn.q, kn.qd, kn.tau)
+    try:
+        srv.wait(t, timeout_us=0)
+        finished_early = True
+    except grid.GridError as e:
+        assert e.status == grid.GRID_ETIMEDOUT
+        finished_early = False
+    if not finished_early:
+        srv.wait(t)                                   # the ticket stays valid after a timeout
+    with pytest.raises(grid.GridError) as e:
+        srv.wait(t)                                   # released by the successful wait
+    assert e.value.status == grid.GRID_EINVAL
+    srv.close()
+
+
+def test_destroy_with_work_in_flight(models):
+    robots, ms = models
+    say("[gpu] server destroy with queued and launched work")
+    n = 12
+    srv = grid.Server(ms[1:2], budget_bytes=4 * (4 * n + 3 * n * n) * 256, max_batch_knots=256,
+                      contexts_per_model=1)
+    for k in range(40):
+        a = synth.random_knots(n, 200, k)
+        srv.submit(0, a.q, a.qd, a.tau)
+    srv.close()                                       # returns: launched work finished, rest canceled
+
+
+def test_per_request_plain_mode(models, orc):
+    robots, ms = models
+    say("[gpu] server per-request staged mode")
+    srv = grid.Server(ms, budget_bytes=1 << 28, max_batch_knots=256,
+                      flags=grid.GRID_SERVER_PER_REQUEST)
+    outs = []
+    for k, N in ((0, 16), (1, 100), (2, 37), (0, 256)):
+        kn = synth.random_knots(robots[k].n, N, 60 + k)
+        t, out = srv.submit(k, kn.q, kn.qd, kn.tau)
+        outs.append((k, kn, t, out))
+    for k, kn, t, out in outs:
+        srv.wait(t)
+        ref = orc.fd_grad_batch(robots[k], kn.q, kn.qd, kn.tau)
+        e = np.abs(out["dqdd_dq"] - ref["dqdd_dq"]).reshape(kn.N, -1).max(1) / \
+            np.abs(ref["dqdd_dq"]).reshape(kn.N, -1).max(1)
+        assert e.max() <= 1e-3
+    assert srv.stats()["launches"] == 4
+    srv.close()
+
+
+def test_loadgen_short_run(models):
+    robots, ms = models
+    say("[gpu] load generator 0.5 s at 5000 req/s")
+    srv = grid.Server(ms, budget_bytes=1 << 30, max_batch_knots=1024)
+    r = srv.loadgen(5000, 0.5, [0.5, 0.3, 0.2], warmup_s=0.2)
+    say(f"  {r}")
+    assert r["requests"] > 1000 and 0 < r["p50_us"] <= r["p99_us"] <= r["max_us"]
+    srv.close()
