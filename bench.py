@@ -12,6 +12,9 @@ Also reported (extra fields of the same line):
   roofline      the fused kernel's algorithmic FLOP rate against the FP32 vector peak,
                 from HIP-event kernel durations measured here;
   io_inclusive  the host-pointer call (pinned staging, H2D + kernel + D2H);
+  served        p50/p99 latency and throughput of an open-loop Poisson request stream
+                (20k req/s over the three robots) through the continuous-batching
+                server, and through one plain staged launch per request;
   cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
@@ -63,6 +66,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-io", action="store_true")
     ap.add_argument("--sweep", default="", help="comma-separated extra knot counts to time")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="measured seconds of the served load (0 disables serving)")
+    ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--serve-sweep", default="", help="extra request rates, comma-separated")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="also run a plain device copy of this size (for counter scaling)")
     return ap.parse_args()
@@ -84,6 +91,35 @@ def time_steps(torch, launch, steps, warmup):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     return wall, start.elapsed_time(end) * 1e-3 / steps
+
+
+def serve(args, grid, synth, chain_model=None):
+    """Open-loop Poisson requests over the three robots (50/30/20 %, N ~ U{16..256}),
+    served with continuous batching and, as the baseline, one staged launch per request."""
+    robots = [synth.chain7(), synth.quad12(), synth.humanoid30()]
+    models = [chain_model or grid.Model(robots[0]), grid.Model(robots[1]), grid.Model(robots[2])]
+    probs = [0.5, 0.3, 0.2]
+    out = {"workload": "Poisson arrivals, chain7/quad12/humanoid30 at 50/30/20 %, "
+                       "N ~ U{16..256}, latency = outputs in host memory - scheduled arrival",
+           "measured_s": args.serve_seconds, "warmup_s": 1.0}
+    rates = [args.serve_rate] + [float(x) for x in args.serve_sweep.split(",") if x]
+    for label, flags in (("batched", 0), ("per_request_plain", grid.GRID_SERVER_PER_REQUEST)):
+        srv = grid.Server(models, budget_bytes=1 << 30, max_batch_knots=2048,
+                          contexts_per_model=3, flags=flags)
+        res = {}
+        for rate in rates:
+            r = srv.loadgen(rate, args.serve_seconds, probs, n_min=16, n_max=256, warmup_s=1.0,
+                            seed=7)
+            res[str(int(rate))] = {"p50_us": r["p50_us"], "p90_us": r["p90_us"],
+                                   "p99_us": r["p99_us"], "max_us": r["max_us"],
+                                   "requests_per_s": r["requests"] / r["seconds"],
+                                   "knot_evals_per_s": r["knots"] / r["seconds"]}
+        res["launches"] = srv.stats()["launches"]
+        srv.close()
+        out[label] = res
+    for m in models[1:] + ([] if chain_model else models[:1]):
+        m.close()
+    return out
 
 
 def main():
@@ -143,7 +179,7 @@ def main():
                 "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
 
     result = {
-        "metric": "dFD knot-evals/sec (7-DoF chain, N=128)",
+        "metric": "dFD knot-evals/sec (7-DoF chain, N=128) + p50/p99 latency served, vs plain",
         "value": N / sec_per_step,
         "unit": "knot-evals/s",
         "n_gpus": 1,
@@ -183,6 +219,9 @@ def main():
             "value": N / wall, "unit": "knot-evals/s", "wall_ms_per_call": wall * 1e3,
             **{k: v / reps for k, v in tot.items()},
             "note": "host-pointer call: pageable->pinned staging, H2D, kernel, D2H, sync"}
+
+    if args.serve_seconds > 0:
+        result["served"] = serve(args, grid, synth, model if args.robot == "chain7" else None)
 
     if args.sweep:
         sweep = {}

@@ -176,6 +176,53 @@ grid_status grid_codegen_source(const grid_model_desc* desc, uint32_t flags, cha
                                 size_t* len);
 grid_status grid_codegen_precompile(const grid_model_desc* desc, uint32_t flags);
 
+/* ------------------------------------------------------------------ mixed batches
+ *
+ * A batch item is one model's knots with their own device buffers (layouts as in
+ * grid_fd_grad). Items of different robots and uneven N run as independent launches.
+ */
+typedef struct grid_item {
+    grid_model model;
+    int32_t N;
+    const float *q, *qd, *tau;
+    float *qdd, *Minv, *dqdd_dq, *dqdd_dqd;
+} grid_item;
+
+typedef struct grid_graph_s* grid_graph;
+
+/* Launch every item's fused kernel on `stream`, one after the other. */
+grid_status grid_fd_grad_batch(const grid_item* items, int32_t count, void* stream);
+
+/* Capture the items into one hipGraph whose kernel nodes are independent (forked onto
+ * side streams and joined), instantiate it, and return it. All models must be on one
+ * device. Errors: EINVAL (NULL, count < 1 or > 64, N < 0), EDEVICE. */
+grid_status grid_graph_create(const grid_item* items, int32_t count, grid_graph* out);
+
+/* Replay the graph on `stream` (one launch call for the whole mixed batch). */
+grid_status grid_graph_launch(grid_graph g, void* stream);
+
+/* Point the graph at new items (other N, other buffers; same count): the graph is
+ * re-captured and the executable updated in place, or re-instantiated if the update is
+ * refused. */
+grid_status grid_graph_update(grid_graph g, const grid_item* items, int32_t count);
+
+grid_status grid_graph_destroy(grid_graph g);
+
+/* ------------------------------------------------------------------ autotuning
+ *
+ * The fused kernel is built three times, allowed 1, 2 or 4 resident wavefronts per SIMD
+ * (register budget against latency hiding). grid_tune times each build on the model's
+ * device for every knot count in Ns (synthetic inputs, HIP events, median of repeats),
+ * keeps the fastest per count, and from then on grid_fd_grad uses, for a batch of N
+ * knots, the choice made for the smallest tuned count >= N (the largest otherwise).
+ * chosen[i] (may be NULL) receives the build index (0, 1, 2) picked for Ns[i]. The
+ * result is also appended to `table_path` (may be NULL) as one JSON line keyed by the
+ * generated source's hash; grid_model_create reads the file named by GRID_TUNE_TABLE,
+ * if set, and applies the last matching line. Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+grid_status grid_tune(grid_model m, const int32_t* Ns, int32_t count, const char* table_path,
+                      int32_t* chosen);
+
 /* ------------------------------------------------------------------ serving
  *
  * A server accepts dFD requests (a model index, N knots, host arrays) from any number of

@@ -1,0 +1,379 @@
+// Mixed-robot batches (one launch per item, or one hipGraph replay for all items) and the
+// autotuner that picks a build of the fused kernel per batch size (include/grid.h).
+#include "grid_internal.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+
+using namespace grid_impl;
+
+namespace {
+
+constexpr int kMaxItems = 64;
+
+grid_status fail(grid_status s, const std::string& msg)
+{
+    set_error(msg);
+    return s;
+}
+
+#define HIP_TRY(expr)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return fail(GRID_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+grid_status check_items(const grid_item* items, int32_t count)
+{
+    if (!items || count < 1 || count > kMaxItems)
+        return fail(GRID_EINVAL, "items must hold 1..64 entries");
+    for (int k = 0; k < count; ++k) {
+        const grid_item& it = items[k];
+        if (!it.model || it.N < 0)
+            return fail(GRID_EINVAL, "item " + std::to_string(k) + ": NULL model or N < 0");
+        if (it.model->device != items[0].model->device)
+            return fail(GRID_EINVAL, "all items must be on one device");
+        if (it.N > 0 && (!it.q || !it.qd || !it.tau || !it.qdd || !it.Minv || !it.dqdd_dq ||
+                         !it.dqdd_dqd))
+            return fail(GRID_EINVAL, "item " + std::to_string(k) + ": a data pointer is NULL");
+    }
+    return GRID_OK;
+}
+
+}  // namespace
+
+struct grid_graph_s {
+    int device = 0;
+    int count = 0;
+    hipStream_t capture = nullptr;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// fork every item onto its own side stream and join them back, so the captured kernel
+// nodes have no edges between them
+grid_status capture(grid_graph g, const grid_item* items, int32_t count, hipGraph_t* out)
+{
+    HIP_TRY(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
+    grid_status st = GRID_OK;
+    hipError_t e = hipEventRecord(g->fork, g->capture);
+    for (int k = 0; k < count && e == hipSuccess && st == GRID_OK; ++k) {
+        e = hipStreamWaitEvent(g->side[k], g->fork, 0);
+        if (e == hipSuccess && items[k].N > 0)
+            st = launch_fused(items[k].model, items[k].N, items[k].q, items[k].qd, items[k].tau,
+                              items[k].qdd, items[k].Minv, items[k].dqdd_dq, items[k].dqdd_dqd,
+                              g->side[k]);
+        if (e == hipSuccess && st == GRID_OK)
+            e = hipEventRecord(g->join[k], g->side[k]);
+        if (e == hipSuccess && st == GRID_OK)
+            e = hipStreamWaitEvent(g->capture, g->join[k], 0);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(g->capture, &graph);
+    if (st != GRID_OK) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return fail(GRID_EDEVICE, std::string("graph capture: ") +
+                                      hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    *out = graph;
+    return GRID_OK;
+}
+
+void destroy_graph(grid_graph g)
+{
+    if (g->exec)
+        (void)hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        (void)hipGraphDestroy(g->graph);
+    for (auto e : g->join)
+        (void)hipEventDestroy(e);
+    if (g->fork)
+        (void)hipEventDestroy(g->fork);
+    for (auto s : g->side)
+        (void)hipStreamDestroy(s);
+    if (g->capture)
+        (void)hipStreamDestroy(g->capture);
+    delete g;
+}
+
+}  // namespace
+
+extern "C" {
+
+grid_status grid_fd_grad_batch(const grid_item* items, int32_t count, void* stream)
+{
+    grid_status st = check_items(items, count);
+    if (st != GRID_OK)
+        return st;
+    HIP_TRY(hipSetDevice(items[0].model->device));
+    for (int k = 0; k < count; ++k) {
+        const grid_item& it = items[k];
+        if (it.N == 0)
+            continue;
+        st = launch_fused(it.model, it.N, it.q, it.qd, it.tau, it.qdd, it.Minv, it.dqdd_dq,
+                          it.dqdd_dqd, (hipStream_t)stream);
+        if (st != GRID_OK)
+            return st;
+    }
+    return GRID_OK;
+}
+
+grid_status grid_graph_create(const grid_item* items, int32_t count, grid_graph* out)
+{
+    if (!out)
+        return fail(GRID_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    grid_status st = check_items(items, count);
+    if (st != GRID_OK)
+        return st;
+    HIP_TRY(hipSetDevice(items[0].model->device));
+    grid_graph g = new (std::nothrow) grid_graph_s;
+    if (!g)
+        return fail(GRID_ENOMEM, "host allocation failed");
+    g->device = items[0].model->device;
+    g->count = count;
+    hipError_t e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming);
+    for (int k = 0; k < count && e == hipSuccess; ++k) {
+        hipStream_t s = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            g->side.push_back(s);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            g->join.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        destroy_graph(g);
+        return fail(GRID_EDEVICE, std::string("graph streams: ") + hipGetErrorString(e));
+    }
+    st = capture(g, items, count, &g->graph);
+    if (st == GRID_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess)
+            st = fail(GRID_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (st != GRID_OK) {
+        destroy_graph(g);
+        return st;
+    }
+    *out = g;
+    return GRID_OK;
+}
+
+grid_status grid_graph_launch(grid_graph g, void* stream)
+{
+    if (!g)
+        return fail(GRID_EINVAL, "graph is NULL");
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return GRID_OK;
+}
+
+grid_status grid_graph_update(grid_graph g, const grid_item* items, int32_t count)
+{
+    if (!g)
+        return fail(GRID_EINVAL, "graph is NULL");
+    grid_status st = check_items(items, count);
+    if (st != GRID_OK)
+        return st;
+    if (count != g->count || items[0].model->device != g->device)
+        return fail(GRID_EINVAL, "an update keeps the item count and the device");
+    HIP_TRY(hipSetDevice(g->device));
+    hipGraph_t fresh = nullptr;
+    st = capture(g, items, count, &fresh);
+    if (st != GRID_OK)
+        return st;
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res;
+    if (hipGraphExecUpdate(g->exec, fresh, &err_node, &res) != hipSuccess ||
+        res != hipGraphExecUpdateSuccess) {
+        (void)hipGetLastError();
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipGraphInstantiate(&exec, fresh, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(fresh);
+            return fail(GRID_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        (void)hipGraphExecDestroy(g->exec);
+        g->exec = exec;
+    }
+    (void)hipGraphDestroy(g->graph);
+    g->graph = fresh;
+    return GRID_OK;
+}
+
+grid_status grid_graph_destroy(grid_graph g)
+{
+    if (!g)
+        return GRID_OK;
+    (void)hipSetDevice(g->device);
+    for (auto s : g->side)
+        (void)hipStreamSynchronize(s);
+    destroy_graph(g);
+    return GRID_OK;
+}
+
+grid_status grid_tune(grid_model m, const int32_t* Ns, int32_t count, const char* table_path,
+                      int32_t* chosen)
+{
+    if (!m || !Ns || count < 1 || count > 64)
+        return fail(GRID_EINVAL, "model and 1..64 knot counts are required");
+    int32_t maxN = 0;
+    for (int k = 0; k < count; ++k) {
+        if (Ns[k] < 1 || Ns[k] > (1 << 22))
+            return fail(GRID_EINVAL, "knot counts must be in 1..2^22");
+        maxN = std::max(maxN, Ns[k]);
+    }
+    HIP_TRY(hipSetDevice(m->device));
+    const size_t n = (size_t)m->topo.n;
+    float *in = nullptr, *outb = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (s)
+            (void)hipStreamSynchronize(s);
+        (void)hipFree(in);
+        (void)hipFree(outb);
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+        if (s)
+            (void)hipStreamDestroy(s);
+    };
+    hipError_t e = hipMalloc(&in, (size_t)maxN * 3 * n * sizeof(float));
+    if (e == hipSuccess)
+        e = hipMalloc(&outb, (size_t)maxN * (n + 3 * n * n) * sizeof(float));
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    if (e == hipSuccess)   // q = qd = tau = 0: a valid state; the timing does not depend on values
+        e = hipMemsetAsync(in, 0, (size_t)maxN * 3 * n * sizeof(float), s);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(GRID_ENOMEM, std::string("tuning buffers: ") + hipGetErrorString(e));
+    }
+    std::vector<std::pair<int32_t, int>> table;
+    for (int k = 0; k < count; ++k) {
+        const int32_t N = Ns[k];
+        const size_t vec = (size_t)N * n, mat = vec * n;
+        float *q = in, *qd = in + vec, *tau = in + 2 * vec;
+        float *qdd = outb, *Mi = outb + vec, *dq = Mi + mat, *dqd = dq + mat;
+        int best = 0;
+        float best_ms = 1e30f;
+        for (int v = 0; v < 3; ++v) {
+            const int reps = 30;
+            float times[5];
+            for (int trial = 0; trial < 5; ++trial) {
+                grid_status st = GRID_OK;
+                for (int w = 0; w < 3 && st == GRID_OK; ++w)
+                    st = grid_impl::launch_fused_variant(m, v, N, q, qd, tau, qdd, Mi, dq, dqd, s);
+                e = hipEventRecord(e0, s);
+                for (int r = 0; r < reps && st == GRID_OK; ++r)
+                    st = grid_impl::launch_fused_variant(m, v, N, q, qd, tau, qdd, Mi, dq, dqd, s);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e1, s);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                if (st != GRID_OK || e != hipSuccess) {
+                    cleanup();
+                    return st != GRID_OK ? st
+                                         : fail(GRID_EDEVICE, std::string("tuning: ") +
+                                                                  hipGetErrorString(e));
+                }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                times[trial] = ms / reps;
+            }
+            std::sort(times, times + 5);
+            if (times[2] < best_ms) {
+                best_ms = times[2];
+                best = v;
+            }
+        }
+        table.emplace_back(N, best);
+        if (chosen)
+            chosen[k] = best;
+    }
+    cleanup();
+    std::sort(table.begin(), table.end());
+    m->tuned = table;
+    if (table_path) {
+        std::ofstream f(table_path, std::ios::app);
+        if (!f)
+            return fail(GRID_EINVAL, std::string("cannot write ") + table_path);
+        f << "{\"arch\": \"gfx950\", \"model\": \"" << std::hex << m->source_hash << std::dec
+          << "\", \"buckets\": [";
+        for (size_t i = 0; i < table.size(); ++i)
+            f << (i ? ", " : "") << "[" << table[i].first << ", " << table[i].second << "]";
+        f << "]}\n";
+    }
+    return GRID_OK;
+}
+
+}  // extern "C"
+
+namespace grid_impl {
+
+// Apply the last line of $GRID_TUNE_TABLE whose model hash matches this model.
+void load_tuning(grid_model m)
+{
+    const char* path = std::getenv("GRID_TUNE_TABLE");
+    if (!path || !*path)
+        return;
+    std::ifstream f(path);
+    if (!f)
+        return;
+    char key[32];
+    std::snprintf(key, sizeof key, "\"model\": \"%llx\"", (unsigned long long)m->source_hash);
+    std::string line, last;
+    while (std::getline(f, line))
+        if (line.find(key) != std::string::npos)
+            last = line;
+    if (last.empty())
+        return;
+    std::vector<std::pair<int32_t, int>> table;
+    size_t p = last.find("\"buckets\": [");
+    if (p == std::string::npos)
+        return;
+    p += 12;
+    while (true) {
+        p = last.find('[', p);
+        if (p == std::string::npos)
+            break;
+        long Nk = 0, v = 0;
+        if (std::sscanf(last.c_str() + p, "[%ld, %ld]", &Nk, &v) != 2 || v < 0 || v > 2)
+            break;
+        table.emplace_back((int32_t)Nk, (int)v);
+        ++p;
+    }
+    std::sort(table.begin(), table.end());
+    m->tuned = table;
+}
+
+}  // namespace grid_impl

@@ -222,6 +222,8 @@ static uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull)
     return h;
 }
 
+uint64_t source_hash(const std::string& source) { return fnv1a(source); }
+
 std::string cache_dir()
 {
     if (const char* env = std::getenv("GRID_KERNEL_CACHE"))

@@ -612,7 +612,22 @@ using namespace grid;
 template <int ST>
 __device__ void grid_dispatch(const Args& args, int block);
 
+// Three builds of the fused kernel differ only in the register budget the compiler may
+// use: 1, 2 or 4 resident wavefronts per SIMD (more registers and no spills, or more
+// wavefronts to hide latency at large N). The autotuner picks one per batch size.
 extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_fused(Args args)
+{
+    grid_dispatch<kFused>(args, (int)blockIdx.x);
+}
+
+extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+grid_fdgrad_fused_w2(Args args)
+{
+    grid_dispatch<kFused>(args, (int)blockIdx.x);
+}
+
+extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
+grid_fdgrad_fused_w4(Args args)
 {
     grid_dispatch<kFused>(args, (int)blockIdx.x);
 }

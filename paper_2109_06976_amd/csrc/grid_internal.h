@@ -67,6 +67,15 @@ int64_t workgroups_for(const Topology& t, int64_t nknots);
 int lanes_per_knot(const Topology& t);
 WorkspaceLayout workspace_layout(const Topology& t);
 grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err);
+uint64_t source_hash(const std::string& source);
+grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
+                         const float* tau, float* qdd, float* Minv, float* dq, float* dqd,
+                         hipStream_t stream);
+grid_status launch_fused_variant(grid_model m, int variant, int32_t N, const float* q,
+                                 const float* qd, const float* tau, float* qdd, float* Minv,
+                                 float* dq, float* dqd, hipStream_t stream);
+int fused_variant_for(grid_model m, int32_t N);
+void load_tuning(grid_model m);
 std::string cache_dir();
 
 void set_error(const std::string& msg);
@@ -80,6 +89,9 @@ struct grid_model_s {
     int device = 0;
     uint32_t flags = 0;
     grid_impl::Topology topo;
+    uint64_t source_hash = 0;           // of the generated source: keys tuning tables
+    hipFunction_t fused_variant[3] = {nullptr, nullptr, nullptr};   // 1, 2, 4 waves/SIMD
+    std::vector<std::pair<int32_t, int>> tuned;   // (largest N, variant), ascending N
     hipModule_t module = nullptr;
     hipFunction_t fused = nullptr;
     hipFunction_t stage[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};

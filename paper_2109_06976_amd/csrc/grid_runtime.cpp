@@ -142,21 +142,40 @@ grid_status launch(hipFunction_t fn, grid_model m, int32_t N, float* work, const
     a.dqdd_dq = dq;
     a.dqdd_dqd = dqd;
     const unsigned blocks = (unsigned)workgroups_for(m->topo, N);
-    size_t size = sizeof(a);
-    void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
-                      HIP_LAUNCH_PARAM_END};
-    HIP_TRY(hipModuleLaunchKernel(fn, blocks, 1, 1, 64, 1, 1, 0, stream, nullptr, config));
+    void* params[] = {&a};   // the kernel takes one argument: the Args block
+    HIP_TRY(hipModuleLaunchKernel(fn, blocks, 1, 1, 64, 1, 1, 0, stream, params, nullptr));
     return GRID_OK;
+}
+
+}  // namespace
+
+namespace grid_impl {
+
+int fused_variant_for(grid_model m, int32_t N)
+{
+    for (const auto& e : m->tuned)
+        if (N <= e.first)
+            return e.second;
+    return m->tuned.empty() ? 0 : m->tuned.back().second;
+}
+
+grid_status launch_fused_variant(grid_model m, int variant, int32_t N, const float* q,
+                                 const float* qd, const float* tau, float* qdd, float* Minv,
+                                 float* dq, float* dqd, hipStream_t stream)
+{
+    return launch(m->fused_variant[variant], m, N, nullptr, q, qd, tau, qdd, Minv, dq, dqd,
+                  stream);
 }
 
 grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
                          const float* tau, float* qdd, float* Minv, float* dq, float* dqd,
                          hipStream_t stream)
 {
-    return launch(m->fused, m, N, nullptr, q, qd, tau, qdd, Minv, dq, dqd, stream);
+    return launch_fused_variant(m, fused_variant_for(m, N), N, q, qd, tau, qdd, Minv, dq, dqd,
+                                stream);
 }
 
-}  // namespace
+}  // namespace grid_impl
 
 extern "C" {
 
@@ -263,15 +282,21 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     m->topo = std::move(topo);
     static const char* const kStages[5] = {"grid_stage_rnea", "grid_stage_minv", "grid_stage_qdd",
                                            "grid_stage_drnea", "grid_stage_fdgrad"};
+    static const char* const kVariants[3] = {"grid_fdgrad_fused", "grid_fdgrad_fused_w2",
+                                             "grid_fdgrad_fused_w4"};
+    m->source_hash = source_hash(src);
     hipError_t e = hipModuleLoadData(&m->module, code.data());
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        e = hipModuleGetFunction(&m->fused_variant[k], m->module, kVariants[k]);
     if (e == hipSuccess)
-        e = hipModuleGetFunction(&m->fused, m->module, "grid_fdgrad_fused");
+        m->fused = m->fused_variant[0];
     for (int k = 0; k < 5 && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->stage[k], m->module, kStages[k]);
     if (e != hipSuccess) {
         grid_model_destroy(m);
         return hip_fail(e, "module load");
     }
+    load_tuning(m);
     *out = m;
     return GRID_OK;
 }

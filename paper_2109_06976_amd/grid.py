@@ -67,6 +67,12 @@ class LoadgenResult(C.Structure):
                 ("offered_rate_per_s", C.c_double)]
 
 
+class GridItem(C.Structure):
+    _fields_ = [("model", C.c_void_p), ("N", C.c_int32), ("q", C.c_void_p), ("qd", C.c_void_p),
+                ("tau", C.c_void_p), ("qdd", C.c_void_p), ("Minv", C.c_void_p),
+                ("dqdd_dq", C.c_void_p), ("dqdd_dqd", C.c_void_p)]
+
+
 class GridError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{status_string(status)}: {message}")
@@ -89,6 +95,13 @@ _SIGS = {
     "grid_fd_grad_staged": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32] + [C.c_void_p] * 7 +
                             [C.c_void_p]),
     "grid_workspace_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "grid_fd_grad_batch": (C.c_int32, [C.POINTER(GridItem), C.c_int32, C.c_void_p]),
+    "grid_graph_create": (C.c_int32, [C.POINTER(GridItem), C.c_int32, C.POINTER(C.c_void_p)]),
+    "grid_graph_launch": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "grid_graph_update": (C.c_int32, [C.c_void_p, C.POINTER(GridItem), C.c_int32]),
+    "grid_graph_destroy": (C.c_int32, [C.c_void_p]),
+    "grid_tune": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_char_p,
+                              C.POINTER(C.c_int32)]),
     "grid_server_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(ServerConfig),
                                        C.POINTER(C.c_void_p)]),
     "grid_server_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 7 +
@@ -266,6 +279,61 @@ class Workspace:
                                        ptr(out["dqdd_dqd"]), C.byref(t)))
         timing = {k: float(getattr(t, k)) for k in ("h2d_ms", "kernel_ms", "d2h_ms", "total_ms")}
         return out, timing
+
+
+def _items(items):
+    """items: sequence of (model, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd) with device
+    tensors (N taken from q)."""
+    arr = (GridItem * len(items))()
+    for k, (m, q, qd, tau, qdd, Mi, dq, dqd) in enumerate(items):
+        arr[k] = GridItem(m.handle.value, int(q.shape[0]), _addr(q), _addr(qd), _addr(tau),
+                          _addr(qdd), _addr(Mi), _addr(dq), _addr(dqd))
+    return arr
+
+
+def fd_grad_batch(items, stream=None):
+    arr = _items(items)
+    _check(lib().grid_fd_grad_batch(arr, len(items), _stream_handle(stream)))
+
+
+class Graph:
+    """grid_graph: a mixed batch of robots captured as one hipGraph."""
+
+    def __init__(self, items):
+        self._h = None
+        arr = _items(items)
+        h = C.c_void_p()
+        _check(lib().grid_graph_create(arr, len(items), C.byref(h)))
+        self._h = h
+        self.count = len(items)
+
+    def launch(self, stream=None):
+        _check(lib().grid_graph_launch(self._h, _stream_handle(stream)))
+
+    def update(self, items):
+        arr = _items(items)
+        _check(lib().grid_graph_update(self._h, arr, len(items)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().grid_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune(model, Ns, table_path=None):
+    """grid_tune: time the fused kernel builds for each N; returns the chosen build per N."""
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    chosen = np.zeros(len(Ns), np.int32)
+    path = table_path.encode() if table_path else None
+    _check(lib().grid_tune(model.handle, Ns.ctypes.data_as(_i32p), len(Ns), path,
+                           chosen.ctypes.data_as(_i32p)))
+    return dict(zip(Ns.tolist(), chosen.tolist()))
 
 
 class Server:

@@ -1,0 +1,120 @@
+"""Mixed-robot batches (serial launches and one hipGraph) and the autotuner's kernel
+builds, on an MI355X through the C ABI."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2109_06976_amd import grid, synth
+
+pytestmark = pytest.mark.gpu
+OUTS = ("qdd", "Minv", "dqdd_dq", "dqdd_dqd")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_item(torch, model, robot, N, seed):
+    kn = synth.random_knots(robot.n, N, seed)
+    ins = [torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)]
+    n = robot.n
+    outs = [torch.full((N, n), float("nan"), device="cuda")] + \
+           [torch.full((N, n, n), float("nan"), device="cuda") for _ in range(3)]
+    return (model, *ins, *outs), kn
+
+
+def alone(torch, model, item):
+    outs = [torch.empty_like(t) for t in item[4:]]
+    model.fd_grad(*item[1:4], *outs)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+def test_mixed_graph_equals_alone_and_updates():
+    import torch
+    quad, chain = synth.quad12(), synth.chain7()
+    mq, mc = grid.Model(quad), grid.Model(chain)
+    pairs = [(64, 37), (256, 181), (1024, 613)]
+    items, _ = zip(*[make_item(torch, mq, quad, 64, 1), make_item(torch, mc, chain, 37, 2)])
+    say("[gpu] mixed graph quad12 64 + chain7 37")
+    g = grid.Graph(list(items))
+    for step, (nq, nc) in enumerate(pairs):
+        if step:
+            say(f"[gpu] graph update quad12 {nq} + chain7 {nc}")
+            items, _ = zip(*[make_item(torch, mq, quad, nq, 10 + step),
+                             make_item(torch, mc, chain, nc, 20 + step)])
+            g.update(list(items))
+        for _ in range(3):                             # replays, with eager work between them
+            g.launch()
+            torch.cuda.synchronize()
+            for item in items:
+                ref = alone(torch, item[0], item)
+                for got, want in zip(item[4:], ref):
+                    np.testing.assert_array_equal(got.cpu().numpy(), want)
+            for t in items[0][4:]:
+                t.fill_(float("nan"))
+    g.close()
+    # the same items through serial launches
+    grid.fd_grad_batch(list(items))
+    torch.cuda.synchronize()
+    for item in items:
+        ref = alone(torch, item[0], item)
+        for got, want in zip(item[4:], ref):
+            np.testing.assert_array_equal(got.cpu().numpy(), want)
+    mq.close()
+    mc.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_every_tuned_build_matches_oracle(orc, tmp_path, variant):
+    import torch
+    robot = synth.humanoid30()
+    table = tmp_path / "tune.json"
+    say(f"[gpu] humanoid30 with fused build {variant}")
+    # tune once to obtain the table line keyed by this model, then force `variant` for
+    # every N and apply it at model creation
+    m = grid.Model(robot)
+    tuned = grid.tune(m, [64], table_path=str(table))
+    assert set(tuned.values()) <= {0, 1, 2}
+    line = table.read_text().strip().splitlines()[-1]
+    forced = line.split('"buckets"')[0] + f'"buckets": [[4194304, {variant}]]}}\n'
+    table.write_text(forced)
+    os.environ["GRID_TUNE_TABLE"] = str(table)
+    try:
+        m2 = grid.Model(robot)
+    finally:
+        del os.environ["GRID_TUNE_TABLE"]
+    kn = synth.random_knots(robot.n, 128, 104)
+    out = grid.fd_grad_torch(m2, *(torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)))
+    torch.cuda.synchronize()
+    ref = orc.fd_grad_batch(robot, kn.q, kn.qd, kn.tau)
+    tol = {"qdd": 1e-4, "Minv": 1e-3, "dqdd_dq": 1e-3, "dqdd_dqd": 1e-3}
+    for k, b in tol.items():
+        y = out[k].cpu().numpy().astype(np.float64).reshape(128, -1)
+        r = ref[k].reshape(128, -1)
+        assert (np.abs(y - r).max(1) / np.abs(r).max(1)).max() <= b, k
+    m.close()
+    m2.close()
+
+
+def test_tune_picks_builds_per_size(tmp_path):
+    m = grid.Model(synth.chain7())
+    say("[gpu] tune chain7 at 128, 1024, 16384 knots")
+    chosen = grid.tune(m, [128, 1024, 16384], table_path=str(tmp_path / "t.json"))
+    say(f"  chosen builds {chosen}")
+    assert sorted(chosen) == [128, 1024, 16384]
+    assert (tmp_path / "t.json").read_text().count("buckets") == 1
+    m.close()
+
+
+def test_graph_rejects_bad_items():
+    import torch
+    m = grid.Model(synth.chain7())
+    t = torch.zeros((4, 7), device="cuda")
+    with pytest.raises(grid.GridError) as e:
+        grid.Graph([(m, t, None, t, t, t, t, t)])
+    assert e.value.status == grid.GRID_EINVAL
+    m.close()
