@@ -11,6 +11,8 @@ Also reported (extra fields of the same line):
                 the same batch, and fused_vs_plain = plain step time / fused step time;
   roofline      the fused kernel's algorithmic FLOP rate against the FP32 vector peak,
                 from HIP-event kernel durations measured here;
+  builds        each build of the fused kernel at this N, and the autotuner's choices
+                (the timed steps run the tuned build);
   io_inclusive  the host-pointer call (pinned staging, H2D + kernel + D2H);
   served        p50/p99 latency and throughput of an open-loop Poisson request stream
                 (20k req/s over the three robots) through the continuous-batching
@@ -35,9 +37,15 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused.json")
 
 
+KERNEL_SOURCES = ("grid_device.hip", "grid_fused.hip", "grid_serial.hip", "grid_codegen.cpp")
+
+
 def kernel_source_hash() -> str:
-    path = os.path.join(ROOT, "paper_2109_06976_amd", "csrc", "grid_device.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of everything the generated kernels are made from."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2109_06976_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str):
@@ -70,6 +78,8 @@ def parse():
                     help="measured seconds of the served load (0 disables serving)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-sweep", default="", help="extra request rates, comma-separated")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (untuned build choice)")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="also run a plain device copy of this size (for counter scaling)")
     return ap.parse_args()
@@ -156,6 +166,22 @@ def main():
         return lambda: model.fd_grad(*ins_, *outs_, N=NK, stream=stream)
 
     launch = launch_for(ins, outs, N)
+    sweep_ns = [int(x) for x in args.sweep.split(",") if x]
+
+    # every build of the fused kernel at this N (pinned one at a time), then the autotuner
+    # over the sizes this run times; the timed steps use the tuned choice
+    builds = {}
+    for b, name in enumerate(grid.BUILD_KERNELS):
+        try:
+            grid.tune_apply(model, {1 << 22: b})
+        except grid.GridError:
+            continue   # not built for this robot
+        st, ks = time_steps(torch, launch, max(200, args.steps // 10), 50)
+        builds[name] = {"us_per_step": round(st * 1e6, 3), "kernel_avg_us": round(ks * 1e6, 3)}
+    grid.tune_apply(model, {})
+    tuned = None if args.no_tune else grid.tune(model, sorted(set([N] + sweep_ns)))
+    build = grid.build_for(model, N)
+
     sec_per_step, kernel_s = time_steps(torch, launch, args.steps, args.warmup)
     avg_ms = kernel_s * 1e3
 
@@ -173,7 +199,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 4), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
                 "traffic": traffic,
-                "kernel": "grid_fdgrad_fused", "kernel_avg_us": round(avg_ms * 1e3, 3),
+                "kernel": grid.BUILD_KERNELS[build], "kernel_avg_us": round(avg_ms * 1e3, 3),
                 "flop_per_knot": fl["total"],
                 "hbm_bytes_per_launch": flops.io_bytes_per_knot(n) * N,
                 "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
@@ -200,6 +226,8 @@ def main():
                   "note": "staged pipeline: 5 launches (RNEA, M^-1, qdd, dRNEA, dFD), "
                           "intermediates through device memory"},
         "fused_vs_plain": plain_step / sec_per_step,
+        "builds": builds,
+        "tuned": tuned,
     }
 
     if not args.no_io:
@@ -225,13 +253,15 @@ def main():
 
     if args.sweep:
         sweep = {}
-        for NK in [int(x) for x in args.sweep.split(",") if x]:
+        for NK in sweep_ns:
             i2, o2 = buffers(NK, args.seed + NK)
             l2 = launch_for(i2, o2, NK)
             s, a = time_steps(torch, l2, max(200, args.steps // 5), 50)
             sweep[str(NK)] = {"knot_evals_per_s": NK / s, "ms_per_step": s * 1e3,
                               "kernel_avg_us": a * 1e6,
+                              "kernel": grid.BUILD_KERNELS[grid.build_for(model, NK)],
                               "alu_frac": fl["total"] * NK / a / 1e12 / PEAK_FP32_TFLOPS}
+            del i2, o2
         result["sweep"] = sweep
 
     if args.copy_calibration_mb > 0:

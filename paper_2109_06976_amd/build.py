@@ -1,7 +1,8 @@
 """Build libgrid.so (hipcc, gfx950) in-tree and fill its kernel cache.
 
 Steps:
-  1. embed csrc/grid_device.hip into a generated include (_build/grid_device_src.inc);
+  1. embed the device sources csrc/grid_device.hip, grid_fused.hip and grid_serial.hip
+     into generated includes (_build/<name>_src.inc);
   2. compile the host runtime (csrc/*.cpp) with hipcc into libgrid.so;
   3. compile the device source with hipcc for gfx950 behind a generated chain prelude
      (a full offline compile check; -save-temps keeps the ISA under _build/);
@@ -33,17 +34,18 @@ def _run(cmd, verbose):
     return r
 
 
-def embed_device_source() -> str:
+def embed_device_source() -> None:
+    """Device sources as byte arrays for the library's code generator."""
     os.makedirs(BUILD, exist_ok=True)
-    src = open(os.path.join(CSRC, "grid_device.hip"), "rb").read()
-    body = ",".join(str(b) for b in src)
-    inc = os.path.join(BUILD, "grid_device_src.inc")
-    text = ("// generated from csrc/grid_device.hip by build.py\n"
-            f"static const char grid_device_src[] = {{{body},0}};\n")
-    if not os.path.exists(inc) or open(inc).read() != text:
-        with open(inc, "w") as f:
-            f.write(text)
-    return inc
+    for name in ("grid_device", "grid_fused", "grid_serial"):
+        src = open(os.path.join(CSRC, f"{name}.hip"), "rb").read()
+        body = ",".join(str(b) for b in src)
+        inc = os.path.join(BUILD, f"{name}_src.inc")
+        text = (f"// generated from csrc/{name}.hip by build.py\n"
+                f"static const char {name}_src[] = {{{body},0}};\n")
+        if not os.path.exists(inc) or open(inc).read() != text:
+            with open(inc, "w") as f:
+                f.write(text)
 
 
 def build_library(verbose=False) -> str:

@@ -286,7 +286,9 @@ grid_status grid_tune(grid_model m, const int32_t* Ns, int32_t count, const char
         float *qdd = outb, *Mi = outb + vec, *dq = Mi + mat, *dqd = dq + mat;
         int best = 0;
         float best_ms = 1e30f;
-        for (int v = 0; v < 3; ++v) {
+        for (int v = 0; v < grid_impl::kNumVariants; ++v) {
+            if (!m->fused_variant[v])
+                continue;   // not built for this model
             const int reps = 30;
             float times[5];
             for (int trial = 0; trial < 5; ++trial) {
@@ -336,6 +338,33 @@ grid_status grid_tune(grid_model m, const int32_t* Ns, int32_t count, const char
     return GRID_OK;
 }
 
+grid_status grid_tune_apply(grid_model m, const int32_t* Ns, const int32_t* builds,
+                            int32_t count)
+{
+    if (!m || count < 0 || count > 64 || (count > 0 && (!Ns || !builds)))
+        return fail(GRID_EINVAL, "model and 0..64 (N, build) pairs are required");
+    std::vector<std::pair<int32_t, int>> table;
+    for (int k = 0; k < count; ++k) {
+        if (Ns[k] < 1 || Ns[k] > (1 << 22) || (k > 0 && Ns[k] <= Ns[k - 1]))
+            return fail(GRID_EINVAL, "knot counts must ascend within 1..2^22");
+        if (builds[k] < 0 || builds[k] >= grid_impl::kNumVariants ||
+            !m->fused_variant[builds[k]])
+            return fail(GRID_EUNSUPPORTED, "build " + std::to_string(builds[k]) +
+                                               " does not exist for this model");
+        table.emplace_back(Ns[k], builds[k]);
+    }
+    m->tuned = table;
+    return GRID_OK;
+}
+
+grid_status grid_build_for(grid_model m, int32_t N, int32_t* build)
+{
+    if (!m || N < 1 || !build)
+        return fail(GRID_EINVAL, "model, N >= 1 and an output pointer are required");
+    *build = grid_impl::fused_variant_for(m, N);
+    return GRID_OK;
+}
+
 }  // extern "C"
 
 namespace grid_impl {
@@ -367,7 +396,8 @@ void load_tuning(grid_model m)
         if (p == std::string::npos)
             break;
         long Nk = 0, v = 0;
-        if (std::sscanf(last.c_str() + p, "[%ld, %ld]", &Nk, &v) != 2 || v < 0 || v > 2)
+        if (std::sscanf(last.c_str() + p, "[%ld, %ld]", &Nk, &v) != 2 || v < 0 ||
+            v >= kNumVariants || !m->fused_variant[v])
             break;
         table.emplace_back((int32_t)Nk, (int)v);
         ++p;

@@ -22,8 +22,10 @@
 
 namespace grid_impl {
 
-// embedded copy of grid_device.hip (generated at build time)
+// embedded copies of grid_device.hip and grid_fused.hip (generated at build time)
 #include "grid_device_src.inc"
+#include "grid_fused_src.inc"
+#include "grid_serial_src.inc"
 
 bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::string* err)
 {
@@ -71,6 +73,16 @@ bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::stri
         shape.L = 2;
         while (shape.L < 2 * shape.B)
             shape.L *= 2;
+        // quad layout: one quad per derivative column; up to 16 quads per wavefront
+        if (2 * shape.B <= 16) {
+            shape.Q = shape.L;
+            shape.W = 1;
+        } else {
+            shape.Q = 16;
+            shape.W = 1;
+            while (16 * shape.W < 2 * shape.B)
+                shape.W *= 2;
+        }
         int sid = -1;
         for (size_t s = 0; s < t.shapes.size(); ++s)
             if (t.shapes[s].parent == shape.parent)
@@ -80,6 +92,7 @@ bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::stri
             t.shapes.push_back(shape);
         }
         inst.shape = sid;
+        t.waves = std::max(t.waves, t.shapes[sid].W);
         inst.coff = coff;
         coff += shape.B * kConstStride;
         t.insts.push_back(inst);
@@ -94,6 +107,56 @@ int64_t workgroups_for(const Topology& t, int64_t nknots)
     for (const BranchInst& inst : t.insts) {
         const int K = 64 / t.shapes[inst.shape].L;
         total += (nknots + K - 1) / K;
+    }
+    return total;
+}
+
+// two-role quad kernel: role B takes the B columns of M in QB quads (the power of two >= B,
+// at most 16, two columns per quad beyond), so a workgroup holds 16 / QB problems; role A
+// takes the 2B derivative columns in two wavefronts (B <= 16) or ceil(2B / 16)
+int pipe_problems(int B)
+{
+    int qb = 1;
+    while (qb < B && qb < 16)
+        qb *= 2;
+    return 16 / qb;
+}
+
+int pipe_waves(const Topology& t)
+{
+    int w = 3;
+    for (const BranchShape& s : t.shapes)
+        w = std::max(w, (2 * s.B + 15) / 16 + 1);
+    return w;
+}
+
+int64_t workgroups_pipe(const Topology& t, int64_t nknots)
+{
+    int64_t total = 0;
+    for (const BranchInst& inst : t.insts) {
+        const int P = pipe_problems(t.shapes[inst.shape].B);
+        total += (nknots + P - 1) / P;
+    }
+    return total;
+}
+
+int64_t workgroups_serial(const Topology& t, int64_t nknots)
+{
+    return (int64_t)t.insts.size() * ((nknots + 63) / 64);
+}
+
+// problems (knot, branch) per workgroup of the quad-layout kernel
+static int quad_problems(const Topology& t, const BranchShape& s)
+{
+    return (t.waves / s.W) * (16 / s.Q);
+}
+
+int64_t workgroups_quad(const Topology& t, int64_t nknots)
+{
+    int64_t total = 0;
+    for (const BranchInst& inst : t.insts) {
+        const int P = quad_problems(t, t.shapes[inst.shape]);
+        total += (nknots + P - 1) / P;
     }
     return total;
 }
@@ -143,6 +206,59 @@ static void emit_floats(std::ostringstream& os, const float* v, size_t k)
     os << "}";
 }
 
+// Per (body, lane c) of the quad layout, 24 floats (c = 3 repeats c = 0; indices mod 3):
+//   [0..4] cos(q), [5..9] sin(q), [10..14] constant coefficients of the entries
+//          E_cc, E_c,c+1, E_c,c+2, E_c+1,c, E_c+2,c of E = E_z(q) E_T, where
+//          row 0 = cos E_T,0 + sin E_T,1, row 1 = cos E_T,1 - sin E_T,0, row 2 = E_T,2
+//   [15] r_c+1  [16] r_c+2  [17] Ibar_cc  [18] Ibar_c,c+1  [19] Ibar_c,c+2
+//   [20] h_c+1  [21] h_c+2  [22..23] zero
+static std::vector<float> quad_constants(const float* c, int B)
+{
+    std::vector<float> out((size_t)B * 4 * 24, 0.0f);
+    for (int i = 0; i < B; ++i) {
+        const float* b = c + (size_t)i * kConstStride;
+        const float* ET = b;          // row-major
+        const float* r = b + 9;
+        const float* Ib = b + 12;     // xx yy zz xy xz yz
+        const float* h = b + 18;
+        auto ibar = [&](int x, int y) -> float {
+            if (x == y)
+                return Ib[x];
+            const int lo = std::min(x, y), hi = std::max(x, y);
+            return lo == 0 ? (hi == 1 ? Ib[3] : Ib[4]) : Ib[5];
+        };
+        for (int lane = 0; lane < 4; ++lane) {
+            const int c0 = lane == 3 ? 0 : lane, c1 = (c0 + 1) % 3, c2 = (c0 + 2) % 3;
+            float* o = out.data() + ((size_t)i * 4 + lane) * 24;
+            const int ent[5][2] = {{c0, c0}, {c0, c1}, {c0, c2}, {c1, c0}, {c2, c0}};
+            for (int e = 0; e < 5; ++e) {
+                const int row = ent[e][0], col = ent[e][1];
+                float kc = 0.0f, ks = 0.0f, k0 = 0.0f;
+                if (row == 0) {
+                    kc = ET[col];
+                    ks = ET[3 + col];
+                } else if (row == 1) {
+                    kc = ET[3 + col];
+                    ks = -ET[col];
+                } else {
+                    k0 = ET[6 + col];
+                }
+                o[e] = kc;
+                o[5 + e] = ks;
+                o[10 + e] = k0;
+            }
+            o[15] = r[c1];
+            o[16] = r[c2];
+            o[17] = ibar(c0, c0);
+            o[18] = ibar(c0, c1);
+            o[19] = ibar(c0, c2);
+            o[20] = h[c1];
+            o[21] = h[c2];
+        }
+    }
+    return out;
+}
+
 std::string generate_source(const Topology& t, const std::vector<float>& consts,
                             const double gravity[3], uint32_t flags)
 {
@@ -158,12 +274,17 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << "#define GRID_WS_C " << ws.c << "\n#define GRID_WS_L " << ws.L << "\n#define GRID_WS_DINV "
        << ws.dinv << "\n#define GRID_WS_DTAU " << ws.dtau << "\n#define GRID_WS_STRIDE "
        << ws.stride << "\n";
+    os << "#define GRID_WAVES " << t.waves << "\n";
+    os << "#define GRID_PIPE_WAVES " << pipe_waves(t) << "\n";
     os << "template <int s> struct Shape;\ntemplate <int k> struct Inst;\n";
     for (size_t s = 0; s < t.shapes.size(); ++s) {
         const BranchShape& sh = t.shapes[s];
         os << "template <> struct Shape<" << s << "> {\n";
         os << "    static constexpr int B = " << sh.B << ";\n";
         os << "    static constexpr int L = " << sh.L << ";\n";
+        os << "    static constexpr int Q = " << sh.Q << ";\n";
+        os << "    static constexpr int W = " << sh.W << ";\n";
+        os << "    static constexpr int PP = " << pipe_problems(sh.B) << ";\n";
         os << "    static constexpr int parent[B] = ";
         emit_list(os, sh.parent);
         os << ";\n    static constexpr unsigned long long anc[B] = ";
@@ -176,6 +297,13 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
         os << "__device__ constexpr float grid_const_" << k << "[" << in.body.size() * kConstStride
            << "] = ";
         emit_floats(os, consts.data() + in.coff, in.body.size() * kConstStride);
+        os << ";\n";
+        // quad layout: per (body, lane c of a quad) the coefficients of the lane's entries
+        // of E = E_z(q) E_T and its translation, inertia and first-moment components
+        const std::vector<float> qc = quad_constants(consts.data() + in.coff, (int)in.body.size());
+        os << "__device__ constexpr float grid_qconst_" << k << "[" << qc.size()
+           << "] __attribute__((aligned(16))) = ";
+        emit_floats(os, qc.data(), qc.size());
         os << ";\n";
         os << "template <> struct Inst<" << k << "> {\n";
         os << "    using S = Shape<" << in.shape << ">;\n";
@@ -190,6 +318,7 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
               "        return r;\n    }\n";
         os << "    __device__ static bool contains(int g) { return (mask >> g) & 1ull; }\n";
         os << "    __device__ static const float* consts() { return grid_const_" << k << "; }\n";
+        os << "    __device__ static const float* qconsts() { return grid_qconst_" << k << "; }\n";
         os << "};\n";
     }
     os << "#line 1 \"grid_device.hip\"\n";
@@ -202,6 +331,38 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
            << "        const int nb = (a.nknots + K - 1) / K;\n"
            << "        if (b < nb) {\n            grid::run_branch<Inst<" << k
            << ">, ST>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
+    }
+    os << "}\n";
+    os << "#line 1 \"grid_fused.hip\"\n";
+    os << grid_fused_src;
+    os << "\n// generated: workgroup -> (branch, problem group), quad layout\n";
+    os << "__device__ void grid_dispatch_q(const grid::Args& a, int block)\n{\n"
+          "    int b = block;\n";
+    for (size_t k = 0; k < t.insts.size(); ++k) {
+        const int P = quad_problems(t, t.shapes[t.insts[k].shape]);
+        os << "    {\n        const int nb = (a.nknots + " << P << " - 1) / " << P << ";\n"
+           << "        if (b < nb) {\n            gridq::run_fused<Inst<" << k
+           << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
+    }
+    os << "}\n";
+    os << "#line 1 \"grid_serial.hip\"\n";
+    os << grid_serial_src;
+    os << "\n// generated: workgroup -> (branch, 64 knots), one lane per knot\n";
+    os << "__device__ void grid_dispatch_s(const grid::Args& a, int block)\n{\n"
+          "    int b = block;\n";
+    for (size_t k = 0; k < t.insts.size(); ++k) {
+        os << "    {\n        const int nb = (a.nknots + 63) / 64;\n"
+           << "        if (b < nb) {\n            grids::run_serial<Inst<" << k
+           << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
+    }
+    os << "}\n";
+    os << "__device__ void grid_dispatch_p(const grid::Args& a, int block)\n{\n"
+          "    int b = block;\n";
+    for (size_t k = 0; k < t.insts.size(); ++k) {
+        const int P = pipe_problems(t.shapes[t.insts[k].shape].B);
+        os << "    {\n        const int nb = (a.nknots + " << P << " - 1) / " << P << ";\n"
+           << "        if (b < nb) {\n            gridq::run_pipe<Inst<" << k
+           << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
     }
     os << "}\n";
     return os.str();

@@ -206,8 +206,10 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
         for (int i = 0; i < B; ++i) {
             const long o = vbase + I::body[i];
             const float* c = C + i * kConstStride;
-            float s, co;
-            sincosf(A.q[o], &s, &co);
+            // sin and cos by the hardware units (angle in revolutions, reduced to [0, 1))
+            const float rev = __builtin_amdgcn_fractf(A.q[o] * 0.159154943091895336f);
+            const float s = __builtin_amdgcn_sinf(rev);
+            const float co = __builtin_amdgcn_cosf(rev);
             qd[i] = A.qd[o];
             tau[i] = A.tau[o];
 #pragma unroll
@@ -330,8 +332,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
         // L_kk = sqrt(M_kk), L_ka = M_ka / L_kk, M_ab -= L_ka L_kb (a, b ancestors of k)
 #pragma unroll
         for (int k = B - 1; k >= 0; --k) {
-            const float d = sqrtf(Lf[k][k]);
-            const float di = 1.0f / d;
+            const float di = __builtin_amdgcn_rsqf(Lf[k][k]);   // 1 / L_kk
             dinv[k] = di;
 #pragma unroll
             for (int b = 0; b < B; ++b)

@@ -1,0 +1,798 @@
+// Fused kernels in quad layout (gfx950).
+//
+// A spatial 6-vector is spread over the four lanes of a quad: lane c (c = 0, 1, 2) holds
+// angular component c and linear component c; lane 3 repeats lane 0. The other two
+// components a lane needs for a cross product or a 3x3 row come from its quad neighbours
+// through DPP quad permutations, so a transform, an inertia product or a cross product
+// costs a few DPP moves and about three FMAs per lane instead of a whole 6-vector per lane.
+// A quad owns one derivative column (u, j) of a (knot, branch) problem, and all quads of a
+// problem run the shared sweeps in lockstep. Per-lane constants (the coefficients of the
+// lane's row and column of the joint rotation, translation and inertia entries) come from a
+// generated per-(body, lane) table; masses are literals.
+//
+// Steps per (knot, branch), float32 (Sec. IV-B): transforms; RNEA(q, qd, 0); column s of M
+// as ID(q, 0, e_s) without gravity; M = L^T L along ancestor paths; qdd; RNEA at qdd as the
+// increment over RNEA(q, qd, 0); the dRNEA forward (Algorithm 1) and backward pass of each
+// column; dqdd/du = -M^-1 dtau/du.
+//
+// grid_fdgrad_quad runs all steps in every quad. A problem with 2B columns uses Q quads
+// (power of two >= 2B, at most 16) in each of W wavefronts (W * Q >= 2B).
+//
+// grid_fdgrad_pipe splits the steps over two roles that run at the same time on different
+// wavefronts of a workgroup, shortening the dependency chain:
+//   role A (2B columns, one per quad, 1..4 wavefronts): RNEA(q, qd, 0); the dRNEA columns
+//                        with the sources taken at qdd = 0
+//   role B (B columns, one or two per quad, one wavefront): M, its factor and M^-1; qdd
+//                        once role A has published the bias forces; RNEA increments at
+//                        qdd; the part of each q-column that depends on qdd
+// dtau/dqd does not depend on qdd, and dtau/dq is affine in the two source terms that do:
+// the parent acceleration (X_j a_lambda(j)) x S enters the forward sweep and the term
+// X_j^T (S x* f_j) the backward sweep, each linearly, so the qdd part of a q-column is the
+// same sweep with the increments X_j Da_lambda(j) and Df_j as sources and dv = 0
+// (da_i = X_i da_lambda + source, df_i = I_i da_i). Role A adds role B's parts and
+// multiplies by M^-1, both read from LDS.
+
+namespace gridq {
+
+using grid::kConstStride;
+
+constexpr int kQConst = 24;   // per (body, component) lane constants, see the table below
+// [0..4] coefficient of cos(q), [5..9] of sin(q), [10..14] constant, for the entries
+//        (E_cc, E_c,c+1, E_c,c+2, E_c+1,c, E_c+2,c) of E = E_z(q) E_T
+// [15] r_{c+1}  [16] r_{c+2}  [17] Ibar_cc  [18] Ibar_c,c+1  [19] Ibar_c,c+2
+// [20] h_{c+1}  [21] h_{c+2}  [22..23] unused       (indices c+1, c+2 taken mod 3)
+
+// quad permutations: lane (0,1,2,3) reads lane (..); lane 3 shadows component 0
+constexpr int kNb1 = 1 | (2 << 2) | (0 << 4) | (1 << 6);   // component c+1
+constexpr int kNb2 = 2 | (0 << 2) | (1 << 4) | (2 << 6);   // component c+2
+constexpr int kZ = 2 | (2 << 2) | (2 << 4) | (2 << 6);     // component 2 (the joint axis)
+constexpr int kXS = 1 | (0 << 2) | (2 << 4) | (1 << 6);    // (x x e_z): lane 0 <- 1, 1 <- 0
+
+template <int CTRL>
+__device__ __forceinline__ float qperm(float x)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+}
+
+struct V {          // this lane's components of a 6-vector
+    float a, l;
+};
+
+struct Nb {         // the quad neighbours' components: a1 = angular c+1, a2 = angular c+2, ...
+    float a1, a2, l1, l2;
+};
+
+__device__ __forceinline__ Nb gather(V x)
+{
+    return Nb{qperm<kNb1>(x.a), qperm<kNb2>(x.a), qperm<kNb1>(x.l), qperm<kNb2>(x.l)};
+}
+
+struct Rot {        // this lane's entries of E: row c (e0, e1, e2) and column c (e0, f1, f2)
+    float e0, e1, e2, f1, f2;
+};
+
+struct LaneK {      // per-lane body constants
+    float rr1, rr2, I0, I1, I2, h1, h2;
+};
+
+struct Lane {       // per-lane selectors of the joint axis S = e_z
+    float sxs;      // (x x S)_c = sxs * x_{c+1 or c-1}: +1 for c = 0, -1 for c = 1, 0 for c = 2
+    float sz;       // S_c: 1 for c = 2
+    float g;        // component c of -g, the base acceleration that carries gravity
+};
+
+__device__ __forceinline__ Lane lane_of(int c3)
+{
+    return Lane{c3 == 0 ? 1.0f : (c3 == 1 ? -1.0f : 0.0f), c3 == 2 ? 1.0f : 0.0f,
+                c3 == 0 ? grid_a0[0] : (c3 == 1 ? grid_a0[1] : grid_a0[2])};
+}
+
+// X m = [E w; E (v - r x w)]
+__device__ __forceinline__ V xmv(const Rot& e, const LaneK& k, V m, Nb n)
+{
+    V y;
+    y.a = e.e0 * m.a + e.e1 * n.a1 + e.e2 * n.a2;
+    const float t = m.l - k.rr1 * n.a2 + k.rr2 * n.a1;
+    y.l = e.e0 * t + e.e1 * qperm<kNb1>(t) + e.e2 * qperm<kNb2>(t);
+    return y;
+}
+
+// X^T f = [E^T n + r x (E^T f_l); E^T f_l]
+__device__ __forceinline__ V xtfv(const Rot& e, const LaneK& k, V f, Nb n)
+{
+    const float l = e.e0 * f.l + e.f1 * n.l1 + e.f2 * n.l2;
+    const float nn = e.e0 * f.a + e.f1 * n.a1 + e.f2 * n.a2;
+    V y;
+    y.a = nn + k.rr1 * qperm<kNb2>(l) - k.rr2 * qperm<kNb1>(l);
+    y.l = l;
+    return y;
+}
+
+// I x = [Ibar w + h x v; m v - h x w]
+__device__ __forceinline__ V imv(const LaneK& k, float m, V x, Nb n)
+{
+    V y;
+    y.a = k.I0 * x.a + k.I1 * n.a1 + k.I2 * n.a2 + (k.h1 * n.l2 - k.h2 * n.l1);
+    y.l = m * x.l - (k.h1 * n.a2 - k.h2 * n.a1);
+    return y;
+}
+
+// v x* f = [w x n + v_l x f_l; w x f_l]
+__device__ __forceinline__ V crf(Nb v, Nb f)
+{
+    V y;
+    y.a = v.a1 * f.a2 - v.a2 * f.a1 + v.l1 * f.l2 - v.l2 * f.l1;
+    y.l = v.a1 * f.l2 - v.a2 * f.l1;
+    return y;
+}
+
+// x x S for S = e_z: (x_1, -x_0, 0) in both halves
+__device__ __forceinline__ V cross_s(const Lane& ln, V x)
+{
+    return V{ln.sxs * qperm<kXS>(x.a), ln.sxs * qperm<kXS>(x.l)};
+}
+
+__device__ __forceinline__ V add(V x, V y) { return V{x.a + y.a, x.l + y.l}; }
+
+__device__ __forceinline__ V neg(V x) { return V{-x.a, -x.l}; }
+
+__device__ __forceinline__ V select(bool take, V x, V keep)
+{
+    return V{take ? x.a : keep.a, take ? x.l : keep.l};
+}
+
+template <int B, class T>
+__device__ __forceinline__ T pick(const T (&arr)[B], int j)
+{
+    T r = arr[0];
+#pragma unroll
+    for (int i = 1; i < B; ++i)
+        r = (i == j) ? arr[i] : r;
+    return r;
+}
+
+__device__ __forceinline__ Rot pick_rot(const Rot& x, bool take, const Rot& keep)
+{
+    return Rot{take ? x.e0 : keep.e0, take ? x.e1 : keep.e1, take ? x.e2 : keep.e2,
+               take ? x.f1 : keep.f1, take ? x.f2 : keep.f2};
+}
+
+template <class S>
+__device__ __forceinline__ constexpr bool is_anc(int a, int i)
+{
+    return (S::anc[i] >> a) & 1ull;
+}
+
+template <class I>
+__device__ __forceinline__ float mass(int i)
+{
+    return I::consts()[i * kConstStride + 21];
+}
+
+// ------------------------------------------------------------------ building blocks
+
+// transforms of the lane's component: E_i from the hardware sin and cos (angle in
+// revolutions, reduced to [0, 1)), and the body constants
+template <class I>
+__device__ __forceinline__ void load_bodies(const grid::Args& A, long vbase, int c,
+                                            float (&qd)[I::S::B], Rot (&E)[I::S::B],
+                                            LaneK (&K)[I::S::B])
+{
+#pragma unroll
+    for (int i = 0; i < I::S::B; ++i) {
+        const long o = vbase + I::body[i];
+        const float rev = __builtin_amdgcn_fractf(A.q[o] * 0.159154943091895336f);
+        const float sn = __builtin_amdgcn_sinf(rev);
+        const float co = __builtin_amdgcn_cosf(rev);
+        qd[i] = A.qd[o];
+        const float4* t = reinterpret_cast<const float4*>(I::qconsts() + (i * 4 + c) * kQConst);
+        const float4 t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3], t4 = t[4], t5 = t[5];
+        // t0 .. t3.y: cos coefficients [0..4], sin coefficients [5..9], constants [10..14]
+        E[i].e0 = t0.x * co + t1.y * sn + t2.z;
+        E[i].e1 = t0.y * co + t1.z * sn + t2.w;
+        E[i].e2 = t0.z * co + t1.w * sn + t3.x;
+        E[i].f1 = t0.w * co + t2.x * sn + t3.y;
+        E[i].f2 = t1.x * co + t2.y * sn + t3.z;
+        K[i] = LaneK{t3.w, t4.x, t4.y, t4.z, t4.w, t5.x, t5.y};
+    }
+}
+
+// RNEA(q, qd, 0): v_i, gamma_i = I_i v_i, f_i accumulated inward, and xa0_i = X_i a_lambda(i)
+template <class I>
+__device__ __forceinline__ void rnea0(const Lane& ln, const float (&qd)[I::S::B],
+                                      const Rot (&E)[I::S::B], const LaneK (&K)[I::S::B],
+                                      V (&v)[I::S::B], V (&gam)[I::S::B], V (&F)[I::S::B],
+                                      V (&xa0)[I::S::B])
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    V a[B];
+    Nb na[B], nv[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const int p = S::parent[i];
+        V xv;
+        if (p >= 0) {
+            xv = xmv(E[i], K[i], v[p < 0 ? 0 : p], nv[p < 0 ? 0 : p]);
+            xa0[i] = xmv(E[i], K[i], a[p < 0 ? 0 : p], na[p < 0 ? 0 : p]);
+        } else {
+            xv = V{0.0f, 0.0f};
+            const V g{0.0f, ln.g};
+            xa0[i] = xmv(E[i], K[i], g, gather(g));
+        }
+        v[i] = V{xv.a + ln.sz * qd[i], xv.l};
+        nv[i] = gather(v[i]);
+        const V vxs = cross_s(ln, v[i]);           // a_i = X a_lambda + (v_i x S) qd_i
+        a[i] = V{xa0[i].a + vxs.a * qd[i], xa0[i].l + vxs.l * qd[i]};
+        na[i] = gather(a[i]);
+        gam[i] = imv(K[i], mass<I>(i), v[i], nv[i]);
+        F[i] = add(imv(K[i], mass<I>(i), a[i], na[i]), crf(nv[i], gather(gam[i])));
+    }
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        const int p = S::parent[i];
+        if (p >= 0)
+            F[p < 0 ? 0 : p] = add(F[p < 0 ? 0 : p], xtfv(E[i], K[i], F[i], gather(F[i])));
+    }
+}
+
+// column jm of M as ID(q, 0, e_jm) without gravity; M_i,jm = S^T f_i is component a of
+// lane 2 of the quad
+template <class I>
+__device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B],
+                                         const LaneK (&K)[I::S::B], int jm, V (&fm)[I::S::B])
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    V am[B];
+    Nb nam[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const int p = S::parent[i];
+        if (p >= 0)
+            am[i] = xmv(E[i], K[i], am[p < 0 ? 0 : p], nam[p < 0 ? 0 : p]);
+        else
+            am[i] = V{0.0f, 0.0f};
+        am[i].a += (i == jm) ? ln.sz : 0.0f;
+        nam[i] = gather(am[i]);
+        fm[i] = imv(K[i], mass<I>(i), am[i], nam[i]);
+    }
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        const int p = S::parent[i];
+        if (p >= 0)
+            fm[p < 0 ? 0 : p] = add(fm[p < 0 ? 0 : p], xtfv(E[i], K[i], fm[i], gather(fm[i])));
+    }
+}
+
+// M = L^T L in place (L lower triangular, nonzero on ancestor paths only): for k from the
+// leaves, L_kk = sqrt(M_kk), L_ka = M_ka / L_kk, M_ab -= L_ka L_kb (a, b ancestors of k)
+template <class S>
+__device__ __forceinline__ void ltl_factor(float (&Lf)[S::B][S::B], float (&dinv)[S::B])
+{
+    constexpr int B = S::B;
+#pragma unroll
+    for (int k = B - 1; k >= 0; --k) {
+        const float di = __builtin_amdgcn_rsqf(Lf[k][k]);   // 1 / L_kk
+        dinv[k] = di;
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (is_anc<S>(b, k))
+                Lf[k][b] *= di;
+#pragma unroll
+        for (int a2 = 0; a2 < B; ++a2)
+            if (is_anc<S>(a2, k))
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    if (b == a2 || is_anc<S>(b, a2))
+                        Lf[a2][b] -= Lf[k][a2] * Lf[k][b];
+    }
+}
+
+// x <- (L^T L)^-1 x
+template <class S>
+__device__ __forceinline__ void ltl_solve(const float (&Lf)[S::B][S::B], const float (&dinv)[S::B],
+                                          float (&x)[S::B])
+{
+    constexpr int B = S::B;
+#pragma unroll
+    for (int k = B - 1; k >= 0; --k) {
+        x[k] *= dinv[k];
+#pragma unroll
+        for (int a = 0; a < B; ++a)
+            if (is_anc<S>(a, k))
+                x[a] -= Lf[k][a] * x[k];
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+#pragma unroll
+        for (int a = 0; a < B; ++a)
+            if (is_anc<S>(a, k))
+                x[k] -= Lf[k][a] * x[a];
+        x[k] *= dinv[k];
+    }
+}
+
+// RNEA increments at qdd (RNEA is affine in qdd): Da_i = X_i Da_lambda + S qdd_i,
+// Df_i = I_i Da_i accumulated inward. Returns xd_i = X_i Da_lambda(i) and Df_i.
+template <class I>
+__device__ __forceinline__ void delta_rnea(const Lane& ln, const Rot (&E)[I::S::B],
+                                           const LaneK (&K)[I::S::B], const float (&qdd)[I::S::B],
+                                           V (&xd)[I::S::B], V (&Df)[I::S::B])
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    V Da[B];
+    Nb nDa[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const int p = S::parent[i];
+        xd[i] = V{0.0f, 0.0f};
+        if (p >= 0)
+            xd[i] = xmv(E[i], K[i], Da[p < 0 ? 0 : p], nDa[p < 0 ? 0 : p]);
+        Da[i] = V{xd[i].a + ln.sz * qdd[i], xd[i].l};
+        nDa[i] = gather(Da[i]);
+        Df[i] = imv(K[i], mass<I>(i), Da[i], nDa[i]);
+    }
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        const int p = S::parent[i];
+        if (p >= 0)
+            Df[p < 0 ? 0 : p] = add(Df[p < 0 ? 0 : p], xtfv(E[i], K[i], Df[i], gather(Df[i])));
+    }
+}
+
+// One dRNEA column (Algorithm 1 forward, then the backward pass) with sources src_v, src_a
+// entering at body j and src_f entering j's parent. kVel = false is the sweep with dv = 0
+// (da_i = X_i da_lambda + source, df_i = I_i da_i). Returns dtau (every lane of the quad).
+template <class I, bool kVel>
+__device__ __forceinline__ void drnea_column(const Lane& ln, const float (&qd)[I::S::B],
+                                             const Rot (&E)[I::S::B], const LaneK (&K)[I::S::B],
+                                             const V (&v)[I::S::B], const V (&gam)[I::S::B],
+                                             int j, V src_v, V src_a, V src_f,
+                                             float (&dx)[I::S::B])
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    V df[B];
+    {
+        V dv[B], da[B];
+        Nb ndv[B], nda[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int p = S::parent[i];
+            const float sel = (i == j) ? 1.0f : 0.0f;
+            V xdv{0.0f, 0.0f}, xda{0.0f, 0.0f};
+            if (p >= 0) {
+                if constexpr (kVel)
+                    xdv = xmv(E[i], K[i], dv[p < 0 ? 0 : p], ndv[p < 0 ? 0 : p]);
+                xda = xmv(E[i], K[i], da[p < 0 ? 0 : p], nda[p < 0 ? 0 : p]);
+            }
+            if constexpr (kVel) {
+                dv[i] = V{xdv.a + sel * src_v.a, xdv.l + sel * src_v.l};
+                ndv[i] = gather(dv[i]);
+                const V dvxs = cross_s(ln, dv[i]);
+                da[i] = V{xda.a + dvxs.a * qd[i] + sel * src_a.a,
+                          xda.l + dvxs.l * qd[i] + sel * src_a.l};
+            } else {
+                da[i] = V{xda.a + sel * src_a.a, xda.l + sel * src_a.l};
+            }
+            nda[i] = gather(da[i]);
+            df[i] = imv(K[i], mass<I>(i), da[i], nda[i]);
+            if constexpr (kVel) {
+                // df_i = I_i da_i + dv_i x* gamma_i + v_i x* (I_i dv_i)
+                const V Idv = imv(K[i], mass<I>(i), dv[i], ndv[i]);
+                df[i] = add(add(df[i], crf(ndv[i], gather(gam[i]))), crf(gather(v[i]), gather(Idv)));
+            }
+        }
+    }
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        dx[i] = qperm<kZ>(df[i].a);
+        const int p = S::parent[i];
+        if (p >= 0) {
+            const float sel = (i == j) ? 1.0f : 0.0f;
+            const V y = xtfv(E[i], K[i], df[i], gather(df[i]));
+            df[p < 0 ? 0 : p] = V{df[p < 0 ? 0 : p].a + y.a + sel * src_f.a,
+                                  df[p < 0 ? 0 : p].l + y.l + sel * src_f.l};
+        }
+    }
+}
+
+// X_j^T (S x* f): the backward source of a q-column
+__device__ __forceinline__ V back_source(const Lane& ln, const Rot& Ej, const LaneK& Kj, V f)
+{
+    const V sxf = neg(cross_s(ln, f));   // S x* f = -(f x S) componentwise for S = e_z
+    return xtfv(Ej, Kj, sxf, gather(sxf));
+}
+
+template <class I>
+__device__ __forceinline__ void pick_joint(const Rot (&E)[I::S::B], const LaneK (&K)[I::S::B],
+                                           int j, Rot& Ej, LaneK& Kj)
+{
+    Ej = E[0];
+    Kj = K[0];
+#pragma unroll
+    for (int i = 1; i < I::S::B; ++i) {
+        Ej = pick_rot(E[i], i == j, Ej);
+        Kj.rr1 = (i == j) ? K[i].rr1 : Kj.rr1;
+        Kj.rr2 = (i == j) ? K[i].rr2 : Kj.rr2;
+    }
+}
+
+// zeros of this branch's rows in the other branches' columns
+template <class I>
+__device__ __forceinline__ void zero_fill(float* out0, float* out1, long mbase, int lane,
+                                          int lanes)
+{
+    constexpr int B = I::S::B;
+    constexpr int N = GRID_N;
+    if constexpr (N > B) {
+        for (int e = lane; e < B * N; e += lanes) {
+            const int i = e / N, c2 = e % N;
+            if (!I::contains(c2)) {
+                const long o = mbase + (long)I::body_of(i) * N + c2;
+                out0[o] = 0.0f;
+                if (out1)
+                    out1[o] = 0.0f;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ grid_fdgrad_quad
+
+template <class I>
+__device__ __forceinline__ void run_fused(const grid::Args& A, int block)
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    constexpr int Q = S::Q;                   // quads per wavefront per problem
+    constexpr int W = S::W;                   // wavefronts per problem
+    constexpr int WB = GRID_WAVES;            // wavefronts per workgroup
+    constexpr int PW = 16 / Q;                // problems per wavefront (W == 1)
+    constexpr int P = (WB / W) * PW;          // problems per workgroup
+    constexpr int N = GRID_N;
+    __shared__ float s_M[P][B][B];
+
+    const int tid = (int)threadIdx.x;
+    const int wave = tid / 64;
+    const int lane = tid % 64;
+    const int c = lane & 3;
+    const Lane ln = lane_of(c == 3 ? 0 : c);
+    const int quad = (lane / 4) % Q;
+    const int pslot = (wave / W) * PW + (lane / 4) / Q;     // problem in the workgroup
+    const int s = quad + Q * (wave % W);                    // column slot in the problem
+    const int kraw = block * P + pslot;
+    const bool valid = kraw < A.nknots;
+    const int knot = valid ? kraw : A.nknots - 1;           // tail slots recompute the last knot
+
+    // roles: M column jm = s, derivative column (u, j): u = 0 -> d/dq, u = 1 -> d/dqd
+    const int jm = s < B ? s : 0;
+    const bool owns_m = s < B;
+    const bool owns_col = s < 2 * B;
+    const int u = owns_col ? s / B : 1;
+    const int j = s % B;
+    const long vbase = (long)knot * N;
+    const long mbase = (long)knot * N * N;
+
+    float qd[B];
+    Rot E[B];
+    LaneK K[B];
+    load_bodies<I>(A, vbase, c, qd, E, K);
+
+    V v[B], gam[B], F[B], xa0[B];
+    rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
+    float x[B];                               // tau - c, then qdd
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+        x[i] = A.tau[vbase + I::body[i]] - qperm<kZ>(F[i].a);
+
+    {
+        V fm[B];
+        m_column<I>(ln, E, K, jm, fm);
+        if (owns_m && c == 2) {
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                s_M[pslot][i][jm] = fm[i].a;
+        }
+    }
+    __syncthreads();
+    float Lf[B][B], dinv[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+        for (int b = 0; b <= i; ++b)
+            if (b == i || is_anc<S>(b, i))
+                Lf[i][b] = s_M[pslot][i][b];
+    ltl_factor<S>(Lf, dinv);
+    ltl_solve<S>(Lf, dinv, x);                // qdd
+
+    V xd[B], Df[B];
+    delta_rnea<I>(ln, E, K, x, xd, Df);
+    const V xdj = pick<B>(xd, j), Dfj = pick<B>(Df, j);
+    Rot Ej;
+    LaneK Kj;
+    pick_joint<I>(E, K, j, Ej, Kj);
+    const V vj = pick<B>(v, j);
+    // sources of column (u, j):
+    //   u = q : dv += v_j x S, da += (X_j a_lambda(j)) x S, backward += X_j^T (S x* f_j)
+    //   u = qd: dv += S,       da += v_j x S
+    const V vxs = cross_s(ln, vj);
+    const V src_v = u == 0 ? vxs : V{ln.sz, 0.0f};
+    const V src_a = u == 0 ? cross_s(ln, add(pick<B>(xa0, j), xdj)) : vxs;
+    const V zeta = back_source(ln, Ej, Kj, add(pick<B>(F, j), Dfj));
+    const V src_f = u == 0 ? zeta : V{0.0f, 0.0f};
+
+    float dx[B];
+    drnea_column<I, true>(ln, qd, E, K, v, gam, j, src_v, src_a, src_f, dx);
+    ltl_solve<S>(Lf, dinv, dx);               // M^-1 dtau/du_j
+    float mc[B];                              // column jm of M^-1
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+        mc[i] = (i == jm) ? 1.0f : 0.0f;
+    ltl_solve<S>(Lf, dinv, mc);
+    if (!valid)
+        return;
+    // lane c of a quad stores the rows i with i % 4 == c
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        if ((i & 3) != c)
+            continue;
+        const int gi = I::body[i];
+        if (s == 0)
+            A.qdd[vbase + gi] = x[i];
+        if (owns_col) {
+            float* out = u == 0 ? A.dqdd_dq : A.dqdd_dqd;
+            out[mbase + (long)gi * N + I::body_of(j)] = -dx[i];
+        }
+        // entry (i, jm) with i <= jm is written to both mirrored positions by the quad
+        // owning column jm, so M^-1 comes out exactly symmetric
+        if (owns_m && i <= jm) {
+            const int gj = I::body_of(jm);
+            A.Minv[mbase + (long)gi * N + gj] = mc[i];
+            A.Minv[mbase + (long)gj * N + gi] = mc[i];
+        }
+    }
+    const int lp = lane % (4 * Q) + 64 * (wave % W);        // lane within the problem
+    zero_fill<I>(A.Minv, nullptr, mbase, lp, 4 * Q * W);
+    zero_fill<I>(A.dqdd_dq, A.dqdd_dqd, mbase, lp, 4 * Q * W);
+}
+
+// ------------------------------------------------------------------ grid_fdgrad_pipe
+
+template <int B>
+struct PipeShape {
+    static_assert(B >= 1 && B <= 32, "branches have at most 32 bodies");
+    static constexpr int pow2(int x) { return x <= 1 ? 1 : 2 * pow2((x + 1) / 2); }
+    static constexpr int CB = B <= 16 ? 1 : 2;            // role B: columns per quad
+    static constexpr int QB = B <= 16 ? pow2(B) : 16;     // role B: quads per problem
+    static constexpr int QA = 2 * B <= 16 ? 2 * QB : 16;  // role A: quads per wavefront
+    static constexpr int WA = (2 * B + 15) / 16;          // role A: wavefronts per problem
+    static constexpr int P = 16 / QB;                     // problems per workgroup
+    static constexpr int PA = WA == 1 ? 16 / QA : 1;      // role A: problems per wavefront
+    static constexpr int AW = WA == 1 ? 2 : WA;           // role A: wavefronts per workgroup
+    static_assert(WA > 1 || P == 2 * PA, "two role-A wavefronts serve the workgroup");
+    static_assert(WA == 1 || P == 1, "one problem per workgroup beyond 8 bodies");
+};
+
+template <class I>
+__device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    using PS = PipeShape<B>;
+    constexpr int P = PS::P;
+    constexpr int N = GRID_N;
+    constexpr int BWAVE = GRID_PIPE_WAVES - 1;   // the role-B wavefront; role A from 0
+    static_assert(P == S::PP, "problems per workgroup disagree with the generated shape");
+    static_assert(PS::AW < GRID_PIPE_WAVES, "workgroup too small for the shape");
+    __shared__ float s_c[P][B];               // bias forces c (role A -> B)
+    __shared__ float s_M[P][B][B];            // M columns (within role B)
+    __shared__ float s_Mi[P][B][B];           // M^-1, row-major (role B -> A)
+    __shared__ float s_D[P][B][B];            // qdd part of the q-columns, [column][row] (B -> A)
+
+    const int tid = (int)threadIdx.x;
+    const int wave = tid / 64;
+    const int lane = tid % 64;
+    const int c = lane & 3;
+    const Lane ln = lane_of(c == 3 ? 0 : c);
+
+    if (wave < PS::AW) {
+        // -------------------------------------------------------- role A
+        constexpr int QA = PS::QA;
+        const int pslot = PS::WA == 1 ? wave * PS::PA + (lane / 4) / QA : 0;
+        const int s = PS::WA == 1 ? (lane / 4) % QA : lane / 4 + 16 * wave;
+        const int kraw = block * P + pslot;
+        const bool valid = kraw < A.nknots;
+        const int knot = valid ? kraw : A.nknots - 1;
+        const bool owns_col = s < 2 * B;
+        const int u = owns_col ? s / B : 1;
+        const int j = s % B;
+        const long vbase = (long)knot * N;
+        const long mbase = (long)knot * N * N;
+
+        float qd[B];
+        Rot E[B];
+        LaneK K[B];
+        load_bodies<I>(A, vbase, c, qd, E, K);
+        V v[B], gam[B], F[B], xa0[B];
+        rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
+        if (wave == 0 && (PS::WA > 1 || (lane / 4) % QA == 0) && c == 2) {
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                s_c[pslot][i] = F[i].a;
+        }
+        __syncthreads();                      // c published
+
+        Rot Ej;
+        LaneK Kj;
+        pick_joint<I>(E, K, j, Ej, Kj);
+        const V vxs = cross_s(ln, pick<B>(v, j));
+        const V src_v = u == 0 ? vxs : V{ln.sz, 0.0f};
+        const V src_a = u == 0 ? cross_s(ln, pick<B>(xa0, j)) : vxs;
+        const V zeta = back_source(ln, Ej, Kj, pick<B>(F, j));
+        const V src_f = u == 0 ? zeta : V{0.0f, 0.0f};
+        float dx[B];
+        drnea_column<I, true>(ln, qd, E, K, v, gam, j, src_v, src_a, src_f, dx);
+        __syncthreads();                      // M^-1 and the qdd parts published
+
+        const float qpart = u == 0 ? 1.0f : 0.0f;
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            dx[i] += qpart * s_D[pslot][j][i];
+        if (!valid)
+            return;
+        // dqdd/du_j = -M^-1 dtau/du_j; lane c of the quad computes and stores rows c, c+4, ..
+        if (owns_col) {
+            float* out = u == 0 ? A.dqdd_dq : A.dqdd_dqd;
+            const int gj = I::body_of(j);
+#pragma unroll
+            for (int r = 0; r < (B + 3) / 4; ++r) {
+                const int i = c + 4 * r;
+                if (i < B) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < B; ++k)
+                        acc += s_Mi[pslot][i][k] * dx[k];
+                    out[mbase + (long)I::body_of(i) * N + gj] = -acc;
+                }
+            }
+        }
+        const int lp = PS::WA == 1 ? lane % (4 * QA) : lane + 64 * wave;
+        zero_fill<I>(A.dqdd_dq, A.dqdd_dqd, mbase, lp, PS::WA == 1 ? 4 * QA : 64 * PS::WA);
+    } else if (wave == BWAVE) {
+        // -------------------------------------------------------- role B
+        constexpr int QB = PS::QB;
+        constexpr int CB = PS::CB;
+        const int pslot = (lane / 4) / QB;
+        const int s = (lane / 4) % QB;        // columns s, s + 16: of M and q-columns
+        const int kraw = block * P + pslot;
+        const bool valid = kraw < A.nknots;
+        const int knot = valid ? kraw : A.nknots - 1;
+        int js[CB];
+        bool owns[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            owns[cb] = s + 16 * cb < B;
+            js[cb] = owns[cb] ? s + 16 * cb : 0;
+        }
+        const long vbase = (long)knot * N;
+        const long mbase = (long)knot * N * N;
+
+        float qd[B];
+        Rot E[B];
+        LaneK K[B];
+        load_bodies<I>(A, vbase, c, qd, E, K);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            V fm[B];
+            m_column<I>(ln, E, K, js[cb], fm);
+            if (owns[cb] && c == 2) {
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+                    s_M[pslot][i][js[cb]] = fm[i].a;
+            }
+        }
+        // the exchange stays inside this wavefront: order its LDS traffic only
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float Lf[B][B], dinv[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+            for (int b = 0; b <= i; ++b)
+                if (b == i || is_anc<S>(b, i))
+                    Lf[i][b] = s_M[pslot][i][b];
+        ltl_factor<S>(Lf, dinv);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int jm = js[cb];
+            float mc[B];                      // column jm of M^-1
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                mc[i] = (i == jm) ? 1.0f : 0.0f;
+            ltl_solve<S>(Lf, dinv, mc);
+            if (owns[cb]) {
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    if ((i & 3) != c)
+                        continue;
+                    s_Mi[pslot][i][jm] = mc[i];
+                    // entry (i, jm), i <= jm, to both mirrored positions: exactly symmetric
+                    if (valid && i <= jm) {
+                        const int gi = I::body[i];
+                        const int gj = I::body_of(jm);
+                        A.Minv[mbase + (long)gi * N + gj] = mc[i];
+                        A.Minv[mbase + (long)gj * N + gi] = mc[i];
+                    }
+                }
+            }
+        }
+        if (valid)
+            zero_fill<I>(A.Minv, nullptr, mbase, lane % (4 * QB), 4 * QB);
+        __syncthreads();                      // c published
+
+        float x[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            x[i] = A.tau[vbase + I::body[i]] - s_c[pslot][i];
+        ltl_solve<S>(Lf, dinv, x);            // qdd
+        if (valid && s == 0) {
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                if ((i & 3) == c)
+                    A.qdd[vbase + I::body[i]] = x[i];
+        }
+        V xd[B], Df[B];
+        delta_rnea<I>(ln, E, K, x, xd, Df);
+        V none[B];                            // velocities do not enter the dv = 0 sweep
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            none[i] = V{0.0f, 0.0f};
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int j = js[cb];
+            Rot Ej;
+            LaneK Kj;
+            pick_joint<I>(E, K, j, Ej, Kj);
+            const V src_a = cross_s(ln, pick<B>(xd, j));
+            const V src_f = back_source(ln, Ej, Kj, pick<B>(Df, j));
+            float dxc[B];
+            drnea_column<I, false>(ln, qd, E, K, none, none, j, V{0.0f, 0.0f}, src_a, src_f,
+                                   dxc);
+            if (owns[cb]) {
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+                    if ((i & 3) == c)
+                        s_D[pslot][j][i] = dxc[i];
+            }
+        }
+        __syncthreads();                      // M^-1 and the qdd parts published
+    } else {
+        // a wavefront this shape does not use still takes part in both barriers
+        __syncthreads();
+        __syncthreads();
+    }
+}
+
+}  // namespace gridq
+
+// defined by the generated epilogue: workgroup -> (branch, problem group)
+__device__ void grid_dispatch_q(const grid::Args& args, int block);
+
+// Fused kernel, quad layout: GRID_WAVES wavefronts per workgroup.
+extern "C" __global__ void __launch_bounds__(64 * GRID_WAVES) grid_fdgrad_quad(grid::Args args)
+{
+    grid_dispatch_q(args, (int)blockIdx.x);
+}
+
+__device__ void grid_dispatch_p(const grid::Args& args, int block);
+
+// Fused kernel, quad layout in two roles: GRID_PIPE_WAVES wavefronts per workgroup.
+extern "C" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) grid_fdgrad_pipe(grid::Args args)
+{
+    grid_dispatch_p(args, (int)blockIdx.x);
+}

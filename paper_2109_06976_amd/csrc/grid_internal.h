@@ -15,10 +15,20 @@ namespace grid_impl {
 constexpr int kMaxBodies = 32;      // the 2B derivative columns of a branch fit one wavefront
 constexpr int kConstStride = 24;    // floats of device constants per body
 
+// builds of the fused kernel: quad layout, lane layout at 1, 2, 4 wavefronts per SIMD,
+// quad layout in two roles, one lane per knot
+constexpr int kVariantQuad = 0;
+constexpr int kVariantLane1 = 1;
+constexpr int kVariantPipe = 4;
+constexpr int kVariantSerial = 5;
+constexpr int kNumVariants = 6;
+
 // A branch hanging off the fixed base, in local numbering (parent before child).
 struct BranchShape {
     int B = 0;                       // bodies
     int L = 0;                       // lanes per knot: power of two >= 2B
+    int Q = 0;                       // quad layout: quads per wavefront per problem
+    int W = 0;                       // quad layout: wavefronts per problem
     std::vector<int> parent;         // local parent, -1 = the fixed base
     std::vector<uint64_t> anc;       // strict ancestors (local bit masks)
 };
@@ -36,6 +46,7 @@ struct Topology {
     std::vector<int> parent;
     std::vector<BranchShape> shapes;
     std::vector<BranchInst> insts;
+    int waves = 1;                   // quad layout: wavefronts per workgroup (max W)
 };
 
 // Staged pipeline workspace per knot (floats): c [n], the factors L of every branch
@@ -64,6 +75,11 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
                             const double gravity[3], uint32_t flags);
 grid_status validate_desc(const grid_model_desc* d, std::string* err);
 int64_t workgroups_for(const Topology& t, int64_t nknots);
+int64_t workgroups_quad(const Topology& t, int64_t nknots);
+int64_t workgroups_pipe(const Topology& t, int64_t nknots);
+int64_t workgroups_serial(const Topology& t, int64_t nknots);
+int pipe_problems(int B);
+int pipe_waves(const Topology& t);
 int lanes_per_knot(const Topology& t);
 WorkspaceLayout workspace_layout(const Topology& t);
 grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err);
@@ -90,10 +106,10 @@ struct grid_model_s {
     uint32_t flags = 0;
     grid_impl::Topology topo;
     uint64_t source_hash = 0;           // of the generated source: keys tuning tables
-    hipFunction_t fused_variant[3] = {nullptr, nullptr, nullptr};   // 1, 2, 4 waves/SIMD
+    int compute_units = 256;
+    hipFunction_t fused_variant[grid_impl::kNumVariants] = {};   // see kVariantQuad
     std::vector<std::pair<int32_t, int>> tuned;   // (largest N, variant), ascending N
     hipModule_t module = nullptr;
-    hipFunction_t fused = nullptr;
     hipFunction_t stage[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 

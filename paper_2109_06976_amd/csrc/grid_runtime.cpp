@@ -127,9 +127,9 @@ grid_status hip_fail(hipError_t e, const char* what)
     } while (0)
 
 
-grid_status launch(hipFunction_t fn, grid_model m, int32_t N, float* work, const float* q,
-                   const float* qd, const float* tau, float* qdd, float* Minv, float* dq,
-                   float* dqd, hipStream_t stream)
+grid_status launch(hipFunction_t fn, unsigned blocks, unsigned threads, int32_t N, float* work,
+                   const float* q, const float* qd, const float* tau, float* qdd, float* Minv,
+                   float* dq, float* dqd, hipStream_t stream)
 {
     KernelArgs a;
     a.nknots = N;
@@ -141,9 +141,8 @@ grid_status launch(hipFunction_t fn, grid_model m, int32_t N, float* work, const
     a.Minv = Minv;
     a.dqdd_dq = dq;
     a.dqdd_dqd = dqd;
-    const unsigned blocks = (unsigned)workgroups_for(m->topo, N);
     void* params[] = {&a};   // the kernel takes one argument: the Args block
-    HIP_TRY(hipModuleLaunchKernel(fn, blocks, 1, 1, 64, 1, 1, 0, stream, params, nullptr));
+    HIP_TRY(hipModuleLaunchKernel(fn, blocks, 1, 1, threads, 1, 1, 0, stream, params, nullptr));
     return GRID_OK;
 }
 
@@ -156,15 +155,33 @@ int fused_variant_for(grid_model m, int32_t N)
     for (const auto& e : m->tuned)
         if (N <= e.first)
             return e.second;
-    return m->tuned.empty() ? 0 : m->tuned.back().second;
+    if (!m->tuned.empty())
+        return m->tuned.back().second;
+    // untuned: the two-role quad layout while its wavefronts fit one per SIMD of the device
+    // (the lowest-latency form), the lane layout beyond (fewer instructions per knot)
+    const int64_t waves = workgroups_pipe(m->topo, N) * pipe_waves(m->topo);
+    return waves <= 4 * (int64_t)m->compute_units ? kVariantPipe : kVariantLane1;
 }
 
 grid_status launch_fused_variant(grid_model m, int variant, int32_t N, const float* q,
                                  const float* qd, const float* tau, float* qdd, float* Minv,
                                  float* dq, float* dqd, hipStream_t stream)
 {
-    return launch(m->fused_variant[variant], m, N, nullptr, q, qd, tau, qdd, Minv, dq, dqd,
-                  stream);
+    if (variant < 0 || variant >= kNumVariants || !m->fused_variant[variant])
+        return fail(GRID_EUNSUPPORTED, "this build of the fused kernel does not exist for the model");
+    if (variant == kVariantQuad)
+        return launch(m->fused_variant[variant], (unsigned)workgroups_quad(m->topo, N),
+                      64u * (unsigned)m->topo.waves, N, nullptr, q, qd, tau, qdd, Minv, dq, dqd,
+                      stream);
+    if (variant == kVariantPipe)
+        return launch(m->fused_variant[variant], (unsigned)workgroups_pipe(m->topo, N),
+                      64u * (unsigned)pipe_waves(m->topo), N, nullptr, q, qd, tau, qdd, Minv, dq,
+                      dqd, stream);
+    if (variant == kVariantSerial)
+        return launch(m->fused_variant[variant], (unsigned)workgroups_serial(m->topo, N), 64u, N,
+                      nullptr, q, qd, tau, qdd, Minv, dq, dqd, stream);
+    return launch(m->fused_variant[variant], (unsigned)workgroups_for(m->topo, N), 64u, N,
+                  nullptr, q, qd, tau, qdd, Minv, dq, dqd, stream);
 }
 
 grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
@@ -282,14 +299,14 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     m->topo = std::move(topo);
     static const char* const kStages[5] = {"grid_stage_rnea", "grid_stage_minv", "grid_stage_qdd",
                                            "grid_stage_drnea", "grid_stage_fdgrad"};
-    static const char* const kVariants[3] = {"grid_fdgrad_fused", "grid_fdgrad_fused_w2",
-                                             "grid_fdgrad_fused_w4"};
+    static const char* const kVariants[kNumVariants] = {
+        "grid_fdgrad_quad", "grid_fdgrad_fused", "grid_fdgrad_fused_w2", "grid_fdgrad_fused_w4",
+        "grid_fdgrad_pipe", "grid_fdgrad_serial"};
     m->source_hash = source_hash(src);
+    m->compute_units = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     hipError_t e = hipModuleLoadData(&m->module, code.data());
-    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+    for (int k = 0; k < kNumVariants && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->fused_variant[k], m->module, kVariants[k]);
-    if (e == hipSuccess)
-        m->fused = m->fused_variant[0];
     for (int k = 0; k < 5 && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->stage[k], m->module, kStages[k]);
     if (e != hipSuccess) {
@@ -361,8 +378,9 @@ grid_status grid_fd_grad_staged(grid_model m, grid_workspace w, int32_t N, const
         return fail(GRID_EINVAL, "a data pointer is NULL");
     HIP_TRY(hipSetDevice(m->device));
     for (int k = 0; k < 5; ++k) {
-        grid_status s = launch(m->stage[k], m, N, w->d_stage, q, qd, tau, qdd, Minv, dqdd_dq,
-                               dqdd_dqd, (hipStream_t)stream);
+        grid_status s = launch(m->stage[k], (unsigned)workgroups_for(m->topo, N), 64u, N,
+                               w->d_stage, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd,
+                               (hipStream_t)stream);
         if (s != GRID_OK)
             return s;
     }

@@ -1,0 +1,412 @@
+// Fused kernel with one lane per (knot, branch) problem (gfx950): grid_fdgrad_serial.
+//
+// Every lane of a wavefront works on the same branch of the same robot for a different knot,
+// so all model constants are instruction literals, nothing crosses lanes, and no work is
+// repeated: the fewest instructions per knot of all the builds (the throughput form; its
+// latency is one lane's whole chain). Per problem, float32 (Sec. IV-B):
+//   1. X_i = (E_i, r_i), E_i = E_z(q_i) E_T,i
+//   2. RNEA(q, qd, 0): v_i, a_i, gamma_i = I_i v_i, f_i, accumulated inward; c_i = S^T f_i
+//   3. M by composite rigid bodies: I^c_i = I_i + sum over children of X^T I^c X, kept as
+//      (mass, first moment, rotational inertia about the origin); M_ii = S^T I^c_i S and
+//      M_ki = S^T (X^T ... X^T I^c_i S) for the ancestors k of i
+//   4. M = L^T L along ancestor paths, M^-1 by B solves, qdd = M^-1 (tau - c)
+//   5. RNEA at qdd as the increment over step 2 (Da_i, Df_i)
+//   6. for each joint j the columns d/dq_j and d/dqd_j together: Algorithm 1 forward over
+//      the subtree of j, the backward pass over the subtree and the ancestors of j, and
+//      dqdd/du_j = -M^-1 dtau/du_j by the two triangular solves
+//
+// Transform of a rigid-body inertia (m, h, Ibar) of frame i into its parent frame, X = (E, r):
+//   m' = m, h' = E^T h + m r,
+//   Ibar' = E^T Ibar E + 2 (r . h~) 1 - r h~^T - h~ r^T + m (|r|^2 1 - r r^T),  h~ = E^T h
+// (from X^T I X written out with a x b x = b a^T - (a . b) 1).
+
+namespace grids {
+
+using grid::crf_mv;
+using grid::cross_S;
+using grid::inertia_mv;
+using grid::kConstStride;
+using grid::x_mv;
+using grid::xt_fv;
+
+template <class S>
+__device__ __forceinline__ bool in_subtree(int i, int j)   // i == j or j a strict ancestor of i
+{
+    return i == j || ((S::anc[i] >> j) & 1ull);
+}
+
+struct RB {         // rigid-body inertia about the frame origin
+    float m, h[3], I[6];   // I: xx yy zz xy xz yz
+};
+
+__device__ __forceinline__ RB rb_to_parent(const float* E, const float* r, const RB& c)
+{
+    const float Ib[3][3] = {{c.I[0], c.I[3], c.I[4]}, {c.I[3], c.I[1], c.I[5]},
+                            {c.I[4], c.I[5], c.I[2]}};
+    float T[3][3];    // Ibar E
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            T[a][b] = Ib[a][0] * E[b] + Ib[a][1] * E[3 + b] + Ib[a][2] * E[6 + b];
+    float ht[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        ht[a] = E[a] * c.h[0] + E[3 + a] * c.h[1] + E[6 + a] * c.h[2];
+    const float rh = r[0] * ht[0] + r[1] * ht[1] + r[2] * ht[2];
+    const float rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    RB o;
+    o.m = c.m;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        o.h[a] = ht[a] + c.m * r[a];
+    const int ia[6] = {0, 1, 2, 0, 0, 1};
+    const int ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const int a = ia[e], b = ib[e];
+        const float etib = E[a] * T[0][b] + E[3 + a] * T[1][b] + E[6 + a] * T[2][b];
+        const float diag = (a == b) ? 2.0f * rh + c.m * rr : 0.0f;
+        o.I[e] = etib + diag - r[a] * ht[b] - ht[a] * r[b] - c.m * r[a] * r[b];
+    }
+    return o;
+}
+
+__device__ __forceinline__ void rb_add(RB& x, const RB& y)
+{
+    x.m += y.m;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        x.h[a] += y.h[a];
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+        x.I[e] += y.I[e];
+}
+
+template <int B>
+__device__ __forceinline__ void pick6(const float (&arr)[B][6], int j, float (&out)[6])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        out[k] = arr[0][k];
+#pragma unroll
+    for (int i = 1; i < B; ++i)
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            out[k] = (i == j) ? arr[i][k] : out[k];
+}
+
+template <class I>
+__device__ __forceinline__ void run_serial(const grid::Args& A, int block)
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    constexpr int N = GRID_N;
+    const int lane = (int)threadIdx.x;
+    const int kraw = block * 64 + lane;
+    const bool valid = kraw < A.nknots;
+    const int knot = valid ? kraw : A.nknots - 1;   // tail lanes recompute the last knot
+    const float* C = I::consts();                   // literals: folded into the code
+    const long vbase = (long)knot * N;
+    const long mbase = (long)knot * N * N;
+
+    // ------------------------------------------------------------ 1. transforms
+    float qd[B], E[B][9];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const long o = vbase + I::body[i];
+        const float* c = C + i * kConstStride;
+        const float rev = __builtin_amdgcn_fractf(A.q[o] * 0.159154943091895336f);
+        const float s = __builtin_amdgcn_sinf(rev);
+        const float co = __builtin_amdgcn_cosf(rev);
+        qd[i] = A.qd[o];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            E[i][k] = co * c[k] + s * c[3 + k];
+            E[i][3 + k] = co * c[3 + k] - s * c[k];
+            E[i][6 + k] = c[6 + k];
+        }
+    }
+    const float a0[6] = {0.0f, 0.0f, 0.0f, grid_a0[0], grid_a0[1], grid_a0[2]};   // -g
+    const float zero6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+
+    // ------------------------------------------------------------ 2. RNEA(q, qd, 0)
+    float v[B][6], gam[B][6], F[B][6], xa[B][6];   // xa_i = X_i a_lambda(i)
+    {
+        float a[B][6];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int p = S::parent[i];
+            const float* c = C + i * kConstStride;
+            x_mv(E[i], c + 9, p < 0 ? zero6 : v[p < 0 ? 0 : p], v[i]);
+            x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa[i]);
+            v[i][2] += qd[i];
+            float vxs[6], Ia[6], w[6];
+            cross_S(v[i], vxs);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                a[i][k] = xa[i][k] + vxs[k] * qd[i];
+            inertia_mv(c, v[i], gam[i]);
+            inertia_mv(c, a[i], Ia);
+            crf_mv(v[i], gam[i], w);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                F[i][k] = Ia[k] + w[k];
+        }
+#pragma unroll
+        for (int i = B - 1; i >= 0; --i) {
+            const int p = S::parent[i];
+            if (p >= 0) {
+                float y[6];
+                xt_fv(E[i], C + i * kConstStride + 9, F[i], y);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    F[p][k] += y[k];
+            }
+        }
+    }
+
+    // ------------------------------------------------------------ 3. M by composite bodies
+    float Lf[B][B], dinv[B];
+    {
+        RB Ic[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const float* c = C + i * kConstStride;
+            Ic[i].m = c[21];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                Ic[i].h[k] = c[18 + k];
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                Ic[i].I[k] = c[12 + k];
+        }
+#pragma unroll
+        for (int i = B - 1; i >= 0; --i) {
+            // I^c_i S for S = e_z: [Ibar e_z; -(h x e_z)]
+            float f[6] = {Ic[i].I[4], Ic[i].I[5], Ic[i].I[2], -Ic[i].h[1], Ic[i].h[0], 0.0f};
+            Lf[i][i] = f[2];
+            // up the ancestor path (ancestors have smaller indices): f into the parent
+            // frame of k, M_{lambda(k), i} = S^T f
+#pragma unroll
+            for (int k = B - 1; k >= 0; --k) {
+                if (k <= i && (k == i || gridq::is_anc<S>(k, i)) && S::parent[k] >= 0) {
+                    float y[6];
+                    xt_fv(E[k], C + k * kConstStride + 9, f, y);
+#pragma unroll
+                    for (int e = 0; e < 6; ++e)
+                        f[e] = y[e];
+                    Lf[i][S::parent[k] < 0 ? 0 : S::parent[k]] = f[2];
+                }
+            }
+            const int p = S::parent[i];
+            if (p >= 0)
+                rb_add(Ic[p], rb_to_parent(E[i], C + i * kConstStride + 9, Ic[i]));
+        }
+    }
+    gridq::ltl_factor<S>(Lf, dinv);
+
+    // ------------------------------------------------------------ 4. M^-1 and qdd
+    if (valid) {
+#pragma unroll
+        for (int jm = 0; jm < B; ++jm) {
+            float mc[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                mc[i] = (i == jm) ? 1.0f : 0.0f;
+            gridq::ltl_solve<S>(Lf, dinv, mc);
+            // entries (i, jm), i <= jm, written to both mirrored positions: exactly symmetric
+#pragma unroll
+            for (int i = 0; i <= jm; ++i) {
+                A.Minv[mbase + (long)I::body[i] * N + I::body[jm]] = mc[i];
+                A.Minv[mbase + (long)I::body[jm] * N + I::body[i]] = mc[i];
+            }
+        }
+    }
+    float x[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+        x[i] = A.tau[vbase + I::body[i]] - F[i][2];
+    gridq::ltl_solve<S>(Lf, dinv, x);
+    if (valid) {
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            A.qdd[vbase + I::body[i]] = x[i];
+    }
+
+    // ------------------------------------------------------------ 5. RNEA at qdd
+    {
+        float Da[B][6], Df[B][6];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int p = S::parent[i];
+            const float* c = C + i * kConstStride;
+            if (p >= 0) {
+                x_mv(E[i], c + 9, Da[p < 0 ? 0 : p], Da[i]);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    xa[i][k] += Da[i][k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    Da[i][k] = 0.0f;
+            }
+            Da[i][2] += x[i];
+            inertia_mv(c, Da[i], Df[i]);
+        }
+#pragma unroll
+        for (int i = B - 1; i >= 0; --i) {
+            const int p = S::parent[i];
+            if (p >= 0) {
+                float y[6];
+                xt_fv(E[i], C + i * kConstStride + 9, Df[i], y);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    Df[p][k] += y[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                F[i][k] += Df[i][k];
+        }
+    }
+
+    // ------------------------------------------------------------ 6. dRNEA and dFD columns
+#pragma unroll 1
+    for (int j = 0; j < B; ++j) {
+        // sources of joint j: u = q: dv += v_j x S, da += (X_j a_lambda(j)) x S,
+        // backward += X_j^T (S x* f_j); u = qd: dv += S, da += v_j x S
+        float vj[6], xaj[6], Fj[6], Ej[9], rj[3];
+        pick6<B>(v, j, vj);
+        pick6<B>(xa, j, xaj);
+        pick6<B>(F, j, Fj);
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            Ej[k] = E[0][k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            rj[k] = C[9 + k];
+#pragma unroll
+        for (int i = 1; i < B; ++i) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                Ej[k] = (i == j) ? E[i][k] : Ej[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                rj[k] = (i == j) ? C[i * kConstStride + 9 + k] : rj[k];
+        }
+        float vxs[6], axs[6], srcf[6];
+        cross_S(vj, vxs);
+        cross_S(xaj, axs);
+        {
+            const float sf[6] = {-Fj[1], Fj[0], 0.0f, -Fj[4], Fj[3], 0.0f};   // S x* f_j
+            xt_fv(Ej, rj, sf, srcf);
+        }
+        // columns d/dq_j (index 0) and d/dqd_j (index 1), side by side
+        float df[2][B][6];
+        {
+            float dv[2][B][6], da[2][B][6];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const int p = S::parent[i];
+                const float* c = C + i * kConstStride;
+                if (in_subtree<S>(i, j)) {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        float xdv[6], xda[6];
+                        if (i == j || p < 0) {
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) {
+                                xdv[k] = 0.0f;
+                                xda[k] = 0.0f;
+                            }
+                        } else {
+                            x_mv(E[i], c + 9, dv[u][p < 0 ? 0 : p], xdv);
+                            x_mv(E[i], c + 9, da[u][p < 0 ? 0 : p], xda);
+                        }
+                        if (i == j) {
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) {
+                                xdv[k] = u == 0 ? vxs[k] : (k == 2 ? 1.0f : 0.0f);
+                                xda[k] = u == 0 ? axs[k] : vxs[k];
+                            }
+                        }
+                        float dvxs[6];
+                        cross_S(xdv, dvxs);
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) {
+                            dv[u][i][k] = xdv[k];
+                            da[u][i][k] = xda[k] + dvxs[k] * qd[i];
+                        }
+                        // df_i = I_i da_i + dv_i x* gamma_i + v_i x* (I_i dv_i)
+                        float t1[6], t2[6], t3[6], Idv[6];
+                        inertia_mv(c, da[u][i], t1);
+                        crf_mv(dv[u][i], gam[i], t2);
+                        inertia_mv(c, dv[u][i], Idv);
+                        crf_mv(v[i], Idv, t3);
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            df[u][i][k] = t1[k] + t2[k] + t3[k];
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            df[u][i][k] = 0.0f;
+                }
+            }
+        }
+        float dx[2][B];
+#pragma unroll
+        for (int i = B - 1; i >= 0; --i) {
+            const int p = S::parent[i];
+            const bool live = in_subtree<S>(i, j) || ((S::anc[j < 0 ? 0 : j] >> i) & 1ull);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                dx[u][i] = df[u][i][2];
+            if (p >= 0 && live) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    float y[6];
+                    xt_fv(E[i], C + i * kConstStride + 9, df[u][i], y);
+                    const float sel = (u == 0 && i == j) ? 1.0f : 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        df[u][p < 0 ? 0 : p][k] += y[k] + sel * srcf[k];
+                }
+            }
+        }
+        gridq::ltl_solve<S>(Lf, dinv, dx[0]);
+        gridq::ltl_solve<S>(Lf, dinv, dx[1]);
+        if (valid) {
+            const int gj = I::body_of(j);
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                A.dqdd_dq[mbase + (long)I::body[i] * N + gj] = -dx[0][i];
+                A.dqdd_dqd[mbase + (long)I::body[i] * N + gj] = -dx[1][i];
+            }
+        }
+    }
+    if (valid && N > B) {
+        // this branch's rows hold zeros in the other branches' columns
+        for (int e = 0; e < B * N; ++e) {
+            const int i = e / N, c2 = e % N;
+            if (!I::contains(c2)) {
+                const long o = mbase + (long)I::body_of(i) * N + c2;
+                A.Minv[o] = 0.0f;
+                A.dqdd_dq[o] = 0.0f;
+                A.dqdd_dqd[o] = 0.0f;
+            }
+        }
+    }
+}
+
+}  // namespace grids
+
+// defined by the generated epilogue: workgroup -> (branch, 64 knots)
+__device__ void grid_dispatch_s(const grid::Args& args, int block);
+
+extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_serial(grid::Args args)
+{
+    grid_dispatch_s(args, (int)blockIdx.x);
+}

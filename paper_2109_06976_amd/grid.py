@@ -102,6 +102,9 @@ _SIGS = {
     "grid_graph_destroy": (C.c_int32, [C.c_void_p]),
     "grid_tune": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_char_p,
                               C.POINTER(C.c_int32)]),
+    "grid_tune_apply": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.c_int32]),
+    "grid_build_for": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "grid_server_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(ServerConfig),
                                        C.POINTER(C.c_void_p)]),
     "grid_server_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 7 +
@@ -334,6 +337,27 @@ def tune(model, Ns, table_path=None):
     _check(lib().grid_tune(model.handle, Ns.ctypes.data_as(_i32p), len(Ns), path,
                            chosen.ctypes.data_as(_i32p)))
     return dict(zip(Ns.tolist(), chosen.tolist()))
+
+
+def tune_apply(model, table):
+    """grid_tune_apply: {largest N: build} (ascending N); {} returns to the untuned choice."""
+    items = sorted(table.items())
+    Ns = np.ascontiguousarray([n for n, _ in items], dtype=np.int32)
+    builds = np.ascontiguousarray([b for _, b in items], dtype=np.int32)
+    _check(lib().grid_tune_apply(model.handle, Ns.ctypes.data_as(_i32p),
+                                 builds.ctypes.data_as(_i32p), len(items)))
+
+
+BUILD_QUAD, BUILD_LANE, BUILD_LANE_W2, BUILD_LANE_W4, BUILD_PIPE, BUILD_SERIAL = range(6)
+BUILD_KERNELS = ("grid_fdgrad_quad", "grid_fdgrad_fused", "grid_fdgrad_fused_w2",
+                 "grid_fdgrad_fused_w4", "grid_fdgrad_pipe", "grid_fdgrad_serial")
+
+
+def build_for(model, N):
+    """grid_build_for: the build index a batch of N knots runs."""
+    b = C.c_int32(0)
+    _check(lib().grid_build_for(model.handle, int(N), C.byref(b)))
+    return b.value
 
 
 class Server:

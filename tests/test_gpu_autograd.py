@@ -83,7 +83,10 @@ def test_staged_pipeline_matches_fused_and_oracle(orc, name, N, seed):
         a, b = a.cpu().numpy(), b.cpu().numpy()
         assert np.all(np.isfinite(b)), key
         assert normwise(b, ref[key]).max() <= tol[key], key
-        assert normwise(b, a.astype(np.float64)).max() <= 1e-5, key
+        # the default fused build computes in another order (two roles, M by columns and
+        # M^-1 by a product): the two agree to the oracle tolerance, not bitwise
+        assert normwise(a, ref[key]).max() <= tol[key], key
+        assert normwise(b, a.astype(np.float64)).max() <= tol[key], key
     ws.close()
     model.close()
 

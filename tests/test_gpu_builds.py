@@ -1,0 +1,81 @@
+"""Every build of the fused kernel against the FP64 oracle, through the C ABI, on an MI355X.
+
+Builds (grid_tune_apply pins one): 0 quad layout, 1-3 lane layout at 1, 2, 4 wavefronts per
+SIMD, 4 quad layout in two roles, 5 one lane per knot. Knot counts 1 and 37 leave ragged workgroups for every
+packing; the tolerances are those of the parity tests (normwise per knot: qdd 1e-4, the
+matrices 1e-3), and M^-1 must come out exactly symmetric.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2109_06976_amd import grid, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"qdd": 1e-4, "Minv": 1e-3, "dqdd_dq": 1e-3, "dqdd_dqd": 1e-3}
+
+ROBOTS = {
+    "chain7": synth.chain7,
+    "quad12": synth.quad12,
+    "humanoid30": synth.humanoid30,
+    "chain1": lambda: synth.random_model(synth.chain_parent(1), 40, "chain1"),
+    "chain2": lambda: synth.random_model(synth.chain_parent(2), 41, "chain2"),
+    "tree3": lambda: synth.random_model(np.array([-1, 0, 0], np.int32), 43, "tree3"),
+    "fork3": lambda: synth.random_model(np.array([-1, -1, 1], np.int32), 44, "fork3"),
+    "binary7": lambda: synth.random_model(np.array([-1, 0, 0, 1, 1, 2, 2], np.int32), 45,
+                                          "binary7"),
+}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name", list(ROBOTS))
+def test_every_build_matches_oracle(orc, name):
+    import torch
+    robot = ROBOTS[name]()
+    m = grid.Model(robot)
+    try:
+        for build in range(6):
+            grid.tune_apply(m, {1 << 22: build})
+            assert grid.build_for(m, 5) == build
+            for N in (1, 37, 130):
+                say(f"[gpu] {name}: build {build}, N={N}")
+                kn = synth.random_knots(robot.n, N, 300 + N)
+                out = grid.fd_grad_torch(m, *(torch.from_numpy(a).cuda()
+                                              for a in (kn.q, kn.qd, kn.tau)))
+                torch.cuda.synchronize()
+                ref = orc.fd_grad_batch(robot, kn.q, kn.qd, kn.tau)
+                errs = {}
+                for k, b in TOL.items():
+                    y = out[k].cpu().numpy().astype(np.float64).reshape(N, -1)
+                    r = ref[k].reshape(N, -1)
+                    errs[k] = float((np.abs(y - r).max(1) / np.abs(r).max(1)).max())
+                say("  " + ", ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+                for k, b in TOL.items():
+                    assert errs[k] <= b, (name, build, N, k)
+                Mi = out["Minv"].cpu().numpy()
+                np.testing.assert_array_equal(Mi, np.swapaxes(Mi, 1, 2))
+    finally:
+        m.close()
+
+
+def test_tune_apply_rejects_bad_tables():
+    m = grid.Model(synth.chain7())
+    try:
+        for Ns, builds, status in (([64, 32], [0, 0], grid.GRID_EINVAL),
+                                   ([0], [0], grid.GRID_EINVAL),
+                                   ([64], [6], grid.GRID_EUNSUPPORTED),
+                                   ([64], [-1], grid.GRID_EUNSUPPORTED)):
+            n = np.array(Ns, np.int32)
+            b = np.array(builds, np.int32)
+            rc = grid.lib().grid_tune_apply(m.handle, n.ctypes.data_as(grid._i32p),
+                                            b.ctypes.data_as(grid._i32p), len(Ns))
+            assert rc == status, (Ns, builds, rc)
+        grid.tune_apply(m, {})
+    finally:
+        m.close()
