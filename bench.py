@@ -48,15 +48,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
-    taken on the current kernel source for this workload."""
+    taken on the current kernel source, for this kernel and workload."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     entry = rec.get(workload)
-    if not entry or entry.get("kernel_source_sha") != kernel_source_hash():
+    if (not entry or entry.get("kernel_source_sha") != kernel_source_hash()
+            or entry.get("kernel") != kernel):
         return None
     return entry.get("bytes_per_launch")
 
@@ -80,6 +81,9 @@ def parse():
     ap.add_argument("--serve-sweep", default="", help="extra request rates, comma-separated")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (untuned build choice)")
+    ap.add_argument("--build", type=int, default=-1,
+                    help="pin one build of the fused kernel (skips the per-build timings and "
+                         "the autotuner; used for profiling one kernel)")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="also run a plain device copy of this size (for counter scaling)")
     return ap.parse_args()
@@ -170,16 +174,18 @@ def main():
 
     # every build of the fused kernel at this N (pinned one at a time), then the autotuner
     # over the sizes this run times; the timed steps use the tuned choice
-    builds = {}
-    for b, name in enumerate(grid.BUILD_KERNELS):
-        try:
+    builds, tuned = {}, None
+    if args.build >= 0:
+        grid.tune_apply(model, {1 << 22: args.build})
+    else:
+        for b, name in enumerate(grid.BUILD_KERNELS):
             grid.tune_apply(model, {1 << 22: b})
-        except grid.GridError:
-            continue   # not built for this robot
-        st, ks = time_steps(torch, launch, max(200, args.steps // 10), 50)
-        builds[name] = {"us_per_step": round(st * 1e6, 3), "kernel_avg_us": round(ks * 1e6, 3)}
-    grid.tune_apply(model, {})
-    tuned = None if args.no_tune else grid.tune(model, sorted(set([N] + sweep_ns)))
+            st, ks = time_steps(torch, launch, max(200, args.steps // 10), 50)
+            builds[name] = {"us_per_step": round(st * 1e6, 3),
+                            "kernel_avg_us": round(ks * 1e6, 3)}
+        grid.tune_apply(model, {})
+        if not args.no_tune:
+            tuned = grid.tune(model, sorted(set([N] + sweep_ns)))
     build = grid.build_for(model, N)
 
     sec_per_step, kernel_s = time_steps(torch, launch, args.steps, args.warmup)
@@ -195,7 +201,7 @@ def main():
     flop_launch = fl["total"] * N
     achieved_tflops = flop_launch / (avg_ms * 1e-3) / 1e12
     workload = f"{args.robot}-N{N}"
-    traffic = measured_traffic(workload)
+    traffic = measured_traffic(workload, grid.BUILD_KERNELS[build])
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 4), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
                 "traffic": traffic,

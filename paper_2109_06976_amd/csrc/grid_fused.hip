@@ -619,7 +619,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         load_bodies<I>(A, vbase, c, qd, E, K);
         V v[B], gam[B], F[B], xa0[B];
         rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
-        if (wave == 0 && (PS::WA > 1 || (lane / 4) % QA == 0) && c == 2) {
+        if (s == 0 && c == 2) {               // quad 0 of each problem publishes c
 #pragma unroll
             for (int i = 0; i < B; ++i)
                 s_c[pslot][i] = F[i].a;
