@@ -54,7 +54,10 @@ def test_every_build_matches_oracle(orc, name):
                 for k, b in TOL.items():
                     y = out[k].cpu().numpy().astype(np.float64).reshape(N, -1)
                     r = ref[k].reshape(N, -1)
-                    errs[k] = float((np.abs(y - r).max(1) / np.abs(r).max(1)).max())
+                    # normwise per knot; a knot whose reference is exactly zero (dqdd/dqd of a
+                    # single joint) is held to the same bound in absolute terms
+                    scale = np.abs(r).max(1)
+                    errs[k] = float((np.abs(y - r).max(1) / np.where(scale > 0, scale, 1.0)).max())
                 say("  " + ", ".join(f"{k}={v:.1e}" for k, v in errs.items()))
                 for k, b in TOL.items():
                     assert errs[k] <= b, (name, build, N, k)
