@@ -191,6 +191,10 @@ def main():
     sec_per_step, kernel_s = time_steps(torch, launch, args.steps, args.warmup)
     avg_ms = kernel_s * 1e3
 
+    # the floor of this measurement: a one-element fill kernel timed the same way
+    tiny = torch.zeros(1, device=dev)
+    floor_step, floor_gpu = time_steps(torch, lambda: tiny.fill_(1.0), max(200, args.steps // 5), 50)
+
     # the plain staged pipeline (five launches, intermediates in HBM) on the same batch
     ws_plain = grid.Workspace(model, N)
     plain = lambda: ws_plain.fd_grad_staged(*ins, *outs, N=N, stream=stream)
@@ -208,7 +212,8 @@ def main():
                 "kernel": grid.BUILD_KERNELS[build], "kernel_avg_us": round(avg_ms * 1e3, 3),
                 "flop_per_knot": fl["total"],
                 "hbm_bytes_per_launch": flops.io_bytes_per_knot(n) * N,
-                "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+                "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                "launch_floor_us": round(floor_gpu * 1e6, 3)}
 
     result = {
         "metric": "dFD knot-evals/sec (7-DoF chain, N=128) + p50/p99 latency served, vs plain",
