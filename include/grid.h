@@ -214,9 +214,9 @@ grid_status grid_graph_destroy(grid_graph g);
  * four lanes of a quad and gives every derivative column its own quad (few instructions per
  * lane: low latency). Builds 1, 2, 3 give every column one lane that runs the shared
  * sweeps itself (fewest instructions per knot: the highest throughput), allowed 1, 2 or 4
- * resident wavefronts per SIMD. Build 4 is build 0 split over two roles on different
- * wavefronts (one computes M, M^-1, qdd and the qdd-dependent part of dtau/dq while the
- * other computes RNEA and the rest of dtau/du), the shortest dependency chain. Build 5
+ * resident wavefronts per SIMD. Build 4 is build 0 split over three roles on different
+ * wavefronts of a workgroup (RNEA and dtau/du at qdd = 0; M, qdd and the qdd-dependent part
+ * of dtau/dq; M^-1), the shortest dependency chain. Build 5
  * gives each (knot, branch) problem
  * one lane (no repeated work: the fewest instructions per knot, the longest latency).
  * Untuned, a batch runs build 4 while its wavefronts fit one per SIMD of the device and

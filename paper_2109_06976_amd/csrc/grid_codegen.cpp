@@ -111,9 +111,10 @@ int64_t workgroups_for(const Topology& t, int64_t nknots)
     return total;
 }
 
-// two-role quad kernel: role B takes the B columns of M in QB quads (the power of two >= B,
-// at most 16, two columns per quad beyond), so a workgroup holds 16 / QB problems; role A
-// takes the 2B derivative columns in two wavefronts (B <= 16) or ceil(2B / 16)
+// three-role quad kernel: roles B and C take the B columns of M and of M^-1 in QB quads (the
+// power of two >= B, at most 16, two columns per quad beyond), so a workgroup holds 16 / QB
+// problems; role A takes the 2B derivative columns in two wavefronts (B <= 16) or
+// ceil(2B / 16)
 int pipe_problems(int B)
 {
     int qb = 1;
@@ -125,8 +126,10 @@ int pipe_problems(int B)
 int pipe_waves(const Topology& t)
 {
     int w = 3;
-    for (const BranchShape& s : t.shapes)
-        w = std::max(w, (2 * s.B + 15) / 16 + 1);
+    for (const BranchShape& s : t.shapes) {
+        const int wa = std::max(2, (2 * s.B + 15) / 16);   // role A
+        w = std::max(w, wa + 1 + (s.B <= 16 ? 1 : 0));      // role B, role C up to 16 bodies
+    }
     return w;
 }
 
@@ -206,59 +209,6 @@ static void emit_floats(std::ostringstream& os, const float* v, size_t k)
     os << "}";
 }
 
-// Per (body, lane c) of the quad layout, 24 floats (c = 3 repeats c = 0; indices mod 3):
-//   [0..4] cos(q), [5..9] sin(q), [10..14] constant coefficients of the entries
-//          E_cc, E_c,c+1, E_c,c+2, E_c+1,c, E_c+2,c of E = E_z(q) E_T, where
-//          row 0 = cos E_T,0 + sin E_T,1, row 1 = cos E_T,1 - sin E_T,0, row 2 = E_T,2
-//   [15] r_c+1  [16] r_c+2  [17] Ibar_cc  [18] Ibar_c,c+1  [19] Ibar_c,c+2
-//   [20] h_c+1  [21] h_c+2  [22..23] zero
-static std::vector<float> quad_constants(const float* c, int B)
-{
-    std::vector<float> out((size_t)B * 4 * 24, 0.0f);
-    for (int i = 0; i < B; ++i) {
-        const float* b = c + (size_t)i * kConstStride;
-        const float* ET = b;          // row-major
-        const float* r = b + 9;
-        const float* Ib = b + 12;     // xx yy zz xy xz yz
-        const float* h = b + 18;
-        auto ibar = [&](int x, int y) -> float {
-            if (x == y)
-                return Ib[x];
-            const int lo = std::min(x, y), hi = std::max(x, y);
-            return lo == 0 ? (hi == 1 ? Ib[3] : Ib[4]) : Ib[5];
-        };
-        for (int lane = 0; lane < 4; ++lane) {
-            const int c0 = lane == 3 ? 0 : lane, c1 = (c0 + 1) % 3, c2 = (c0 + 2) % 3;
-            float* o = out.data() + ((size_t)i * 4 + lane) * 24;
-            const int ent[5][2] = {{c0, c0}, {c0, c1}, {c0, c2}, {c1, c0}, {c2, c0}};
-            for (int e = 0; e < 5; ++e) {
-                const int row = ent[e][0], col = ent[e][1];
-                float kc = 0.0f, ks = 0.0f, k0 = 0.0f;
-                if (row == 0) {
-                    kc = ET[col];
-                    ks = ET[3 + col];
-                } else if (row == 1) {
-                    kc = ET[3 + col];
-                    ks = -ET[col];
-                } else {
-                    k0 = ET[6 + col];
-                }
-                o[e] = kc;
-                o[5 + e] = ks;
-                o[10 + e] = k0;
-            }
-            o[15] = r[c1];
-            o[16] = r[c2];
-            o[17] = ibar(c0, c0);
-            o[18] = ibar(c0, c1);
-            o[19] = ibar(c0, c2);
-            o[20] = h[c1];
-            o[21] = h[c2];
-        }
-    }
-    return out;
-}
-
 std::string generate_source(const Topology& t, const std::vector<float>& consts,
                             const double gravity[3], uint32_t flags)
 {
@@ -298,13 +248,6 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
            << "] = ";
         emit_floats(os, consts.data() + in.coff, in.body.size() * kConstStride);
         os << ";\n";
-        // quad layout: per (body, lane c of a quad) the coefficients of the lane's entries
-        // of E = E_z(q) E_T and its translation, inertia and first-moment components
-        const std::vector<float> qc = quad_constants(consts.data() + in.coff, (int)in.body.size());
-        os << "__device__ constexpr float grid_qconst_" << k << "[" << qc.size()
-           << "] __attribute__((aligned(16))) = ";
-        emit_floats(os, qc.data(), qc.size());
-        os << ";\n";
         os << "template <> struct Inst<" << k << "> {\n";
         os << "    using S = Shape<" << in.shape << ">;\n";
         os << "    static constexpr int body[S::B] = ";
@@ -318,7 +261,6 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
               "        return r;\n    }\n";
         os << "    __device__ static bool contains(int g) { return (mask >> g) & 1ull; }\n";
         os << "    __device__ static const float* consts() { return grid_const_" << k << "; }\n";
-        os << "    __device__ static const float* qconsts() { return grid_qconst_" << k << "; }\n";
         os << "};\n";
     }
     os << "#line 1 \"grid_device.hip\"\n";

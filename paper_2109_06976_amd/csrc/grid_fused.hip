@@ -6,9 +6,8 @@
 // through DPP quad permutations, so a transform, an inertia product or a cross product
 // costs a few DPP moves and about three FMAs per lane instead of a whole 6-vector per lane.
 // A quad owns one derivative column (u, j) of a (knot, branch) problem, and all quads of a
-// problem run the shared sweeps in lockstep. Per-lane constants (the coefficients of the
-// lane's row and column of the joint rotation, translation and inertia entries) come from a
-// generated per-(body, lane) table; masses are literals.
+// problem run the shared sweeps in lockstep. Every model constant is an instruction literal;
+// a lane picks its components with a one-hot of c and takes its neighbours' by DPP.
 //
 // Steps per (knot, branch), float32 (Sec. IV-B): transforms; RNEA(q, qd, 0); column s of M
 // as ID(q, 0, e_s) without gravity; M = L^T L along ancestor paths; qdd; RNEA at qdd as the
@@ -18,29 +17,26 @@
 // grid_fdgrad_quad runs all steps in every quad. A problem with 2B columns uses Q quads
 // (power of two >= 2B, at most 16) in each of W wavefronts (W * Q >= 2B).
 //
-// grid_fdgrad_pipe splits the steps over two roles that run at the same time on different
+// grid_fdgrad_pipe splits the steps over three roles that run at the same time on different
 // wavefronts of a workgroup, shortening the dependency chain:
-//   role A (2B columns, one per quad, 1..4 wavefronts): RNEA(q, qd, 0); the dRNEA columns
+//   role A (2B columns, one per quad, 2..4 wavefronts): RNEA(q, qd, 0); the dRNEA columns
 //                        with the sources taken at qdd = 0
-//   role B (B columns, one or two per quad, one wavefront): M, its factor and M^-1; qdd
-//                        once role A has published the bias forces; RNEA increments at
-//                        qdd; the part of each q-column that depends on qdd
+//   role B (B columns, one or two per quad, one wavefront): M and its factor; qdd once
+//                        role A has published the bias forces; RNEA increments at qdd; the
+//                        part of each q-column that depends on qdd
+//   role C (B columns, one wavefront; branches of up to 16 bodies, beyond which role B
+//                        does this itself): once role B has published M, its factor and M^-1
 // dtau/dqd does not depend on qdd, and dtau/dq is affine in the two source terms that do:
 // the parent acceleration (X_j a_lambda(j)) x S enters the forward sweep and the term
 // X_j^T (S x* f_j) the backward sweep, each linearly, so the qdd part of a q-column is the
 // same sweep with the increments X_j Da_lambda(j) and Df_j as sources and dv = 0
 // (da_i = X_i da_lambda + source, df_i = I_i da_i). Role A adds role B's parts and
-// multiplies by M^-1, both read from LDS.
+// multiplies by role C's M^-1, both read from LDS. Two workgroup barriers: after RNEA and
+// the columns of M, and before the final products.
 
 namespace gridq {
 
 using grid::kConstStride;
-
-constexpr int kQConst = 24;   // per (body, component) lane constants, see the table below
-// [0..4] coefficient of cos(q), [5..9] of sin(q), [10..14] constant, for the entries
-//        (E_cc, E_c,c+1, E_c,c+2, E_c+1,c, E_c+2,c) of E = E_z(q) E_T
-// [15] r_{c+1}  [16] r_{c+2}  [17] Ibar_cc  [18] Ibar_c,c+1  [19] Ibar_c,c+2
-// [20] h_{c+1}  [21] h_{c+2}  [22..23] unused       (indices c+1, c+2 taken mod 3)
 
 // quad permutations: lane (0,1,2,3) reads lane (..); lane 3 shadows component 0
 constexpr int kNb1 = 1 | (2 << 2) | (0 << 4) | (1 << 6);   // component c+1
@@ -76,16 +72,24 @@ struct LaneK {      // per-lane body constants
     float rr1, rr2, I0, I1, I2, h1, h2;
 };
 
-struct Lane {       // per-lane selectors of the joint axis S = e_z
+struct Lane {       // per-lane selectors
     float sxs;      // (x x S)_c = sxs * x_{c+1 or c-1}: +1 for c = 0, -1 for c = 1, 0 for c = 2
     float sz;       // S_c: 1 for c = 2
     float g;        // component c of -g, the base acceleration that carries gravity
+    float oh0, oh1, oh2;   // one-hot of the lane's component c
 };
 
 __device__ __forceinline__ Lane lane_of(int c3)
 {
     return Lane{c3 == 0 ? 1.0f : (c3 == 1 ? -1.0f : 0.0f), c3 == 2 ? 1.0f : 0.0f,
-                c3 == 0 ? grid_a0[0] : (c3 == 1 ? grid_a0[1] : grid_a0[2])};
+                c3 == 0 ? grid_a0[0] : (c3 == 1 ? grid_a0[1] : grid_a0[2]),
+                c3 == 0 ? 1.0f : 0.0f, c3 == 1 ? 1.0f : 0.0f, c3 == 2 ? 1.0f : 0.0f};
+}
+
+// component c of a 3-vector given as three literals (products with the one-hot are exact)
+__device__ __forceinline__ float comp(const Lane& ln, float x0, float x1, float x2)
+{
+    return ln.oh0 * x0 + ln.oh1 * x1 + ln.oh2 * x2;
 }
 
 // X m = [E w; E (v - r x w)]
@@ -172,29 +176,48 @@ __device__ __forceinline__ float mass(int i)
 
 // ------------------------------------------------------------------ building blocks
 
-// transforms of the lane's component: E_i from the hardware sin and cos (angle in
-// revolutions, reduced to [0, 1)), and the body constants
+// The lane's share of every body: E_i = E_z(q_i) E_T,i from the hardware sin and cos (angle
+// in revolutions, reduced to [0, 1)), and the body constants, all from the model's literals
+// (no table: per-lane loads of constants would all pass through the CU's texture data path).
+// Row c of E is alpha E_T,0 + beta E_T,1 + gamma E_T,2 with (alpha, beta, gamma) = (cos, sin, 0),
+// (-sin, cos, 0), (0, 0, 1) for c = 0, 1, 2 (rows of E_z). The lane keeps its row in the order
+// (E_cc, E_c,c+1, E_c,c+2); the column entries E_c+1,c and E_c+2,c are the neighbours' third
+// and second row entries. Likewise r_c, h_c, Ibar_cc, Ibar_c,c+1 are picked by the one-hot and
+// the other components come from the neighbours (Ibar_c,c+2 = Ibar_c+2,c).
 template <class I>
-__device__ __forceinline__ void load_bodies(const grid::Args& A, long vbase, int c,
+__device__ __forceinline__ void load_bodies(const grid::Args& A, long vbase, const Lane& ln,
                                             float (&qd)[I::S::B], Rot (&E)[I::S::B],
                                             LaneK (&K)[I::S::B])
 {
 #pragma unroll
     for (int i = 0; i < I::S::B; ++i) {
+        const float* k = I::consts() + i * kConstStride;   // E_T, r, Ibar, h, m
+        const float r_c = comp(ln, k[9], k[10], k[11]);
+        const float h_c = comp(ln, k[18], k[19], k[20]);
+        const float i_cc = comp(ln, k[12], k[13], k[14]);   // xx, yy, zz
+        const float i_c1 = comp(ln, k[15], k[17], k[16]);   // xy, yz, zx
+        K[i] = LaneK{qperm<kNb1>(r_c), qperm<kNb2>(r_c), i_cc, i_c1, qperm<kNb2>(i_c1),
+                     qperm<kNb1>(h_c), qperm<kNb2>(h_c)};
+    }
+#pragma unroll
+    for (int i = 0; i < I::S::B; ++i) {
         const long o = vbase + I::body[i];
+        const float* k = I::consts() + i * kConstStride;
         const float rev = __builtin_amdgcn_fractf(A.q[o] * 0.159154943091895336f);
         const float sn = __builtin_amdgcn_sinf(rev);
         const float co = __builtin_amdgcn_cosf(rev);
         qd[i] = A.qd[o];
-        const float4* t = reinterpret_cast<const float4*>(I::qconsts() + (i * 4 + c) * kQConst);
-        const float4 t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3], t4 = t[4], t5 = t[5];
-        // t0 .. t3.y: cos coefficients [0..4], sin coefficients [5..9], constants [10..14]
-        E[i].e0 = t0.x * co + t1.y * sn + t2.z;
-        E[i].e1 = t0.y * co + t1.z * sn + t2.w;
-        E[i].e2 = t0.z * co + t1.w * sn + t3.x;
-        E[i].f1 = t0.w * co + t2.x * sn + t3.y;
-        E[i].f2 = t1.x * co + t2.y * sn + t3.z;
-        K[i] = LaneK{t3.w, t4.x, t4.y, t4.z, t4.w, t5.x, t5.y};
+        const float al = ln.oh0 * co - ln.oh1 * sn;
+        const float be = ln.oh0 * sn + ln.oh1 * co;
+        float R[3];                                      // row c of E, columns 0, 1, 2
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            R[j] = al * k[j] + be * k[3 + j] + ln.oh2 * k[6 + j];
+        E[i].e0 = comp(ln, R[0], R[1], R[2]);
+        E[i].e1 = comp(ln, R[1], R[2], R[0]);
+        E[i].e2 = comp(ln, R[2], R[0], R[1]);
+        E[i].f1 = qperm<kNb1>(E[i].e2);
+        E[i].f2 = qperm<kNb2>(E[i].e1);
     }
 }
 
@@ -480,7 +503,7 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
     float qd[B];
     Rot E[B];
     LaneK K[B];
-    load_bodies<I>(A, vbase, c, qd, E, K);
+    load_bodies<I>(A, vbase, ln, qd, E, K);
 
     V v[B], gam[B], F[B], xa0[B];
     rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
@@ -562,6 +585,47 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
 
 // ------------------------------------------------------------------ grid_fdgrad_pipe
 
+// columns s and s + 16 (those below B) of M^-1 from the factor: to LDS (for the final
+// products) and to the output, entries (i, jm), i <= jm, in both mirrored positions so that
+// M^-1 comes out exactly symmetric; then this branch's zeros in other branches' columns
+template <class I, int CB, int P>
+__device__ __forceinline__ void minv_columns(const grid::Args& A,
+                                             const float (&Lf)[I::S::B][I::S::B],
+                                             const float (&dinv)[I::S::B], int pslot, int s, int c,
+                                             bool valid, long mbase, int lp, int lanes,
+                                             float (&s_Mi)[P][I::S::B][I::S::B])
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    constexpr int N = GRID_N;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const bool owns = s + 16 * cb < B;
+        const int jm = owns ? s + 16 * cb : 0;
+        float mc[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            mc[i] = (i == jm) ? 1.0f : 0.0f;
+        ltl_solve<S>(Lf, dinv, mc);
+        if (owns) {
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                if ((i & 3) != c)
+                    continue;
+                s_Mi[pslot][i][jm] = mc[i];
+                if (valid && i <= jm) {
+                    const int gi = I::body[i];
+                    const int gj = I::body_of(jm);
+                    A.Minv[mbase + (long)gi * N + gj] = mc[i];
+                    A.Minv[mbase + (long)gj * N + gi] = mc[i];
+                }
+            }
+        }
+    }
+    if (valid)
+        zero_fill<I>(A.Minv, nullptr, mbase, lp, lanes);
+}
+
 template <int B>
 struct PipeShape {
     static_assert(B >= 1 && B <= 32, "branches have at most 32 bodies");
@@ -573,6 +637,10 @@ struct PipeShape {
     static constexpr int P = 16 / QB;                     // problems per workgroup
     static constexpr int PA = WA == 1 ? 16 / QA : 1;      // role A: problems per wavefront
     static constexpr int AW = WA == 1 ? 2 : WA;           // role A: wavefronts per workgroup
+    // role C (M^-1 on its own wavefront) up to 16 bodies; beyond, role B computes M^-1 and
+    // the workgroup stays at four wavefronts (one per SIMD, the full register file each)
+    static constexpr bool HASC = B <= 16;
+    static constexpr int WAVES = AW + 1 + (HASC ? 1 : 0);
     static_assert(WA > 1 || P == 2 * PA, "two role-A wavefronts serve the workgroup");
     static_assert(WA == 1 || P == 1, "one problem per workgroup beyond 8 bodies");
 };
@@ -585,12 +653,13 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     using PS = PipeShape<B>;
     constexpr int P = PS::P;
     constexpr int N = GRID_N;
-    constexpr int BWAVE = GRID_PIPE_WAVES - 1;   // the role-B wavefront; role A from 0
+    constexpr int BWAVE = PS::AW;             // role A on wavefronts 0 .. AW-1, then B, then C
+    constexpr int CWAVE = PS::HASC ? PS::AW + 1 : -1;
     static_assert(P == S::PP, "problems per workgroup disagree with the generated shape");
-    static_assert(PS::AW < GRID_PIPE_WAVES, "workgroup too small for the shape");
+    static_assert(PS::WAVES <= GRID_PIPE_WAVES, "workgroup too small for the shape");
     __shared__ float s_c[P][B];               // bias forces c (role A -> B)
-    __shared__ float s_M[P][B][B];            // M columns (within role B)
-    __shared__ float s_Mi[P][B][B];           // M^-1, row-major (role B -> A)
+    __shared__ float s_M[P][B][B];            // M columns (role B -> B, C)
+    __shared__ float s_Mi[P][B][B];           // M^-1, row-major (role C -> A)
     __shared__ float s_D[P][B][B];            // qdd part of the q-columns, [column][row] (B -> A)
 
     const int tid = (int)threadIdx.x;
@@ -616,7 +685,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         float qd[B];
         Rot E[B];
         LaneK K[B];
-        load_bodies<I>(A, vbase, c, qd, E, K);
+        load_bodies<I>(A, vbase, ln, qd, E, K);
         V v[B], gam[B], F[B], xa0[B];
         rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
         if (s == 0 && c == 2) {               // quad 0 of each problem publishes c
@@ -684,7 +753,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         float qd[B];
         Rot E[B];
         LaneK K[B];
-        load_bodies<I>(A, vbase, c, qd, E, K);
+        load_bodies<I>(A, vbase, ln, qd, E, K);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             V fm[B];
@@ -707,32 +776,9 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 if (b == i || is_anc<S>(b, i))
                     Lf[i][b] = s_M[pslot][i][b];
         ltl_factor<S>(Lf, dinv);
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int jm = js[cb];
-            float mc[B];                      // column jm of M^-1
-#pragma unroll
-            for (int i = 0; i < B; ++i)
-                mc[i] = (i == jm) ? 1.0f : 0.0f;
-            ltl_solve<S>(Lf, dinv, mc);
-            if (owns[cb]) {
-#pragma unroll
-                for (int i = 0; i < B; ++i) {
-                    if ((i & 3) != c)
-                        continue;
-                    s_Mi[pslot][i][jm] = mc[i];
-                    // entry (i, jm), i <= jm, to both mirrored positions: exactly symmetric
-                    if (valid && i <= jm) {
-                        const int gi = I::body[i];
-                        const int gj = I::body_of(jm);
-                        A.Minv[mbase + (long)gi * N + gj] = mc[i];
-                        A.Minv[mbase + (long)gj * N + gi] = mc[i];
-                    }
-                }
-            }
-        }
-        if (valid)
-            zero_fill<I>(A.Minv, nullptr, mbase, lane % (4 * QB), 4 * QB);
+        if constexpr (!PS::HASC)
+            minv_columns<I, CB>(A, Lf, dinv, pslot, s, c, valid, mbase, lane % (4 * QB), 4 * QB,
+                                s_Mi);
         __syncthreads();                      // c published
 
         float x[B];
@@ -771,6 +817,27 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
             }
         }
         __syncthreads();                      // M^-1 and the qdd parts published
+    } else if (wave == CWAVE) {
+        // -------------------------------------------------------- role C
+        constexpr int QB = PS::QB;
+        constexpr int CB = PS::CB;
+        const int pslot = (lane / 4) / QB;
+        const int s = (lane / 4) % QB;        // columns s, s + 16 of M^-1
+        const int kraw = block * P + pslot;
+        const bool valid = kraw < A.nknots;
+        const int knot = valid ? kraw : A.nknots - 1;
+        const long mbase = (long)knot * N * N;
+        __syncthreads();                      // role B's columns of M are in LDS
+        float Lf[B][B], dinv[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+            for (int b = 0; b <= i; ++b)
+                if (b == i || is_anc<S>(b, i))
+                    Lf[i][b] = s_M[pslot][i][b];
+        ltl_factor<S>(Lf, dinv);
+        minv_columns<I, CB>(A, Lf, dinv, pslot, s, c, valid, mbase, lane % (4 * QB), 4 * QB, s_Mi);
+        __syncthreads();                      // M^-1 published
     } else {
         // a wavefront this shape does not use still takes part in both barriers
         __syncthreads();
@@ -791,7 +858,7 @@ extern "C" __global__ void __launch_bounds__(64 * GRID_WAVES) grid_fdgrad_quad(g
 
 __device__ void grid_dispatch_p(const grid::Args& args, int block);
 
-// Fused kernel, quad layout in two roles: GRID_PIPE_WAVES wavefronts per workgroup.
+// Fused kernel, quad layout in three roles: GRID_PIPE_WAVES wavefronts per workgroup.
 extern "C" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) grid_fdgrad_pipe(grid::Args args)
 {
     grid_dispatch_p(args, (int)blockIdx.x);
