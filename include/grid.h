@@ -208,6 +208,31 @@ grid_status grid_graph_update(grid_graph g, const grid_item* items, int32_t coun
 
 grid_status grid_graph_destroy(grid_graph g);
 
+/* ------------------------------------------------------------------ the other algorithms
+ *
+ * The paper's other rigid-body algorithms on the same batched layout (Sec. IV-B), one
+ * kernel launch each, per knot and per base branch; device pointers, `stream` a
+ * hipStream_t, asynchronous. Arrays: q, qd, qdd, tau [N][n]; Minv, dtau_dq, dtau_dqd
+ * [N][n][n] row-major (dtau_dq[k][i][j] = d tau_i / d q_j). Errors: EINVAL (N < 0, a
+ * required pointer NULL with N > 0, N > 2^31/64), EDEVICE (launch failure).
+ */
+
+/* Inverse dynamics tau = ID(q, qd, qdd) by RNEA with gravity (Sec. IV-B, Eq. 1). */
+grid_status grid_id(grid_model m, int32_t N, const float* q, const float* qd, const float* qdd,
+                    float* tau, void* stream);
+
+/* Forward dynamics qdd = M^-1 (tau - RNEA(q, qd, 0)) (Sec. IV-B, Eq. 1). */
+grid_status grid_fd(grid_model m, int32_t N, const float* q, const float* qd, const float* tau,
+                    float* qdd, void* stream);
+
+/* The mass-matrix inverse M(q)^-1 (Sec. IV-B), exactly symmetric. */
+grid_status grid_minv(grid_model m, int32_t N, const float* q, float* Minv, void* stream);
+
+/* The gradient of inverse dynamics at the given qdd: dtau/dq and dtau/dqd (Sec. IV-B,
+ * Algorithm 1 and its backward pass). */
+grid_status grid_id_grad(grid_model m, int32_t N, const float* q, const float* qd,
+                         const float* qdd, float* dtau_dq, float* dtau_dqd, void* stream);
+
 /* ------------------------------------------------------------------ autotuning
  *
  * The fused kernel exists in up to five builds. Build 0 spreads each spatial vector over the

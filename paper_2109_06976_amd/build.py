@@ -1,8 +1,8 @@
 """Build libgrid.so (hipcc, gfx950) in-tree and fill its kernel cache.
 
 Steps:
-  1. embed the device sources csrc/grid_device.hip, grid_fused.hip and grid_serial.hip
-     into generated includes (_build/<name>_src.inc);
+  1. embed the device sources csrc/grid_device.hip, grid_fused.hip, grid_serial.hip and
+     grid_ops.hip into generated includes (_build/<name>_src.inc);
   2. compile the host runtime (csrc/*.cpp) with hipcc into libgrid.so;
   3. compile the device source with hipcc for gfx950 behind a generated chain prelude
      (a full offline compile check; -save-temps keeps the ISA under _build/);
@@ -37,7 +37,7 @@ def _run(cmd, verbose):
 def embed_device_source() -> None:
     """Device sources as byte arrays for the library's code generator."""
     os.makedirs(BUILD, exist_ok=True)
-    for name in ("grid_device", "grid_fused", "grid_serial"):
+    for name in ("grid_device", "grid_fused", "grid_serial", "grid_ops"):
         src = open(os.path.join(CSRC, f"{name}.hip"), "rb").read()
         body = ",".join(str(b) for b in src)
         inc = os.path.join(BUILD, f"{name}_src.inc")

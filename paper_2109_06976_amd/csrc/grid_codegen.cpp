@@ -26,6 +26,7 @@ namespace grid_impl {
 #include "grid_device_src.inc"
 #include "grid_fused_src.inc"
 #include "grid_serial_src.inc"
+#include "grid_ops_src.inc"
 
 bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::string* err)
 {
@@ -146,6 +147,20 @@ int64_t workgroups_pipe(const Topology& t, int64_t nknots)
 int64_t workgroups_serial(const Topology& t, int64_t nknots)
 {
     return (int64_t)t.insts.size() * ((nknots + 63) / 64);
+}
+
+// standalone algorithms (ID, FD, M^-1, dID): problems per workgroup, as in grid_ops.hip
+int64_t workgroups_op(const Topology& t, int64_t nknots, int op)
+{
+    int64_t total = 0;
+    for (const BranchInst& inst : t.insts) {
+        const BranchShape& sh = t.shapes[inst.shape];
+        const int P = op == kOpId ? 16
+                      : op == kOpIdGrad ? (t.waves / sh.W) * (16 / sh.Q)
+                                        : pipe_problems(sh.B);
+        total += (nknots + P - 1) / P;
+    }
+    return total;
 }
 
 // problems (knot, branch) per workgroup of the quad-layout kernel
@@ -305,6 +320,18 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
         os << "    {\n        const int nb = (a.nknots + " << P << " - 1) / " << P << ";\n"
            << "        if (b < nb) {\n            gridq::run_pipe<Inst<" << k
            << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
+    }
+    os << "}\n";
+    os << "#line 1 \"grid_ops.hip\"\n";
+    os << grid_ops_src;
+    os << "\n// generated: workgroup -> (branch, problem group), standalone algorithms\n";
+    os << "template <int OP>\n__device__ void grid_dispatch_op(const gridq::OpArgs& a, int block)\n{\n"
+          "    int b = block;\n";
+    for (size_t k = 0; k < t.insts.size(); ++k) {
+        os << "    {\n        constexpr int P = gridq::op_problems<Inst<" << k << ">::S, OP>();\n"
+           << "        const int nb = (a.nknots + P - 1) / P;\n"
+           << "        if (b < nb) {\n            gridq::run_op<Inst<" << k
+           << ">, OP>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
     }
     os << "}\n";
     return os.str();

@@ -184,10 +184,10 @@ __device__ __forceinline__ float mass(int i)
 // (E_cc, E_c,c+1, E_c,c+2); the column entries E_c+1,c and E_c+2,c are the neighbours' third
 // and second row entries. Likewise r_c, h_c, Ibar_cc, Ibar_c,c+1 are picked by the one-hot and
 // the other components come from the neighbours (Ibar_c,c+2 = Ibar_c+2,c).
-template <class I>
-__device__ __forceinline__ void load_bodies(const grid::Args& A, long vbase, const Lane& ln,
-                                            float (&qd)[I::S::B], Rot (&E)[I::S::B],
-                                            LaneK (&K)[I::S::B])
+template <class I, bool kQd = true>
+__device__ __forceinline__ void load_bodies(const float* q_in, const float* qd_in, long vbase,
+                                            const Lane& ln, float (&qd)[I::S::B],
+                                            Rot (&E)[I::S::B], LaneK (&K)[I::S::B])
 {
 #pragma unroll
     for (int i = 0; i < I::S::B; ++i) {
@@ -203,10 +203,10 @@ __device__ __forceinline__ void load_bodies(const grid::Args& A, long vbase, con
     for (int i = 0; i < I::S::B; ++i) {
         const long o = vbase + I::body[i];
         const float* k = I::consts() + i * kConstStride;
-        const float rev = __builtin_amdgcn_fractf(A.q[o] * 0.159154943091895336f);
+        const float rev = __builtin_amdgcn_fractf(q_in[o] * 0.159154943091895336f);
         const float sn = __builtin_amdgcn_sinf(rev);
         const float co = __builtin_amdgcn_cosf(rev);
-        qd[i] = A.qd[o];
+        qd[i] = kQd ? qd_in[o] : 0.0f;
         const float al = ln.oh0 * co - ln.oh1 * sn;
         const float be = ln.oh0 * sn + ln.oh1 * co;
         float R[3];                                      // row c of E, columns 0, 1, 2
@@ -248,6 +248,46 @@ __device__ __forceinline__ void rnea0(const Lane& ln, const float (&qd)[I::S::B]
         nv[i] = gather(v[i]);
         const V vxs = cross_s(ln, v[i]);           // a_i = X a_lambda + (v_i x S) qd_i
         a[i] = V{xa0[i].a + vxs.a * qd[i], xa0[i].l + vxs.l * qd[i]};
+        na[i] = gather(a[i]);
+        gam[i] = imv(K[i], mass<I>(i), v[i], nv[i]);
+        F[i] = add(imv(K[i], mass<I>(i), a[i], na[i]), crf(nv[i], gather(gam[i])));
+    }
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        const int p = S::parent[i];
+        if (p >= 0)
+            F[p < 0 ? 0 : p] = add(F[p < 0 ? 0 : p], xtfv(E[i], K[i], F[i], gather(F[i])));
+    }
+}
+
+// RNEA(q, qd, qdd): v_i, gamma_i = I_i v_i, f_i accumulated inward, and xa_i = X_i a_lambda(i)
+// (a_lambda at this qdd)
+template <class I>
+__device__ __forceinline__ void rnea_at(const Lane& ln, const float (&qd)[I::S::B],
+                                        const float (&qdd)[I::S::B], const Rot (&E)[I::S::B],
+                                        const LaneK (&K)[I::S::B], V (&v)[I::S::B],
+                                        V (&gam)[I::S::B], V (&F)[I::S::B], V (&xa)[I::S::B])
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    V a[B];
+    Nb na[B], nv[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const int p = S::parent[i];
+        V xv;
+        if (p >= 0) {
+            xv = xmv(E[i], K[i], v[p < 0 ? 0 : p], nv[p < 0 ? 0 : p]);
+            xa[i] = xmv(E[i], K[i], a[p < 0 ? 0 : p], na[p < 0 ? 0 : p]);
+        } else {
+            xv = V{0.0f, 0.0f};
+            const V g{0.0f, ln.g};
+            xa[i] = xmv(E[i], K[i], g, gather(g));
+        }
+        v[i] = V{xv.a + ln.sz * qd[i], xv.l};
+        nv[i] = gather(v[i]);
+        const V vxs = cross_s(ln, v[i]);   // a_i = X a_lambda + S qdd_i + (v_i x S) qd_i
+        a[i] = V{xa[i].a + ln.sz * qdd[i] + vxs.a * qd[i], xa[i].l + vxs.l * qd[i]};
         na[i] = gather(a[i]);
         gam[i] = imv(K[i], mass<I>(i), v[i], nv[i]);
         F[i] = add(imv(K[i], mass<I>(i), a[i], na[i]), crf(nv[i], gather(gam[i])));
@@ -503,7 +543,7 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
     float qd[B];
     Rot E[B];
     LaneK K[B];
-    load_bodies<I>(A, vbase, ln, qd, E, K);
+    load_bodies<I>(A.q, A.qd, vbase, ln, qd, E, K);
 
     V v[B], gam[B], F[B], xa0[B];
     rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
@@ -588,9 +628,8 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
 // columns s and s + 16 (those below B) of M^-1 from the factor: to LDS (for the final
 // products) and to the output, entries (i, jm), i <= jm, in both mirrored positions so that
 // M^-1 comes out exactly symmetric; then this branch's zeros in other branches' columns
-template <class I, int CB, int P>
-__device__ __forceinline__ void minv_columns(const grid::Args& A,
-                                             const float (&Lf)[I::S::B][I::S::B],
+template <class I, int CB, int P, bool kLds = true>
+__device__ __forceinline__ void minv_columns(float* Minv, const float (&Lf)[I::S::B][I::S::B],
                                              const float (&dinv)[I::S::B], int pslot, int s, int c,
                                              bool valid, long mbase, int lp, int lanes,
                                              float (&s_Mi)[P][I::S::B][I::S::B])
@@ -612,18 +651,19 @@ __device__ __forceinline__ void minv_columns(const grid::Args& A,
             for (int i = 0; i < B; ++i) {
                 if ((i & 3) != c)
                     continue;
-                s_Mi[pslot][i][jm] = mc[i];
+                if constexpr (kLds)
+                    s_Mi[pslot][i][jm] = mc[i];
                 if (valid && i <= jm) {
                     const int gi = I::body[i];
                     const int gj = I::body_of(jm);
-                    A.Minv[mbase + (long)gi * N + gj] = mc[i];
-                    A.Minv[mbase + (long)gj * N + gi] = mc[i];
+                    Minv[mbase + (long)gi * N + gj] = mc[i];
+                    Minv[mbase + (long)gj * N + gi] = mc[i];
                 }
             }
         }
     }
     if (valid)
-        zero_fill<I>(A.Minv, nullptr, mbase, lp, lanes);
+        zero_fill<I>(Minv, nullptr, mbase, lp, lanes);
 }
 
 template <int B>
@@ -685,7 +725,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         float qd[B];
         Rot E[B];
         LaneK K[B];
-        load_bodies<I>(A, vbase, ln, qd, E, K);
+        load_bodies<I>(A.q, A.qd, vbase, ln, qd, E, K);
         V v[B], gam[B], F[B], xa0[B];
         rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
         if (s == 0 && c == 2) {               // quad 0 of each problem publishes c
@@ -753,7 +793,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         float qd[B];
         Rot E[B];
         LaneK K[B];
-        load_bodies<I>(A, vbase, ln, qd, E, K);
+        load_bodies<I>(A.q, A.qd, vbase, ln, qd, E, K);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             V fm[B];
@@ -777,7 +817,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                     Lf[i][b] = s_M[pslot][i][b];
         ltl_factor<S>(Lf, dinv);
         if constexpr (!PS::HASC)
-            minv_columns<I, CB>(A, Lf, dinv, pslot, s, c, valid, mbase, lane % (4 * QB), 4 * QB,
+            minv_columns<I, CB>(A.Minv, Lf, dinv, pslot, s, c, valid, mbase, lane % (4 * QB), 4 * QB,
                                 s_Mi);
         __syncthreads();                      // c published
 
@@ -836,7 +876,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 if (b == i || is_anc<S>(b, i))
                     Lf[i][b] = s_M[pslot][i][b];
         ltl_factor<S>(Lf, dinv);
-        minv_columns<I, CB>(A, Lf, dinv, pslot, s, c, valid, mbase, lane % (4 * QB), 4 * QB, s_Mi);
+        minv_columns<I, CB>(A.Minv, Lf, dinv, pslot, s, c, valid, mbase, lane % (4 * QB), 4 * QB, s_Mi);
         __syncthreads();                      // M^-1 published
     } else {
         // a wavefront this shape does not use still takes part in both barriers

@@ -23,6 +23,23 @@ constexpr int kVariantPipe = 4;
 constexpr int kVariantSerial = 5;
 constexpr int kNumVariants = 6;
 
+// standalone algorithms (grid_ops.hip)
+constexpr int kOpId = 0;
+constexpr int kOpFd = 1;
+constexpr int kOpMinv = 2;
+constexpr int kOpIdGrad = 3;
+constexpr int kNumOps = 4;
+
+// argument block of the standalone kernels; must match gridq::OpArgs in grid_ops.hip
+struct OpArgs {
+    int nknots;
+    const float* q;
+    const float* qd;
+    const float* u;
+    float* out0;
+    float* out1;
+};
+
 // A branch hanging off the fixed base, in local numbering (parent before child).
 struct BranchShape {
     int B = 0;                       // bodies
@@ -78,6 +95,7 @@ int64_t workgroups_for(const Topology& t, int64_t nknots);
 int64_t workgroups_quad(const Topology& t, int64_t nknots);
 int64_t workgroups_pipe(const Topology& t, int64_t nknots);
 int64_t workgroups_serial(const Topology& t, int64_t nknots);
+int64_t workgroups_op(const Topology& t, int64_t nknots, int op);
 int pipe_problems(int B);
 int pipe_waves(const Topology& t);
 int lanes_per_knot(const Topology& t);
@@ -108,6 +126,7 @@ struct grid_model_s {
     uint64_t source_hash = 0;           // of the generated source: keys tuning tables
     int compute_units = 256;
     hipFunction_t fused_variant[grid_impl::kNumVariants] = {};   // see kVariantQuad
+    hipFunction_t op[grid_impl::kNumOps] = {};                    // see kOpId
     std::vector<std::pair<int32_t, int>> tuned;   // (largest N, variant), ascending N
     hipModule_t module = nullptr;
     hipFunction_t stage[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};

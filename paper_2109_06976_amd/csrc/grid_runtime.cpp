@@ -307,6 +307,10 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     hipError_t e = hipModuleLoadData(&m->module, code.data());
     for (int k = 0; k < kNumVariants && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->fused_variant[k], m->module, kVariants[k]);
+    static const char* const kOps[kNumOps] = {"grid_op_id", "grid_op_fd", "grid_op_minv",
+                                              "grid_op_idgrad"};
+    for (int k = 0; k < kNumOps && e == hipSuccess; ++k)
+        e = hipModuleGetFunction(&m->op[k], m->module, kOps[k]);
     for (int k = 0; k < 5 && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->stage[k], m->module, kStages[k]);
     if (e != hipSuccess) {
@@ -360,6 +364,59 @@ grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* q
         return fail(GRID_EINVAL, "a data pointer is NULL");
     HIP_TRY(hipSetDevice(m->device));
     return launch_fused(m, N, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, (hipStream_t)stream);
+}
+
+static grid_status launch_op(grid_model m, int op, int32_t N, const float* q, const float* qd,
+                             const float* u, float* out0, float* out1, void* stream)
+{
+    if (!m)
+        return fail(GRID_EINVAL, "model is NULL");
+    if (N < 0)
+        return fail(GRID_EINVAL, "N must be >= 0");
+    if (N == 0)
+        return GRID_OK;
+    if (N > (1 << 30) / 64)
+        return fail(GRID_EINVAL, "N too large");
+    const bool needs_qd = op != kOpMinv, needs_u = op != kOpMinv, needs_out1 = op == kOpIdGrad;
+    if (!q || (needs_qd && !qd) || (needs_u && !u) || !out0 || (needs_out1 && !out1))
+        return fail(GRID_EINVAL, "a data pointer is NULL");
+    HIP_TRY(hipSetDevice(m->device));
+    OpArgs a;
+    a.nknots = N;
+    a.q = q;
+    a.qd = needs_qd ? qd : nullptr;
+    a.u = needs_u ? u : nullptr;
+    a.out0 = out0;
+    a.out1 = needs_out1 ? out1 : nullptr;
+    const unsigned blocks = (unsigned)workgroups_op(m->topo, N, op);
+    const unsigned threads = op == kOpIdGrad ? 64u * (unsigned)m->topo.waves : 64u;
+    void* params[] = {&a};
+    HIP_TRY(hipModuleLaunchKernel(m->op[op], blocks, 1, 1, threads, 1, 1, 0, (hipStream_t)stream,
+                                  params, nullptr));
+    return GRID_OK;
+}
+
+grid_status grid_id(grid_model m, int32_t N, const float* q, const float* qd, const float* qdd,
+                    float* tau, void* stream)
+{
+    return launch_op(m, kOpId, N, q, qd, qdd, tau, nullptr, stream);
+}
+
+grid_status grid_fd(grid_model m, int32_t N, const float* q, const float* qd, const float* tau,
+                    float* qdd, void* stream)
+{
+    return launch_op(m, kOpFd, N, q, qd, tau, qdd, nullptr, stream);
+}
+
+grid_status grid_minv(grid_model m, int32_t N, const float* q, float* Minv, void* stream)
+{
+    return launch_op(m, kOpMinv, N, q, nullptr, nullptr, Minv, nullptr, stream);
+}
+
+grid_status grid_id_grad(grid_model m, int32_t N, const float* q, const float* qd,
+                         const float* qdd, float* dtau_dq, float* dtau_dqd, void* stream)
+{
+    return launch_op(m, kOpIdGrad, N, q, qd, qdd, dtau_dq, dtau_dqd, stream);
 }
 
 grid_status grid_fd_grad_staged(grid_model m, grid_workspace w, int32_t N, const float* q,

@@ -105,6 +105,13 @@ _SIGS = {
     "grid_tune_apply": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.c_int32]),
     "grid_build_for": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "grid_id": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_void_p]),
+    "grid_fd": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_void_p]),
+    "grid_minv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "grid_id_grad": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
     "grid_server_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(ServerConfig),
                                        C.POINTER(C.c_void_p)]),
     "grid_server_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 7 +
@@ -224,6 +231,31 @@ class Model:
         _check(lib().grid_fd_grad(self._h, int(N), _addr(q), _addr(qd), _addr(tau), _addr(qdd),
                                   _addr(Minv), _addr(dqdd_dq), _addr(dqdd_dqd),
                                   _stream_handle(stream)))
+
+
+    # the paper's other algorithms (device buffers, asynchronous)
+    def id(self, q, qd, qdd, tau, N=None, stream=None):
+        """grid_id: tau = ID(q, qd, qdd)."""
+        N = int(q.shape[0]) if N is None else N
+        _check(lib().grid_id(self._h, int(N), _addr(q), _addr(qd), _addr(qdd), _addr(tau),
+                             _stream_handle(stream)))
+
+    def fd(self, q, qd, tau, qdd, N=None, stream=None):
+        """grid_fd: qdd = FD(q, qd, tau)."""
+        N = int(q.shape[0]) if N is None else N
+        _check(lib().grid_fd(self._h, int(N), _addr(q), _addr(qd), _addr(tau), _addr(qdd),
+                             _stream_handle(stream)))
+
+    def minv(self, q, Minv, N=None, stream=None):
+        """grid_minv: M(q)^-1."""
+        N = int(q.shape[0]) if N is None else N
+        _check(lib().grid_minv(self._h, int(N), _addr(q), _addr(Minv), _stream_handle(stream)))
+
+    def id_grad(self, q, qd, qdd, dtau_dq, dtau_dqd, N=None, stream=None):
+        """grid_id_grad: dtau/dq and dtau/dqd at the given qdd."""
+        N = int(q.shape[0]) if N is None else N
+        _check(lib().grid_id_grad(self._h, int(N), _addr(q), _addr(qd), _addr(qdd),
+                                  _addr(dtau_dq), _addr(dtau_dqd), _stream_handle(stream)))
 
 
 def fd_vjp(model, dqdd_dq, dqdd_dqd, Minv, gbar, qbar, qdbar, taubar, N=None, stream=None):
