@@ -17,6 +17,8 @@ Also reported (extra fields of the same line):
   served        p50/p99 latency and throughput of an open-loop Poisson request stream
                 (20k req/s over the three robots) through the continuous-batching
                 server, and through one plain staged launch per request;
+  single_knot_us  one knot (N = 1) of ID, M^-1, FD, dID and dFD on each robot, as the
+                paper's single-computation table, with the paper's GPU numbers as context;
   cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
@@ -79,6 +81,8 @@ def parse():
                     help="measured seconds of the served load (0 disables serving)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-sweep", default="", help="extra request rates, comma-separated")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-knot latency table (ID, Minv, FD, dID, dFD at N = 1)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (untuned build choice)")
     ap.add_argument("--build", type=int, default=-1,
@@ -105,6 +109,41 @@ def time_steps(torch, launch, steps, warmup):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     return wall, start.elapsed_time(end) * 1e-3 / steps
+
+
+# the paper's single-computation GPU latencies (Table I; RTX 3080, microseconds): context
+PAPER_TABLE1_GPU_US = {
+    "chain7": {"ID": 3.0, "Minv": 5.2, "FD": 7.7, "dID": 6.3, "dFD": 12.9},
+    "quad12": {"ID": 3.2, "Minv": 5.6, "FD": 6.9, "dID": 5.8, "dFD": 11.0},
+    "humanoid30": {"ID": 8.0, "Minv": 17.4, "FD": 22.4, "dID": 19.5, "dFD": 42.1},
+}
+
+
+def single_knot_table(torch, grid, synth, steps):
+    """Latency of one knot (N = 1) for each algorithm on each robot: HIP-event time per
+    launch over back-to-back launches, as the paper's single-computation table."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    table = {}
+    for name in ("chain7", "quad12", "humanoid30"):
+        robot = synth.model_by_name(name)
+        n = robot.n
+        m = grid.Model(robot)
+        k = synth.random_knots(n, 1, 9)
+        q, qd, tau = (torch.from_numpy(a).to(dev) for a in (k.q, k.qd, k.tau))
+        v = [torch.empty((1, n), device=dev) for _ in range(2)]
+        mats = [torch.empty((1, n, n), device=dev) for _ in range(3)]
+        ops = {
+            "ID": lambda: m.id(q, qd, tau, v[0], N=1, stream=stream),
+            "Minv": lambda: m.minv(q, mats[0], N=1, stream=stream),
+            "FD": lambda: m.fd(q, qd, tau, v[0], N=1, stream=stream),
+            "dID": lambda: m.id_grad(q, qd, tau, mats[0], mats[1], N=1, stream=stream),
+            "dFD": lambda: m.fd_grad(q, qd, tau, v[1], *mats, N=1, stream=stream),
+        }
+        table[name] = {op: round(time_steps(torch, f, steps, 100)[1] * 1e6, 3)
+                       for op, f in ops.items()}
+        m.close()
+    return table
 
 
 def serve(args, grid, synth, chain_model=None):
@@ -274,6 +313,10 @@ def main():
                               "alu_frac": fl["total"] * NK / a / 1e12 / PEAK_FP32_TFLOPS}
             del i2, o2
         result["sweep"] = sweep
+
+    if not args.no_single:
+        result["single_knot_us"] = single_knot_table(torch, grid, synth, 1000)
+        result["single_knot_us"]["paper_table1_gpu_us"] = PAPER_TABLE1_GPU_US
 
     if args.copy_calibration_mb > 0:
         nbytes = int(args.copy_calibration_mb * 2**20)
