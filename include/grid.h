@@ -10,10 +10,13 @@
  * Conventions shared by every call
  *   - Bodies are numbered 0..n-1 with parent[i] < i; parent -1 is the fixed base
  *     (Sec. III-B). Outputs use the caller's numbering.
- *   - Every joint is revolute about its own z axis (S_i = e_3); the joint transform is
- *     iX_lambda(q_i) = rot(E_z(q_i)) * X_T,i, with X_T,i given by tree_rot (rotation from
- *     the parent frame to the joint frame) and tree_pos (the joint origin in parent
- *     coordinates) (Sec. III-B).
+ *   - Every joint is revolute about a unit axis a_i of its joint frame (S_i = (a_i, 0);
+ *     +z unless `axis` is given); the joint transform is iX_lambda(q_i) =
+ *     rot(E_a(q_i)) * X_T,i with E_a the coordinate rotation by q_i about a_i and X_T,i
+ *     given by tree_rot (rotation from the parent frame to the joint frame) and tree_pos
+ *     (the joint origin in parent coordinates) (Sec. III-B). The library rotates every
+ *     body frame so that its joint axis becomes z before generating the kernel (a change
+ *     of body coordinates that leaves every joint-space quantity unchanged).
  *   - Spatial vectors are ordered [angular; linear] (Eq. 2). SI units, radians.
  *   - Fixed base, fully actuated (B = I in Eq. 1), no external forces (F = 0).
  *   - Batched arrays are knot-major and row-major float32:
@@ -61,7 +64,8 @@ typedef struct grid_model_desc {
     int32_t n;                   /* number of joints/bodies, 1..32 */
     const int32_t* parent;       /* [n], -1 <= parent[i] < i */
     const int32_t* joint_type;   /* [n] GRID_JOINT_REVOLUTE, or NULL for all revolute */
-    const double* axis;          /* [n][3] joint axis in the joint frame: must be (0,0,1); NULL = z */
+    const double* axis;          /* [n][3] unit joint axis in the joint frame (norm within
+                                    1e-6 of 1, normalised); NULL = +z for every joint */
     const double* tree_rot;      /* [n][3][3] E_T, row-major, parent frame -> joint frame */
     const double* tree_pos;      /* [n][3] joint origin in parent coordinates (m) */
     const double* mass;          /* [n] link mass (kg), > 0 */
@@ -93,8 +97,8 @@ const char* grid_last_error(void);
  * the kernel cache (directory GRID_KERNEL_CACHE, else the package's _kcache), and
  * loads it on the device.
  * flags: reserved, must be 0. On success *out owns the loaded code object until
- * grid_model_destroy. Errors: EINVAL (bad description), EUNSUPPORTED (non-z axis,
- * non-revolute joint, n > 32), ECOMPILE, EDEVICE, ENOMEM.
+ * grid_model_destroy. Errors: EINVAL (bad description, an axis not of unit length),
+ * EUNSUPPORTED (non-revolute joint, n > 32), ECOMPILE, EDEVICE, ENOMEM.
  */
 grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint32_t flags,
                               grid_model* out);

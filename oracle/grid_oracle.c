@@ -38,9 +38,16 @@ static int check_model(const orc_model *m)
 {
     if (!m || m->n <= 0 || !m->parent || !m->E_T || !m->r || !m->mass || !m->com || !m->Ic)
         return -1;
-    for (int i = 0; i < m->n; ++i)
+    for (int i = 0; i < m->n; ++i) {
         if (m->parent[i] < -1 || m->parent[i] >= i)
             return -1;
+        if (m->axis) {
+            const double *a = m->axis + 3 * i;
+            const double nrm = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+            if (!(fabs(nrm - 1.0) < 1e-6))
+                return -1;
+        }
+    }
     return 0;
 }
 
@@ -138,18 +145,17 @@ int orc_minv_cholesky(const orc_model *m, const double *q, double *Minv)
 /*
  * Direct M^-1 (Sec. IV-B): the articulated-body recursion with qd = 0, g = 0 and the
  * identity as n right-hand sides. F_i and P_i are 6 x n; row_i is 1 x n.
- *   inward:  U_i = IA_i S, D_i = S^T U_i, row_i = (e_i^T - S^T F_i) / D_i,
+ *   inward:  U_i = IA_i S_i, D_i = S_i^T U_i, row_i = (e_i^T - S_i^T F_i) / D_i,
  *            IA_lambda += X^T (IA_i - U_i U_i^T / D_i) X,
  *            F_lambda  += X^T (F_i + U_i row_i)
  *   outward: A = X_i P_lambda (0 at the base), row_i -= U_i^T A / D_i,
- *            P_i = A + S row_i;   M^-1[i, :] = row_i
+ *            P_i = A + S_i row_i;   M^-1[i, :] = row_i
  */
 int orc_minv_direct(const orc_model *m, const double *q, double *Minv)
 {
     if (check_model(m))
         return -1;
     const int n = m->n;
-    const int ax = S_axis_d;
     double (*X)[36] = malloc(sizeof(double[36]) * n);
     double (*IA)[36] = malloc(sizeof(double[36]) * n);
     double (*U)[6] = malloc(sizeof(double[6]) * n);
@@ -165,15 +171,22 @@ int orc_minv_direct(const orc_model *m, const double *q, double *Minv)
     for (int i = n - 1; !st && i >= 0; --i) {
         const int p = m->parent[i];
         double *Fi = F + (size_t)i * 6 * n;
+        double S[6];
+        joint_S_d(m, i, S);
+        mv6_d(IA[i], S, U[i]);
+        D[i] = 0;
         for (int k = 0; k < 6; ++k)
-            U[i][k] = IA[i][k * 6 + ax];
-        D[i] = U[i][ax];
+            D[i] += S[k] * U[i][k];
         if (!(D[i] > 0)) {
             st = -2;
             break;
         }
-        for (int c = 0; c < n; ++c)
-            row[i * n + c] = ((c == i ? 1.0 : 0.0) - Fi[ax * n + c]) / D[i];
+        for (int c = 0; c < n; ++c) {
+            double sf = 0;
+            for (int k = 0; k < 6; ++k)
+                sf += S[k] * Fi[k * n + c];
+            row[i * n + c] = ((c == i ? 1.0 : 0.0) - sf) / D[i];
+        }
         if (p >= 0) {
             double Ia[36], t[36], u[36];
             for (int a = 0; a < 6; ++a)
@@ -197,6 +210,8 @@ int orc_minv_direct(const orc_model *m, const double *q, double *Minv)
     for (int i = 0; !st && i < n; ++i) {
         const int p = m->parent[i];
         double *Pi = P + (size_t)i * 6 * n;
+        double S[6];
+        joint_S_d(m, i, S);
         for (int c = 0; c < n; ++c) {
             double A[6] = {0, 0, 0, 0, 0, 0};
             if (p >= 0) {
@@ -211,7 +226,7 @@ int orc_minv_direct(const orc_model *m, const double *q, double *Minv)
                 UA += U[i][k] * A[k];
             row[i * n + c] -= UA / D[i];
             for (int k = 0; k < 6; ++k)
-                Pi[k * n + c] = A[k] + (k == ax ? row[i * n + c] : 0.0);
+                Pi[k * n + c] = A[k] + S[k] * row[i * n + c];
         }
     }
     if (!st)
@@ -223,12 +238,12 @@ int orc_minv_direct(const orc_model *m, const double *q, double *Minv)
 /*
  * Gradient of inverse dynamics at (q, qd, qdd) (Algorithm 1 and its backward pass).
  * For u in {q, qd} and each column j, with dv_0 = da_0 = 0:
- *   outward: dv_i = X_i dv_lambda + [i==j] {(X_i v_lambda) x S  if u = q;  S  if u = qd}
- *            da_i = X_i da_lambda + (dv_i x) S qd_i
- *                   + [i==j] {(X_i a_lambda) x S  if u = q;  (v_i x) S  if u = qd}
+ *   outward: dv_i = X_i dv_lambda + [i==j] {(X_i v_lambda) x S_i  if u = q;  S_i  if u = qd}
+ *            da_i = X_i da_lambda + (dv_i x) S_i qd_i
+ *                   + [i==j] {(X_i a_lambda) x S_i  if u = q;  (v_i x) S_i  if u = qd}
  *            df_i = I_i da_i + (dv_i x*) I_i v_i + (v_i x*) I_i dv_i
- *   inward:  dtau_i/du_j = S^T df_i
- *            df_lambda += X_i^T df_i + [i==j and u = q] X_i^T (S x*) f_i
+ *   inward:  dtau_i/du_j = S_i^T df_i
+ *            df_lambda += X_i^T df_i + [i==j and u = q] X_i^T (S_i x*) f_i
  * v, a and the accumulated forces f come from RNEA(q, qd, qdd). The velocity term in
  * da_i uses dv_i (the derivative of v_i, which multiplies S qd_i in the RNEA), and the
  * bracketed source terms act only in the joint's own column.
@@ -251,8 +266,11 @@ int orc_rnea_grad(const orc_model *m, const double *q, const double *qd, const d
     int st = (X && Ib && v && a && f && dv && da && df && tau) ? 0 : -1;
     if (!st)
         st = rnea_d(m, q, qd, qdd, 1, tau, &v[0][0], &a[0][0], &f[0][0]);
-    double S[6] = {0, 0, 0, 0, 0, 0};
-    S[S_axis_d] = 1;
+    double (*S)[6] = malloc(sizeof(double[6]) * n);       /* S_i per joint */
+    if (!S)
+        st = -1;
+    for (int i = 0; !st && i < n; ++i)
+        joint_S_d(m, i, S[i]);
     double a0[6] = {0, 0, 0, -m->gravity[0], -m->gravity[1], -m->gravity[2]};
     double zero6[6] = {0, 0, 0, 0, 0, 0};
     for (int i = 0; !st && i < n; ++i) {
@@ -273,23 +291,23 @@ int orc_rnea_grad(const orc_model *m, const double *q, const double *qd, const d
                 if (i == j) {
                     if (u == 0) {
                         mv6_d(X[i], vp, t);
-                        crm_apply_d(t, S, s);
+                        crm_apply_d(t, S[i], s);
                     } else {
-                        memcpy(s, S, sizeof s);
+                        memcpy(s, S[i], sizeof s);
                     }
                     for (int k = 0; k < 6; ++k)
                         dv[i][k] += s[k];
                 }
                 mv6_d(X[i], dap, da[i]);
-                crm_apply_d(dv[i], S, s);
+                crm_apply_d(dv[i], S[i], s);
                 for (int k = 0; k < 6; ++k)
                     da[i][k] += s[k] * qd[i];
                 if (i == j) {
                     if (u == 0) {
                         mv6_d(X[i], ap, t);
-                        crm_apply_d(t, S, s);
+                        crm_apply_d(t, S[i], s);
                     } else {
-                        crm_apply_d(v[i], S, s);
+                        crm_apply_d(v[i], S[i], s);
                     }
                     for (int k = 0; k < 6; ++k)
                         da[i][k] += s[k];
@@ -307,14 +325,17 @@ int orc_rnea_grad(const orc_model *m, const double *q, const double *qd, const d
             }
             for (int i = n - 1; i >= 0; --i) {
                 const int p = m->parent[i];
-                out[i * n + j] = df[i][S_axis_d];
+                double st_ = 0;
+                for (int k = 0; k < 6; ++k)
+                    st_ += S[i][k] * df[i][k];
+                out[i * n + j] = st_;
                 if (p >= 0) {
                     double t[6], s[6];
                     mtv6_d(X[i], df[i], t);
                     for (int k = 0; k < 6; ++k)
                         df[p][k] += t[k];
                     if (u == 0 && i == j) {
-                        crf_apply_d(S, f[i], s);
+                        crf_apply_d(S[i], f[i], s);
                         mtv6_d(X[i], s, t);
                         for (int k = 0; k < 6; ++k)
                             df[p][k] += t[k];
@@ -324,6 +345,7 @@ int orc_rnea_grad(const orc_model *m, const double *q, const double *qd, const d
         }
     }
     free(X); free(Ib); free(v); free(a); free(f); free(dv); free(da); free(df); free(tau);
+    free(S);
     return st;
 }
 

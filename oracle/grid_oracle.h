@@ -12,9 +12,10 @@
  * Conventions (paper Sec. III-B and Eq. 2):
  *   - bodies i = 0..n-1, parent[i] < i, parent -1 = fixed base;
  *   - spatial vectors ordered [angular; linear];
- *   - X_i = X_J(q_i) X_T,i with X_J a rotation about the joint z axis, X_T the
- *     fixed parent-to-joint transform given by rotation E_T and origin r;
- *   - S_i = (0,0,1,0,0,0): every joint is revolute about its own z axis;
+ *   - X_i = X_J(q_i) X_T,i with X_J the rotation by q_i about the joint axis a_i (a unit
+ *     vector in joint coordinates, +z unless given), X_T the fixed parent-to-joint
+ *     transform given by rotation E_T and origin r;
+ *   - S_i = (a_i, 0): every joint is revolute about its axis;
  *   - gravity enters as the fictitious base acceleration a_0 = -g;
  *   - matrices are row-major; dtau_dq[i*n+j] = d tau_i / d q_j.
  */
@@ -36,6 +37,8 @@ typedef struct {
     const double *com;     /* [n][3] centre of mass, body coordinates */
     const double *Ic;      /* [n][6] xx yy zz xy xz yz, about the centre of mass */
     double gravity[3];     /* base-frame gravity vector */
+    const double *axis;    /* [n][3] joint axes in joint coordinates (normalised here);
+                              NULL: +z for every joint */
 } orc_model;
 
 /* status: 0 ok, -1 invalid model, -2 matrix not positive definite */

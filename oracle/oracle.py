@@ -22,7 +22,7 @@ _ip = C.POINTER(C.c_int)
 
 class _Model(C.Structure):
     _fields_ = [("n", C.c_int), ("parent", _ip), ("E_T", _dp), ("r", _dp), ("mass", _dp),
-                ("com", _dp), ("Ic", _dp), ("gravity", C.c_double * 3)]
+                ("com", _dp), ("Ic", _dp), ("gravity", C.c_double * 3), ("axis", _dp)]
 
 
 class OracleError(RuntimeError):
@@ -80,8 +80,10 @@ class OracleModel:
         self.com = _f64(model.com, (n, 3))
         self.Ic = _f64(model.Ic, (n, 6))
         g = _f64(model.gravity, (3,))
+        ax = getattr(model, "axis", None)
+        self.axis = None if ax is None else _f64(ax, (n, 3))
         self.c = _Model(n, _ptr(self.parent), _ptr(self.E_T), _ptr(self.r), _ptr(self.mass),
-                        _ptr(self.com), _ptr(self.Ic), (C.c_double * 3)(*g))
+                        _ptr(self.com), _ptr(self.Ic), (C.c_double * 3)(*g), _ptr(self.axis))
 
     @property
     def ref(self):

@@ -72,6 +72,9 @@ def standard_models():
     for parent, seed in [([-1], 40), ([-1, 0], 41), ([-1, 0, 1], 42), ([-1, 0, 0], 43),
                          ([-1, -1, 1], 44), ([-1, 0, 0, 1, 1, 2, 2], 45)]:
         models.append(synth.random_model(np.array(parent, np.int32), seed))
+    # joints about random axes
+    models.append(synth.random_model(synth.chain_parent(7), 0, axes="random"))
+    models.append(synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6, axes="random"))
     return models
 
 

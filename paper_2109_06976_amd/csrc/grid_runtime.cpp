@@ -43,8 +43,10 @@ grid_status validate_desc(const grid_model_desc* d, std::string* err)
             return fail_to(err, GRID_EUNSUPPORTED, "only revolute joints are supported");
         if (d->axis) {
             const double* a = d->axis + 3 * i;
-            if (a[0] != 0.0 || a[1] != 0.0 || a[2] != 1.0)
-                return fail_to(err, GRID_EUNSUPPORTED, "joint axes other than +z are not supported");
+            const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+            if (!(std::fabs(nrm - 1.0) <= 1e-6))
+                return fail_to(err, GRID_EINVAL, "axis[" + std::to_string(i) +
+                                                     "] must be a unit vector");
         }
     }
     if (!finite_all(d->tree_rot, 9 * n) || !finite_all(d->tree_pos, 3 * n) ||
@@ -76,20 +78,93 @@ grid_status validate_desc(const grid_model_desc* d, std::string* err)
 
 // device constants, branch by branch in local order, kConstStride floats per body:
 // E_T, r, Ibar = Ic + m (|c|^2 1 - c c^T) about the body origin, h = m c, m
+// A rotation R with R a = e_z for a unit vector a (rotation about a x e_z; a half turn
+// about x when a = -e_z). Row-major.
+static void align_to_z(const double* a, double* R)
+{
+    const double c = a[2];                                   // a . e_z
+    const double v[3] = {a[1], -a[0], 0.0};                   // a x e_z
+    const double s2 = v[0] * v[0] + v[1] * v[1];
+    for (int k = 0; k < 9; ++k)
+        R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    if (s2 < 1e-24) {
+        if (c < 0.0) {   // a = -e_z
+            R[4] = -1.0;
+            R[8] = -1.0;
+        }
+        return;
+    }
+    // R = 1 + [v]x + [v]x^2 / (1 + c)
+    const double K[9] = {0.0, -v[2], v[1], v[2], 0.0, -v[0], -v[1], v[0], 0.0};
+    double K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k)
+                acc += K[3 * i + k] * K[3 * k + j];
+            K2[3 * i + j] = acc;
+        }
+    for (int k = 0; k < 9; ++k)
+        R[k] += K[k] + K2[k] / (1.0 + c);
+}
+
+static void mat3(const double* A, const double* B, double* C, bool transB = false)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k)
+                acc += A[3 * i + k] * (transB ? B[3 * j + k] : B[3 * k + j]);
+            C[3 * i + j] = acc;
+        }
+}
+
+// Body constants for the kernels, branch by branch: E_T, r, Ibar (about the body origin),
+// h = m c, m. A joint axis a_i other than +z is turned into +z by re-expressing body i in
+// the frame R_i (R_i a_i = e_z): E_T' = R_i E_T R_lambda^T, r' = R_lambda r, c' = R_i c,
+// Ic' = R_i Ic R_i^T. Coordinates of body frames change; joint-space quantities do not.
 std::vector<float> pack_constants(const grid_model_desc* d, const Topology& t)
 {
-    std::vector<float> out((size_t)d->n * kConstStride, 0.0f);
+    const int n = d->n;
+    std::vector<double> R((size_t)9 * n);
+    for (int i = 0; i < n; ++i) {
+        double a[3] = {0.0, 0.0, 1.0};
+        if (d->axis) {
+            const double* ai = d->axis + 3 * i;
+            const double nrm = std::sqrt(ai[0] * ai[0] + ai[1] * ai[1] + ai[2] * ai[2]);
+            for (int k = 0; k < 3; ++k)
+                a[k] = ai[k] / nrm;
+        }
+        align_to_z(a, R.data() + 9 * i);
+    }
+    static const double kI3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    std::vector<float> out((size_t)n * kConstStride, 0.0f);
     for (const BranchInst& inst : t.insts)
         for (size_t k = 0; k < inst.body.size(); ++k) {
             const int i = inst.body[k];
+            const int p = d->parent[i];
+            const double* Ri = R.data() + 9 * i;
+            const double* Rp = p < 0 ? kI3 : R.data() + 9 * p;
             float* b = out.data() + inst.coff + k * kConstStride;
+            double tmp[9], ET[9];
+            mat3(Ri, d->tree_rot + 9 * i, tmp);
+            mat3(tmp, Rp, ET, true);
             for (int e = 0; e < 9; ++e)
-                b[e] = (float)d->tree_rot[9 * i + e];
+                b[e] = (float)ET[e];
+            const double* r = d->tree_pos + 3 * i;
             for (int e = 0; e < 3; ++e)
-                b[9 + e] = (float)d->tree_pos[3 * i + e];
+                b[9 + e] = (float)(Rp[3 * e] * r[0] + Rp[3 * e + 1] * r[1] + Rp[3 * e + 2] * r[2]);
             const double m = d->mass[i];
-            const double* c = d->com + 3 * i;
-            const double* J = d->inertia_com + 6 * i;
+            const double* c0 = d->com + 3 * i;
+            double c[3];
+            for (int e = 0; e < 3; ++e)
+                c[e] = Ri[3 * e] * c0[0] + Ri[3 * e + 1] * c0[1] + Ri[3 * e + 2] * c0[2];
+            const double* J0 = d->inertia_com + 6 * i;
+            const double Jm[9] = {J0[0], J0[3], J0[4], J0[3], J0[1], J0[5], J0[4], J0[5], J0[2]};
+            double RJ[9], Jr[9];
+            mat3(Ri, Jm, RJ);
+            mat3(RJ, Ri, Jr, true);
+            const double J[6] = {Jr[0], Jr[4], Jr[8], Jr[1], Jr[2], Jr[5]};
             b[12] = (float)(J[0] + m * (c[1] * c[1] + c[2] * c[2]));
             b[13] = (float)(J[1] + m * (c[0] * c[0] + c[2] * c[2]));
             b[14] = (float)(J[2] + m * (c[0] * c[0] + c[1] * c[1]));

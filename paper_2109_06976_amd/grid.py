@@ -188,7 +188,11 @@ class _Desc:
         E_T, r, mass, com, Ic = self.arrays
         g = np.asarray(robot.gravity, dtype=np.float64).reshape(3)
         p = lambda a: a.ctypes.data_as(_f64p)
-        self.c = GridDesc(n, self.parent.ctypes.data_as(_i32p), None, None, p(E_T), p(r),
+        ax = getattr(robot, "axis", None)
+        self.axis = None if ax is None else np.ascontiguousarray(
+            np.asarray(ax, dtype=np.float64).reshape(n, 3))
+        self.c = GridDesc(n, self.parent.ctypes.data_as(_i32p), None,
+                          None if self.axis is None else p(self.axis), p(E_T), p(r),
                           p(mass), p(com), p(Ic), (C.c_double * 3)(*g))
 
 

@@ -51,6 +51,7 @@ class RobotModel:
     Ic: np.ndarray              # float64 [n, 6]  (xx, yy, zz, xy, xz, yz)
     gravity: np.ndarray = field(default_factory=lambda: np.array(GRAVITY))
     base_mass: float | None = None   # mass of a fixed base link (cannot affect outputs)
+    axis: np.ndarray | None = None   # float64 [n, 3] unit joint axes (None: every joint +z)
 
     @property
     def n(self) -> int:
@@ -59,7 +60,8 @@ class RobotModel:
     def copy(self) -> "RobotModel":
         return RobotModel(self.name, self.parent.copy(), self.E_T.copy(), self.r.copy(),
                           self.mass.copy(), self.com.copy(), self.Ic.copy(),
-                          self.gravity.copy(), self.base_mass)
+                          self.gravity.copy(), self.base_mass,
+                          None if self.axis is None else self.axis.copy())
 
 
 # ---------------------------------------------------------------- topologies
@@ -124,8 +126,12 @@ def _haar_rotation(rng: np.random.Generator) -> np.ndarray:
 
 
 def random_model(parent, seed: int, name: str = "robot", base_mass: float | None = None,
-                 gravity=GRAVITY) -> RobotModel:
-    """Draw per-body parameters in a fixed order: r, E_T, mass, com, inertia."""
+                 gravity=GRAVITY, axes: str = "z") -> RobotModel:
+    """Draw per-body parameters in a fixed order: r, E_T, mass, com, inertia.
+
+    axes: "z" (every joint about its own +z) or "random" (unit axes drawn uniformly on the
+    sphere from a second stream seeded by (seed, 1), so the other parameters are the same
+    as with "z")."""
     parent = np.asarray(parent, dtype=np.int32)
     n = parent.shape[0]
     for i, p in enumerate(parent):
@@ -146,8 +152,15 @@ def random_model(parent, seed: int, name: str = "robot", base_mass: float | None
         d = rng.uniform(0.01, 0.1, 3)
         J = R @ np.diag(d) @ R.T
         Ic[i] = [J[0, 0], J[1, 1], J[2, 2], J[0, 1], J[0, 2], J[1, 2]]
+    axis = None
+    if axes == "random":
+        arng = np.random.default_rng([seed, 1])
+        a = arng.standard_normal((n, 3))
+        axis = _f32(a / np.linalg.norm(a, axis=1, keepdims=True))
+    elif axes != "z":
+        raise ValueError(axes)
     return RobotModel(name, parent, _f32(E_T), _f32(r), _f32(mass), _f32(com), _f32(Ic),
-                      _f32(np.asarray(gravity, dtype=np.float64)), base_mass)
+                      _f32(np.asarray(gravity, dtype=np.float64)), base_mass, axis)
 
 
 def chain7(seed: int = SEED_CHAIN7) -> RobotModel:

@@ -47,6 +47,7 @@ def _bad(robot, **changes):
     (lambda r: _bad(r, Ic=np.tile([0.1, 0.1, 0.1, 0.5, 0, 0], (7, 1))), grid.GRID_EINVAL),
     (lambda r: _bad(r, r=np.where(np.arange(21).reshape(7, 3) == 4, np.nan, r.r)),
      grid.GRID_EINVAL),
+    (lambda r: _bad(r, axis=np.tile([0.0, 0.0, 1.01], (7, 1))), grid.GRID_EINVAL),
 ])
 def test_model_create_rejects_bad_descriptions_before_device_work(mutate, status):
     with pytest.raises(grid.GridError) as e:

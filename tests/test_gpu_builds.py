@@ -26,6 +26,11 @@ ROBOTS = {
     "fork3": lambda: synth.random_model(np.array([-1, -1, 1], np.int32), 44, "fork3"),
     "binary7": lambda: synth.random_model(np.array([-1, 0, 0, 1, 1, 2, 2], np.int32), 45,
                                           "binary7"),
+    # joints about random unit axes (the library rotates body frames to make them z)
+    "chain7-axes": lambda: synth.random_model(synth.chain_parent(7), 0, "chain7-axes",
+                                              axes="random"),
+    "tree5-axes": lambda: synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6,
+                                             "tree5-axes", axes="random"),
 }
 
 

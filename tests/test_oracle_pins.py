@@ -33,6 +33,11 @@ ALL_MODELS = {
     "humanoid30": synth.humanoid30,
     "humanoid30-literal": lambda: synth.humanoid30(variant="literal"),
     "tree3": lambda: synth.random_model(np.array([-1, 0, 0], np.int32), 5, "tree3"),
+    # joints about random unit axes of their joint frames
+    "chain7-axes": lambda: synth.random_model(synth.chain_parent(7), 0, "chain7-axes",
+                                              axes="random"),
+    "tree5-axes": lambda: synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6,
+                                             "tree5-axes", axes="random"),
 }
 
 
@@ -121,6 +126,98 @@ def test_pendulum_closed_form(orc):
     # vertical axis: gravity does no work about it
     mv = _model_1link(np.eye(3), com, mass, Ic)
     assert abs(orc.rnea(mv, [1.1], [0.0], [0.0])[0]) < 1e-14
+
+
+def _skew(a):
+    return np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+
+
+def test_pendulum_about_a_tilted_axis(orc):
+    """Single revolute joint about a unit axis a: tau = a^T I_O a qdd - a . (c x m g_body),
+    I_O the rotational inertia about the joint origin, g_body = exp(q [a]x)^T g (the matrix
+    exponential from scipy, not the oracle's joint rotation); no velocity term."""
+    from scipy.linalg import expm
+    a = np.array([0.3, -0.5, 0.81])
+    a /= np.linalg.norm(a)
+    com = np.array([0.25, -0.1, 0.07])
+    Ic = (0.02, 0.03, 0.04, 0.001, -0.002, 0.003)
+    mass = 2.0
+    m = _model_1link(np.eye(3), com, mass, Ic)
+    m.axis = a[None]
+    J = np.array([[Ic[0], Ic[3], Ic[4]], [Ic[3], Ic[1], Ic[5]], [Ic[4], Ic[5], Ic[2]]])
+    I_O = J + mass * (com @ com * np.eye(3) - np.outer(com, com))
+    I_axis = a @ I_O @ a
+    g = np.array([0, 0, -9.81])
+    for q in np.linspace(-3, 3, 13):
+        g_body = expm(q * _skew(a)).T @ g
+        grav = a @ np.cross(com, mass * g_body)
+        for qd, qdd in [(0.0, 0.0), (1.7, -0.4), (-3.0, 2.5)]:
+            tau = orc.rnea(m, [q], [qd], [qdd])[0]
+            assert tau == pytest.approx(I_axis * qdd - grav, abs=1e-12)
+    assert orc.crba(m, [0.4])[0, 0] == pytest.approx(I_axis, rel=1e-13)
+    # amplitude of the gravity torque: m |c_perp| |g_perp| (components normal to the axis)
+    taus = np.array([orc.rnea(m, [q], [0.0], [0.0])[0] for q in np.linspace(-np.pi, np.pi, 721)])
+    c_perp = com - (com @ a) * a
+    g_perp = g - (g @ a) * a
+    assert np.abs(taus).max() == pytest.approx(
+        mass * np.linalg.norm(c_perp) * np.linalg.norm(g_perp), rel=1e-4)
+
+
+def _rotate_axes_to_z(model):
+    """The same robot with every joint about +z: body frame i re-expressed in R_i
+    (R_i a_i = e_z, built here with scipy's rotation alignment)."""
+    from scipy.spatial.transform import Rotation
+    n = model.n
+    R = np.zeros((n, 3, 3))
+    for i in range(n):
+        a = np.asarray(model.axis[i], float)
+        a = a / np.linalg.norm(a)
+        rot, _ = Rotation.align_vectors([[0.0, 0.0, 1.0]], [a])
+        R[i] = rot.as_matrix()
+        assert np.allclose(R[i] @ a, [0, 0, 1], atol=1e-12)
+    E_T = np.zeros((n, 3, 3))
+    r = np.zeros((n, 3))
+    com = np.zeros((n, 3))
+    Ic = np.zeros((n, 6))
+    for i in range(n):
+        p = model.parent[i]
+        Rp = np.eye(3) if p < 0 else R[p]
+        E_T[i] = R[i] @ np.asarray(model.E_T[i], float) @ Rp.T
+        r[i] = Rp @ np.asarray(model.r[i], float)
+        com[i] = R[i] @ np.asarray(model.com[i], float)
+        c = np.asarray(model.Ic[i], float)
+        J = np.array([[c[0], c[3], c[4]], [c[3], c[1], c[5]], [c[4], c[5], c[2]]])
+        Jr = R[i] @ J @ R[i].T
+        Ic[i] = [Jr[0, 0], Jr[1, 1], Jr[2, 2], Jr[0, 1], Jr[0, 2], Jr[1, 2]]
+    return synth.RobotModel(model.name + "-z", model.parent.copy(), E_T, r,
+                            np.asarray(model.mass, float), com, Ic,
+                            np.asarray(model.gravity, float))
+
+
+@pytest.mark.parametrize("name", ["chain7-axes", "tree5-axes"])
+def test_joint_axes_are_a_change_of_body_coordinates(orc, name):
+    """Rotating every body frame so that its joint axis becomes z changes no joint-space
+    quantity: ID, M, dID and dFD agree between the two descriptions."""
+    model = ALL_MODELS[name]()
+    zmodel = _rotate_axes_to_z(model)
+    q, qd, tau = _knot(model, 21)
+    qdd = orc.fd(model, q, qd, tau)
+    np.testing.assert_allclose(orc.rnea(zmodel, q, qd, qdd), orc.rnea(model, q, qd, qdd),
+                               rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(orc.crba(zmodel, q), orc.crba(model, q), rtol=1e-11, atol=1e-12)
+    for got, want in zip(orc.rnea_grad(zmodel, q, qd, qdd), orc.rnea_grad(model, q, qd, qdd)):
+        np.testing.assert_allclose(got, want, rtol=1e-10, atol=1e-10)
+    for got, want in zip(orc.fd_grad(zmodel, q, qd, tau), orc.fd_grad(model, q, qd, tau)):
+        np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-9)
+
+
+def test_explicit_z_axes_equal_default(orc):
+    model = synth.chain7()
+    explicit = model.copy()
+    explicit.axis = np.tile([0.0, 0.0, 1.0], (7, 1))
+    q, qd, tau = _knot(model, 3)
+    for a, b in zip(orc.fd_grad(model, q, qd, tau), orc.fd_grad(explicit, q, qd, tau)):
+        np.testing.assert_array_equal(a, b)
 
 
 def test_planar_two_link_textbook(orc):
