@@ -212,6 +212,20 @@ grid_status grid_graph_update(grid_graph g, const grid_item* items, int32_t coun
 
 grid_status grid_graph_destroy(grid_graph g);
 
+/*
+ * Jacobians of the discrete-time dynamics of one semi-implicit Euler step of length dt,
+ * qd' = qd + dt qdd(q, qd, tau), q' = q + dt qd', the form trajectory optimisation uses
+ * (Sec. I: dFD feeds the optimiser's knot points). From the outputs of grid_fd_grad:
+ *   A[k] = d(q', qd')/d(q, qd) = [[1 + dt^2 Dq, dt 1 + dt^2 Dqd], [dt Dq, 1 + dt Dqd]]
+ *   B[k] = d(q', qd')/dtau     = [[dt^2 M^-1], [dt M^-1]]
+ * with Dq = dqdd/dq, Dqd = dqdd/dqd; A is [N][2n][2n] and B [N][2n][n], row-major, device
+ * pointers, asynchronous on `stream`. Errors: EINVAL (N < 0, dt not positive and finite,
+ * NULL pointers, 6 N n^2 >= 2^31), EDEVICE.
+ */
+grid_status grid_dt_jacobians(grid_model m, int32_t N, float dt, const float* dqdd_dq,
+                              const float* dqdd_dqd, const float* Minv, float* A, float* B,
+                              void* stream);
+
 /* ------------------------------------------------------------------ the other algorithms
  *
  * The paper's other rigid-body algorithms on the same batched layout (Sec. IV-B), one

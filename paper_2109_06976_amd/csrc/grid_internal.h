@@ -116,6 +116,8 @@ void set_error(const std::string& msg);
 
 hipError_t launch_vjp(int nknots, int n, const float* dq, const float* dqd, const float* Minv,
                       const float* g, float* qbar, float* qdbar, float* taubar, hipStream_t stream);
+hipError_t launch_dt(int nknots, int n, float dt, const float* dq, const float* dqd,
+                     const float* Minv, float* A, float* B, hipStream_t stream);
 
 }  // namespace grid_impl
 

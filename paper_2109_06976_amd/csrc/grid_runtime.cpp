@@ -537,6 +537,27 @@ grid_status grid_fd_vjp(grid_model m, int32_t N, const float* dqdd_dq, const flo
     return GRID_OK;
 }
 
+grid_status grid_dt_jacobians(grid_model m, int32_t N, float dt, const float* dqdd_dq,
+                              const float* dqdd_dqd, const float* Minv, float* A, float* B,
+                              void* stream)
+{
+    if (!m)
+        return fail(GRID_EINVAL, "model is NULL");
+    if (N < 0 || N > (1 << 30) / 64)
+        return fail(GRID_EINVAL, "N out of range");
+    if (!(dt > 0.0f) || !std::isfinite(dt))
+        return fail(GRID_EINVAL, "dt must be positive and finite");
+    if (N == 0)
+        return GRID_OK;
+    if ((long)N * 6L * m->topo.n * m->topo.n > (1L << 31) - 256)
+        return fail(GRID_EINVAL, "N too large for one launch");
+    if (!dqdd_dq || !dqdd_dqd || !Minv || !A || !B)
+        return fail(GRID_EINVAL, "a data pointer is NULL");
+    HIP_TRY(hipSetDevice(m->device));
+    HIP_TRY(launch_dt(N, m->topo.n, dt, dqdd_dq, dqdd_dqd, Minv, A, B, (hipStream_t)stream));
+    return GRID_OK;
+}
+
 grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspace* out)
 {
     if (!m || !out)

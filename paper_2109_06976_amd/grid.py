@@ -112,6 +112,9 @@ _SIGS = {
     "grid_minv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "grid_id_grad": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    "grid_dt_jacobians": (C.c_int32, [C.c_void_p, C.c_int32, C.c_float, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
     "grid_server_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(ServerConfig),
                                        C.POINTER(C.c_void_p)]),
     "grid_server_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 7 +
@@ -269,6 +272,16 @@ def fd_vjp(model, dqdd_dq, dqdd_dqd, Minv, gbar, qbar, qdbar, taubar, N=None, st
     _check(lib().grid_fd_vjp(model.handle, int(N), _addr(dqdd_dq), _addr(dqdd_dqd), _addr(Minv),
                              _addr(gbar), _addr(qbar), _addr(qdbar), _addr(taubar),
                              _stream_handle(stream)))
+
+
+def dt_jacobians(model, dt, dqdd_dq, dqdd_dqd, Minv, A, B, N=None, stream=None):
+    """grid_dt_jacobians: A = d(q', qd')/d(q, qd), B = d(q', qd')/dtau of one semi-implicit
+    Euler step from the dFD outputs (device buffers, asynchronous)."""
+    if N is None:
+        N = int(dqdd_dq.shape[0])
+    _check(lib().grid_dt_jacobians(model.handle, int(N), float(dt), _addr(dqdd_dq),
+                                   _addr(dqdd_dqd), _addr(Minv), _addr(A), _addr(B),
+                                   _stream_handle(stream)))
 
 
 class Workspace:

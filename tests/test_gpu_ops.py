@@ -113,3 +113,45 @@ def test_ops_reject_bad_arguments():
         m.minv(t, t, N=0)     # N = 0 is a no-op
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30", "tree5-axes"])
+def test_dt_jacobians_match_central_differences_of_the_oracle_step(orc, name):
+    # A, B of one semi-implicit Euler step from the GPU's dFD, against central differences
+    # of the step computed with the oracle's forward dynamics (FP64)
+    import torch
+    robot = ROBOTS[name]()
+    n = robot.n
+    N, dt, h = 5, 0.02, 1e-6
+    m = grid.Model(robot)
+    try:
+        kn = synth.random_knots(n, N, 901)
+        out = grid.fd_grad_torch(m, *(torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)))
+        A = torch.full((N, 2 * n, 2 * n), float("nan"), device="cuda")
+        B = torch.full((N, 2 * n, n), float("nan"), device="cuda")
+        say(f"[gpu] {name}: discrete-time Jacobians, N={N}, dt={dt}")
+        grid.dt_jacobians(m, dt, out["dqdd_dq"], out["dqdd_dqd"], out["Minv"], A, B)
+        torch.cuda.synchronize()
+        A, B = A.cpu().numpy().astype(np.float64), B.cpu().numpy().astype(np.float64)
+
+        def step(q, qd, tau):
+            qd1 = qd + dt * orc.fd(robot, q, qd, tau)
+            return np.concatenate([q + dt * qd1, qd1])
+
+        for k in range(N):
+            q, qd, tau = (a[k].astype(float) for a in (kn.q, kn.qd, kn.tau))
+            x = np.concatenate([q, qd])
+            Afd = np.stack([(step(*np.split(x + h * e, 2), tau) - step(*np.split(x - h * e, 2), tau))
+                            / (2 * h) for e in np.eye(2 * n)], axis=1)
+            Bfd = np.stack([(step(q, qd, tau + h * e) - step(q, qd, tau - h * e)) / (2 * h)
+                            for e in np.eye(n)], axis=1)
+            # the step's Jacobians are 1 + O(dt): compare their dynamic parts normwise
+            eA = np.abs(A[k] - Afd).max() / np.abs(Afd - np.eye(2 * n)).max()
+            eB = np.abs(B[k] - Bfd).max() / np.abs(Bfd).max()
+            assert eA <= 1e-3 and eB <= 1e-3, (name, k, eA, eB)
+        with pytest.raises(grid.GridError) as e:
+            grid.dt_jacobians(m, 0.0, out["dqdd_dq"], out["dqdd_dqd"], out["Minv"], A=None, B=None,
+                              N=N)
+        assert e.value.status == grid.GRID_EINVAL
+    finally:
+        m.close()
