@@ -251,6 +251,18 @@ grid_status grid_minv(grid_model m, int32_t N, const float* q, float* Minv, void
 grid_status grid_id_grad(grid_model m, int32_t N, const float* q, const float* qd,
                          const float* qdd, float* dtau_dq, float* dtau_dqd, void* stream);
 
+/* The vector-Jacobian product of forward dynamics without forming its Jacobians: from
+ * q, qd and the forward result qdd = FD(q, qd, tau), and a cotangent gbar [N][n],
+ *   taubar = M^-1 gbar,  qbar = -(dtau/dq)^T taubar,  qdbar = -(dtau/dqd)^T taubar
+ * (the same values as grid_fd_vjp, Sec. IV-B: dqdd/du = -M^-1 dRNEA/du). The transposed
+ * products come from one reverse sweep over RNEA, O(n) per knot instead of the n^2
+ * columns: with the virtual displacement u_i = X_i u_lambda + S_i taubar_i,
+ * taubar^T tau = sum_i u_i . f_i, differentiated backwards through the sweep. Writes
+ * [N][n] vectors qbar, qdbar, taubar. */
+grid_status grid_fd_vjp_adjoint(grid_model m, int32_t N, const float* q, const float* qd,
+                                const float* qdd, const float* gbar, float* qbar, float* qdbar,
+                                float* taubar, void* stream);
+
 /* ------------------------------------------------------------------ autotuning
  *
  * The fused kernel exists in up to five builds. Build 0 spreads each spatial vector over the

@@ -149,7 +149,7 @@ int64_t workgroups_serial(const Topology& t, int64_t nknots)
     return (int64_t)t.insts.size() * ((nknots + 63) / 64);
 }
 
-// standalone algorithms (ID, FD, M^-1, dID): problems per workgroup, as in grid_ops.hip
+// standalone algorithms (ID, FD, M^-1, dID, VJP): problems per workgroup, as in grid_ops.hip
 int64_t workgroups_op(const Topology& t, int64_t nknots, int op)
 {
     int64_t total = 0;
@@ -157,7 +157,7 @@ int64_t workgroups_op(const Topology& t, int64_t nknots, int op)
         const BranchShape& sh = t.shapes[inst.shape];
         const int P = op == kOpId ? 16
                       : op == kOpIdGrad ? (t.waves / sh.W) * (16 / sh.Q)
-                                        : pipe_problems(sh.B);
+                                        : pipe_problems(sh.B);   // FD, M^-1, VJP
         total += (nknots + P - 1) / P;
     }
     return total;

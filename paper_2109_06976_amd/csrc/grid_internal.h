@@ -28,7 +28,8 @@ constexpr int kOpId = 0;
 constexpr int kOpFd = 1;
 constexpr int kOpMinv = 2;
 constexpr int kOpIdGrad = 3;
-constexpr int kNumOps = 4;
+constexpr int kOpVjp = 4;
+constexpr int kNumOps = 5;
 
 // argument block of the standalone kernels; must match gridq::OpArgs in grid_ops.hip
 struct OpArgs {
@@ -36,8 +37,10 @@ struct OpArgs {
     const float* q;
     const float* qd;
     const float* u;
+    const float* u2;
     float* out0;
     float* out1;
+    float* out2;
 };
 
 // A branch hanging off the fixed base, in local numbering (parent before child).

@@ -383,7 +383,7 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     for (int k = 0; k < kNumVariants && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->fused_variant[k], m->module, kVariants[k]);
     static const char* const kOps[kNumOps] = {"grid_op_id", "grid_op_fd", "grid_op_minv",
-                                              "grid_op_idgrad"};
+                                              "grid_op_idgrad", "grid_op_vjp"};
     for (int k = 0; k < kNumOps && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->op[k], m->module, kOps[k]);
     for (int k = 0; k < 5 && e == hipSuccess; ++k)
@@ -442,7 +442,8 @@ grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* q
 }
 
 static grid_status launch_op(grid_model m, int op, int32_t N, const float* q, const float* qd,
-                             const float* u, float* out0, float* out1, void* stream)
+                             const float* u, float* out0, float* out1, void* stream,
+                             const float* u2 = nullptr, float* out2 = nullptr)
 {
     if (!m)
         return fail(GRID_EINVAL, "model is NULL");
@@ -452,8 +453,10 @@ static grid_status launch_op(grid_model m, int op, int32_t N, const float* q, co
         return GRID_OK;
     if (N > (1 << 30) / 64)
         return fail(GRID_EINVAL, "N too large");
-    const bool needs_qd = op != kOpMinv, needs_u = op != kOpMinv, needs_out1 = op == kOpIdGrad;
-    if (!q || (needs_qd && !qd) || (needs_u && !u) || !out0 || (needs_out1 && !out1))
+    const bool needs_qd = op != kOpMinv, needs_u = op != kOpMinv;
+    const bool needs_out1 = op == kOpIdGrad || op == kOpVjp, vjp = op == kOpVjp;
+    if (!q || (needs_qd && !qd) || (needs_u && !u) || !out0 || (needs_out1 && !out1) ||
+        (vjp && (!u2 || !out2)))
         return fail(GRID_EINVAL, "a data pointer is NULL");
     HIP_TRY(hipSetDevice(m->device));
     OpArgs a;
@@ -461,8 +464,10 @@ static grid_status launch_op(grid_model m, int op, int32_t N, const float* q, co
     a.q = q;
     a.qd = needs_qd ? qd : nullptr;
     a.u = needs_u ? u : nullptr;
+    a.u2 = vjp ? u2 : nullptr;
     a.out0 = out0;
     a.out1 = needs_out1 ? out1 : nullptr;
+    a.out2 = vjp ? out2 : nullptr;
     const unsigned blocks = (unsigned)workgroups_op(m->topo, N, op);
     const unsigned threads = op == kOpIdGrad ? 64u * (unsigned)m->topo.waves : 64u;
     void* params[] = {&a};
@@ -492,6 +497,13 @@ grid_status grid_id_grad(grid_model m, int32_t N, const float* q, const float* q
                          const float* qdd, float* dtau_dq, float* dtau_dqd, void* stream)
 {
     return launch_op(m, kOpIdGrad, N, q, qd, qdd, dtau_dq, dtau_dqd, stream);
+}
+
+grid_status grid_fd_vjp_adjoint(grid_model m, int32_t N, const float* q, const float* qd,
+                                const float* qdd, const float* gbar, float* qbar, float* qdbar,
+                                float* taubar, void* stream)
+{
+    return launch_op(m, kOpVjp, N, q, qd, qdd, qbar, qdbar, stream, gbar, taubar);
 }
 
 grid_status grid_fd_grad_staged(grid_model m, grid_workspace w, int32_t N, const float* q,

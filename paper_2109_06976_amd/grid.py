@@ -115,6 +115,9 @@ _SIGS = {
     "grid_dt_jacobians": (C.c_int32, [C.c_void_p, C.c_int32, C.c_float, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
+    "grid_fd_vjp_adjoint": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]),
     "grid_server_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(ServerConfig),
                                        C.POINTER(C.c_void_p)]),
     "grid_server_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 7 +
@@ -263,6 +266,15 @@ class Model:
         N = int(q.shape[0]) if N is None else N
         _check(lib().grid_id_grad(self._h, int(N), _addr(q), _addr(qd), _addr(qdd),
                                   _addr(dtau_dq), _addr(dtau_dqd), _stream_handle(stream)))
+
+
+def fd_vjp_adjoint(model, q, qd, qdd, gbar, qbar, qdbar, taubar, N=None, stream=None):
+    """grid_fd_vjp_adjoint: the VJP of FD by one reverse sweep (no Jacobians needed)."""
+    if N is None:
+        N = int(gbar.shape[0])
+    _check(lib().grid_fd_vjp_adjoint(model.handle, int(N), _addr(q), _addr(qd), _addr(qdd),
+                                     _addr(gbar), _addr(qbar), _addr(qdbar), _addr(taubar),
+                                     _stream_handle(stream)))
 
 
 def fd_vjp(model, dqdd_dq, dqdd_dqd, Minv, gbar, qbar, qdbar, taubar, N=None, stream=None):

@@ -3,7 +3,8 @@ staged pipeline, on an MI355X through the C ABI.
 
 Autograd workload: the 30-joint humanoid, N = 128 knots read as two trajectories of 64
 knot points whose (q, qd, tau) are independent leaves; L = sum_k ||qdd_k||^2. Gradients are
-compared with the FP64 oracle's VJP, normwise per knot, within 1e-3.
+compared with the FP64 oracle's VJP, normwise per knot, within 1e-3, for both backward modes
+(stored Jacobians; one reverse sweep over RNEA).
 """
 import sys
 
@@ -26,17 +27,20 @@ def normwise(y, ref):
     return d / np.abs(ref).reshape(N, -1).max(axis=1)
 
 
+@pytest.mark.parametrize("mode", ["jacobians", "adjoint"])
 @pytest.mark.parametrize("name,N,seed", [("humanoid30", 128, 104), ("chain7", 64, 17),
-                                         ("quad12", 40, 18)])
-def test_autograd_matches_oracle_vjp(orc, name, N, seed):
+                                         ("quad12", 40, 18), ("tree5-axes", 33, 19)])
+def test_autograd_matches_oracle_vjp(orc, name, N, seed, mode):
     import torch
     from paper_2109_06976_amd.autograd import forward_dynamics
-    robot = synth.model_by_name(name)
+    robot = (synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6, "tree5-axes",
+                                axes="random") if name == "tree5-axes"
+             else synth.model_by_name(name))
     model = grid.Model(robot)
-    say(f"[gpu] autograd {name} N={N}")
+    say(f"[gpu] autograd {name} N={N} mode={mode}")
     kn = synth.random_knots(robot.n, N, seed)
     q, qd, tau = (torch.from_numpy(a).cuda().requires_grad_(True) for a in (kn.q, kn.qd, kn.tau))
-    qdd = forward_dynamics(model, q, qd, tau)
+    qdd = forward_dynamics(model, q, qd, tau, mode=mode)
     loss = (qdd * qdd).sum()
     loss.backward()
     torch.cuda.synchronize()

@@ -155,3 +155,31 @@ def test_dt_jacobians_match_central_differences_of_the_oracle_step(orc, name):
         assert e.value.status == grid.GRID_EINVAL
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("name", list(ROBOTS))
+def test_vjp_adjoint_matches_oracle(orc, name):
+    # the reverse-sweep VJP from (q, qd, qdd) against the oracle's dense dFD products
+    import torch
+    robot = ROBOTS[name]()
+    n, N = robot.n, 37
+    m = grid.Model(robot)
+    try:
+        kn = synth.random_knots(n, N, 950)
+        gbar = np.random.default_rng(951).standard_normal((N, n)).astype(np.float32)
+        ref = orc.fd_grad_batch(robot, kn.q, kn.qd, kn.tau)
+        q, qd, qdd, g = (torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+                         for a in (kn.q, kn.qd, ref["qdd"], gbar))
+        outs = [torch.full((N, n), float("nan"), device="cuda") for _ in range(3)]
+        say(f"[gpu] {name}: adjoint VJP, N={N}")
+        grid.fd_vjp_adjoint(m, q, qd, qdd, g, *outs)
+        torch.cuda.synchronize()
+        want = {"q": np.einsum("kij,ki->kj", ref["dqdd_dq"], gbar),
+                "qd": np.einsum("kij,ki->kj", ref["dqdd_dqd"], gbar),
+                "tau": np.einsum("kij,ki->kj", ref["Minv"], gbar)}
+        for k, got in zip(("q", "qd", "tau"), outs):
+            e = normwise(got.cpu().numpy(), want[k]).max()
+            say(f"  {k}bar {e:.1e}")
+            assert e <= 1e-3, (name, k, e)
+    finally:
+        m.close()
