@@ -17,6 +17,8 @@ Also reported (extra fields of the same line):
   served        p50/p99 latency and throughput of an open-loop Poisson request stream
                 (20k req/s over the three robots) through the continuous-batching
                 server, and through one plain staged launch per request;
+  autograd      the humanoid autograd workload (forward + backward per step) with the
+                stored-Jacobian and the reverse-sweep backward;
   single_knot_us  one knot (N = 1) of ID, M^-1, FD, dID and dFD on each robot, as the
                 paper's single-computation table, with the paper's GPU numbers as context;
   cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
@@ -144,6 +146,31 @@ def single_knot_table(torch, grid, synth, steps):
                        for op, f in ops.items()}
         m.close()
     return table
+
+
+def autograd_steps(torch, grid, synth, steps):
+    """The autograd workload (humanoid, N = 128 knots as two 64-knot trajectories,
+    L = sum of squared qdd): time per forward + backward step, for the stored-Jacobian and
+    the reverse-sweep backward."""
+    from paper_2109_06976_amd.autograd import forward_dynamics
+    dev = torch.device("cuda:0")
+    robot = synth.humanoid30()
+    m = grid.Model(robot)
+    kn = synth.random_knots(robot.n, 128, 104)
+    leaves = [torch.from_numpy(a).to(dev).requires_grad_(True) for a in (kn.q, kn.qd, kn.tau)]
+    out = {}
+    for mode in ("jacobians", "adjoint"):
+        def step():
+            for x in leaves:
+                x.grad = None
+            qdd = forward_dynamics(m, *leaves, mode=mode)
+            (qdd * qdd).sum().backward()
+        wall, _ = time_steps(torch, step, steps, 20)
+        out[mode] = {"us_per_step": round(wall * 1e6, 2),
+                     "knot_evals_per_s": round(128 / wall, 1)}
+    m.close()
+    return {"workload": "humanoid30, N=128 (2 x 64 knots), L = sum |qdd|^2, forward + backward",
+            **out}
 
 
 def serve(args, grid, synth, chain_model=None):
@@ -315,6 +342,7 @@ def main():
         result["sweep"] = sweep
 
     if not args.no_single:
+        result["autograd"] = autograd_steps(torch, grid, synth, 300)
         result["single_knot_us"] = single_knot_table(torch, grid, synth, 1000)
         result["single_knot_us"]["paper_table1_gpu_us"] = PAPER_TABLE1_GPU_US
 
