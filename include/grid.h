@@ -59,11 +59,23 @@ typedef int32_t grid_status;
 #define GRID_ECANCELED (-8)     /* the server was destroyed before the request ran */
 
 #define GRID_JOINT_REVOLUTE 0
+#define GRID_JOINT_PRISMATIC 1   /* rejected with GRID_EUNSUPPORTED */
+#define GRID_JOINT_FIXED 2
 
+/*
+ * A fixed joint welds its body to the parent. The library merges every such body into its
+ * nearest ancestor with a revolute joint (its inertia re-expressed there; dropped if welded
+ * to the base) and attaches the children to that ancestor through the composed transform
+ * (a fixed joint's transform is X_T alone). All arrays of every call then hold the
+ * revolute joints only, in increasing body order: n_dof of them (grid_model_info reports
+ * n_dof); at least one joint must be revolute.
+ */
 typedef struct grid_model_desc {
-    int32_t n;                   /* number of joints/bodies, 1..32 */
+    int32_t n;                   /* number of bodies, 1..32 (and of revolute joints, when
+                                    joint_type is NULL) */
     const int32_t* parent;       /* [n], -1 <= parent[i] < i */
-    const int32_t* joint_type;   /* [n] GRID_JOINT_REVOLUTE, or NULL for all revolute */
+    const int32_t* joint_type;   /* [n] GRID_JOINT_REVOLUTE or GRID_JOINT_FIXED; NULL for all
+                                    revolute */
     const double* axis;          /* [n][3] unit joint axis in the joint frame (norm within
                                     1e-6 of 1, normalised); NULL = +z for every joint */
     const double* tree_rot;      /* [n][3][3] E_T, row-major, parent frame -> joint frame */
@@ -107,9 +119,9 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
  * model that still has launches in flight. */
 grid_status grid_model_destroy(grid_model m);
 
-/* n, bytes moved per knot by the host-pointer call (inputs + outputs), and the number
- * of wavefront lanes one knot occupies (summed over its base branches). Any pointer
- * may be NULL. */
+/* n (the revolute joints the arrays hold), bytes moved per knot by the host-pointer call
+ * (inputs + outputs), and the number of wavefront lanes one knot occupies (summed over its
+ * base branches). Any pointer may be NULL. */
 grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
                             int32_t* lanes);
 

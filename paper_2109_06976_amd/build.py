@@ -75,6 +75,12 @@ def standard_models():
     # joints about random axes
     models.append(synth.random_model(synth.chain_parent(7), 0, axes="random"))
     models.append(synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6, axes="random"))
+    # fixed joints
+    models.append(synth.with_fixed_joints(synth.chain7(), [2, 5]))
+    models.append(synth.with_fixed_joints(
+        synth.random_model(np.array([-1, 0, 0, 1, 3, -1, 5], np.int32), 77), [1, 3, 6]))
+    models.append(synth.with_fixed_joints(
+        synth.random_model(synth.chain_parent(7), 0, axes="random"), [0, 4]))
     return models
 
 

@@ -39,8 +39,16 @@ grid_status validate_desc(const grid_model_desc* d, std::string* err)
         return fail_to(err, GRID_EINVAL, "a required model array is NULL");
     const int n = d->n;
     for (int i = 0; i < n; ++i) {
-        if (d->joint_type && d->joint_type[i] != GRID_JOINT_REVOLUTE)
-            return fail_to(err, GRID_EUNSUPPORTED, "only revolute joints are supported");
+        if (d->parent[i] < -1 || d->parent[i] >= i)
+            return fail_to(err, GRID_EINVAL, "parent[" + std::to_string(i) + "] = " +
+                                                 std::to_string(d->parent[i]) +
+                                                 " must satisfy -1 <= parent[i] < i");
+        if (d->joint_type && d->joint_type[i] == GRID_JOINT_PRISMATIC)
+            return fail_to(err, GRID_EUNSUPPORTED, "prismatic joints are not supported");
+        if (d->joint_type && d->joint_type[i] != GRID_JOINT_REVOLUTE &&
+            d->joint_type[i] != GRID_JOINT_FIXED)
+            return fail_to(err, GRID_EINVAL, "joint_type[" + std::to_string(i) +
+                                                 "] is not a joint type");
         if (d->axis) {
             const double* a = d->axis + 3 * i;
             const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
@@ -290,6 +298,127 @@ const char* grid_status_string(grid_status s)
 const char* grid_last_error(void) { return t_last_error.c_str(); }
 
 // validated description -> topology, packed constants and generated source
+// The model without its fixed joints: every body on a fixed joint merges into its nearest
+// ancestor on a revolute joint (its owner; -1 when the chain of fixed joints reaches the
+// base). Transforms are (E, r) with x_child = E (x_parent - r); the owner-to-body transform
+// of a fixed body composes (E2, r2) after (E1, r1) as (E2 E1, r1 + E1^T r2). Inertias are
+// summed about the owner's origin: mass, first moment and the rotational inertia there.
+struct ReducedDesc {
+    std::vector<int32_t> parent;
+    std::vector<double> axis, rot, pos, mass, com, inertia;
+    grid_model_desc d{};
+};
+
+static void reduce_fixed(const grid_model_desc* src, ReducedDesc* out)
+{
+    const int n = src->n;
+    std::vector<int> owner(n, -1), newidx(n, -1);
+    std::vector<double> Eo((size_t)9 * n), ro((size_t)3 * n);   // owner frame -> body frame
+    std::vector<double> M, H, IO;                                 // per revolute body: m, m c, I_O
+    int nd = 0;
+    for (int i = 0; i < n; ++i) {
+        const int p = src->parent[i];
+        const double* ET = src->tree_rot + 9 * i;
+        const double* rT = src->tree_pos + 3 * i;
+        // owner frame -> this joint's frame (the parent's chain composed with X_T)
+        double E[9], r[3];
+        const int po = p < 0 ? -1 : owner[p];
+        if (p < 0) {
+            std::memcpy(E, ET, sizeof E);
+            std::memcpy(r, rT, sizeof r);
+        } else {
+            const double* E1 = Eo.data() + 9 * p;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 3; ++k)
+                        acc += ET[3 * a + k] * E1[3 * k + b];
+                    E[3 * a + b] = acc;
+                }
+            for (int a = 0; a < 3; ++a)
+                r[a] = ro[3 * p + a] + E1[a] * rT[0] + E1[3 + a] * rT[1] + E1[6 + a] * rT[2];
+        }
+        const bool fixed = src->joint_type && src->joint_type[i] == GRID_JOINT_FIXED;
+        const double m = src->mass[i];
+        const double* c = src->com + 3 * i;
+        const double* J = src->inertia_com + 6 * i;
+        const double Jm[9] = {J[0], J[3], J[4], J[3], J[1], J[5], J[4], J[5], J[2]};
+        if (!fixed) {
+            owner[i] = i;
+            newidx[i] = nd++;
+            out->parent.push_back(po < 0 ? -1 : newidx[po]);
+            out->rot.insert(out->rot.end(), E, E + 9);
+            out->pos.insert(out->pos.end(), r, r + 3);
+            for (int k = 0; k < 3; ++k)
+                out->axis.push_back(src->axis ? src->axis[3 * i + k] : (k == 2 ? 1.0 : 0.0));
+            for (int k = 0; k < 9; ++k)
+                Eo[9 * i + k] = (k % 4 == 0) ? 1.0 : 0.0;
+            for (int k = 0; k < 3; ++k)
+                ro[3 * i + k] = 0.0;
+            // the body's own inertia about its origin
+            M.push_back(m);
+            for (int k = 0; k < 3; ++k)
+                H.push_back(m * c[k]);
+            const double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    IO.push_back(Jm[3 * a + b] + m * ((a == b ? cc : 0.0) - c[a] * c[b]));
+        } else {
+            owner[i] = po;
+            std::memcpy(Eo.data() + 9 * i, E, sizeof E);
+            std::memcpy(ro.data() + 3 * i, r, sizeof r);
+            if (po >= 0) {
+                // this body in the owner's frame: centre r + E^T c, inertia E^T J E there
+                const int o = newidx[po];
+                double co[3], Jo[9];
+                for (int a = 0; a < 3; ++a)
+                    co[a] = r[a] + E[a] * c[0] + E[3 + a] * c[1] + E[6 + a] * c[2];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double acc = 0.0;
+                        for (int k = 0; k < 3; ++k)
+                            for (int l = 0; l < 3; ++l)
+                                acc += E[3 * k + a] * Jm[3 * k + l] * E[3 * l + b];
+                        Jo[3 * a + b] = acc;
+                    }
+                const double cc = co[0] * co[0] + co[1] * co[1] + co[2] * co[2];
+                M[o] += m;
+                for (int k = 0; k < 3; ++k)
+                    H[3 * o + k] += m * co[k];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        IO[9 * o + 3 * a + b] += Jo[3 * a + b] + m * ((a == b ? cc : 0.0) - co[a] * co[b]);
+            }
+        }
+    }
+    for (int o = 0; o < nd; ++o) {
+        const double m = M[o];
+        double c[3];
+        for (int k = 0; k < 3; ++k)
+            c[k] = H[3 * o + k] / m;
+        const double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        double Jc[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                Jc[3 * a + b] = IO[9 * o + 3 * a + b] - m * ((a == b ? cc : 0.0) - c[a] * c[b]);
+        out->mass.push_back(m);
+        out->com.insert(out->com.end(), c, c + 3);
+        const double J6[6] = {Jc[0], Jc[4], Jc[8], Jc[1], Jc[2], Jc[5]};
+        out->inertia.insert(out->inertia.end(), J6, J6 + 6);
+    }
+    grid_model_desc& d = out->d;
+    d.n = nd;
+    d.parent = out->parent.data();
+    d.joint_type = nullptr;
+    d.axis = src->axis ? out->axis.data() : nullptr;
+    d.tree_rot = out->rot.data();
+    d.tree_pos = out->pos.data();
+    d.mass = out->mass.data();
+    d.com = out->com.data();
+    d.inertia_com = out->inertia.data();
+    std::memcpy(d.gravity, src->gravity, sizeof d.gravity);
+}
+
 static grid_status prepare(const grid_model_desc* desc, uint32_t flags, Topology* topo,
                            std::string* src)
 {
@@ -299,9 +428,13 @@ static grid_status prepare(const grid_model_desc* desc, uint32_t flags, Topology
         return fail(s, err);
     if (flags != 0)
         return fail(GRID_EINVAL, "unknown flag bits");
-    if (!analyse_topology(desc->parent, desc->n, topo, &err))
+    ReducedDesc red;
+    reduce_fixed(desc, &red);
+    if (red.d.n < 1)
+        return fail(GRID_EINVAL, "the model has no revolute joint");
+    if (!analyse_topology(red.d.parent, red.d.n, topo, &err))
         return fail(GRID_EINVAL, err);
-    *src = generate_source(*topo, pack_constants(desc, *topo), desc->gravity, flags);
+    *src = generate_source(*topo, pack_constants(&red.d, *topo), red.d.gravity, flags);
     return GRID_OK;
 }
 

@@ -197,7 +197,10 @@ class _Desc:
         ax = getattr(robot, "axis", None)
         self.axis = None if ax is None else np.ascontiguousarray(
             np.asarray(ax, dtype=np.float64).reshape(n, 3))
-        self.c = GridDesc(n, self.parent.ctypes.data_as(_i32p), None,
+        jt = getattr(robot, "joint_type", None)
+        self.joint_type = None if jt is None else np.ascontiguousarray(jt, dtype=np.int32)
+        self.c = GridDesc(n, self.parent.ctypes.data_as(_i32p),
+                          None if self.joint_type is None else self.joint_type.ctypes.data_as(_i32p),
                           None if self.axis is None else p(self.axis), p(E_T), p(r),
                           p(mass), p(com), p(Ic), (C.c_double * 3)(*g))
 
@@ -410,6 +413,7 @@ def tune_apply(model, table):
 
 
 BUILD_QUAD, BUILD_LANE, BUILD_LANE_W2, BUILD_LANE_W4, BUILD_PIPE, BUILD_SERIAL = range(6)
+JOINT_REVOLUTE, JOINT_PRISMATIC, JOINT_FIXED = 0, 1, 2
 BUILD_KERNELS = ("grid_fdgrad_quad", "grid_fdgrad_fused", "grid_fdgrad_fused_w2",
                  "grid_fdgrad_fused_w4", "grid_fdgrad_pipe", "grid_fdgrad_serial")
 

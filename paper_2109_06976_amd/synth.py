@@ -52,6 +52,7 @@ class RobotModel:
     gravity: np.ndarray = field(default_factory=lambda: np.array(GRAVITY))
     base_mass: float | None = None   # mass of a fixed base link (cannot affect outputs)
     axis: np.ndarray | None = None   # float64 [n, 3] unit joint axes (None: every joint +z)
+    joint_type: np.ndarray | None = None   # int32 [n]: 0 revolute, 2 fixed (None: all revolute)
 
     @property
     def n(self) -> int:
@@ -61,7 +62,8 @@ class RobotModel:
         return RobotModel(self.name, self.parent.copy(), self.E_T.copy(), self.r.copy(),
                           self.mass.copy(), self.com.copy(), self.Ic.copy(),
                           self.gravity.copy(), self.base_mass,
-                          None if self.axis is None else self.axis.copy())
+                          None if self.axis is None else self.axis.copy(),
+                          None if self.joint_type is None else self.joint_type.copy())
 
 
 # ---------------------------------------------------------------- topologies
@@ -173,6 +175,16 @@ def quad12(seed: int = SEED_QUAD12) -> RobotModel:
 
 def humanoid30(seed: int = SEED_HUMANOID30, variant: str = "anatomical") -> RobotModel:
     return random_model(humanoid_parent(variant), seed, f"humanoid30-{variant}")
+
+
+def with_fixed_joints(model: RobotModel, fixed) -> RobotModel:
+    """The same bodies with the listed joints fixed (welded to their parents)."""
+    m = model.copy()
+    jt = np.zeros(m.n, np.int32)
+    jt[list(fixed)] = 2
+    m.joint_type = jt
+    m.name = f"{model.name}-fixed{''.join(str(i) for i in fixed)}"
+    return m
 
 
 def model_by_name(name: str) -> RobotModel:
