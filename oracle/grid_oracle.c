@@ -47,6 +47,8 @@ static int check_model(const orc_model *m)
             if (!(fabs(nrm - 1.0) < 1e-6))
                 return -1;
         }
+        if (m->prismatic && m->prismatic[i] != 0 && m->prismatic[i] != 1)
+            return -1;
     }
     return 0;
 }

