@@ -10,14 +10,18 @@
  * Conventions shared by every call
  *   - Bodies are numbered 0..n-1 with parent[i] < i; parent -1 is the fixed base
  *     (Sec. III-B). Outputs use the caller's numbering.
- *   - Every joint is revolute about a unit axis a_i of its joint frame (S_i = (a_i, 0);
- *     +z unless `axis` is given); the joint transform is iX_lambda(q_i) =
- *     rot(E_a(q_i)) * X_T,i with E_a the coordinate rotation by q_i about a_i and X_T,i
- *     given by tree_rot (rotation from the parent frame to the joint frame) and tree_pos
- *     (the joint origin in parent coordinates) (Sec. III-B). The library rotates every
- *     body frame so that its joint axis becomes z before generating the kernel (a change
- *     of body coordinates that leaves every joint-space quantity unchanged).
- *   - Spatial vectors are ordered [angular; linear] (Eq. 2). SI units, radians.
+ *   - Joints move along a unit axis a_i of their joint frame (+z unless `axis` is given):
+ *     a revolute joint rotates about it (S_i = (a_i, 0), q_i in radians), a prismatic joint
+ *     slides along it (S_i = (0, a_i), q_i in metres), and a fixed joint does not move
+ *     (GRiD's three joint types, Sec. IV). The joint transform is iX_lambda(q_i) =
+ *     X_J(q_i) * X_T,i with X_J the coordinate rotation by q_i about a_i (revolute) or
+ *     the translation by q_i a_i (prismatic), and X_T,i given by tree_rot (rotation from
+ *     the parent frame to the joint frame) and tree_pos (the joint origin in parent
+ *     coordinates) (Sec. III-B). The library rotates every body frame so that its joint
+ *     axis becomes z before generating the kernel (a change of body coordinates that
+ *     leaves every joint-space quantity unchanged).
+ *   - Spatial vectors are ordered [angular; linear] (Eq. 2). SI units: radians for revolute
+ *     joints, metres for prismatic ones (and N m or N for tau).
  *   - Fixed base, fully actuated (B = I in Eq. 1), no external forces (F = 0).
  *   - Batched arrays are knot-major and row-major float32:
  *       q, qd, tau, qdd       [N][n]
@@ -59,23 +63,23 @@ typedef int32_t grid_status;
 #define GRID_ECANCELED (-8)     /* the server was destroyed before the request ran */
 
 #define GRID_JOINT_REVOLUTE 0
-#define GRID_JOINT_PRISMATIC 1   /* rejected with GRID_EUNSUPPORTED */
+#define GRID_JOINT_PRISMATIC 1
 #define GRID_JOINT_FIXED 2
 
 /*
  * A fixed joint welds its body to the parent. The library merges every such body into its
- * nearest ancestor with a revolute joint (its inertia re-expressed there; dropped if welded
- * to the base) and attaches the children to that ancestor through the composed transform
- * (a fixed joint's transform is X_T alone). All arrays of every call then hold the
- * revolute joints only, in increasing body order: n_dof of them (grid_model_info reports
- * n_dof); at least one joint must be revolute.
+ * nearest ancestor with a movable (revolute or prismatic) joint (its inertia re-expressed
+ * there; dropped if welded to the base) and attaches the children to that ancestor through
+ * the composed transform (a fixed joint's transform is X_T alone). All arrays of every call
+ * then hold the movable joints only, in increasing body order: n_dof of them
+ * (grid_model_info reports n_dof); at least one joint must be movable.
  */
 typedef struct grid_model_desc {
-    int32_t n;                   /* number of bodies, 1..32 (and of revolute joints, when
+    int32_t n;                   /* number of bodies, 1..32 (and of movable joints, when
                                     joint_type is NULL) */
     const int32_t* parent;       /* [n], -1 <= parent[i] < i */
-    const int32_t* joint_type;   /* [n] GRID_JOINT_REVOLUTE or GRID_JOINT_FIXED; NULL for all
-                                    revolute */
+    const int32_t* joint_type;   /* [n] GRID_JOINT_REVOLUTE, GRID_JOINT_PRISMATIC or
+                                    GRID_JOINT_FIXED; NULL for all revolute */
     const double* axis;          /* [n][3] unit joint axis in the joint frame (norm within
                                     1e-6 of 1, normalised); NULL = +z for every joint */
     const double* tree_rot;      /* [n][3][3] E_T, row-major, parent frame -> joint frame */
@@ -110,7 +114,7 @@ const char* grid_last_error(void);
  * loads it on the device.
  * flags: reserved, must be 0. On success *out owns the loaded code object until
  * grid_model_destroy. Errors: EINVAL (bad description, an axis not of unit length),
- * EUNSUPPORTED (non-revolute joint, n > 32), ECOMPILE, EDEVICE, ENOMEM.
+ * EUNSUPPORTED (n > 32), ECOMPILE, EDEVICE, ENOMEM.
  */
 grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint32_t flags,
                               grid_model* out);
@@ -119,7 +123,7 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
  * model that still has launches in flight. */
 grid_status grid_model_destroy(grid_model m);
 
-/* n (the revolute joints the arrays hold), bytes moved per knot by the host-pointer call
+/* n (the movable joints the arrays hold), bytes moved per knot by the host-pointer call
  * (inputs + outputs), and the number of wavefront lanes one knot occupies (summed over its
  * base branches). Any pointer may be NULL. */
 grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,

@@ -81,7 +81,26 @@ def standard_models():
         synth.random_model(np.array([-1, 0, 0, 1, 3, -1, 5], np.int32), 77), [1, 3, 6]))
     models.append(synth.with_fixed_joints(
         synth.random_model(synth.chain_parent(7), 0, axes="random"), [0, 4]))
+    # prismatic joints (with revolute ones; random axes; on a branch beyond 16 bodies;
+    # with fixed joints, one welded to a prismatic owner)
+    models.extend(prismatic_models().values())
     return models
+
+
+def prismatic_models():
+    """The robots with prismatic joints that the tests run, by name."""
+    import numpy as np
+    from paper_2109_06976_amd import synth
+    tree5 = synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6, "tree5-axes",
+                               axes="random")
+    tree7 = synth.random_model(np.array([-1, 0, 0, 1, 3, -1, 5], np.int32), 77, "tree7")
+    return {
+        "chain7-prism": synth.with_prismatic_joints(synth.chain7(), [1, 4]),
+        "tree5-axes-prism": synth.with_prismatic_joints(tree5, [0, 3, 4]),
+        "humanoid30-prism": synth.with_prismatic_joints(synth.humanoid30(), [1, 9, 20, 29]),
+        "tree7-fixed-prism": synth.with_prismatic_joints(
+            synth.with_fixed_joints(tree7, [1, 3, 6]), [0, 4]),
+    }
 
 
 def offline_compile_check(verbose=False):

@@ -269,6 +269,7 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
         emit_list(os, in.body);
         os << ";\n    static constexpr int loff = " << ws.loff[k] << ";\n";
         os << "    static constexpr unsigned long long mask = " << in.mask << "ull;\n";
+        os << "    static constexpr unsigned long long prism = " << in.prism << "ull;\n";
         os << "    __device__ static int body_of(int i) {\n"
               "        int r = body[0];\n"
               "#pragma unroll\n"

@@ -22,7 +22,8 @@
 // they own. The single exchange is the mass matrix, passed through LDS once.
 //
 // Per (knot, branch), all float32 (Sec. IV-B):
-//   1. X_i = (E_i, r_i), E_i = E_z(q_i) E_T,i
+//   1. X_i = (E_i, r_i): E_i = E_z(q_i) E_T,i for a revolute joint; E_i = E_T,i and
+//      r_i = r_T,i + q_i E_T,i^T e_z for a prismatic joint
 //   2. RNEA(q, qd, 0): v_i, a_i, f_i outward, accumulated f inward; c_i = S^T f_i
 //   3. column t of M as ID(q, 0, e_t) without gravity (one column per lane), LDS exchange
 //   4. M = L^T L, sparse factorization along ancestor paths (no fill-in on a tree)
@@ -33,7 +34,8 @@
 //   7. dRNEA forward (Algorithm 1) and backward pass for the lane's column (u, j)
 //   8. dqdd/du_j = -M^-1 dtau/du_j and column t of M^-1 by the same solves; stores
 //
-// Spatial vectors are [angular; linear]; S = e_3 (revolute about the joint z axis).
+// Spatial vectors are [angular; linear]; S = e_3 for a joint revolute about its z axis and
+// S = e_6 for one prismatic along it (Inst::prism marks the prismatic bodies).
 
 #ifndef GRID_N
 #error "GRID_N must be defined by the generated prelude"
@@ -116,14 +118,38 @@ __device__ __forceinline__ void crf_mv(const float* v, const float* f, float* y)
     y[5] = v[0] * f[4] - v[1] * f[3];
 }
 
-// (m x) S for S = e_3
-__device__ __forceinline__ void cross_S(const float* m, float* y)
+// joint i of branch I is prismatic (S = e_6) rather than revolute (S = e_3)
+template <class I>
+__device__ __forceinline__ constexpr bool prismatic(int i)
 {
-    y[0] = m[1];
-    y[1] = -m[0];
+    return (I::prism >> i) & 1ull;
+}
+
+// the component S selects: angular z (revolute) or linear z (prismatic)
+__device__ __forceinline__ constexpr int s_index(bool pr)
+{
+    return pr ? 5 : 2;
+}
+
+// (m x) S: (m_1, -m_0, 0, m_4, -m_3, 0) for S = e_3, (0, 0, 0, m_1, -m_0, 0) for S = e_6
+__device__ __forceinline__ void cross_S(bool pr, const float* m, float* y)
+{
+    y[0] = pr ? 0.0f : m[1];
+    y[1] = pr ? 0.0f : -m[0];
     y[2] = 0.0f;
-    y[3] = m[4];
-    y[4] = -m[3];
+    y[3] = pr ? m[1] : m[4];
+    y[4] = pr ? -m[0] : -m[3];
+    y[5] = 0.0f;
+}
+
+// S x* f: (-f_1, f_0, 0, -f_4, f_3, 0) for S = e_3, (-f_4, f_3, 0, 0, 0, 0) for S = e_6
+__device__ __forceinline__ void s_crf(bool pr, const float* f, float* y)
+{
+    y[0] = pr ? -f[4] : -f[1];
+    y[1] = pr ? f[3] : f[0];
+    y[2] = 0.0f;
+    y[3] = pr ? 0.0f : -f[4];
+    y[4] = pr ? 0.0f : f[3];
     y[5] = 0.0f;
 }
 
@@ -200,23 +226,35 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
     const long mbase = (long)knot * N * N;
 
     // ------------------------------------------------------------ 1. transforms
-    float qd[B], tau[B], E[B][9];
+    float qd[B], tau[B], E[B][9], R[B][3];
     if constexpr (kNeedsX) {
 #pragma unroll
         for (int i = 0; i < B; ++i) {
             const long o = vbase + I::body[i];
             const float* c = C + i * kConstStride;
-            // sin and cos by the hardware units (angle in revolutions, reduced to [0, 1))
-            const float rev = __builtin_amdgcn_fractf(A.q[o] * 0.159154943091895336f);
-            const float s = __builtin_amdgcn_sinf(rev);
-            const float co = __builtin_amdgcn_cosf(rev);
+            const float qi = A.q[o];
             qd[i] = A.qd[o];
             tau[i] = A.tau[o];
+            if (prismatic<I>(i)) {
+                // translation along the joint z axis: E = E_T, r = r_T + q E_T^T e_z
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    E[i][k] = c[k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    R[i][k] = c[9 + k] + qi * c[6 + k];
+                continue;
+            }
+            // sin and cos by the hardware units (angle in revolutions, reduced to [0, 1))
+            const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
+            const float s = __builtin_amdgcn_sinf(rev);
+            const float co = __builtin_amdgcn_cosf(rev);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 E[i][k] = co * c[k] + s * c[3 + k];
                 E[i][3 + k] = co * c[3 + k] - s * c[k];
                 E[i][6 + k] = c[6 + k];
+                R[i][k] = c[9 + k];
             }
         }
     }
@@ -241,10 +279,10 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
             const int p = S::parent[i];
             const float* c = C + i * kConstStride;
             float xv[6], xa[6], vxs[6], Ia[6], w[6];
-            x_mv(E[i], c + 9, p < 0 ? zero6 : v[p < 0 ? 0 : p], xv);
-            x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa);
-            xv[2] += qd[i];
-            cross_S(xv, vxs);
+            x_mv(E[i], R[i], p < 0 ? zero6 : v[p < 0 ? 0 : p], xv);
+            x_mv(E[i], R[i], p < 0 ? a0 : a[p < 0 ? 0 : p], xa);
+            xv[s_index(prismatic<I>(i))] += qd[i];
+            cross_S(prismatic<I>(i), xv, vxs);
             const bool mine = i == j;
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
@@ -265,7 +303,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
             const int p = S::parent[i];
             if (p >= 0) {
                 float y[6];
-                xt_fv(E[i], C + i * kConstStride + 9, F[i], y);
+                xt_fv(E[i], R[i], F[i], y);
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
                     F[p][k] += y[k];
@@ -273,13 +311,13 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
         }
 #pragma unroll
         for (int i = 0; i < B; ++i)
-            x[i] = tau[i] - F[i][2];              // tau - c
+            x[i] = tau[i] - F[i][s_index(prismatic<I>(i))];   // tau - c
         if constexpr (ST == kStageRnea) {
             if (valid && t < B) {
 #pragma unroll
                 for (int i = 0; i < B; ++i)
                     if (t == i)
-                        W[GRID_WS_C + I::body[i]] = F[i][2];
+                        W[GRID_WS_C + I::body[i]] = F[i][s_index(prismatic<I>(i))];
             }
             return;
         }
@@ -296,12 +334,12 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
                 const int p = S::parent[i];
                 const float* c = C + i * kConstStride;
                 if (p >= 0)
-                    x_mv(E[i], c + 9, am[p < 0 ? 0 : p], am[i]);
+                    x_mv(E[i], R[i], am[p < 0 ? 0 : p], am[i]);
                 else
 #pragma unroll
                     for (int k = 0; k < 6; ++k)
                         am[i][k] = 0.0f;
-                am[i][2] += (i == jm) ? 1.0f : 0.0f;
+                am[i][s_index(prismatic<I>(i))] += (i == jm) ? 1.0f : 0.0f;
                 inertia_mv(c, am[i], fm[i]);
             }
 #pragma unroll
@@ -309,7 +347,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
                 const int p = S::parent[i];
                 if (p >= 0) {
                     float y[6];
-                    xt_fv(E[i], C + i * kConstStride + 9, fm[i], y);
+                    xt_fv(E[i], R[i], fm[i], y);
 #pragma unroll
                     for (int k = 0; k < 6; ++k)
                         fm[p][k] += y[k];
@@ -318,7 +356,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
             if (t < B) {
 #pragma unroll
                 for (int i = 0; i < B; ++i)
-                    s_M[g][i][t] = fm[i][2];
+                    s_M[g][i][t] = fm[i][s_index(prismatic<I>(i))];
             }
         }
         wave_sync();
@@ -438,7 +476,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
                 const float* c = C + i * kConstStride;
                 float xd[6];
                 if (p >= 0)
-                    x_mv(E[i], c + 9, Da[p < 0 ? 0 : p], xd);
+                    x_mv(E[i], R[i], Da[p < 0 ? 0 : p], xd);
                 else
 #pragma unroll
                     for (int k = 0; k < 6; ++k)
@@ -449,7 +487,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
                     Da[i][k] = xd[k];
                     ab[k] = mine ? ab[k] + xd[k] : ab[k];      // X_j a_lambda(j) at qdd
                 }
-                Da[i][2] += x[i];
+                Da[i][s_index(prismatic<I>(i))] += x[i];
                 inertia_mv(c, Da[i], Df[i]);
             }
 #pragma unroll
@@ -457,7 +495,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
                 const int p = S::parent[i];
                 if (p >= 0) {
                     float y[6];
-                    xt_fv(E[i], C + i * kConstStride + 9, Df[i], y);
+                    xt_fv(E[i], R[i], Df[i], y);
 #pragma unroll
                     for (int k = 0; k < 6; ++k)
                         Df[p][k] += y[k];
@@ -475,7 +513,6 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
 #pragma unroll
             for (int i = 0; i < B; ++i) {
                 const bool mine = i == j;
-                const float* c = C + i * kConstStride;
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
                     Fj[k] = mine ? F[i][k] + Df[i][k] : Fj[k];
@@ -484,7 +521,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
                     Ej[k] = mine ? E[i][k] : Ej[k];
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
-                    rj[k] = mine ? c[9 + k] : rj[k];
+                    rj[k] = mine ? R[i][k] : rj[k];
             }
         }
         // source terms of column (u, j):
@@ -493,15 +530,16 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
         //   u = qd: dv += S,                             da += v_j x S
         float src_v[6], src_a[6], src_f[6];
         {
-            float vxs[6], axs[6];
-            cross_S(av, vxs);
-            cross_S(ab, axs);
+            const bool pj = (I::prism >> j) & 1ull;        // joint j is prismatic
+            float vxs[6], axs[6], sf[6];
+            cross_S(pj, av, vxs);
+            cross_S(pj, ab, axs);
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                src_v[k] = u == 0 ? vxs[k] : (k == 2 ? 1.0f : 0.0f);
+                src_v[k] = u == 0 ? vxs[k] : (k == s_index(pj) ? 1.0f : 0.0f);
                 src_a[k] = u == 0 ? axs[k] : vxs[k];
             }
-            float sf[6] = {-Fj[1], Fj[0], 0.0f, -Fj[4], Fj[3], 0.0f};   // S x* f
+            s_crf(pj, Fj, sf);                                   // S x* f
             xt_fv(Ej, rj, sf, src_f);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
@@ -519,8 +557,8 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
                 const float sel = (i == j) ? 1.0f : 0.0f;
                 float xdv[6], xda[6];
                 if (p >= 0) {
-                    x_mv(E[i], c + 9, dv[p < 0 ? 0 : p], xdv);
-                    x_mv(E[i], c + 9, da[p < 0 ? 0 : p], xda);
+                    x_mv(E[i], R[i], dv[p < 0 ? 0 : p], xdv);
+                    x_mv(E[i], R[i], da[p < 0 ? 0 : p], xda);
                 } else {
 #pragma unroll
                     for (int k = 0; k < 6; ++k) {
@@ -532,7 +570,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
                 for (int k = 0; k < 6; ++k)
                     dv[i][k] = xdv[k] + sel * src_v[k];
                 float dvxs[6];
-                cross_S(dv[i], dvxs);
+                cross_S(prismatic<I>(i), dv[i], dvxs);
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
                     da[i][k] = xda[k] + dvxs[k] * qd[i] + sel * src_a[k];
@@ -549,12 +587,12 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
         }
 #pragma unroll
         for (int i = B - 1; i >= 0; --i) {
-            dx[i] = df[i][2];
+            dx[i] = df[i][s_index(prismatic<I>(i))];
             const int p = S::parent[i];
             if (p >= 0) {
                 const float sel = (i == j) ? 1.0f : 0.0f;
                 float y[6];
-                xt_fv(E[i], C + i * kConstStride + 9, df[i], y);
+                xt_fv(E[i], R[i], df[i], y);
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
                     df[p][k] += y[k] + sel * src_f[k];

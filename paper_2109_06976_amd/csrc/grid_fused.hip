@@ -37,6 +37,7 @@
 namespace gridq {
 
 using grid::kConstStride;
+using grid::prismatic;
 
 // quad permutations: lane (0,1,2,3) reads lane (..); lane 3 shadows component 0
 constexpr int kNb1 = 1 | (2 << 2) | (0 << 4) | (1 << 6);   // component c+1
@@ -131,10 +132,33 @@ __device__ __forceinline__ V crf(Nb v, Nb f)
     return y;
 }
 
-// x x S for S = e_z: (x_1, -x_0, 0) in both halves
-__device__ __forceinline__ V cross_s(const Lane& ln, V x)
+// The joint axis is e_z of the joint frame: S = (e_z, 0) for a revolute joint (pr = false),
+// (0, e_z) for a prismatic one (pr = true).
+
+// S s: s in component 2 of the angular (revolute) or linear (prismatic) half
+__device__ __forceinline__ V s_vec(const Lane& ln, bool pr, float s)
 {
-    return V{ln.sxs * qperm<kXS>(x.a), ln.sxs * qperm<kXS>(x.l)};
+    return pr ? V{0.0f, ln.sz * s} : V{ln.sz * s, 0.0f};
+}
+
+// x x S: (x_1, -x_0, 0) in both halves (revolute); (0; w_1, -w_0, 0) (prismatic)
+__device__ __forceinline__ V cross_s(const Lane& ln, bool pr, V x)
+{
+    const float pa = ln.sxs * qperm<kXS>(x.a);
+    return pr ? V{0.0f, pa} : V{pa, ln.sxs * qperm<kXS>(x.l)};
+}
+
+// S x* f: (e_z x n; e_z x f_l) (revolute); (e_z x f_l; 0) (prismatic)
+__device__ __forceinline__ V s_crf(const Lane& ln, bool pr, V f)
+{
+    const float pl = -ln.sxs * qperm<kXS>(f.l);
+    return pr ? V{pl, 0.0f} : V{-ln.sxs * qperm<kXS>(f.a), pl};
+}
+
+// the half whose component 2 is S^T x (read on lane 2 of the quad)
+__device__ __forceinline__ float s_half(bool pr, V x)
+{
+    return pr ? x.l : x.a;
 }
 
 __device__ __forceinline__ V add(V x, V y) { return V{x.a + y.a, x.l + y.l}; }
@@ -177,7 +201,8 @@ __device__ __forceinline__ float mass(int i)
 // ------------------------------------------------------------------ building blocks
 
 // The lane's share of every body: E_i = E_z(q_i) E_T,i from the hardware sin and cos (angle
-// in revolutions, reduced to [0, 1)), and the body constants, all from the model's literals
+// in revolutions, reduced to [0, 1)), or E_i = E_T,i and r_i = r_T,i + q_i E_T,i^T e_z for a
+// prismatic joint, and the body constants, all from the model's literals
 // (no table: per-lane loads of constants would all pass through the CU's texture data path).
 // Row c of E is alpha E_T,0 + beta E_T,1 + gamma E_T,2 with (alpha, beta, gamma) = (cos, sin, 0),
 // (-sin, cos, 0), (0, 0, 1) for c = 0, 1, 2 (rows of E_z). The lane keeps its row in the order
@@ -203,9 +228,18 @@ __device__ __forceinline__ void load_bodies(const float* q_in, const float* qd_i
     for (int i = 0; i < I::S::B; ++i) {
         const long o = vbase + I::body[i];
         const float* k = I::consts() + i * kConstStride;
-        const float rev = __builtin_amdgcn_fractf(q_in[o] * 0.159154943091895336f);
-        const float sn = __builtin_amdgcn_sinf(rev);
-        const float co = __builtin_amdgcn_cosf(rev);
+        const float qi = q_in[o];
+        float sn = 0.0f, co = 1.0f;                      // prismatic: E = E_T
+        if (prismatic<I>(i)) {
+            // translation along the joint z axis: r = r_T + q E_T^T e_z
+            const float r_c = comp(ln, k[9] + qi * k[6], k[10] + qi * k[7], k[11] + qi * k[8]);
+            K[i].rr1 = qperm<kNb1>(r_c);
+            K[i].rr2 = qperm<kNb2>(r_c);
+        } else {
+            const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
+            sn = __builtin_amdgcn_sinf(rev);
+            co = __builtin_amdgcn_cosf(rev);
+        }
         qd[i] = kQd ? qd_in[o] : 0.0f;
         const float al = ln.oh0 * co - ln.oh1 * sn;
         const float be = ln.oh0 * sn + ln.oh1 * co;
@@ -244,9 +278,10 @@ __device__ __forceinline__ void rnea0(const Lane& ln, const float (&qd)[I::S::B]
             const V g{0.0f, ln.g};
             xa0[i] = xmv(E[i], K[i], g, gather(g));
         }
-        v[i] = V{xv.a + ln.sz * qd[i], xv.l};
+        const bool pr = prismatic<I>(i);
+        v[i] = add(xv, s_vec(ln, pr, qd[i]));
         nv[i] = gather(v[i]);
-        const V vxs = cross_s(ln, v[i]);           // a_i = X a_lambda + (v_i x S) qd_i
+        const V vxs = cross_s(ln, pr, v[i]);       // a_i = X a_lambda + (v_i x S) qd_i
         a[i] = V{xa0[i].a + vxs.a * qd[i], xa0[i].l + vxs.l * qd[i]};
         na[i] = gather(a[i]);
         gam[i] = imv(K[i], mass<I>(i), v[i], nv[i]);
@@ -284,10 +319,11 @@ __device__ __forceinline__ void rnea_at(const Lane& ln, const float (&qd)[I::S::
             const V g{0.0f, ln.g};
             xa[i] = xmv(E[i], K[i], g, gather(g));
         }
-        v[i] = V{xv.a + ln.sz * qd[i], xv.l};
+        const bool pr = prismatic<I>(i);
+        v[i] = add(xv, s_vec(ln, pr, qd[i]));
         nv[i] = gather(v[i]);
-        const V vxs = cross_s(ln, v[i]);   // a_i = X a_lambda + S qdd_i + (v_i x S) qd_i
-        a[i] = V{xa[i].a + ln.sz * qdd[i] + vxs.a * qd[i], xa[i].l + vxs.l * qd[i]};
+        const V vxs = cross_s(ln, pr, v[i]);   // a_i = X a_lambda + S qdd_i + (v_i x S) qd_i
+        a[i] = add(V{xa[i].a + vxs.a * qd[i], xa[i].l + vxs.l * qd[i]}, s_vec(ln, pr, qdd[i]));
         na[i] = gather(a[i]);
         gam[i] = imv(K[i], mass<I>(i), v[i], nv[i]);
         F[i] = add(imv(K[i], mass<I>(i), a[i], na[i]), crf(nv[i], gather(gam[i])));
@@ -300,7 +336,7 @@ __device__ __forceinline__ void rnea_at(const Lane& ln, const float (&qd)[I::S::
     }
 }
 
-// column jm of M as ID(q, 0, e_jm) without gravity; M_i,jm = S^T f_i is component a of
+// column jm of M as ID(q, 0, e_jm) without gravity; M_i,jm = S^T f_i is s_half(f_i) on
 // lane 2 of the quad
 template <class I>
 __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B],
@@ -317,7 +353,7 @@ __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B]
             am[i] = xmv(E[i], K[i], am[p < 0 ? 0 : p], nam[p < 0 ? 0 : p]);
         else
             am[i] = V{0.0f, 0.0f};
-        am[i].a += (i == jm) ? ln.sz : 0.0f;
+        am[i] = add(am[i], s_vec(ln, prismatic<I>(i), (i == jm) ? 1.0f : 0.0f));
         nam[i] = gather(am[i]);
         fm[i] = imv(K[i], mass<I>(i), am[i], nam[i]);
     }
@@ -394,7 +430,7 @@ __device__ __forceinline__ void delta_rnea(const Lane& ln, const Rot (&E)[I::S::
         xd[i] = V{0.0f, 0.0f};
         if (p >= 0)
             xd[i] = xmv(E[i], K[i], Da[p < 0 ? 0 : p], nDa[p < 0 ? 0 : p]);
-        Da[i] = V{xd[i].a + ln.sz * qdd[i], xd[i].l};
+        Da[i] = add(xd[i], s_vec(ln, prismatic<I>(i), qdd[i]));
         nDa[i] = gather(Da[i]);
         Df[i] = imv(K[i], mass<I>(i), Da[i], nDa[i]);
     }
@@ -435,7 +471,7 @@ __device__ __forceinline__ void drnea_column(const Lane& ln, const float (&qd)[I
             if constexpr (kVel) {
                 dv[i] = V{xdv.a + sel * src_v.a, xdv.l + sel * src_v.l};
                 ndv[i] = gather(dv[i]);
-                const V dvxs = cross_s(ln, dv[i]);
+                const V dvxs = cross_s(ln, prismatic<I>(i), dv[i]);
                 da[i] = V{xda.a + dvxs.a * qd[i] + sel * src_a.a,
                           xda.l + dvxs.l * qd[i] + sel * src_a.l};
             } else {
@@ -452,7 +488,7 @@ __device__ __forceinline__ void drnea_column(const Lane& ln, const float (&qd)[I
     }
 #pragma unroll
     for (int i = B - 1; i >= 0; --i) {
-        dx[i] = qperm<kZ>(df[i].a);
+        dx[i] = qperm<kZ>(s_half(prismatic<I>(i), df[i]));
         const int p = S::parent[i];
         if (p >= 0) {
             const float sel = (i == j) ? 1.0f : 0.0f;
@@ -463,10 +499,11 @@ __device__ __forceinline__ void drnea_column(const Lane& ln, const float (&qd)[I
     }
 }
 
-// X_j^T (S x* f): the backward source of a q-column
-__device__ __forceinline__ V back_source(const Lane& ln, const Rot& Ej, const LaneK& Kj, V f)
+// X_j^T (S x* f): the backward source of a q-column (pj: joint j is prismatic)
+__device__ __forceinline__ V back_source(const Lane& ln, bool pj, const Rot& Ej, const LaneK& Kj,
+                                         V f)
 {
-    const V sxf = neg(cross_s(ln, f));   // S x* f = -(f x S) componentwise for S = e_z
+    const V sxf = s_crf(ln, pj, f);
     return xtfv(Ej, Kj, sxf, gather(sxf));
 }
 
@@ -550,7 +587,7 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
     float x[B];                               // tau - c, then qdd
 #pragma unroll
     for (int i = 0; i < B; ++i)
-        x[i] = A.tau[vbase + I::body[i]] - qperm<kZ>(F[i].a);
+        x[i] = A.tau[vbase + I::body[i]] - qperm<kZ>(s_half(prismatic<I>(i), F[i]));
 
     {
         V fm[B];
@@ -558,7 +595,7 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
         if (owns_m && c == 2) {
 #pragma unroll
             for (int i = 0; i < B; ++i)
-                s_M[pslot][i][jm] = fm[i].a;
+                s_M[pslot][i][jm] = s_half(prismatic<I>(i), fm[i]);
         }
     }
     __syncthreads();
@@ -579,13 +616,14 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
     LaneK Kj;
     pick_joint<I>(E, K, j, Ej, Kj);
     const V vj = pick<B>(v, j);
+    const bool pj = prismatic<I>(j);
     // sources of column (u, j):
     //   u = q : dv += v_j x S, da += (X_j a_lambda(j)) x S, backward += X_j^T (S x* f_j)
     //   u = qd: dv += S,       da += v_j x S
-    const V vxs = cross_s(ln, vj);
-    const V src_v = u == 0 ? vxs : V{ln.sz, 0.0f};
-    const V src_a = u == 0 ? cross_s(ln, add(pick<B>(xa0, j), xdj)) : vxs;
-    const V zeta = back_source(ln, Ej, Kj, add(pick<B>(F, j), Dfj));
+    const V vxs = cross_s(ln, pj, vj);
+    const V src_v = u == 0 ? vxs : s_vec(ln, pj, 1.0f);
+    const V src_a = u == 0 ? cross_s(ln, pj, add(pick<B>(xa0, j), xdj)) : vxs;
+    const V zeta = back_source(ln, pj, Ej, Kj, add(pick<B>(F, j), Dfj));
     const V src_f = u == 0 ? zeta : V{0.0f, 0.0f};
 
     float dx[B];
@@ -731,17 +769,18 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         if (s == 0 && c == 2) {               // quad 0 of each problem publishes c
 #pragma unroll
             for (int i = 0; i < B; ++i)
-                s_c[pslot][i] = F[i].a;
+                s_c[pslot][i] = s_half(prismatic<I>(i), F[i]);
         }
         __syncthreads();                      // c published
 
         Rot Ej;
         LaneK Kj;
         pick_joint<I>(E, K, j, Ej, Kj);
-        const V vxs = cross_s(ln, pick<B>(v, j));
-        const V src_v = u == 0 ? vxs : V{ln.sz, 0.0f};
-        const V src_a = u == 0 ? cross_s(ln, pick<B>(xa0, j)) : vxs;
-        const V zeta = back_source(ln, Ej, Kj, pick<B>(F, j));
+        const bool pj = prismatic<I>(j);
+        const V vxs = cross_s(ln, pj, pick<B>(v, j));
+        const V src_v = u == 0 ? vxs : s_vec(ln, pj, 1.0f);
+        const V src_a = u == 0 ? cross_s(ln, pj, pick<B>(xa0, j)) : vxs;
+        const V zeta = back_source(ln, pj, Ej, Kj, pick<B>(F, j));
         const V src_f = u == 0 ? zeta : V{0.0f, 0.0f};
         float dx[B];
         drnea_column<I, true>(ln, qd, E, K, v, gam, j, src_v, src_a, src_f, dx);
@@ -801,7 +840,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
             if (owns[cb] && c == 2) {
 #pragma unroll
                 for (int i = 0; i < B; ++i)
-                    s_M[pslot][i][js[cb]] = fm[i].a;
+                    s_M[pslot][i][js[cb]] = s_half(prismatic<I>(i), fm[i]);
             }
         }
         // the exchange stays inside this wavefront: order its LDS traffic only
@@ -844,8 +883,9 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
             Rot Ej;
             LaneK Kj;
             pick_joint<I>(E, K, j, Ej, Kj);
-            const V src_a = cross_s(ln, pick<B>(xd, j));
-            const V src_f = back_source(ln, Ej, Kj, pick<B>(Df, j));
+            const bool pj = prismatic<I>(j);
+            const V src_a = cross_s(ln, pj, pick<B>(xd, j));
+            const V src_f = back_source(ln, pj, Ej, Kj, pick<B>(Df, j));
             float dxc[B];
             drnea_column<I, false>(ln, qd, E, K, none, none, j, V{0.0f, 0.0f}, src_a, src_f,
                                    dxc);

@@ -59,6 +59,7 @@ struct BranchInst {
     std::vector<int> body;           // robot index of each local body
     int coff = 0;                    // float offset of the branch's constants
     uint64_t mask = 0;               // robot bodies in this branch
+    uint64_t prism = 0;              // local bodies on prismatic joints
 };
 
 struct Topology {

@@ -75,12 +75,13 @@ __device__ __forceinline__ void drnea_adjoint(const Lane& ln, const float (&qd)[
                 xa[i] = xmv(E[i], K[i], g, gather(g));
                 xu[i] = V{0.0f, 0.0f};
             }
-            v[i] = V{xv[i].a + ln.sz * qd[i], xv[i].l};
+            const bool pr = prismatic<I>(i);
+            v[i] = add(xv[i], s_vec(ln, pr, qd[i]));
             nv[i] = gather(v[i]);
-            const V vxs = cross_s(ln, v[i]);
-            a[i] = V{xa[i].a + ln.sz * qdd[i] + vxs.a * qd[i], xa[i].l + vxs.l * qd[i]};
+            const V vxs = cross_s(ln, pr, v[i]);
+            a[i] = add(V{xa[i].a + vxs.a * qd[i], xa[i].l + vxs.l * qd[i]}, s_vec(ln, pr, qdd[i]));
             na[i] = gather(a[i]);
-            u[i] = V{xu[i].a + ln.sz * w[i], xu[i].l};
+            u[i] = add(xu[i], s_vec(ln, pr, w[i]));
             nu[i] = gather(u[i]);
             const float m = mass<I>(i);
             const V Iv = imv(K[i], m, v[i], nv[i]);
@@ -92,12 +93,14 @@ __device__ __forceinline__ void drnea_adjoint(const Lane& ln, const float (&qd)[
     }
 #pragma unroll
     for (int i = B - 1; i >= 0; --i) {
-        const V sxab = neg(cross_s(ln, ab[i]));            // S x* ab_i
+        const bool pr = prismatic<I>(i);
+        const V sxab = s_crf(ln, pr, ab[i]);                // S x* ab_i
         vb[i] = V{vb[i].a + sxab.a * qd[i], vb[i].l + sxab.l * qd[i]};
         // S x y = -(y x S)
-        gq[i] = -(dot6(ub[i], neg(cross_s(ln, xu[i]))) + dot6(vb[i], neg(cross_s(ln, xv[i]))) +
-                  dot6(ab[i], neg(cross_s(ln, xa[i]))));
-        gqd[i] = qperm<kZ>(vb[i].a) + dot6(ab[i], cross_s(ln, v[i]));
+        gq[i] = -(dot6(ub[i], neg(cross_s(ln, pr, xu[i]))) +
+                  dot6(vb[i], neg(cross_s(ln, pr, xv[i]))) +
+                  dot6(ab[i], neg(cross_s(ln, pr, xa[i]))));
+        gqd[i] = qperm<kZ>(s_half(pr, vb[i])) + dot6(ab[i], cross_s(ln, pr, v[i]));
         const int p = S::parent[i];
         if (p >= 0) {
             ub[p < 0 ? 0 : p] = add(ub[p < 0 ? 0 : p], xtfv(E[i], K[i], ub[i], gather(ub[i])));
@@ -159,7 +162,7 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
             if (valid) {
 #pragma unroll
                 for (int i = 0; i < B; ++i) {
-                    const float tau = qperm<kZ>(F[i].a);
+                    const float tau = qperm<kZ>(s_half(prismatic<I>(i), F[i]));
                     if ((i & 3) == c)
                         A.out0[vbase + I::body[i]] = tau;
                 }
@@ -172,10 +175,11 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
             Rot Ej;
             LaneK Kj;
             pick_joint<I>(E, K, j, Ej, Kj);
-            const V vxs = cross_s(ln, pick<B>(v, j));
-            const V src_v = u == 0 ? vxs : V{ln.sz, 0.0f};
-            const V src_a = u == 0 ? cross_s(ln, pick<B>(xa, j)) : vxs;
-            const V zeta = back_source(ln, Ej, Kj, pick<B>(F, j));
+            const bool pj = prismatic<I>(j);
+            const V vxs = cross_s(ln, pj, pick<B>(v, j));
+            const V src_v = u == 0 ? vxs : s_vec(ln, pj, 1.0f);
+            const V src_a = u == 0 ? cross_s(ln, pj, pick<B>(xa, j)) : vxs;
+            const V zeta = back_source(ln, pj, Ej, Kj, pick<B>(F, j));
             const V src_f = u == 0 ? zeta : V{0.0f, 0.0f};
             float dx[B];
             drnea_column<I, true>(ln, qd, E, K, v, gam, j, src_v, src_a, src_f, dx);
@@ -203,7 +207,7 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
             if (owns && c == 2) {
 #pragma unroll
                 for (int i = 0; i < B; ++i)
-                    s_M[pslot][i][jm] = fm[i].a;
+                    s_M[pslot][i][jm] = s_half(prismatic<I>(i), fm[i]);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -245,7 +249,7 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
             float x[B];
 #pragma unroll
             for (int i = 0; i < B; ++i)
-                x[i] = A.u[vbase + I::body[i]] - qperm<kZ>(F[i].a);
+                x[i] = A.u[vbase + I::body[i]] - qperm<kZ>(s_half(prismatic<I>(i), F[i]));
             ltl_solve<S>(Lf, dinv, x);
             if (valid && s == 0) {
 #pragma unroll

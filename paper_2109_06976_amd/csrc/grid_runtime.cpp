@@ -43,10 +43,8 @@ grid_status validate_desc(const grid_model_desc* d, std::string* err)
             return fail_to(err, GRID_EINVAL, "parent[" + std::to_string(i) + "] = " +
                                                  std::to_string(d->parent[i]) +
                                                  " must satisfy -1 <= parent[i] < i");
-        if (d->joint_type && d->joint_type[i] == GRID_JOINT_PRISMATIC)
-            return fail_to(err, GRID_EUNSUPPORTED, "prismatic joints are not supported");
         if (d->joint_type && d->joint_type[i] != GRID_JOINT_REVOLUTE &&
-            d->joint_type[i] != GRID_JOINT_FIXED)
+            d->joint_type[i] != GRID_JOINT_PRISMATIC && d->joint_type[i] != GRID_JOINT_FIXED)
             return fail_to(err, GRID_EINVAL, "joint_type[" + std::to_string(i) +
                                                  "] is not a joint type");
         if (d->axis) {
@@ -299,12 +297,12 @@ const char* grid_last_error(void) { return t_last_error.c_str(); }
 
 // validated description -> topology, packed constants and generated source
 // The model without its fixed joints: every body on a fixed joint merges into its nearest
-// ancestor on a revolute joint (its owner; -1 when the chain of fixed joints reaches the
-// base). Transforms are (E, r) with x_child = E (x_parent - r); the owner-to-body transform
+// ancestor on a movable (revolute or prismatic) joint (its owner; -1 when the chain of fixed
+// joints reaches the base). Transforms are (E, r) with x_child = E (x_parent - r); the owner-to-body transform
 // of a fixed body composes (E2, r2) after (E1, r1) as (E2 E1, r1 + E1^T r2). Inertias are
 // summed about the owner's origin: mass, first moment and the rotational inertia there.
 struct ReducedDesc {
-    std::vector<int32_t> parent;
+    std::vector<int32_t> parent, joint_type;
     std::vector<double> axis, rot, pos, mass, com, inertia;
     grid_model_desc d{};
 };
@@ -314,7 +312,7 @@ static void reduce_fixed(const grid_model_desc* src, ReducedDesc* out)
     const int n = src->n;
     std::vector<int> owner(n, -1), newidx(n, -1);
     std::vector<double> Eo((size_t)9 * n), ro((size_t)3 * n);   // owner frame -> body frame
-    std::vector<double> M, H, IO;                                 // per revolute body: m, m c, I_O
+    std::vector<double> M, H, IO;                                 // per movable body: m, m c, I_O
     int nd = 0;
     for (int i = 0; i < n; ++i) {
         const int p = src->parent[i];
@@ -347,6 +345,7 @@ static void reduce_fixed(const grid_model_desc* src, ReducedDesc* out)
             owner[i] = i;
             newidx[i] = nd++;
             out->parent.push_back(po < 0 ? -1 : newidx[po]);
+            out->joint_type.push_back(src->joint_type ? src->joint_type[i] : GRID_JOINT_REVOLUTE);
             out->rot.insert(out->rot.end(), E, E + 9);
             out->pos.insert(out->pos.end(), r, r + 3);
             for (int k = 0; k < 3; ++k)
@@ -409,7 +408,7 @@ static void reduce_fixed(const grid_model_desc* src, ReducedDesc* out)
     grid_model_desc& d = out->d;
     d.n = nd;
     d.parent = out->parent.data();
-    d.joint_type = nullptr;
+    d.joint_type = out->joint_type.data();
     d.axis = src->axis ? out->axis.data() : nullptr;
     d.tree_rot = out->rot.data();
     d.tree_pos = out->pos.data();
@@ -431,9 +430,13 @@ static grid_status prepare(const grid_model_desc* desc, uint32_t flags, Topology
     ReducedDesc red;
     reduce_fixed(desc, &red);
     if (red.d.n < 1)
-        return fail(GRID_EINVAL, "the model has no revolute joint");
+        return fail(GRID_EINVAL, "the model has no movable joint");
     if (!analyse_topology(red.d.parent, red.d.n, topo, &err))
         return fail(GRID_EINVAL, err);
+    for (BranchInst& inst : topo->insts)
+        for (size_t k = 0; k < inst.body.size(); ++k)
+            if (red.d.joint_type[inst.body[k]] == GRID_JOINT_PRISMATIC)
+                inst.prism |= 1ull << k;
     *src = generate_source(*topo, pack_constants(&red.d, *topo), red.d.gravity, flags);
     return GRID_OK;
 }

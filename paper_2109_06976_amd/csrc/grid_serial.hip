@@ -4,7 +4,8 @@
 // so all model constants are instruction literals, nothing crosses lanes, and no work is
 // repeated: the fewest instructions per knot of all the builds (the throughput form; its
 // latency is one lane's whole chain). Per problem, float32 (Sec. IV-B):
-//   1. X_i = (E_i, r_i), E_i = E_z(q_i) E_T,i
+//   1. X_i = (E_i, r_i), E_i = E_z(q_i) E_T,i (revolute), or E_i = E_T,i and
+//      r_i = r_T,i + q_i E_T,i^T e_z (prismatic)
 //   2. RNEA(q, qd, 0): v_i, a_i, gamma_i = I_i v_i, f_i, accumulated inward; c_i = S^T f_i
 //   3. M by composite rigid bodies: I^c_i = I_i + sum over children of X^T I^c X, kept as
 //      (mass, first moment, rotational inertia about the origin); M_ii = S^T I^c_i S and
@@ -26,6 +27,9 @@ using grid::crf_mv;
 using grid::cross_S;
 using grid::inertia_mv;
 using grid::kConstStride;
+using grid::prismatic;
+using grid::s_crf;
+using grid::s_index;
 using grid::x_mv;
 using grid::xt_fv;
 
@@ -111,20 +115,32 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
     const long mbase = (long)knot * N * N;
 
     // ------------------------------------------------------------ 1. transforms
-    float qd[B], E[B][9];
+    float qd[B], E[B][9], R[B][3];
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         const long o = vbase + I::body[i];
         const float* c = C + i * kConstStride;
-        const float rev = __builtin_amdgcn_fractf(A.q[o] * 0.159154943091895336f);
+        const float qi = A.q[o];
+        qd[i] = A.qd[o];
+        if (prismatic<I>(i)) {
+            // translation along the joint z axis: E = E_T, r = r_T + q E_T^T e_z
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                E[i][k] = c[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                R[i][k] = c[9 + k] + qi * c[6 + k];
+            continue;
+        }
+        const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
         const float s = __builtin_amdgcn_sinf(rev);
         const float co = __builtin_amdgcn_cosf(rev);
-        qd[i] = A.qd[o];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             E[i][k] = co * c[k] + s * c[3 + k];
             E[i][3 + k] = co * c[3 + k] - s * c[k];
             E[i][6 + k] = c[6 + k];
+            R[i][k] = c[9 + k];
         }
     }
     const float a0[6] = {0.0f, 0.0f, 0.0f, grid_a0[0], grid_a0[1], grid_a0[2]};   // -g
@@ -138,11 +154,11 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
         for (int i = 0; i < B; ++i) {
             const int p = S::parent[i];
             const float* c = C + i * kConstStride;
-            x_mv(E[i], c + 9, p < 0 ? zero6 : v[p < 0 ? 0 : p], v[i]);
-            x_mv(E[i], c + 9, p < 0 ? a0 : a[p < 0 ? 0 : p], xa[i]);
-            v[i][2] += qd[i];
+            x_mv(E[i], R[i], p < 0 ? zero6 : v[p < 0 ? 0 : p], v[i]);
+            x_mv(E[i], R[i], p < 0 ? a0 : a[p < 0 ? 0 : p], xa[i]);
+            v[i][s_index(prismatic<I>(i))] += qd[i];
             float vxs[6], Ia[6], w[6];
-            cross_S(v[i], vxs);
+            cross_S(prismatic<I>(i), v[i], vxs);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
                 a[i][k] = xa[i][k] + vxs[k] * qd[i];
@@ -158,7 +174,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
             const int p = S::parent[i];
             if (p >= 0) {
                 float y[6];
-                xt_fv(E[i], C + i * kConstStride + 9, F[i], y);
+                xt_fv(E[i], R[i], F[i], y);
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
                     F[p][k] += y[k];
@@ -183,25 +199,34 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
         }
 #pragma unroll
         for (int i = B - 1; i >= 0; --i) {
-            // I^c_i S for S = e_z: [Ibar e_z; -(h x e_z)]
+            // I^c_i S: [Ibar e_z; -(h x e_z)] for S = (e_z, 0), [h x e_z; m e_z] for (0, e_z)
             float f[6] = {Ic[i].I[4], Ic[i].I[5], Ic[i].I[2], -Ic[i].h[1], Ic[i].h[0], 0.0f};
-            Lf[i][i] = f[2];
+            if (prismatic<I>(i)) {
+                f[0] = Ic[i].h[1];
+                f[1] = -Ic[i].h[0];
+                f[2] = 0.0f;
+                f[3] = 0.0f;
+                f[4] = 0.0f;
+                f[5] = Ic[i].m;
+            }
+            Lf[i][i] = f[s_index(prismatic<I>(i))];
             // up the ancestor path (ancestors have smaller indices): f into the parent
             // frame of k, M_{lambda(k), i} = S^T f
 #pragma unroll
             for (int k = B - 1; k >= 0; --k) {
                 if (k <= i && (k == i || gridq::is_anc<S>(k, i)) && S::parent[k] >= 0) {
                     float y[6];
-                    xt_fv(E[k], C + k * kConstStride + 9, f, y);
+                    xt_fv(E[k], R[k], f, y);
 #pragma unroll
                     for (int e = 0; e < 6; ++e)
                         f[e] = y[e];
-                    Lf[i][S::parent[k] < 0 ? 0 : S::parent[k]] = f[2];
+                    const int pk = S::parent[k] < 0 ? 0 : S::parent[k];
+                    Lf[i][pk] = f[s_index(prismatic<I>(pk))];
                 }
             }
             const int p = S::parent[i];
             if (p >= 0)
-                rb_add(Ic[p], rb_to_parent(E[i], C + i * kConstStride + 9, Ic[i]));
+                rb_add(Ic[p], rb_to_parent(E[i], R[i], Ic[i]));
         }
     }
     gridq::ltl_factor<S>(Lf, dinv);
@@ -226,7 +251,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
     float x[B];
 #pragma unroll
     for (int i = 0; i < B; ++i)
-        x[i] = A.tau[vbase + I::body[i]] - F[i][2];
+        x[i] = A.tau[vbase + I::body[i]] - F[i][s_index(prismatic<I>(i))];
     gridq::ltl_solve<S>(Lf, dinv, x);
     if (valid) {
 #pragma unroll
@@ -242,7 +267,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
             const int p = S::parent[i];
             const float* c = C + i * kConstStride;
             if (p >= 0) {
-                x_mv(E[i], c + 9, Da[p < 0 ? 0 : p], Da[i]);
+                x_mv(E[i], R[i], Da[p < 0 ? 0 : p], Da[i]);
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
                     xa[i][k] += Da[i][k];
@@ -251,7 +276,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
                 for (int k = 0; k < 6; ++k)
                     Da[i][k] = 0.0f;
             }
-            Da[i][2] += x[i];
+            Da[i][s_index(prismatic<I>(i))] += x[i];
             inertia_mv(c, Da[i], Df[i]);
         }
 #pragma unroll
@@ -259,7 +284,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
             const int p = S::parent[i];
             if (p >= 0) {
                 float y[6];
-                xt_fv(E[i], C + i * kConstStride + 9, Df[i], y);
+                xt_fv(E[i], R[i], Df[i], y);
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
                     Df[p][k] += y[k];
@@ -284,7 +309,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
             Ej[k] = E[0][k];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            rj[k] = C[9 + k];
+            rj[k] = R[0][k];
 #pragma unroll
         for (int i = 1; i < B; ++i) {
 #pragma unroll
@@ -292,13 +317,15 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
                 Ej[k] = (i == j) ? E[i][k] : Ej[k];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                rj[k] = (i == j) ? C[i * kConstStride + 9 + k] : rj[k];
+                rj[k] = (i == j) ? R[i][k] : rj[k];
         }
+        const bool pj = (I::prism >> j) & 1ull;            // joint j is prismatic
         float vxs[6], axs[6], srcf[6];
-        cross_S(vj, vxs);
-        cross_S(xaj, axs);
+        cross_S(pj, vj, vxs);
+        cross_S(pj, xaj, axs);
         {
-            const float sf[6] = {-Fj[1], Fj[0], 0.0f, -Fj[4], Fj[3], 0.0f};   // S x* f_j
+            float sf[6];
+            s_crf(pj, Fj, sf);                               // S x* f_j
             xt_fv(Ej, rj, sf, srcf);
         }
         // columns d/dq_j (index 0) and d/dqd_j (index 1), side by side
@@ -320,18 +347,18 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
                                 xda[k] = 0.0f;
                             }
                         } else {
-                            x_mv(E[i], c + 9, dv[u][p < 0 ? 0 : p], xdv);
-                            x_mv(E[i], c + 9, da[u][p < 0 ? 0 : p], xda);
+                            x_mv(E[i], R[i], dv[u][p < 0 ? 0 : p], xdv);
+                            x_mv(E[i], R[i], da[u][p < 0 ? 0 : p], xda);
                         }
                         if (i == j) {
 #pragma unroll
                             for (int k = 0; k < 6; ++k) {
-                                xdv[k] = u == 0 ? vxs[k] : (k == 2 ? 1.0f : 0.0f);
+                                xdv[k] = u == 0 ? vxs[k] : (k == s_index(pj) ? 1.0f : 0.0f);
                                 xda[k] = u == 0 ? axs[k] : vxs[k];
                             }
                         }
                         float dvxs[6];
-                        cross_S(xdv, dvxs);
+                        cross_S(prismatic<I>(i), xdv, dvxs);
 #pragma unroll
                         for (int k = 0; k < 6; ++k) {
                             dv[u][i][k] = xdv[k];
@@ -363,12 +390,12 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
             const bool live = in_subtree<S>(i, j) || ((S::anc[j < 0 ? 0 : j] >> i) & 1ull);
 #pragma unroll
             for (int u = 0; u < 2; ++u)
-                dx[u][i] = df[u][i][2];
+                dx[u][i] = df[u][i][s_index(prismatic<I>(i))];
             if (p >= 0 && live) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     float y[6];
-                    xt_fv(E[i], C + i * kConstStride + 9, df[u][i], y);
+                    xt_fv(E[i], R[i], df[u][i], y);
                     const float sel = (u == 0 && i == j) ? 1.0f : 0.0f;
 #pragma unroll
                     for (int k = 0; k < 6; ++k)

@@ -80,19 +80,27 @@ def test_reduced_constants_match_oracle_compositions(orc, parent, fixed):
                                    atol=2e-6)
 
 
-def test_fixed_and_prismatic_joint_errors():
+def test_joint_type_errors():
     robot = synth.chain7()
     with pytest.raises(grid.GridError) as e:
         grid.codegen_source(synth.with_fixed_joints(robot, range(7)))
     assert e.value.status == grid.GRID_EINVAL
-    pr = robot.copy()
-    pr.joint_type = np.zeros(7, np.int32)
-    pr.joint_type[3] = grid.JOINT_PRISMATIC
-    with pytest.raises(grid.GridError) as e:
-        grid.codegen_source(pr)
-    assert e.value.status == grid.GRID_EUNSUPPORTED
     bad = robot.copy()
     bad.joint_type = np.full(7, 9, np.int32)
     with pytest.raises(grid.GridError) as e:
         grid.codegen_source(bad)
     assert e.value.status == grid.GRID_EINVAL
+
+
+def test_prismatic_joints_marked_per_branch():
+    """The generated kernel marks each branch's prismatic bodies in local numbering: tree7
+    reduces to branches (0, 2, 4) and (5) of the original bodies; 0 and 4 slide."""
+    from paper_2109_06976_amd.build import prismatic_models
+    robot = prismatic_models()["tree7-fixed-prism"]
+    assert list(robot.joint_type) == [1, 2, 0, 2, 1, 0, 2]
+    src = grid.codegen_source(robot)
+    assert "static constexpr unsigned long long prism = 5ull;" in src      # local 0 and 2
+    assert "static constexpr unsigned long long prism = 0ull;" in src
+    m = grid.codegen_source(prismatic_models()["chain7-prism"])
+    assert "static constexpr unsigned long long prism = 18ull;" in m       # joints 1 and 4
+    assert "prism = 0ull;" in grid.codegen_source(synth.chain7())

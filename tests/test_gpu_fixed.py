@@ -1,8 +1,8 @@
 """Robots with fixed joints through the C ABI on an MI355X, every build, against the FP64
 oracle. Reference: the oracle's full model with each fixed joint held at q = qd = qdd = 0 (a
-fixed joint is a revolute joint that cannot move): M_r = M[r, r], c_r = RNEA(q, qd, 0)[r],
+fixed joint is a joint that cannot move): M_r = M[r, r], c_r = RNEA(q, qd, 0)[r],
 qdd_r = M_r^-1 (tau_r - c_r), dqdd_r/du_r = -M_r^-1 dtau[r, r]/du_r with dtau from the
-oracle's dRNEA at qdd = (qdd_r, 0); r the revolute joints. Tolerances as for dFD.
+oracle's dRNEA at qdd = (qdd_r, 0); r the movable joints. Tolerances as for dFD.
 """
 import sys
 
@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2109_06976_amd import grid, synth
+from paper_2109_06976_amd.build import prismatic_models
 
 pytestmark = pytest.mark.gpu
 
@@ -19,6 +20,8 @@ CASES = {
         synth.random_model(np.array([-1, 0, 0, 1, 3, -1, 5], np.int32), 77, "tree7"), [1, 3, 6]),
     "chain7-axes-fixed04": lambda: synth.with_fixed_joints(
         synth.random_model(synth.chain_parent(7), 0, "chain7-axes", axes="random"), [0, 4]),
+    # prismatic joints 0 and 4, fixed bodies 1 and 3 welded to the prismatic body 0
+    "tree7-fixed-prism": lambda: prismatic_models()["tree7-fixed-prism"],
 }
 
 

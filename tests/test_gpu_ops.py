@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2109_06976_amd import grid, synth
+from paper_2109_06976_amd.build import prismatic_models
 
 pytestmark = pytest.mark.gpu
 
@@ -27,6 +28,10 @@ ROBOTS = {
                                               axes="random"),
     "tree5-axes": lambda: synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6,
                                              "tree5-axes", axes="random"),
+    # prismatic joints among revolute ones (z axes, random axes, a 30-body branch set)
+    "chain7-prism": lambda: prismatic_models()["chain7-prism"],
+    "tree5-axes-prism": lambda: prismatic_models()["tree5-axes-prism"],
+    "humanoid30-prism": lambda: prismatic_models()["humanoid30-prism"],
 }
 
 

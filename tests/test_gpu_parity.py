@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2109_06976_amd import grid, synth
+from paper_2109_06976_amd.build import prismatic_models
 
 pytestmark = pytest.mark.gpu
 
@@ -33,6 +34,10 @@ ROBOTS = {
                                               axes="random"),
     "tree5-axes": lambda: synth.random_model(np.array([-1, 0, 0, 1, -1], np.int32), 6,
                                              "tree5-axes", axes="random"),
+    # prismatic joints among revolute ones (z axes, random axes, a 30-body branch set)
+    "chain7-prism": lambda: prismatic_models()["chain7-prism"],
+    "tree5-axes-prism": lambda: prismatic_models()["tree5-axes-prism"],
+    "humanoid30-prism": lambda: prismatic_models()["humanoid30-prism"],
 }
 
 _models = {}
@@ -107,6 +112,9 @@ def check(orc, robot, kn, got, tol=TOL, label=""):
     ("binary7", 13, 13),
     ("chain7-axes", 128, 14),
     ("tree5-axes", 41, 15),
+    ("chain7-prism", 128, 16),
+    ("tree5-axes-prism", 41, 17),
+    ("humanoid30-prism", 37, 18),
 ])
 def test_fd_grad_matches_oracle(torch_cuda, orc, name, N, seed):
     robot, model = get_model(name)
