@@ -141,6 +141,12 @@ __device__ __forceinline__ V s_vec(const Lane& ln, bool pr, float s)
     return pr ? V{0.0f, ln.sz * s} : V{ln.sz * s, 0.0f};
 }
 
+// x + S s (the other half untouched)
+__device__ __forceinline__ V add_s(const Lane& ln, bool pr, V x, float s)
+{
+    return pr ? V{x.a, x.l + ln.sz * s} : V{x.a + ln.sz * s, x.l};
+}
+
 // x x S: (x_1, -x_0, 0) in both halves (revolute); (0; w_1, -w_0, 0) (prismatic)
 __device__ __forceinline__ V cross_s(const Lane& ln, bool pr, V x)
 {
@@ -279,7 +285,7 @@ __device__ __forceinline__ void rnea0(const Lane& ln, const float (&qd)[I::S::B]
             xa0[i] = xmv(E[i], K[i], g, gather(g));
         }
         const bool pr = prismatic<I>(i);
-        v[i] = add(xv, s_vec(ln, pr, qd[i]));
+        v[i] = add_s(ln, pr, xv, qd[i]);
         nv[i] = gather(v[i]);
         const V vxs = cross_s(ln, pr, v[i]);       // a_i = X a_lambda + (v_i x S) qd_i
         a[i] = V{xa0[i].a + vxs.a * qd[i], xa0[i].l + vxs.l * qd[i]};
@@ -320,10 +326,11 @@ __device__ __forceinline__ void rnea_at(const Lane& ln, const float (&qd)[I::S::
             xa[i] = xmv(E[i], K[i], g, gather(g));
         }
         const bool pr = prismatic<I>(i);
-        v[i] = add(xv, s_vec(ln, pr, qd[i]));
+        v[i] = add_s(ln, pr, xv, qd[i]);
         nv[i] = gather(v[i]);
         const V vxs = cross_s(ln, pr, v[i]);   // a_i = X a_lambda + S qdd_i + (v_i x S) qd_i
-        a[i] = add(V{xa[i].a + vxs.a * qd[i], xa[i].l + vxs.l * qd[i]}, s_vec(ln, pr, qdd[i]));
+        const V xs = add_s(ln, pr, xa[i], qdd[i]);
+        a[i] = V{xs.a + vxs.a * qd[i], xs.l + vxs.l * qd[i]};
         na[i] = gather(a[i]);
         gam[i] = imv(K[i], mass<I>(i), v[i], nv[i]);
         F[i] = add(imv(K[i], mass<I>(i), a[i], na[i]), crf(nv[i], gather(gam[i])));
@@ -353,7 +360,8 @@ __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B]
             am[i] = xmv(E[i], K[i], am[p < 0 ? 0 : p], nam[p < 0 ? 0 : p]);
         else
             am[i] = V{0.0f, 0.0f};
-        am[i] = add(am[i], s_vec(ln, prismatic<I>(i), (i == jm) ? 1.0f : 0.0f));
+        const float e = (i == jm) ? ln.sz : 0.0f;
+        am[i] = prismatic<I>(i) ? V{am[i].a, am[i].l + e} : V{am[i].a + e, am[i].l};
         nam[i] = gather(am[i]);
         fm[i] = imv(K[i], mass<I>(i), am[i], nam[i]);
     }
@@ -430,7 +438,7 @@ __device__ __forceinline__ void delta_rnea(const Lane& ln, const Rot (&E)[I::S::
         xd[i] = V{0.0f, 0.0f};
         if (p >= 0)
             xd[i] = xmv(E[i], K[i], Da[p < 0 ? 0 : p], nDa[p < 0 ? 0 : p]);
-        Da[i] = add(xd[i], s_vec(ln, prismatic<I>(i), qdd[i]));
+        Da[i] = add_s(ln, prismatic<I>(i), xd[i], qdd[i]);
         nDa[i] = gather(Da[i]);
         Df[i] = imv(K[i], mass<I>(i), Da[i], nDa[i]);
     }

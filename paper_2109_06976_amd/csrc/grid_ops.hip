@@ -76,12 +76,13 @@ __device__ __forceinline__ void drnea_adjoint(const Lane& ln, const float (&qd)[
                 xu[i] = V{0.0f, 0.0f};
             }
             const bool pr = prismatic<I>(i);
-            v[i] = add(xv[i], s_vec(ln, pr, qd[i]));
+            v[i] = add_s(ln, pr, xv[i], qd[i]);
             nv[i] = gather(v[i]);
             const V vxs = cross_s(ln, pr, v[i]);
-            a[i] = add(V{xa[i].a + vxs.a * qd[i], xa[i].l + vxs.l * qd[i]}, s_vec(ln, pr, qdd[i]));
+            const V xs = add_s(ln, pr, xa[i], qdd[i]);
+            a[i] = V{xs.a + vxs.a * qd[i], xs.l + vxs.l * qd[i]};
             na[i] = gather(a[i]);
-            u[i] = add(xu[i], s_vec(ln, pr, w[i]));
+            u[i] = add_s(ln, pr, xu[i], w[i]);
             nu[i] = gather(u[i]);
             const float m = mass<I>(i);
             const V Iv = imv(K[i], m, v[i], nv[i]);
