@@ -281,60 +281,52 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     }
     os << "#line 1 \"grid_device.hip\"\n";
     os << grid_device_src;
+    // A dispatcher walks the branches: workgroups [0, nb_0) run branch 0, the next nb_1 run
+    // branch 1, and so on. The grid holds exactly sum nb_k workgroups, so the last branch
+    // takes the rest without a bound check: with one branch nothing waits for nknots before
+    // the other kernel arguments are loaded. (A workgroup past the end would still only
+    // recompute the last knot and store nothing: every store checks its knot.)
+    auto dispatch = [&](const char* sig, const std::string& per_block,
+                        const std::string& call) {
+        os << sig << "\n{\n    int b = block;\n";
+        for (size_t k = 0; k < t.insts.size(); ++k) {
+            const std::string K = "Inst<" + std::to_string(k) + ">";
+            auto sub = [&](std::string x) {
+                for (size_t at; (at = x.find("@")) != std::string::npos;)
+                    x.replace(at, 1, K);
+                return x;
+            };
+            if (k + 1 == t.insts.size()) {
+                os << "    " << sub(call) << ";\n";
+                break;
+            }
+            os << "    {\n        const int P = " << sub(per_block) << ";\n"
+               << "        const int nb = (a.nknots + P - 1) / P;\n"
+               << "        if (b < nb) {\n            " << sub(call) << ";\n            return;\n"
+               << "        }\n        b -= nb;\n    }\n";
+        }
+        os << "}\n";
+    };
     os << "\n// generated: workgroup -> (branch, knot group)\n";
-    os << "template <int ST>\n__device__ void grid_dispatch(const grid::Args& a, int block)\n{\n"
-          "    int b = block;\n";
-    for (size_t k = 0; k < t.insts.size(); ++k) {
-        os << "    {\n        constexpr int K = 64 / Inst<" << k << ">::S::L;\n"
-           << "        const int nb = (a.nknots + K - 1) / K;\n"
-           << "        if (b < nb) {\n            grid::run_branch<Inst<" << k
-           << ">, ST>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
-    }
-    os << "}\n";
+    dispatch("template <int ST>\n__device__ void grid_dispatch(const grid::Args& a, int block)",
+             "64 / @::S::L", "grid::run_branch<@, ST>(a, b)");
     os << "#line 1 \"grid_fused.hip\"\n";
     os << grid_fused_src;
     os << "\n// generated: workgroup -> (branch, problem group), quad layout\n";
-    os << "__device__ void grid_dispatch_q(const grid::Args& a, int block)\n{\n"
-          "    int b = block;\n";
-    for (size_t k = 0; k < t.insts.size(); ++k) {
-        const int P = quad_problems(t, t.shapes[t.insts[k].shape]);
-        os << "    {\n        const int nb = (a.nknots + " << P << " - 1) / " << P << ";\n"
-           << "        if (b < nb) {\n            gridq::run_fused<Inst<" << k
-           << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
-    }
-    os << "}\n";
+    dispatch("__device__ void grid_dispatch_q(const grid::Args& a, int block)",
+             "(GRID_WAVES / @::S::W) * (16 / @::S::Q)", "gridq::run_fused<@>(a, b)");
     os << "#line 1 \"grid_serial.hip\"\n";
     os << grid_serial_src;
     os << "\n// generated: workgroup -> (branch, 64 knots), one lane per knot\n";
-    os << "__device__ void grid_dispatch_s(const grid::Args& a, int block)\n{\n"
-          "    int b = block;\n";
-    for (size_t k = 0; k < t.insts.size(); ++k) {
-        os << "    {\n        const int nb = (a.nknots + 63) / 64;\n"
-           << "        if (b < nb) {\n            grids::run_serial<Inst<" << k
-           << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
-    }
-    os << "}\n";
-    os << "__device__ void grid_dispatch_p(const grid::Args& a, int block)\n{\n"
-          "    int b = block;\n";
-    for (size_t k = 0; k < t.insts.size(); ++k) {
-        const int P = pipe_problems(t.shapes[t.insts[k].shape].B);
-        os << "    {\n        const int nb = (a.nknots + " << P << " - 1) / " << P << ";\n"
-           << "        if (b < nb) {\n            gridq::run_pipe<Inst<" << k
-           << ">>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
-    }
-    os << "}\n";
+    dispatch("__device__ void grid_dispatch_s(const grid::Args& a, int block)", "64",
+             "grids::run_serial<@>(a, b)");
+    dispatch("__device__ void grid_dispatch_p(const grid::Args& a, int block)", "@::S::PP",
+             "gridq::run_pipe<@>(a, b)");
     os << "#line 1 \"grid_ops.hip\"\n";
     os << grid_ops_src;
     os << "\n// generated: workgroup -> (branch, problem group), standalone algorithms\n";
-    os << "template <int OP>\n__device__ void grid_dispatch_op(const gridq::OpArgs& a, int block)\n{\n"
-          "    int b = block;\n";
-    for (size_t k = 0; k < t.insts.size(); ++k) {
-        os << "    {\n        constexpr int P = gridq::op_problems<Inst<" << k << ">::S, OP>();\n"
-           << "        const int nb = (a.nknots + P - 1) / P;\n"
-           << "        if (b < nb) {\n            gridq::run_op<Inst<" << k
-           << ">, OP>(a, b);\n            return;\n        }\n        b -= nb;\n    }\n";
-    }
-    os << "}\n";
+    dispatch("template <int OP>\n__device__ void grid_dispatch_op(const gridq::OpArgs& a, int block)",
+             "gridq::op_problems<@::S, OP>()", "gridq::run_op<@, OP>(a, b)");
     return os.str();
 }
 

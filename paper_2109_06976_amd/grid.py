@@ -246,6 +246,26 @@ class Model:
                                   _stream_handle(stream)))
 
 
+    def fd_grad_call(self, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, N=None, stream=None):
+        """grid_fd_grad bound to fixed device buffers: returns a callable that makes the call.
+        For loops that launch on the same buffers again and again (the arguments are
+        converted to C once, which takes most of the Python-side cost of a call). The
+        callable keeps the buffers alive; it raises GridError like fd_grad."""
+        if N is None:
+            N = int(q.shape[0])
+        bufs = (q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd)
+        args = (self._h, C.c_int(int(N)), *(C.c_void_p(_addr(x)) for x in bufs),
+                C.c_void_p(_stream_handle(stream)))
+        fn = lib().grid_fd_grad
+
+        def call():
+            st = fn(*args)
+            if st != GRID_OK:
+                raise GridError(st, last_error())
+
+        call.buffers = bufs
+        return call
+
     # the paper's other algorithms (device buffers, asynchronous)
     def id(self, q, qd, qdd, tau, N=None, stream=None):
         """grid_id: tau = ID(q, qd, qdd)."""

@@ -173,3 +173,24 @@ def test_invalid_launch_arguments(torch_cuda):
     with pytest.raises(grid.GridError) as e:
         model.fd_grad(t, None, t, t, t, t, t, N=4)
     assert e.value.status == grid.GRID_EINVAL
+
+
+def test_bound_call_matches_plain_call(torch_cuda):
+    """fd_grad_call (arguments converted once, called repeatedly) gives bitwise the outputs of
+    fd_grad on the same buffers."""
+    robot, model = get_model("chain7")
+    say("[gpu] bound call chain7 N=77")
+    kn = synth.random_knots(robot.n, 77, 41)
+    ins = [torch_cuda.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)]
+    n = robot.n
+    outs = [torch_cuda.empty((77, n), device="cuda")] + \
+        [torch_cuda.empty((77, n, n), device="cuda") for _ in range(3)]
+    ref = run_device(torch_cuda, model, kn)
+    call = model.fd_grad_call(*ins, *outs)
+    for _ in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        call()
+        torch_cuda.cuda.synchronize()
+        for key, o in zip(OUTS, outs):
+            np.testing.assert_array_equal(o.cpu().numpy(), ref[key])
