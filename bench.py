@@ -52,18 +52,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
-    taken on the current kernel source, for this kernel and workload."""
+def measured_counters(workload: str, kernel: str):
+    """The committed rocprofv3 counter record (HBM bytes and VALU instructions per launch)
+    for this kernel and workload, if it was taken on the current kernel source."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
-        return None
+        return {}
     entry = rec.get(workload)
     if (not entry or entry.get("kernel_source_sha") != kernel_source_hash()
             or entry.get("kernel") != kernel):
-        return None
-    return entry.get("bytes_per_launch")
+        return {}
+    return entry
 
 
 def parse():
@@ -274,7 +274,9 @@ def main():
     flop_launch = fl["total"] * N
     achieved_tflops = flop_launch / (avg_ms * 1e-3) / 1e12
     workload = f"{args.robot}-N{N}"
-    traffic = measured_traffic(workload, grid.BUILD_KERNELS[build])
+    counters = measured_counters(workload, grid.BUILD_KERNELS[build])
+    traffic = counters.get("bytes_per_launch")
+    executed = counters.get("executed_fp32_flop_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 4), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_TFLOPS,
                 "traffic": traffic,
@@ -282,7 +284,12 @@ def main():
                 "flop_per_knot": fl["total"],
                 "hbm_bytes_per_launch": flops.io_bytes_per_knot(n) * N,
                 "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                "launch_floor_us": round(floor_gpu * 1e6, 3)}
+                "launch_floor_us": round(floor_gpu * 1e6, 3),
+                # FP32 FLOP the kernel executes per launch (rocprofv3 VALU instruction counters
+                # over all 64 lanes; counts the layout's redundant work), and its rate
+                "executed_flop_per_launch": executed,
+                "executed_tflops": (round(executed / (avg_ms * 1e-3) / 1e12, 4)
+                                    if executed else None)}
 
     result = {
         "metric": "dFD knot-evals/sec (7-DoF chain, N=128) + p50/p99 latency served, vs plain",

@@ -24,8 +24,10 @@
 //   role B (B columns, one or two per quad, one wavefront): M and its factor; qdd once
 //                        role A has published the bias forces; RNEA increments at qdd; the
 //                        part of each q-column that depends on qdd
-//   role C (B columns, one wavefront; branches of up to 16 bodies, beyond which role B
-//                        does this itself): once role B has published M, its factor and M^-1
+//   role C (B columns, one wavefront; branches of up to 16 bodies): once role B has
+//                        published M, its factor and M^-1. Beyond 16 bodies role B publishes
+//                        its factor instead, and role A ends with two triangular solves per
+//                        column, the qd-columns also solving for the columns of M^-1
 // dtau/dqd does not depend on qdd, and dtau/dq is affine in the two source terms that do:
 // the parent acceleration (X_j a_lambda(j)) x S enters the forward sweep and the term
 // X_j^T (S x* f_j) the backward sweep, each linearly, so the qdd part of a q-column is the
@@ -745,7 +747,9 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     static_assert(PS::WAVES <= GRID_PIPE_WAVES, "workgroup too small for the shape");
     __shared__ float s_c[P][B];               // bias forces c (role A -> B)
     __shared__ float s_M[P][B][B];            // M columns (role B -> B, C)
-    __shared__ float s_Mi[P][B][B];           // M^-1, row-major (role C -> A)
+    __shared__ float s_Mi[P][B][B];           // M^-1, row-major (role C -> A); beyond 16
+                                              // bodies the factor L instead (B -> A)
+    __shared__ float s_dinv[P][B];            // 1 / L_kk beyond 16 bodies (B -> A)
     __shared__ float s_D[P][B][B];            // qdd part of the q-columns, [column][row] (B -> A)
 
     const int tid = (int)threadIdx.x;
@@ -798,6 +802,42 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
 #pragma unroll
         for (int i = 0; i < B; ++i)
             dx[i] += qpart * s_D[pslot][j][i];
+        const int lp = PS::WA == 1 ? lane % (4 * QA) : lane + 64 * wave;
+        if constexpr (!PS::HASC) {
+            // beyond 16 bodies: dqdd/du_j = -(L^T L)^-1 dtau/du_j by the two triangular solves
+            // with role B's factor, and the quad of column (qd, j) also solves for column j of
+            // M^-1 (entries (i, j), i <= j, to both mirrored positions: exactly symmetric)
+            float Lf[B][B], dinv[B], mc[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                dinv[i] = s_dinv[pslot][i];
+                mc[i] = (i == j) ? 1.0f : 0.0f;
+#pragma unroll
+                for (int b = 0; b < i; ++b)
+                    if (is_anc<S>(b, i))
+                        Lf[i][b] = s_Mi[pslot][i][b];
+            }
+            ltl_solve<S>(Lf, dinv, dx);
+            ltl_solve<S>(Lf, dinv, mc);
+            if (!valid)
+                return;
+            const int gj = I::body_of(j);
+            float* out = u == 0 ? A.dqdd_dq : A.dqdd_dqd;
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                if ((i & 3) != c || !owns_col)
+                    continue;
+                const int gi = I::body[i];
+                out[mbase + (long)gi * N + gj] = -dx[i];
+                if (u == 1 && i <= j) {
+                    A.Minv[mbase + (long)gi * N + gj] = mc[i];
+                    A.Minv[mbase + (long)gj * N + gi] = mc[i];
+                }
+            }
+            zero_fill<I>(A.Minv, nullptr, mbase, lp, 64 * PS::WA);
+            zero_fill<I>(A.dqdd_dq, A.dqdd_dqd, mbase, lp, 64 * PS::WA);
+            return;
+        }
         if (!valid)
             return;
         // dqdd/du_j = -M^-1 dtau/du_j; lane c of the quad computes and stores rows c, c+4, ..
@@ -816,7 +856,6 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 }
             }
         }
-        const int lp = PS::WA == 1 ? lane % (4 * QA) : lane + 64 * wave;
         zero_fill<I>(A.dqdd_dq, A.dqdd_dqd, mbase, lp, PS::WA == 1 ? 4 * QA : 64 * PS::WA);
     } else if (wave == BWAVE) {
         // -------------------------------------------------------- role B
@@ -863,9 +902,20 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 if (b == i || is_anc<S>(b, i))
                     Lf[i][b] = s_M[pslot][i][b];
         ltl_factor<S>(Lf, dinv);
-        if constexpr (!PS::HASC)
-            minv_columns<I, CB>(A.Minv, Lf, dinv, pslot, s, c, valid, mbase, lane % (4 * QB), 4 * QB,
-                                s_Mi);
+        if constexpr (!PS::HASC) {
+            // no role C beyond 16 bodies: the factor goes to role A, which finishes with
+            // triangular solves (and the columns of M^-1) after the second barrier
+            if (lane == 0) {
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    s_dinv[pslot][i] = dinv[i];
+#pragma unroll
+                    for (int b = 0; b < i; ++b)
+                        if (is_anc<S>(b, i))
+                            s_Mi[pslot][i][b] = Lf[i][b];
+                }
+            }
+        }
         __syncthreads();                      // c published
 
         float x[B];
