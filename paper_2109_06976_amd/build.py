@@ -84,7 +84,18 @@ def standard_models():
     # prismatic joints (with revolute ones; random axes; on a branch beyond 16 bodies;
     # with fixed joints, one welded to a prismatic owner)
     models.extend(prismatic_models().values())
+    # the largest robot the library accepts (32 bodies)
+    models.append(max_size_model())
     return models
+
+
+def max_size_model():
+    """32 bodies (the library's maximum): the humanoid with a hand on each arm, so the
+    torso tree is one branch of 20 bodies."""
+    import numpy as np
+    from paper_2109_06976_amd import synth
+    parent = np.concatenate([synth.humanoid_parent(), np.array([22, 29], np.int32)])
+    return synth.random_model(parent.astype(np.int32), 47, "humanoid32")
 
 
 def prismatic_models():
@@ -117,13 +128,26 @@ def offline_compile_check(verbose=False):
               "-save-temps=obj", "-o", out, path], verbose)
 
 
-def precompile(verbose=False):
+def _precompile_one(robot):
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
     from paper_2109_06976_amd import grid
-    for robot in standard_models():
-        grid.codegen_precompile(robot)
-        if verbose:
-            print(f"cached kernel for {robot.name} parent={list(map(int, robot.parent))}",
-                  flush=True)
+    grid.codegen_precompile(robot)
+    return robot.name
+
+
+def precompile(verbose=False, workers=None):
+    """Compile every standard model's kernels into the cache, several at a time (one
+    process each: a compile is single-threaded), the largest robots first."""
+    import concurrent.futures
+    import multiprocessing
+    robots = sorted(standard_models(), key=lambda r: -r.n)
+    workers = workers or max(1, min(8, os.cpu_count() or 1))
+    ctx = multiprocessing.get_context("fork")
+    with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as pool:
+        for name in pool.map(_precompile_one, robots):
+            if verbose:
+                print(f"cached kernels for {name}", flush=True)
 
 
 def build(verbose=False):

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2109_06976_amd import grid, synth
-from paper_2109_06976_amd.build import prismatic_models
+from paper_2109_06976_amd.build import max_size_model, prismatic_models
 
 pytestmark = pytest.mark.gpu
 
@@ -36,6 +36,8 @@ ROBOTS = {
     "chain7-prism": lambda: prismatic_models()["chain7-prism"],
     "tree5-axes-prism": lambda: prismatic_models()["tree5-axes-prism"],
     "humanoid30-prism": lambda: prismatic_models()["humanoid30-prism"],
+    # the largest robot the library accepts: 32 bodies, one branch of 20
+    "humanoid32": max_size_model,
 }
 
 
