@@ -26,7 +26,6 @@ Also reported (extra fields of the same line):
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -41,27 +40,16 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused.json")
 
 
-KERNEL_SOURCES = ("grid_device.hip", "grid_fused.hip", "grid_serial.hip", "grid_codegen.cpp")
-
-
-def kernel_source_hash() -> str:
-    """Hash of everything the generated kernels are made from."""
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2109_06976_amd", "csrc", name), "rb").read())
-    return h.hexdigest()[:16]
-
-
-def measured_counters(workload: str, kernel: str):
+def measured_counters(workload: str, kernel: str, code_hash: str):
     """The committed rocprofv3 counter record (HBM bytes and VALU instructions per launch)
-    for this kernel and workload, if it was taken on the current kernel source."""
+    for this kernel and workload, if it was taken on the same machine code (the hash of the
+    model's loaded code object)."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return {}
     entry = rec.get(workload)
-    if (not entry or entry.get("kernel_source_sha") != kernel_source_hash()
-            or entry.get("kernel") != kernel):
+    if not entry or entry.get("code_hash") != code_hash or entry.get("kernel") != kernel:
         return {}
     return entry
 
@@ -274,7 +262,7 @@ def main():
     flop_launch = fl["total"] * N
     achieved_tflops = flop_launch / (avg_ms * 1e-3) / 1e12
     workload = f"{args.robot}-N{N}"
-    counters = measured_counters(workload, grid.BUILD_KERNELS[build])
+    counters = measured_counters(workload, grid.BUILD_KERNELS[build], model.code_hash)
     traffic = counters.get("bytes_per_launch")
     executed = counters.get("executed_fp32_flop_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 4), "peak": PEAK_FP32_TFLOPS,
@@ -285,6 +273,7 @@ def main():
                 "hbm_bytes_per_launch": flops.io_bytes_per_knot(n) * N,
                 "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                 "launch_floor_us": round(floor_gpu * 1e6, 3),
+                "code_hash": model.code_hash,
                 # FP32 FLOP the kernel executes per launch (rocprofv3 VALU instruction counters
                 # over all 64 lanes; counts the layout's redundant work), and its rate
                 "executed_flop_per_launch": executed,

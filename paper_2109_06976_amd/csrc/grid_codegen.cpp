@@ -263,6 +263,35 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
            << "] = ";
         emit_floats(os, consts.data() + in.coff, in.body.size() * kConstStride);
         os << ";\n";
+        // per-lane constants of the quad layout for lane component c = 0, 1, 2, 16 floats
+        // per (c, body): r_c+1, r_c+2, Ibar_cc, Ibar_c,c+1, Ibar_c+2,c, h_c+1, h_c+2, then
+        // E_T[row][(c + col) % 3] for row, col = 0..2 (indices mod 3); read through LDS
+        {
+            const int B = (int)in.body.size();
+            std::vector<float> lk((size_t)3 * B * 16);
+            for (int c = 0; c < 3; ++c)
+                for (int i = 0; i < B; ++i) {
+                    const float* b = consts.data() + in.coff + (size_t)i * kConstStride;
+                    const float* r = b + 9;
+                    const float* Ib = b + 12;   // xx yy zz xy xz yz
+                    const float* h = b + 18;
+                    const float ic1[3] = {Ib[3], Ib[5], Ib[4]};   // xy, yz, zx
+                    float* o = lk.data() + ((size_t)c * B + i) * 16;
+                    o[0] = r[(c + 1) % 3];
+                    o[1] = r[(c + 2) % 3];
+                    o[2] = Ib[c];
+                    o[3] = ic1[c];
+                    o[4] = ic1[(c + 2) % 3];
+                    o[5] = h[(c + 1) % 3];
+                    o[6] = h[(c + 2) % 3];
+                    for (int row = 0; row < 3; ++row)
+                        for (int col = 0; col < 3; ++col)
+                            o[7 + 3 * row + col] = b[3 * row + (c + col) % 3];
+                }
+            os << "__device__ alignas(16) const float grid_lk_" << k << "[" << lk.size() << "] = ";
+            emit_floats(os, lk.data(), lk.size());
+            os << ";\n";
+        }
         os << "template <> struct Inst<" << k << "> {\n";
         os << "    using S = Shape<" << in.shape << ">;\n";
         os << "    static constexpr int body[S::B] = ";
@@ -277,6 +306,7 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
               "        return r;\n    }\n";
         os << "    __device__ static bool contains(int g) { return (mask >> g) & 1ull; }\n";
         os << "    __device__ static const float* consts() { return grid_const_" << k << "; }\n";
+        os << "    __device__ static const float* lanek() { return grid_lk_" << k << "; }\n";
         os << "};\n";
     }
     os << "#line 1 \"grid_device.hip\"\n";

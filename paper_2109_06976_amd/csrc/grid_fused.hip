@@ -263,6 +263,46 @@ __device__ __forceinline__ void load_bodies(const float* q_in, const float* qd_i
     }
 }
 
+// As load_bodies, with the per-lane constants read from the model's lane table (copied to
+// LDS by the workgroup; `tab` points at this lane's component): per body four 16-byte reads
+// (r_c+1, r_c+2, Ibar_cc, Ibar_c,c+1, Ibar_c+2,c, h_c+1, h_c+2 and E_T[row][(c + col) % 3])
+// instead of the one-hot picks and permutations of the literals.
+template <class I>
+__device__ __forceinline__ void load_bodies_lds(const float* q_in, const float* qd_in, long vbase,
+                                                const Lane& ln, const float* tab,
+                                                float (&qd)[I::S::B], Rot (&E)[I::S::B],
+                                                LaneK (&K)[I::S::B])
+{
+#pragma unroll
+    for (int i = 0; i < I::S::B; ++i) {
+        const float4* t = reinterpret_cast<const float4*>(tab + i * 16);
+        const float4 t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3];
+        // t1.w, t2, t3: E_T[row][(c + col) % 3] at 3 row + col
+        const float pT[3][3] = {{t1.w, t2.x, t2.y}, {t2.z, t2.w, t3.x}, {t3.y, t3.z, t3.w}};
+        const long o = vbase + I::body[i];
+        const float qi = q_in[o];
+        qd[i] = qd_in[o];
+        K[i] = LaneK{t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z};
+        float sn = 0.0f, co = 1.0f;                      // prismatic: E = E_T
+        if (prismatic<I>(i)) {
+            // r = r_T + q E_T^T e_z: components c+1 and c+2 of the third row of E_T
+            K[i].rr1 += qi * pT[2][1];
+            K[i].rr2 += qi * pT[2][2];
+        } else {
+            const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
+            sn = __builtin_amdgcn_sinf(rev);
+            co = __builtin_amdgcn_cosf(rev);
+        }
+        const float al = ln.oh0 * co - ln.oh1 * sn;
+        const float be = ln.oh0 * sn + ln.oh1 * co;
+        E[i].e0 = al * pT[0][0] + be * pT[1][0] + ln.oh2 * pT[2][0];
+        E[i].e1 = al * pT[0][1] + be * pT[1][1] + ln.oh2 * pT[2][1];
+        E[i].e2 = al * pT[0][2] + be * pT[1][2] + ln.oh2 * pT[2][2];
+        E[i].f1 = qperm<kNb1>(E[i].e2);
+        E[i].f2 = qperm<kNb2>(E[i].e1);
+    }
+}
+
 // RNEA(q, qd, 0): v_i, gamma_i = I_i v_i, f_i accumulated inward, and xa0_i = X_i a_lambda(i)
 template <class I>
 __device__ __forceinline__ void rnea0(const Lane& ln, const float (&qd)[I::S::B],
@@ -751,12 +791,17 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                                               // bodies the factor L instead (B -> A)
     __shared__ float s_dinv[P][B];            // 1 / L_kk beyond 16 bodies (B -> A)
     __shared__ float s_D[P][B][B];            // qdd part of the q-columns, [column][row] (B -> A)
+    __shared__ float4 s_tab[3 * B * 4];       // the model's lane table (roles A, B)
 
     const int tid = (int)threadIdx.x;
     const int wave = tid / 64;
     const int lane = tid % 64;
     const int c = lane & 3;
     const Lane ln = lane_of(c == 3 ? 0 : c);
+    for (int e = tid; e < 3 * B * 4; e += 64 * GRID_PIPE_WAVES)
+        s_tab[e] = reinterpret_cast<const float4*>(I::lanek())[e];
+    __syncthreads();                          // lane table in LDS
+    const float* tab = reinterpret_cast<const float*>(s_tab) + (c == 3 ? 0 : c) * B * 16;
 
     if (wave < PS::AW) {
         // -------------------------------------------------------- role A
@@ -775,7 +820,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         float qd[B];
         Rot E[B];
         LaneK K[B];
-        load_bodies<I>(A.q, A.qd, vbase, ln, qd, E, K);
+        load_bodies_lds<I>(A.q, A.qd, vbase, ln, tab, qd, E, K);
         V v[B], gam[B], F[B], xa0[B];
         rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
         if (s == 0 && c == 2) {               // quad 0 of each problem publishes c
@@ -874,12 +919,11 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
             js[cb] = owns[cb] ? s + 16 * cb : 0;
         }
         const long vbase = (long)knot * N;
-        const long mbase = (long)knot * N * N;
 
         float qd[B];
         Rot E[B];
         LaneK K[B];
-        load_bodies<I>(A.q, A.qd, vbase, ln, qd, E, K);
+        load_bodies_lds<I>(A.q, A.qd, vbase, ln, tab, qd, E, K);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             V fm[B];

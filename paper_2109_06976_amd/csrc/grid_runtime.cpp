@@ -508,6 +508,7 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     m->device = device;
     m->flags = flags;
     m->topo = std::move(topo);
+    m->code_hash = source_hash(std::string(code.begin(), code.end()));
     static const char* const kStages[5] = {"grid_stage_rnea", "grid_stage_minv", "grid_stage_qdd",
                                            "grid_stage_drnea", "grid_stage_fdgrad"};
     static const char* const kVariants[kNumVariants] = {
@@ -556,6 +557,14 @@ grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
         *io_bytes_per_knot = sizeof(float) * (3 * nn + nn + 3 * nn * nn);
     if (lanes)
         *lanes = lanes_per_knot(m->topo);
+    return GRID_OK;
+}
+
+grid_status grid_model_code_hash(grid_model m, uint64_t* hash)
+{
+    if (!m || !hash)
+        return fail(GRID_EINVAL, "model and hash must not be NULL");
+    *hash = m->code_hash;
     return GRID_OK;
 }
 

@@ -88,6 +88,7 @@ _SIGS = {
     "grid_model_create": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_uint32,
                                       C.POINTER(C.c_void_p)]),
     "grid_model_destroy": (C.c_int32, [C.c_void_p]),
+    "grid_model_code_hash": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "grid_model_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_size_t),
                                     C.POINTER(C.c_int32)]),
     "grid_fd_grad": (C.c_int32, [C.c_void_p, C.c_int32] + [C.c_void_p] * 7 + [C.c_void_p]),
@@ -225,6 +226,13 @@ class Model:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def code_hash(self) -> str:
+        """grid_model_code_hash: hash of the loaded code object, as 16 hex digits."""
+        h = C.c_uint64()
+        _check(lib().grid_model_code_hash(self._h, C.byref(h)))
+        return f"{h.value:016x}"
 
     def close(self):
         if self._h is not None and self._h.value:
