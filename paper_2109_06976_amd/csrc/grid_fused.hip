@@ -6,8 +6,8 @@
 // through DPP quad permutations, so a transform, an inertia product or a cross product
 // costs a few DPP moves and about three FMAs per lane instead of a whole 6-vector per lane.
 // A quad owns one derivative column (u, j) of a (knot, branch) problem, and all quads of a
-// problem run the shared sweeps in lockstep. Every model constant is an instruction literal;
-// a lane picks its components with a one-hot of c and takes its neighbours' by DPP.
+// problem run the shared sweeps in lockstep. The per-lane model constants come from a lane
+// table generated with the model and copied to LDS by each workgroup.
 //
 // Steps per (knot, branch), float32 (Sec. IV-B): transforms; RNEA(q, qd, 0); column s of M
 // as ID(q, 0, e_s) without gravity; M = L^T L along ancestor paths; qdd; RNEA at qdd as the
@@ -87,12 +87,6 @@ __device__ __forceinline__ Lane lane_of(int c3)
     return Lane{c3 == 0 ? 1.0f : (c3 == 1 ? -1.0f : 0.0f), c3 == 2 ? 1.0f : 0.0f,
                 c3 == 0 ? grid_a0[0] : (c3 == 1 ? grid_a0[1] : grid_a0[2]),
                 c3 == 0 ? 1.0f : 0.0f, c3 == 1 ? 1.0f : 0.0f, c3 == 2 ? 1.0f : 0.0f};
-}
-
-// component c of a 3-vector given as three literals (products with the one-hot are exact)
-__device__ __forceinline__ float comp(const Lane& ln, float x0, float x1, float x2)
-{
-    return ln.oh0 * x0 + ln.oh1 * x1 + ln.oh2 * x2;
 }
 
 // X m = [E w; E (v - r x w)]
@@ -208,67 +202,28 @@ __device__ __forceinline__ float mass(int i)
 
 // ------------------------------------------------------------------ building blocks
 
-// The lane's share of every body: E_i = E_z(q_i) E_T,i from the hardware sin and cos (angle
-// in revolutions, reduced to [0, 1)), or E_i = E_T,i and r_i = r_T,i + q_i E_T,i^T e_z for a
-// prismatic joint, and the body constants, all from the model's literals
-// (no table: per-lane loads of constants would all pass through the CU's texture data path).
-// Row c of E is alpha E_T,0 + beta E_T,1 + gamma E_T,2 with (alpha, beta, gamma) = (cos, sin, 0),
-// (-sin, cos, 0), (0, 0, 1) for c = 0, 1, 2 (rows of E_z). The lane keeps its row in the order
-// (E_cc, E_c,c+1, E_c,c+2); the column entries E_c+1,c and E_c+2,c are the neighbours' third
-// and second row entries. Likewise r_c, h_c, Ibar_cc, Ibar_c,c+1 are picked by the one-hot and
-// the other components come from the neighbours (Ibar_c,c+2 = Ibar_c+2,c).
-template <class I, bool kQd = true>
-__device__ __forceinline__ void load_bodies(const float* q_in, const float* qd_in, long vbase,
-                                            const Lane& ln, float (&qd)[I::S::B],
-                                            Rot (&E)[I::S::B], LaneK (&K)[I::S::B])
+// The workgroup copies the model's lane table of branch I to LDS (16 floats per lane
+// component c and body: r_c+1, r_c+2, Ibar_cc, Ibar_c,c+1, Ibar_c+2,c, h_c+1, h_c+2 and
+// E_T[row][(c + col) % 3]); returns this lane's part. Every thread of the workgroup calls it.
+template <class I, int THREADS>
+__device__ __forceinline__ const float* lane_table(float4 (&s_tab)[3 * I::S::B * 4], int tid,
+                                                   int c)
 {
-#pragma unroll
-    for (int i = 0; i < I::S::B; ++i) {
-        const float* k = I::consts() + i * kConstStride;   // E_T, r, Ibar, h, m
-        const float r_c = comp(ln, k[9], k[10], k[11]);
-        const float h_c = comp(ln, k[18], k[19], k[20]);
-        const float i_cc = comp(ln, k[12], k[13], k[14]);   // xx, yy, zz
-        const float i_c1 = comp(ln, k[15], k[17], k[16]);   // xy, yz, zx
-        K[i] = LaneK{qperm<kNb1>(r_c), qperm<kNb2>(r_c), i_cc, i_c1, qperm<kNb2>(i_c1),
-                     qperm<kNb1>(h_c), qperm<kNb2>(h_c)};
-    }
-#pragma unroll
-    for (int i = 0; i < I::S::B; ++i) {
-        const long o = vbase + I::body[i];
-        const float* k = I::consts() + i * kConstStride;
-        const float qi = q_in[o];
-        float sn = 0.0f, co = 1.0f;                      // prismatic: E = E_T
-        if (prismatic<I>(i)) {
-            // translation along the joint z axis: r = r_T + q E_T^T e_z
-            const float r_c = comp(ln, k[9] + qi * k[6], k[10] + qi * k[7], k[11] + qi * k[8]);
-            K[i].rr1 = qperm<kNb1>(r_c);
-            K[i].rr2 = qperm<kNb2>(r_c);
-        } else {
-            const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
-            sn = __builtin_amdgcn_sinf(rev);
-            co = __builtin_amdgcn_cosf(rev);
-        }
-        qd[i] = kQd ? qd_in[o] : 0.0f;
-        const float al = ln.oh0 * co - ln.oh1 * sn;
-        const float be = ln.oh0 * sn + ln.oh1 * co;
-        float R[3];                                      // row c of E, columns 0, 1, 2
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            R[j] = al * k[j] + be * k[3 + j] + ln.oh2 * k[6 + j];
-        E[i].e0 = comp(ln, R[0], R[1], R[2]);
-        E[i].e1 = comp(ln, R[1], R[2], R[0]);
-        E[i].e2 = comp(ln, R[2], R[0], R[1]);
-        E[i].f1 = qperm<kNb1>(E[i].e2);
-        E[i].f2 = qperm<kNb2>(E[i].e1);
-    }
+    for (int e = tid; e < 3 * I::S::B * 4; e += THREADS)
+        s_tab[e] = reinterpret_cast<const float4*>(I::lanek())[e];
+    __syncthreads();                          // lane table in LDS
+    return reinterpret_cast<const float*>(s_tab) + (c == 3 ? 0 : c) * I::S::B * 16;
 }
 
-// As load_bodies, with the per-lane constants read from the model's lane table (copied to
-// LDS by the workgroup; `tab` points at this lane's component): per body four 16-byte reads
-// (r_c+1, r_c+2, Ibar_cc, Ibar_c,c+1, Ibar_c+2,c, h_c+1, h_c+2 and E_T[row][(c + col) % 3])
-// instead of the one-hot picks and permutations of the literals.
-template <class I>
-__device__ __forceinline__ void load_bodies_lds(const float* q_in, const float* qd_in, long vbase,
+// The lane's share of every body: E_i = E_z(q_i) E_T,i from the hardware sin and cos (angle
+// in revolutions, reduced to [0, 1)), or E_i = E_T,i and r_i = r_T,i + q_i E_T,i^T e_z for a
+// prismatic joint, and the per-lane constants from the lane table (`tab`, this lane's part):
+// four 16-byte LDS reads per body. Row c of E is alpha E_T,0 + beta E_T,1 + gamma E_T,2 with
+// (alpha, beta, gamma) = (cos, sin, 0), (-sin, cos, 0), (0, 0, 1) for c = 0, 1, 2 (rows of
+// E_z); the lane keeps its row in the order (E_cc, E_c,c+1, E_c,c+2), and the column entries
+// E_c+1,c and E_c+2,c are the neighbours' third and second row entries.
+template <class I, bool kQd = true>
+__device__ __forceinline__ void load_bodies(const float* q_in, const float* qd_in, long vbase,
                                                 const Lane& ln, const float* tab,
                                                 float (&qd)[I::S::B], Rot (&E)[I::S::B],
                                                 LaneK (&K)[I::S::B])
@@ -281,7 +236,7 @@ __device__ __forceinline__ void load_bodies_lds(const float* q_in, const float* 
         const float pT[3][3] = {{t1.w, t2.x, t2.y}, {t2.z, t2.w, t3.x}, {t3.y, t3.z, t3.w}};
         const long o = vbase + I::body[i];
         const float qi = q_in[o];
-        qd[i] = qd_in[o];
+        qd[i] = kQd ? qd_in[o] : 0.0f;
         K[i] = LaneK{t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z};
         float sn = 0.0f, co = 1.0f;                      // prismatic: E = E_T
         if (prismatic<I>(i)) {
@@ -605,6 +560,7 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
     constexpr int P = (WB / W) * PW;          // problems per workgroup
     constexpr int N = GRID_N;
     __shared__ float s_M[P][B][B];
+    __shared__ float4 s_tab[3 * B * 4];
 
     const int tid = (int)threadIdx.x;
     const int wave = tid / 64;
@@ -630,7 +586,7 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
     float qd[B];
     Rot E[B];
     LaneK K[B];
-    load_bodies<I>(A.q, A.qd, vbase, ln, qd, E, K);
+    load_bodies<I>(A.q, A.qd, vbase, ln, lane_table<I, 64 * WB>(s_tab, tid, c), qd, E, K);
 
     V v[B], gam[B], F[B], xa0[B];
     rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
@@ -798,10 +754,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     const int lane = tid % 64;
     const int c = lane & 3;
     const Lane ln = lane_of(c == 3 ? 0 : c);
-    for (int e = tid; e < 3 * B * 4; e += 64 * GRID_PIPE_WAVES)
-        s_tab[e] = reinterpret_cast<const float4*>(I::lanek())[e];
-    __syncthreads();                          // lane table in LDS
-    const float* tab = reinterpret_cast<const float*>(s_tab) + (c == 3 ? 0 : c) * B * 16;
+    const float* tab = lane_table<I, 64 * GRID_PIPE_WAVES>(s_tab, tid, c);
 
     if (wave < PS::AW) {
         // -------------------------------------------------------- role A
@@ -820,7 +773,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         float qd[B];
         Rot E[B];
         LaneK K[B];
-        load_bodies_lds<I>(A.q, A.qd, vbase, ln, tab, qd, E, K);
+        load_bodies<I>(A.q, A.qd, vbase, ln, tab, qd, E, K);
         V v[B], gam[B], F[B], xa0[B];
         rnea0<I>(ln, qd, E, K, v, gam, F, xa0);
         if (s == 0 && c == 2) {               // quad 0 of each problem publishes c
@@ -923,7 +876,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         float qd[B];
         Rot E[B];
         LaneK K[B];
-        load_bodies_lds<I>(A.q, A.qd, vbase, ln, tab, qd, E, K);
+        load_bodies<I>(A.q, A.qd, vbase, ln, tab, qd, E, K);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             V fm[B];

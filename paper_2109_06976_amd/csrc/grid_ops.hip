@@ -132,6 +132,7 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
                                         : PipeShape<B>::QB;   // quads per problem per wavefront
     constexpr int W = OP == kOpIdGrad ? S::W : 1;             // wavefronts per problem
     __shared__ float s_M[OP == kOpFd || OP == kOpMinv || OP == kOpVjp ? P : 1][B][B];
+    __shared__ float4 s_tab[3 * B * 4];
 
     const int tid = (int)threadIdx.x;
     const int wave = tid / 64;
@@ -150,7 +151,8 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
     float qd[B];
     Rot E[B];
     LaneK K[B];
-    load_bodies<I, OP != kOpMinv>(A.q, A.qd, vbase, ln, qd, E, K);
+    const float* tab = lane_table<I, OP == kOpIdGrad ? 64 * GRID_WAVES : 64>(s_tab, tid, c);
+    load_bodies<I, OP != kOpMinv>(A.q, A.qd, vbase, ln, tab, qd, E, K);
 
     if constexpr (OP == kOpId || OP == kOpIdGrad) {
         float qdd[B];
