@@ -26,8 +26,9 @@
 //                        part of each q-column that depends on qdd
 //   role C (B columns, one wavefront; branches of up to 16 bodies): once role B has
 //                        published M, its factor and M^-1. Beyond 16 bodies role B publishes
-//                        its factor instead, and role A ends with two triangular solves per
-//                        column, the qd-columns also solving for the columns of M^-1
+//                        its factor instead: role A's qd-columns solve for the columns of
+//                        M^-1 before the second barrier, and every column ends with two
+//                        triangular solves
 // dtau/dqd does not depend on qdd, and dtau/dq is affine in the two source terms that do:
 // the parent acceleration (X_j a_lambda(j)) x S enters the forward sweep and the term
 // X_j^T (S x* f_j) the backward sweep, each linearly, so the qdd part of a q-column is the
@@ -794,18 +795,13 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         const V src_f = u == 0 ? zeta : V{0.0f, 0.0f};
         float dx[B];
         drnea_column<I, true>(ln, qd, E, K, v, gam, j, src_v, src_a, src_f, dx);
-        __syncthreads();                      // M^-1 and the qdd parts published
-
-        const float qpart = u == 0 ? 1.0f : 0.0f;
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-            dx[i] += qpart * s_D[pslot][j][i];
         const int lp = PS::WA == 1 ? lane % (4 * QA) : lane + 64 * wave;
+        float Lf[B][B], dinv[B];              // beyond 16 bodies: role B's factor
         if constexpr (!PS::HASC) {
-            // beyond 16 bodies: dqdd/du_j = -(L^T L)^-1 dtau/du_j by the two triangular solves
-            // with role B's factor, and the quad of column (qd, j) also solves for column j of
-            // M^-1 (entries (i, j), i <= j, to both mirrored positions: exactly symmetric)
-            float Lf[B][B], dinv[B], mc[B];
+            // the factor has been in LDS since the first barrier: the quad of column (qd, j)
+            // solves for column j of M^-1 while role B is still on the qdd parts (entries
+            // (i, j), i <= j, to both mirrored positions: exactly symmetric)
+            float mc[B];
 #pragma unroll
             for (int i = 0; i < B; ++i) {
                 dinv[i] = s_dinv[pslot][i];
@@ -815,8 +811,29 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                     if (is_anc<S>(b, i))
                         Lf[i][b] = s_Mi[pslot][i][b];
             }
-            ltl_solve<S>(Lf, dinv, dx);
             ltl_solve<S>(Lf, dinv, mc);
+            if (valid) {
+                const int gj = I::body_of(j);
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    if ((i & 3) != c || !owns_col || u != 1 || i > j)
+                        continue;
+                    const int gi = I::body[i];
+                    A.Minv[mbase + (long)gi * N + gj] = mc[i];
+                    A.Minv[mbase + (long)gj * N + gi] = mc[i];
+                }
+                zero_fill<I>(A.Minv, nullptr, mbase, lp, 64 * PS::WA);
+            }
+        }
+        __syncthreads();                      // M^-1 and the qdd parts published
+
+        const float qpart = u == 0 ? 1.0f : 0.0f;
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            dx[i] += qpart * s_D[pslot][j][i];
+        if constexpr (!PS::HASC) {
+            // beyond 16 bodies: dqdd/du_j = -(L^T L)^-1 dtau/du_j by the two triangular solves
+            ltl_solve<S>(Lf, dinv, dx);
             if (!valid)
                 return;
             const int gj = I::body_of(j);
@@ -825,14 +842,8 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
             for (int i = 0; i < B; ++i) {
                 if ((i & 3) != c || !owns_col)
                     continue;
-                const int gi = I::body[i];
-                out[mbase + (long)gi * N + gj] = -dx[i];
-                if (u == 1 && i <= j) {
-                    A.Minv[mbase + (long)gi * N + gj] = mc[i];
-                    A.Minv[mbase + (long)gj * N + gi] = mc[i];
-                }
+                out[mbase + (long)I::body[i] * N + gj] = -dx[i];
             }
-            zero_fill<I>(A.Minv, nullptr, mbase, lp, 64 * PS::WA);
             zero_fill<I>(A.dqdd_dq, A.dqdd_dqd, mbase, lp, 64 * PS::WA);
             return;
         }
