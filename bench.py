@@ -195,9 +195,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the batched gradient of forward dynamics shards "
-              "knots across GPUs with no exchange, and this build runs on a single MI355X "
-              "(use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): the batched gradient of forward dynamics "
+              "shards knots across GPUs with no exchange, so a multi-GPU figure is N times "
+              "one GPU's share and is not measured here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -56,7 +56,7 @@ typedef int32_t grid_status;
 #define GRID_EINVAL (-1)        /* bad argument or model description */
 #define GRID_ENOMEM (-2)        /* device or host allocation failed */
 #define GRID_EDEVICE (-3)       /* HIP runtime error, no device, or a kernel fault */
-#define GRID_EUNSUPPORTED (-4)  /* valid request this build does not implement */
+#define GRID_EUNSUPPORTED (-4)  /* valid request the library does not implement */
 #define GRID_ECOMPILE (-5)      /* generating or compiling the robot's kernel failed */
 #define GRID_EBUSY (-6)         /* a request larger than the server's admission budget */
 #define GRID_ETIMEDOUT (-7)     /* the wait ended before the request completed */

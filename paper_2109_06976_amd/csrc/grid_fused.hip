@@ -168,11 +168,6 @@ __device__ __forceinline__ V add(V x, V y) { return V{x.a + y.a, x.l + y.l}; }
 
 __device__ __forceinline__ V neg(V x) { return V{-x.a, -x.l}; }
 
-__device__ __forceinline__ V select(bool take, V x, V keep)
-{
-    return V{take ? x.a : keep.a, take ? x.l : keep.l};
-}
-
 template <int B, class T>
 __device__ __forceinline__ T pick(const T (&arr)[B], int j)
 {

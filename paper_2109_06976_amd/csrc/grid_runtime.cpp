@@ -249,7 +249,7 @@ grid_status launch_fused_variant(grid_model m, int variant, int32_t N, const flo
                                  float* dq, float* dqd, hipStream_t stream)
 {
     if (variant < 0 || variant >= kNumVariants || !m->fused_variant[variant])
-        return fail(GRID_EUNSUPPORTED, "this build of the fused kernel does not exist for the model");
+        return fail(GRID_EUNSUPPORTED, "the requested build of the fused kernel does not exist for the model");
     if (variant == kVariantQuad)
         return launch(m->fused_variant[variant], (unsigned)workgroups_quad(m->topo, N),
                       64u * (unsigned)m->topo.waves, N, nullptr, q, qd, tau, qdd, Minv, dq, dqd,
