@@ -141,7 +141,7 @@ def autograd_steps(torch, grid, synth, steps):
     """The autograd workload (humanoid, N = 128 knots as two 64-knot trajectories,
     L = sum of squared qdd): time per forward + backward step, for the stored-Jacobian and
     the reverse-sweep backward."""
-    from paper_2109_06976_amd.autograd import forward_dynamics
+    from paper_2109_06976_amd.autograd import CapturedStep, forward_dynamics
     dev = torch.device("cuda:0")
     robot = synth.humanoid30()
     m = grid.Model(robot)
@@ -157,8 +157,15 @@ def autograd_steps(torch, grid, synth, steps):
         wall, _ = time_steps(torch, step, steps, 20)
         out[mode] = {"us_per_step": round(wall * 1e6, 2),
                      "knot_evals_per_s": round(128 / wall, 1)}
+        # the same step captured once in a HIP graph and replayed (host cost of one launch)
+        captured = CapturedStep(m, *leaves, mode=mode)
+        wall, _ = time_steps(torch, captured.replay, steps, 20)
+        out[mode + "_graph"] = {"us_per_step": round(wall * 1e6, 2),
+                                "knot_evals_per_s": round(128 / wall, 1)}
+        del captured
     m.close()
-    return {"workload": "humanoid30, N=128 (2 x 64 knots), L = sum |qdd|^2, forward + backward",
+    return {"workload": "humanoid30, N=128 (2 x 64 knots), L = sum |qdd|^2, forward + backward "
+                        "(eager through torch, and the step captured in a HIP graph)",
             **out}
 
 

@@ -55,3 +55,38 @@ class ForwardDynamics(torch.autograd.Function):
 def forward_dynamics(model: "grid.Model", q, qd, tau, mode: str = "jacobians"):
     """qdd = FD(q, qd, tau) for [N, n] float32 CUDA tensors, differentiable in all three."""
     return ForwardDynamics.apply(q, qd, tau, model, mode)
+
+
+class CapturedStep:
+    """One forward + backward of L = sum(qdd^2) through ForwardDynamics captured in a HIP
+    graph (torch.cuda.CUDAGraph), for loops that repeat the same step on new inputs.
+
+    The inputs live in static tensors `q`, `qd`, `tau` (copy new values into them); replay()
+    reruns the captured kernels, after which `loss`, `qdd` and `grads` (dL/dq, dL/dqd,
+    dL/dtau) hold the results. Capture warms up on a side stream first, as torch requires.
+    Every kernel of the step is an asynchronous launch on the capturing stream; the library
+    calls allocate nothing and do not synchronize, so they can be captured."""
+
+    def __init__(self, model, q, qd, tau, mode: str = "jacobians", warmup: int = 3):
+        import torch as _torch
+        self.model, self.mode = model, mode
+        self.q, self.qd, self.tau = (x.detach().clone().contiguous().float().requires_grad_(True)
+                                     for x in (q, qd, tau))
+        side = _torch.cuda.Stream(device=self.q.device)
+        side.wait_stream(_torch.cuda.current_stream(self.q.device))
+        with _torch.cuda.stream(side):
+            for _ in range(warmup):
+                self._step()
+        _torch.cuda.current_stream(self.q.device).wait_stream(side)
+        self.graph = _torch.cuda.CUDAGraph()
+        with _torch.cuda.graph(self.graph):
+            self.qdd, self.loss, self.grads = self._step()
+
+    def _step(self):
+        qdd = forward_dynamics(self.model, self.q, self.qd, self.tau, self.mode)
+        loss = (qdd * qdd).sum()
+        grads = torch.autograd.grad(loss, (self.q, self.qd, self.tau))
+        return qdd, loss, grads
+
+    def replay(self):
+        self.graph.replay()
