@@ -17,8 +17,10 @@ Also reported (extra fields of the same line):
   served        p50/p99 latency and throughput of an open-loop Poisson request stream
                 (20k req/s over the three robots) through the continuous-batching
                 server, and through one plain staged launch per request;
+  mixed         quad12 + chain7 batches at uneven knot counts per step: two calls, one
+                batch call, one hipGraph launch;
   autograd      the humanoid autograd workload (forward + backward per step) with the
-                stored-Jacobian and the reverse-sweep backward;
+                stored-Jacobian and the reverse-sweep backward, eager and graph-replayed;
   single_knot_us  one knot (N = 1) of ID, M^-1, FD, dID and dFD on each robot, as the
                 paper's single-computation table, with the paper's GPU numbers as context;
   cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
@@ -167,6 +169,43 @@ def autograd_steps(torch, grid, synth, steps):
     return {"workload": "humanoid30, N=128 (2 x 64 knots), L = sum |qdd|^2, forward + backward "
                         "(eager through torch, and the step captured in a HIP graph)",
             **out}
+
+
+def mixed_batches(torch, grid, synth, chain_model, steps):
+    """Quad12 and chain7 batches at uneven knot counts in one step, issued three ways: two
+    fd_grad calls, one grid_fd_grad_batch call, and the mixed batch captured as one hipGraph
+    and launched."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    quad = grid.Model(synth.quad12())
+    out = {"workload": "quad12 + chain7 at uneven knot counts in one step (knot-evals/s over "
+                       "both robots)"}
+    for nq, nc in ((64, 37), (256, 181), (1024, 613)):
+        items = []
+        for m, n, NK, seed in ((quad, 12, nq, 300 + nq), (chain_model, 7, nc, 400 + nc)):
+            k = synth.random_knots(n, NK, seed)
+            ins = [torch.from_numpy(a).to(dev) for a in (k.q, k.qd, k.tau)]
+            outs = [torch.empty((NK, n), device=dev)] + \
+                [torch.empty((NK, n, n), device=dev) for _ in range(3)]
+            items.append((m, *ins, *outs))
+        calls = [it[0].fd_grad_call(*it[1:], stream=stream) for it in items]
+
+        def separate():
+            for c in calls:
+                c()
+
+        graph = grid.Graph(items)
+        res = {}
+        for label, fn in (("two_calls", separate),
+                          ("batch_call", lambda: grid.fd_grad_batch(items, stream=stream)),
+                          ("graph", lambda: graph.launch(stream=stream))):
+            wall, _ = time_steps(torch, fn, steps, 50)
+            res[label] = {"us_per_step": round(wall * 1e6, 3),
+                          "knot_evals_per_s": round((nq + nc) / wall, 1)}
+        graph.close()
+        out[f"{nq}+{nc}"] = res
+    quad.close()
+    return out
 
 
 def serve(args, grid, synth, chain_model=None):
@@ -345,6 +384,8 @@ def main():
         result["sweep"] = sweep
 
     if not args.no_single:
+        if args.robot == "chain7":
+            result["mixed"] = mixed_batches(torch, grid, synth, model, 1000)
         result["autograd"] = autograd_steps(torch, grid, synth, 300)
         result["single_knot_us"] = single_knot_table(torch, grid, synth, 1000)
         result["single_knot_us"]["paper_table1_gpu_us"] = PAPER_TABLE1_GPU_US

@@ -219,9 +219,9 @@ typedef struct grid_graph_s* grid_graph;
 /* Launch every item's fused kernel on `stream`, one after the other. */
 grid_status grid_fd_grad_batch(const grid_item* items, int32_t count, void* stream);
 
-/* Capture the items into one hipGraph whose kernel nodes are independent (forked onto
- * side streams and joined), instantiate it, and return it. All models must be on one
- * device. Errors: EINVAL (NULL, count < 1 or > 64, N < 0), EDEVICE. */
+/* Capture the items into one hipGraph (their kernels as a chain of kernel nodes, in item
+ * order), instantiate it, and return it. All models must be on one device. Errors: EINVAL
+ * (NULL, count < 1 or > 64, N < 0), EDEVICE. */
 grid_status grid_graph_create(const grid_item* items, int32_t count, grid_graph* out);
 
 /* Replay the graph on `stream` (one launch call for the whole mixed batch). */

@@ -53,45 +53,35 @@ struct grid_graph_s {
     int device = 0;
     int count = 0;
     hipStream_t capture = nullptr;
-    std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> join;
-    hipEvent_t fork = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-// fork every item onto its own side stream and join them back, so the captured kernel
-// nodes have no edges between them
+// the items' kernels in sequence on the capture stream: a chain of kernel nodes. (A first
+// version forked every item onto a side stream so that the nodes had no edges between them;
+// on ROCm 7.2 launching that graph took 39 us of host time for two nodes, the chain 14 us.)
 grid_status capture(grid_graph g, const grid_item* items, int32_t count, hipGraph_t* out)
 {
     HIP_TRY(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
     grid_status st = GRID_OK;
-    hipError_t e = hipEventRecord(g->fork, g->capture);
-    for (int k = 0; k < count && e == hipSuccess && st == GRID_OK; ++k) {
-        e = hipStreamWaitEvent(g->side[k], g->fork, 0);
-        if (e == hipSuccess && items[k].N > 0)
+    for (int k = 0; k < count && st == GRID_OK; ++k)
+        if (items[k].N > 0)
             st = launch_fused(items[k].model, items[k].N, items[k].q, items[k].qd, items[k].tau,
                               items[k].qdd, items[k].Minv, items[k].dqdd_dq, items[k].dqdd_dqd,
-                              g->side[k]);
-        if (e == hipSuccess && st == GRID_OK)
-            e = hipEventRecord(g->join[k], g->side[k]);
-        if (e == hipSuccess && st == GRID_OK)
-            e = hipStreamWaitEvent(g->capture, g->join[k], 0);
-    }
+                              g->capture);
     hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(g->capture, &graph);
+    const hipError_t e2 = hipStreamEndCapture(g->capture, &graph);
     if (st != GRID_OK) {
         if (graph)
             (void)hipGraphDestroy(graph);
         return st;
     }
-    if (e != hipSuccess || e2 != hipSuccess) {
+    if (e2 != hipSuccess) {
         if (graph)
             (void)hipGraphDestroy(graph);
-        return fail(GRID_EDEVICE, std::string("graph capture: ") +
-                                      hipGetErrorString(e != hipSuccess ? e : e2));
+        return fail(GRID_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
     }
     *out = graph;
     return GRID_OK;
@@ -103,12 +93,6 @@ void destroy_graph(grid_graph g)
         (void)hipGraphExecDestroy(g->exec);
     if (g->graph)
         (void)hipGraphDestroy(g->graph);
-    for (auto e : g->join)
-        (void)hipEventDestroy(e);
-    if (g->fork)
-        (void)hipEventDestroy(g->fork);
-    for (auto s : g->side)
-        (void)hipStreamDestroy(s);
     if (g->capture)
         (void)hipStreamDestroy(g->capture);
     delete g;
@@ -151,22 +135,9 @@ grid_status grid_graph_create(const grid_item* items, int32_t count, grid_graph*
     g->device = items[0].model->device;
     g->count = count;
     hipError_t e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
-    if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming);
-    for (int k = 0; k < count && e == hipSuccess; ++k) {
-        hipStream_t s = nullptr;
-        hipEvent_t ev = nullptr;
-        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-        if (e == hipSuccess)
-            g->side.push_back(s);
-        if (e == hipSuccess)
-            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e == hipSuccess)
-            g->join.push_back(ev);
-    }
     if (e != hipSuccess) {
         destroy_graph(g);
-        return fail(GRID_EDEVICE, std::string("graph streams: ") + hipGetErrorString(e));
+        return fail(GRID_EDEVICE, std::string("graph stream: ") + hipGetErrorString(e));
     }
     st = capture(g, items, count, &g->graph);
     if (st == GRID_OK) {
@@ -229,8 +200,7 @@ grid_status grid_graph_destroy(grid_graph g)
     if (!g)
         return GRID_OK;
     (void)hipSetDevice(g->device);
-    for (auto s : g->side)
-        (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(g->capture);
     destroy_graph(g);
     return GRID_OK;
 }
