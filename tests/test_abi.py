@@ -188,3 +188,11 @@ def test_server_rejects_bad_arguments_without_a_device():
     assert lib.grid_server_wait(None, 1, 0) == grid.GRID_EINVAL
     assert lib.grid_server_destroy(None) == grid.GRID_OK
     assert grid.status_string(grid.GRID_ETIMEDOUT) == "GRID_ETIMEDOUT"
+
+
+def test_model_queries_reject_null_without_a_device():
+    import ctypes as C
+    h = C.c_uint64()
+    assert grid.lib().grid_model_code_hash(None, C.byref(h)) == grid.GRID_EINVAL
+    n = C.c_int32()
+    assert grid.lib().grid_model_info(None, C.byref(n), None, None) == grid.GRID_EINVAL
