@@ -84,9 +84,18 @@ def standard_models():
     # prismatic joints (with revolute ones; random axes; on a branch beyond 16 bodies;
     # with fixed joints, one welded to a prismatic owner)
     models.extend(prismatic_models().values())
-    # the largest robot the library accepts (32 bodies)
+    # the largest robot the library accepts (32 bodies), and 32 bodies each on the base
     models.append(max_size_model())
+    models.append(star_model())
     return models
+
+
+def star_model():
+    """32 bodies, each on its own joint to the fixed base: 32 branches of one body, M
+    diagonal (the degenerate tree)."""
+    import numpy as np
+    from paper_2109_06976_amd import synth
+    return synth.random_model(np.full(32, -1, np.int32), 48, "star32")
 
 
 def max_size_model():

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2109_06976_amd import grid, synth
-from paper_2109_06976_amd.build import max_size_model, prismatic_models
+from paper_2109_06976_amd.build import max_size_model, prismatic_models, star_model
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +38,8 @@ ROBOTS = {
     "humanoid30-prism": lambda: prismatic_models()["humanoid30-prism"],
     # the largest robot the library accepts: 32 bodies, one branch of 20
     "humanoid32": max_size_model,
+    # 32 bodies each on the base: 32 one-body branches, M diagonal
+    "star32": star_model,
 }
 
 
