@@ -172,12 +172,13 @@ def autograd_steps(torch, grid, synth, steps):
 
 
 def mixed_batches(torch, grid, synth, chain_model, steps):
-    """Quad12 and chain7 batches at uneven knot counts in one step, issued three ways: two
-    fd_grad calls, one grid_fd_grad_batch call, and the mixed batch captured as one hipGraph
-    and launched."""
+    """Quad12 and chain7 batches at uneven knot counts in one step, issued four ways: two
+    fd_grad calls, one grid_fd_grad_batch call, the mixed batch captured as one hipGraph
+    and launched, and one kernel launch of a module holding both robots (grid_mixed)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     quad = grid.Model(synth.quad12())
+    mixed = grid.Mixed([synth.quad12(), synth.chain7()])
     out = {"workload": "quad12 + chain7 at uneven knot counts in one step (knot-evals/s over "
                        "both robots)"}
     for nq, nc in ((64, 37), (256, 181), (1024, 613)):
@@ -195,15 +196,18 @@ def mixed_batches(torch, grid, synth, chain_model, steps):
                 c()
 
         graph = grid.Graph(items)
+        table = [(r, *it[1:]) for r, it in enumerate(items)]   # robot 0: quad12, 1: chain7
         res = {}
         for label, fn in (("two_calls", separate),
                           ("batch_call", lambda: grid.fd_grad_batch(items, stream=stream)),
-                          ("graph", lambda: graph.launch(stream=stream))):
+                          ("graph", lambda: graph.launch(stream=stream)),
+                          ("one_launch", lambda: mixed.launch(table, stream=stream))):
             wall, _ = time_steps(torch, fn, steps, 50)
             res[label] = {"us_per_step": round(wall * 1e6, 3),
                           "knot_evals_per_s": round((nq + nc) / wall, 1)}
         graph.close()
         out[f"{nq}+{nc}"] = res
+    mixed.close()
     quad.close()
     return out
 

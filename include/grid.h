@@ -234,6 +234,49 @@ grid_status grid_graph_update(grid_graph g, const grid_item* items, int32_t coun
 
 grid_status grid_graph_destroy(grid_graph g);
 
+/* ------------------------------------------------------------------ one launch, several robots
+ *
+ * The whole path of grid_fd_grad (Sec. IV: RNEA, dRNEA, M^-1 and dFD = -M^-1 dID, fused) for
+ * a table of items of different robots and uneven N in ONE kernel launch. A mixed module is
+ * compiled for a fixed list of robot models (at most 16); it holds the fused kernel build that
+ * runs each base branch of a knot on one workgroup of role-split wavefronts (the build
+ * grid_fd_grad picks for small batches), instantiated for every branch of every robot. A launch
+ * splits its grid into segments, one per (item, branch): the workgroups of item 0's branches
+ * first, then item 1's, and so on; each workgroup finds its segment in a table passed with the
+ * kernel arguments. Results are those of that build run on each item alone.
+ */
+typedef struct grid_mixed_s* grid_mixed;
+
+typedef struct grid_mixed_item {
+    int32_t robot;      /* index into the descs the module was created from */
+    int32_t N;          /* knots, >= 0 (0: the item is skipped) */
+    const float *q, *qd, *tau;                  /* device, layouts as in grid_fd_grad */
+    float *qdd, *Minv, *dqdd_dq, *dqdd_dqd;     /* device, written for the item's N knots */
+} grid_mixed_item;
+
+/* Validate `count` (1..16) robot descriptions, generate and compile (or take from the kernel
+ * cache) their common module, and load it on `device`. The descriptions are read during the
+ * call only. Errors: EINVAL (a description invalid, as grid_model_create), ECOMPILE, EDEVICE,
+ * EUNSUPPORTED (not a gfx950 device). */
+grid_status grid_mixed_create(const grid_model_desc* descs, int32_t count, int32_t device,
+                              grid_mixed* out);
+
+/* Launch the items (1..16, any robot of the module, in any order, a robot more than once) as
+ * one kernel on `stream`. Items must not share output buffers. At most 64 (item, branch)
+ * segments per launch (an item has as many branches as its robot has bodies on the fixed
+ * base). Errors: EINVAL (NULL, a robot index out of range, N < 0, a NULL data pointer of an
+ * item with N > 0, too many segments), EDEVICE. Nothing is launched when every N is 0. */
+grid_status grid_mixed_launch(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                              void* stream);
+
+grid_status grid_mixed_destroy(grid_mixed mx);
+
+/* The generated source of a mixed module and its compilation into the kernel cache, without
+ * a device (buffer protocol as grid_codegen_source). */
+grid_status grid_mixed_source(const grid_model_desc* descs, int32_t count, char* buf,
+                              size_t* len);
+grid_status grid_mixed_precompile(const grid_model_desc* descs, int32_t count);
+
 /*
  * Jacobians of the discrete-time dynamics of one semi-implicit Euler step of length dt,
  * qd' = qd + dt qdd(q, qd, tau), q' = q + dt qd', the form trajectory optimisation uses

@@ -123,6 +123,18 @@ def prismatic_models():
     }
 
 
+def mixed_sets():
+    """The robot lists of the mixed modules (one launch, several robots) that the tests and
+    the benchmark create."""
+    from paper_2109_06976_amd import synth
+    prism = prismatic_models()
+    return [
+        [synth.quad12(), synth.chain7()],
+        [synth.chain7(), synth.quad12(), synth.humanoid30(), prism["tree5-axes-prism"],
+         prism["tree7-fixed-prism"], star_model()],
+    ]
+
+
 def offline_compile_check(verbose=False):
     """hipcc --genco of the generated source for the three workload robots."""
     from paper_2109_06976_amd import grid, synth
@@ -145,16 +157,28 @@ def _precompile_one(robot):
     return robot.name
 
 
+def _precompile_mixed(k):
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    from paper_2109_06976_amd import grid
+    robots = mixed_sets()[k]
+    grid.mixed_precompile(robots)
+    return "+".join(r.name for r in robots)
+
+
 def precompile(verbose=False, workers=None):
-    """Compile every standard model's kernels into the cache, several at a time (one
-    process each: a compile is single-threaded), the largest robots first."""
+    """Compile every standard model's kernels and the mixed modules into the cache, several
+    at a time (one process each: a compile is single-threaded), the largest first."""
     import concurrent.futures
     import multiprocessing
     robots = sorted(standard_models(), key=lambda r: -r.n)
     workers = workers or max(1, min(8, os.cpu_count() or 1))
     ctx = multiprocessing.get_context("fork")
     with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as pool:
-        for name in pool.map(_precompile_one, robots):
+        jobs = [pool.submit(_precompile_mixed, k) for k in range(len(mixed_sets()))]
+        jobs += [pool.submit(_precompile_one, r) for r in robots]
+        for job in jobs:
+            name = job.result()
             if verbose:
                 print(f"cached kernels for {name}", flush=True)
 

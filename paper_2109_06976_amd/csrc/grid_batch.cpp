@@ -205,6 +205,192 @@ grid_status grid_graph_destroy(grid_graph g)
     return GRID_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ one launch, several robots
+
+struct grid_mixed_s {
+    int device = 0;
+    std::vector<Topology> topo;       // per robot
+    std::vector<int> inst_base;       // per robot: index of its first branch in the module
+    int waves = 1;                    // wavefronts per workgroup (the largest robot's)
+    hipModule_t module = nullptr;
+    hipFunction_t fn = nullptr;
+};
+
+namespace {
+
+// the robots' topologies, constants and the module source
+grid_status mixed_source(const grid_model_desc* descs, int32_t count, std::vector<Topology>* topo,
+                         std::vector<int>* inst_base, std::string* src)
+{
+    if (!descs || count < 1 || count > kMixedItems)
+        return fail(GRID_EINVAL, "descs must hold 1.." + std::to_string(kMixedItems) + " models");
+    topo->assign(count, Topology());
+    std::vector<std::vector<float>> consts(count);
+    std::vector<RobotSource> rs;
+    for (int r = 0; r < count; ++r) {
+        std::string err;
+        const grid_status st = prepare_robot(&descs[r], &(*topo)[r], &consts[r], &err);
+        if (st != GRID_OK)
+            return fail(st, "model " + std::to_string(r) + ": " + err);
+    }
+    for (int r = 0; r < count; ++r)
+        rs.push_back(RobotSource{&(*topo)[r], &consts[r],
+                                 {descs[r].gravity[0], descs[r].gravity[1], descs[r].gravity[2]}});
+    inst_base->clear();
+    *src = generate_mixed_source(rs, inst_base);
+    return GRID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+grid_status grid_mixed_source(const grid_model_desc* descs, int32_t count, char* buf, size_t* len)
+{
+    if (!len)
+        return fail(GRID_EINVAL, "len must not be NULL");
+    std::vector<Topology> topo;
+    std::vector<int> base;
+    std::string src;
+    const grid_status st = mixed_source(descs, count, &topo, &base, &src);
+    if (st != GRID_OK)
+        return st;
+    const size_t need = src.size() + 1;
+    const bool fits = buf && *len >= need;
+    if (fits)
+        std::memcpy(buf, src.c_str(), need);
+    *len = need;
+    if (buf && !fits)
+        return fail(GRID_EINVAL, "buffer too small");
+    return GRID_OK;
+}
+
+grid_status grid_mixed_precompile(const grid_model_desc* descs, int32_t count)
+{
+    std::vector<Topology> topo;
+    std::vector<int> base;
+    std::string src, err;
+    grid_status st = mixed_source(descs, count, &topo, &base, &src);
+    if (st != GRID_OK)
+        return st;
+    std::vector<char> code;
+    st = compile_cached(src, &code, &err);
+    return st == GRID_OK ? GRID_OK : fail(st, err);
+}
+
+grid_status grid_mixed_create(const grid_model_desc* descs, int32_t count, int32_t device,
+                              grid_mixed* out)
+{
+    if (!out)
+        return fail(GRID_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    std::vector<Topology> topo;
+    std::vector<int> base;
+    std::string src, err;
+    grid_status st = mixed_source(descs, count, &topo, &base, &src);
+    if (st != GRID_OK)
+        return st;
+    std::vector<char> code;
+    st = compile_cached(src, &code, &err);
+    if (st != GRID_OK)
+        return fail(st, err);
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return fail(GRID_EINVAL, "device index out of range");
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GRID_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName +
+                                           ", kernels are built for gfx950");
+    grid_mixed mx = new (std::nothrow) grid_mixed_s;
+    if (!mx)
+        return fail(GRID_ENOMEM, "host allocation failed");
+    mx->device = device;
+    mx->topo = std::move(topo);
+    mx->inst_base = std::move(base);
+    for (const Topology& t : mx->topo)
+        mx->waves = std::max(mx->waves, pipe_waves(t));
+    hipError_t e = hipModuleLoadData(&mx->module, code.data());
+    if (e == hipSuccess)
+        e = hipModuleGetFunction(&mx->fn, mx->module, "grid_fdgrad_pipe_mixed");
+    if (e != hipSuccess) {
+        grid_mixed_destroy(mx);
+        return fail(GRID_EDEVICE, std::string("mixed module load: ") + hipGetErrorString(e));
+    }
+    *out = mx;
+    return GRID_OK;
+}
+
+grid_status grid_mixed_launch(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                              void* stream)
+{
+    if (!mx)
+        return fail(GRID_EINVAL, "mixed module is NULL");
+    if (!items || count < 1 || count > kMixedItems)
+        return fail(GRID_EINVAL, "items must hold 1.." + std::to_string(kMixedItems) + " entries");
+    MixedArgs a;
+    std::memset(&a, 0, sizeof a);
+    int64_t blocks = 0;
+    for (int j = 0; j < count; ++j) {
+        const grid_mixed_item& it = items[j];
+        if (it.robot < 0 || it.robot >= (int)mx->topo.size())
+            return fail(GRID_EINVAL, "item " + std::to_string(j) + ": robot index out of range");
+        if (it.N < 0 || it.N > (1 << 30) / 64)
+            return fail(GRID_EINVAL, "item " + std::to_string(j) + ": N out of range");
+        if (it.N > 0 && (!it.q || !it.qd || !it.tau || !it.qdd || !it.Minv || !it.dqdd_dq ||
+                         !it.dqdd_dqd))
+            return fail(GRID_EINVAL, "item " + std::to_string(j) + ": a data pointer is NULL");
+        KernelArgs& k = a.item[j];
+        k.nknots = it.N;
+        k.work = nullptr;
+        k.q = it.q;
+        k.qd = it.qd;
+        k.tau = it.tau;
+        k.qdd = it.qdd;
+        k.Minv = it.Minv;
+        k.dqdd_dq = it.dqdd_dq;
+        k.dqdd_dqd = it.dqdd_dqd;
+        if (it.N == 0)
+            continue;
+        const Topology& t = mx->topo[it.robot];
+        for (size_t b = 0; b < t.insts.size(); ++b) {
+            if (a.nseg == kMixedSegs)
+                return fail(GRID_EINVAL, "more than " + std::to_string(kMixedSegs) +
+                                             " (item, branch) segments in one launch");
+            const int P = pipe_problems(t.shapes[t.insts[b].shape].B);
+            a.seg_start[a.nseg] = (int)blocks;
+            a.seg_inst[a.nseg] = mx->inst_base[it.robot] + (int)b;
+            a.seg_item[a.nseg] = j;
+            ++a.nseg;
+            blocks += (it.N + P - 1) / P;
+        }
+    }
+    if (blocks == 0)
+        return GRID_OK;
+    if (blocks > INT32_MAX)
+        return fail(GRID_EINVAL, "too many knots in one launch");
+    HIP_TRY(hipSetDevice(mx->device));
+    void* params[] = {&a};   // the kernel takes one argument: the MixedArgs block
+    HIP_TRY(hipModuleLaunchKernel(mx->fn, (unsigned)blocks, 1, 1, 64u * (unsigned)mx->waves, 1, 1,
+                                  0, (hipStream_t)stream, params, nullptr));
+    return GRID_OK;
+}
+
+grid_status grid_mixed_destroy(grid_mixed mx)
+{
+    if (!mx)
+        return GRID_OK;
+    (void)hipSetDevice(mx->device);
+    if (mx->module)
+        (void)hipModuleUnload(mx->module);
+    delete mx;
+    return GRID_OK;
+}
+
 grid_status grid_tune(grid_model m, const int32_t* Ns, int32_t count, const char* table_path,
                       int32_t* chosen)
 {

@@ -15,6 +15,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <fstream>
 #include <mutex>
@@ -224,26 +225,33 @@ static void emit_floats(std::ostringstream& os, const float* v, size_t k)
     os << "}";
 }
 
-std::string generate_source(const Topology& t, const std::vector<float>& consts,
-                            const double gravity[3], uint32_t flags)
+// Compile-time structures of one or several robots: the workgroup-size macros (maxima over
+// the robots), the distinct branch shapes, and one Inst<k> per branch (numbered across the
+// robots) with its robot's joint count, gravity, constants and lane table. inst_base[r] is
+// the first Inst index of robot r.
+static void emit_prelude(std::ostringstream& os, const std::vector<RobotSource>& robots,
+                         std::vector<int>* inst_base)
 {
-    (void)flags;
-    std::ostringstream os;
-    os << "// generated: one robot as compile-time structures and constants\n";
-    os << "#define GRID_N " << t.n << "\n";
-    const float a0[3] = {(float)-gravity[0], (float)-gravity[1], (float)-gravity[2]};
-    os << "__device__ constexpr float grid_a0[3] = ";
-    emit_floats(os, a0, 3);
-    os << ";\n";
-    const WorkspaceLayout ws = workspace_layout(t);
+    const Topology& t0 = *robots[0].topo;
+    const WorkspaceLayout ws = workspace_layout(t0);   // the staged pipeline: one robot only
     os << "#define GRID_WS_C " << ws.c << "\n#define GRID_WS_L " << ws.L << "\n#define GRID_WS_DINV "
        << ws.dinv << "\n#define GRID_WS_DTAU " << ws.dtau << "\n#define GRID_WS_STRIDE "
        << ws.stride << "\n";
-    os << "#define GRID_WAVES " << t.waves << "\n";
-    os << "#define GRID_PIPE_WAVES " << pipe_waves(t) << "\n";
+    int waves = 1, pwaves = 1;
+    for (const RobotSource& r : robots) {
+        waves = std::max(waves, r.topo->waves);
+        pwaves = std::max(pwaves, pipe_waves(*r.topo));
+    }
+    os << "#define GRID_WAVES " << waves << "\n";
+    os << "#define GRID_PIPE_WAVES " << pwaves << "\n";
     os << "template <int s> struct Shape;\ntemplate <int k> struct Inst;\n";
-    for (size_t s = 0; s < t.shapes.size(); ++s) {
-        const BranchShape& sh = t.shapes[s];
+    std::vector<BranchShape> shapes;   // distinct shapes over all robots
+    auto shape_id = [&](const BranchShape& sh) {
+        for (size_t s = 0; s < shapes.size(); ++s)
+            if (shapes[s].parent == sh.parent)
+                return (int)s;
+        shapes.push_back(sh);
+        const int s = (int)shapes.size() - 1;
         os << "template <> struct Shape<" << s << "> {\n";
         os << "    static constexpr int B = " << sh.B << ";\n";
         os << "    static constexpr int L = " << sh.L << ";\n";
@@ -255,60 +263,88 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
         os << ";\n    static constexpr unsigned long long anc[B] = ";
         emit_list(os, sh.anc, "ull");
         os << ";\n};\n";
-    }
-    for (size_t k = 0; k < t.insts.size(); ++k) {
-        const BranchInst& in = t.insts[k];
-        // E_T (9), r (3), Ibar (6), h (3), m, 2 unused: per body in local order
-        os << "__device__ constexpr float grid_const_" << k << "[" << in.body.size() * kConstStride
-           << "] = ";
-        emit_floats(os, consts.data() + in.coff, in.body.size() * kConstStride);
+        return s;
+    };
+    int kk = 0;
+    for (size_t ri = 0; ri < robots.size(); ++ri) {
+        const Topology& t = *robots[ri].topo;
+        const std::vector<float>& consts = *robots[ri].consts;
+        const WorkspaceLayout wsr = workspace_layout(t);
+        inst_base->push_back(kk);
+        const float a0[3] = {(float)-robots[ri].gravity[0], (float)-robots[ri].gravity[1],
+                             (float)-robots[ri].gravity[2]};
+        os << "__device__ constexpr float grid_a0_" << ri << "[3] = ";
+        emit_floats(os, a0, 3);
         os << ";\n";
-        // per-lane constants of the quad layout for lane component c = 0, 1, 2, 16 floats
-        // per (c, body): r_c+1, r_c+2, Ibar_cc, Ibar_c,c+1, Ibar_c+2,c, h_c+1, h_c+2, then
-        // E_T[row][(c + col) % 3] for row, col = 0..2 (indices mod 3); read through LDS
-        {
-            const int B = (int)in.body.size();
-            std::vector<float> lk((size_t)3 * B * 16);
-            for (int c = 0; c < 3; ++c)
-                for (int i = 0; i < B; ++i) {
-                    const float* b = consts.data() + in.coff + (size_t)i * kConstStride;
-                    const float* r = b + 9;
-                    const float* Ib = b + 12;   // xx yy zz xy xz yz
-                    const float* h = b + 18;
-                    const float ic1[3] = {Ib[3], Ib[5], Ib[4]};   // xy, yz, zx
-                    float* o = lk.data() + ((size_t)c * B + i) * 16;
-                    o[0] = r[(c + 1) % 3];
-                    o[1] = r[(c + 2) % 3];
-                    o[2] = Ib[c];
-                    o[3] = ic1[c];
-                    o[4] = ic1[(c + 2) % 3];
-                    o[5] = h[(c + 1) % 3];
-                    o[6] = h[(c + 2) % 3];
-                    for (int row = 0; row < 3; ++row)
-                        for (int col = 0; col < 3; ++col)
-                            o[7 + 3 * row + col] = b[3 * row + (c + col) % 3];
-                }
-            os << "__device__ alignas(16) const float grid_lk_" << k << "[" << lk.size() << "] = ";
-            emit_floats(os, lk.data(), lk.size());
+        for (size_t k0 = 0; k0 < t.insts.size(); ++k0, ++kk) {
+            const BranchInst& in = t.insts[k0];
+            const int sid = shape_id(t.shapes[in.shape]);
+            const int k = kk;
+            // E_T (9), r (3), Ibar (6), h (3), m, 2 unused: per body in local order
+            os << "__device__ constexpr float grid_const_" << k << "[" << in.body.size() * kConstStride
+               << "] = ";
+            emit_floats(os, consts.data() + in.coff, in.body.size() * kConstStride);
             os << ";\n";
+            // per-lane constants of the quad layout for lane component c = 0, 1, 2, 16 floats
+            // per (c, body): r_c+1, r_c+2, Ibar_cc, Ibar_c,c+1, Ibar_c+2,c, h_c+1, h_c+2, then
+            // E_T[row][(c + col) % 3] for row, col = 0..2 (indices mod 3); read through LDS
+            {
+                const int B = (int)in.body.size();
+                std::vector<float> lk((size_t)3 * B * 16);
+                for (int c = 0; c < 3; ++c)
+                    for (int i = 0; i < B; ++i) {
+                        const float* b = consts.data() + in.coff + (size_t)i * kConstStride;
+                        const float* r = b + 9;
+                        const float* Ib = b + 12;   // xx yy zz xy xz yz
+                        const float* h = b + 18;
+                        const float ic1[3] = {Ib[3], Ib[5], Ib[4]};   // xy, yz, zx
+                        float* o = lk.data() + ((size_t)c * B + i) * 16;
+                        o[0] = r[(c + 1) % 3];
+                        o[1] = r[(c + 2) % 3];
+                        o[2] = Ib[c];
+                        o[3] = ic1[c];
+                        o[4] = ic1[(c + 2) % 3];
+                        o[5] = h[(c + 1) % 3];
+                        o[6] = h[(c + 2) % 3];
+                        for (int row = 0; row < 3; ++row)
+                            for (int col = 0; col < 3; ++col)
+                                o[7 + 3 * row + col] = b[3 * row + (c + col) % 3];
+                    }
+                os << "__device__ alignas(16) const float grid_lk_" << k << "[" << lk.size() << "] = ";
+                emit_floats(os, lk.data(), lk.size());
+                os << ";\n";
+            }
+            os << "template <> struct Inst<" << k << "> {\n";
+            os << "    using S = Shape<" << sid << ">;\n";
+            os << "    static constexpr int N = " << t.n << ";\n";
+            os << "    static constexpr int body[S::B] = ";
+            emit_list(os, in.body);
+            os << ";\n    static constexpr int loff = " << wsr.loff[k0] << ";\n";
+            os << "    static constexpr unsigned long long mask = " << in.mask << "ull;\n";
+            os << "    static constexpr unsigned long long prism = " << in.prism << "ull;\n";
+            os << "    __device__ static int body_of(int i) {\n"
+                  "        int r = body[0];\n"
+                  "#pragma unroll\n"
+                  "        for (int k = 1; k < S::B; ++k) r = (i == k) ? body[k] : r;\n"
+                  "        return r;\n    }\n";
+            os << "    __device__ static bool contains(int g) { return (mask >> g) & 1ull; }\n";
+            os << "    __device__ static const float* consts() { return grid_const_" << k << "; }\n";
+            os << "    __device__ static const float* lanek() { return grid_lk_" << k << "; }\n";
+            os << "    __device__ static const float* a0() { return grid_a0_" << ri << "; }\n";
+            os << "};\n";
         }
-        os << "template <> struct Inst<" << k << "> {\n";
-        os << "    using S = Shape<" << in.shape << ">;\n";
-        os << "    static constexpr int body[S::B] = ";
-        emit_list(os, in.body);
-        os << ";\n    static constexpr int loff = " << ws.loff[k] << ";\n";
-        os << "    static constexpr unsigned long long mask = " << in.mask << "ull;\n";
-        os << "    static constexpr unsigned long long prism = " << in.prism << "ull;\n";
-        os << "    __device__ static int body_of(int i) {\n"
-              "        int r = body[0];\n"
-              "#pragma unroll\n"
-              "        for (int k = 1; k < S::B; ++k) r = (i == k) ? body[k] : r;\n"
-              "        return r;\n    }\n";
-        os << "    __device__ static bool contains(int g) { return (mask >> g) & 1ull; }\n";
-        os << "    __device__ static const float* consts() { return grid_const_" << k << "; }\n";
-        os << "    __device__ static const float* lanek() { return grid_lk_" << k << "; }\n";
-        os << "};\n";
     }
+}
+
+std::string generate_source(const Topology& t, const std::vector<float>& consts,
+                            const double gravity[3], uint32_t flags)
+{
+    (void)flags;
+    std::ostringstream os;
+    os << "// generated: one robot as compile-time structures and constants\n";
+    std::vector<int> base;
+    RobotSource rs{&t, &consts, {gravity[0], gravity[1], gravity[2]}};
+    emit_prelude(os, {rs}, &base);
     os << "#line 1 \"grid_device.hip\"\n";
     os << grid_device_src;
     // A dispatcher walks the branches: workgroups [0, nb_0) run branch 0, the next nb_1 run
@@ -357,6 +393,47 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << "\n// generated: workgroup -> (branch, problem group), standalone algorithms\n";
     dispatch("template <int OP>\n__device__ void grid_dispatch_op(const gridq::OpArgs& a, int block)",
              "gridq::op_problems<@::S, OP>()", "gridq::run_op<@, OP>(a, b)");
+    return os.str();
+}
+
+// Several robots in one module holding only the fused pipe kernel: a launch runs a table of
+// items, each one robot's knots with its own buffers. The host splits the grid into segments,
+// one per (item, branch) with work, and passes their first workgroups; a workgroup finds its
+// segment by a scan of that short table (uniform, scalar loads) and runs the segment's branch.
+std::string generate_mixed_source(const std::vector<RobotSource>& robots,
+                                  std::vector<int>* inst_base)
+{
+    std::ostringstream os;
+    os << "// generated: " << robots.size() << " robots as compile-time structures and constants\n";
+    os << "#define GRID_PIPE_ONLY 1\n";
+    emit_prelude(os, robots, inst_base);
+    os << "#line 1 \"grid_device.hip\"\n";
+    os << grid_device_src;
+    os << "#line 1 \"grid_fused.hip\"\n";
+    os << grid_fused_src;
+    int ninst = 0;
+    for (const RobotSource& r : robots)
+        ninst += (int)r.topo->insts.size();
+    os << "\n// generated: workgroup -> (segment: item, branch), fused pipe kernel\n";
+    os << "struct MixedArgs {\n    int nseg;\n    int seg_start[" << kMixedSegs
+       << "];\n    int seg_inst[" << kMixedSegs << "];\n    int seg_item[" << kMixedSegs
+       << "];\n    grid::Args item[" << kMixedItems << "];\n};\n";
+    os << "extern \"C\" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) "
+          "grid_fdgrad_pipe_mixed(MixedArgs args)\n{\n"
+          "    const int b = (int)blockIdx.x;\n"
+          "    int s = 0;\n"
+          "    while (s + 1 < args.nseg && b >= args.seg_start[s + 1])\n"
+          "        ++s;\n"
+          "    const grid::Args& x = args.item[args.seg_item[s]];\n"
+          "    const int lb = b - args.seg_start[s];\n"
+          "    switch (args.seg_inst[s]) {\n";
+    for (int k = 0; k < ninst; ++k) {
+        if (k + 1 == ninst)
+            os << "    default: gridq::run_pipe<Inst<" << k << ">>(x, lb); break;\n";
+        else
+            os << "    case " << k << ": gridq::run_pipe<Inst<" << k << ">>(x, lb); break;\n";
+    }
+    os << "    }\n}\n";
     return os.str();
 }
 

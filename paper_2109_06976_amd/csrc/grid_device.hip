@@ -2,13 +2,13 @@
 //
 // Compiled at model-creation time (hiprtc) behind a generated prelude that writes one
 // robot's topology out as compile-time structures (grid_codegen.cpp):
-//   GRID_N                      joints of the robot
-//   grid_a0[3]                  -g, the base acceleration that carries gravity
+//   GRID_WS_*                   staged-pipeline workspace offsets
 //   Shape<s>  { B, L, parent[B], anc[B] }   a base branch shape: B bodies in local
 //                               numbering, lanes per knot L, parents, strict-ancestor masks
-//   Inst<k>   { using S; body[B]; consts() } one base branch of the robot: its shape,
-//                               the robot index of each local body, and its constants as
-//                               float literals (folded into the instructions)
+//   Inst<k>   { using S; N; body[B]; consts(); a0() } one base branch of a robot: its shape,
+//                               the robot's joint count N, the robot index of each local body,
+//                               its constants as float literals (folded into the
+//                               instructions) and -g, the base acceleration carrying gravity
 //   grid_dispatch(args, block)  maps a workgroup to (branch, knot group) and runs it
 //
 // Branches hanging off the fixed base are dynamically independent: M is block diagonal
@@ -36,10 +36,6 @@
 //
 // Spatial vectors are [angular; linear]; S = e_3 for a joint revolute about its z axis and
 // S = e_6 for one prismatic along it (Inst::prism marks the prismatic bodies).
-
-#ifndef GRID_N
-#error "GRID_N must be defined by the generated prelude"
-#endif
 
 namespace grid {
 
@@ -202,7 +198,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
     constexpr int B = S::B;
     constexpr int L = S::L;
     constexpr int K = 64 / L;
-    constexpr int N = GRID_N;
+    constexpr int N = I::N;
     constexpr bool kFullSweeps = ST == kFused || ST == kStageRnea || ST == kStageDrnea;
     constexpr bool kNeedsX = kFullSweeps || ST == kStageMinv;
     __shared__ float s_M[K][B][B];
@@ -258,7 +254,7 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
             }
         }
     }
-    const float a0[6] = {0.0f, 0.0f, 0.0f, grid_a0[0], grid_a0[1], grid_a0[2]};   // -g
+    const float a0[6] = {0.0f, 0.0f, 0.0f, I::a0()[0], I::a0()[1], I::a0()[2]};   // -g
     const float zero6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 
     // ------------------------------------------------------------ 2. RNEA(q, qd, 0)
@@ -647,6 +643,10 @@ __device__ __forceinline__ void run_branch(const Args& A, int kg)
 
 using namespace grid;
 
+// kernels of a one-robot module (a module of several robots defines GRID_PIPE_ONLY and its
+// own entry point, grid_fdgrad_pipe_mixed)
+#ifndef GRID_PIPE_ONLY
+
 // defined by the generated epilogue: workgroup -> (branch, knot group)
 template <int ST>
 __device__ void grid_dispatch(const Args& args, int block);
@@ -695,3 +695,5 @@ extern "C" __global__ void __launch_bounds__(64) grid_stage_fdgrad(Args args)
 {
     grid_dispatch<kStageFdgrad>(args, (int)blockIdx.x);
 }
+
+#endif  // GRID_PIPE_ONLY

@@ -83,10 +83,11 @@ struct Lane {       // per-lane selectors
     float oh0, oh1, oh2;   // one-hot of the lane's component c
 };
 
-__device__ __forceinline__ Lane lane_of(int c3)
+// a0: -g, the robot's base acceleration
+__device__ __forceinline__ Lane lane_of(int c3, const float* a0)
 {
     return Lane{c3 == 0 ? 1.0f : (c3 == 1 ? -1.0f : 0.0f), c3 == 2 ? 1.0f : 0.0f,
-                c3 == 0 ? grid_a0[0] : (c3 == 1 ? grid_a0[1] : grid_a0[2]),
+                c3 == 0 ? a0[0] : (c3 == 1 ? a0[1] : a0[2]),
                 c3 == 0 ? 1.0f : 0.0f, c3 == 1 ? 1.0f : 0.0f, c3 == 2 ? 1.0f : 0.0f};
 }
 
@@ -528,7 +529,7 @@ __device__ __forceinline__ void zero_fill(float* out0, float* out1, long mbase, 
                                           int lanes)
 {
     constexpr int B = I::S::B;
-    constexpr int N = GRID_N;
+    constexpr int N = I::N;
     if constexpr (N > B) {
         for (int e = lane; e < B * N; e += lanes) {
             const int i = e / N, c2 = e % N;
@@ -554,7 +555,7 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
     constexpr int WB = GRID_WAVES;            // wavefronts per workgroup
     constexpr int PW = 16 / Q;                // problems per wavefront (W == 1)
     constexpr int P = (WB / W) * PW;          // problems per workgroup
-    constexpr int N = GRID_N;
+    constexpr int N = I::N;
     __shared__ float s_M[P][B][B];
     __shared__ float4 s_tab[3 * B * 4];
 
@@ -562,7 +563,7 @@ __device__ __forceinline__ void run_fused(const grid::Args& A, int block)
     const int wave = tid / 64;
     const int lane = tid % 64;
     const int c = lane & 3;
-    const Lane ln = lane_of(c == 3 ? 0 : c);
+    const Lane ln = lane_of(c == 3 ? 0 : c, I::a0());
     const int quad = (lane / 4) % Q;
     const int pslot = (wave / W) * PW + (lane / 4) / Q;     // problem in the workgroup
     const int s = quad + Q * (wave % W);                    // column slot in the problem
@@ -676,7 +677,7 @@ __device__ __forceinline__ void minv_columns(float* Minv, const float (&Lf)[I::S
 {
     using S = typename I::S;
     constexpr int B = S::B;
-    constexpr int N = GRID_N;
+    constexpr int N = I::N;
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         const bool owns = s + 16 * cb < B;
@@ -732,7 +733,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     constexpr int B = S::B;
     using PS = PipeShape<B>;
     constexpr int P = PS::P;
-    constexpr int N = GRID_N;
+    constexpr int N = I::N;
     constexpr int BWAVE = PS::AW;             // role A on wavefronts 0 .. AW-1, then B, then C
     constexpr int CWAVE = PS::HASC ? PS::AW + 1 : -1;
     static_assert(P == S::PP, "problems per workgroup disagree with the generated shape");
@@ -749,7 +750,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     const int wave = tid / 64;
     const int lane = tid % 64;
     const int c = lane & 3;
-    const Lane ln = lane_of(c == 3 ? 0 : c);
+    const Lane ln = lane_of(c == 3 ? 0 : c, I::a0());
     const float* tab = lane_table<I, 64 * GRID_PIPE_WAVES>(s_tab, tid, c);
 
     if (wave < PS::AW) {
@@ -988,6 +989,10 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
 
 }  // namespace gridq
 
+// kernels of a one-robot module (a module of several robots defines GRID_PIPE_ONLY and its
+// own entry point, grid_fdgrad_pipe_mixed)
+#ifndef GRID_PIPE_ONLY
+
 // defined by the generated epilogue: workgroup -> (branch, problem group)
 __device__ void grid_dispatch_q(const grid::Args& args, int block);
 
@@ -1004,3 +1009,5 @@ extern "C" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) grid_fdgrad_p
 {
     grid_dispatch_p(args, (int)blockIdx.x);
 }
+
+#endif  // GRID_PIPE_ONLY

@@ -90,10 +90,35 @@ struct KernelArgs {
     float* dqdd_dqd;
 };
 
+// A robot as the code generator sees it: topology, packed constants and gravity.
+struct RobotSource {
+    const Topology* topo;
+    const std::vector<float>* consts;
+    double gravity[3];
+};
+
+// One module for several robots (the fused pipe kernel only): workgroup segments of a launch
+// name the item they serve and the branch (Inst index over all robots) they run.
+constexpr int kMixedItems = 16;
+constexpr int kMixedSegs = 64;
+
+// Kernel argument block of the mixed kernel; must match MixedArgs of the generated source.
+struct MixedArgs {
+    int nseg;
+    int seg_start[kMixedSegs];       // first workgroup of the segment, ascending
+    int seg_inst[kMixedSegs];        // the branch the segment runs
+    int seg_item[kMixedSegs];        // the item whose buffers it reads and writes
+    KernelArgs item[kMixedItems];
+};
+
 bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::string* err);
 std::vector<float> pack_constants(const grid_model_desc* d, const Topology& t);
 std::string generate_source(const Topology& t, const std::vector<float>& consts,
                             const double gravity[3], uint32_t flags);
+std::string generate_mixed_source(const std::vector<RobotSource>& robots,
+                                  std::vector<int>* inst_base);
+grid_status prepare_robot(const grid_model_desc* desc, Topology* topo,
+                          std::vector<float>* consts, std::string* err);
 grid_status validate_desc(const grid_model_desc* d, std::string* err);
 int64_t workgroups_for(const Topology& t, int64_t nknots);
 int64_t workgroups_quad(const Topology& t, int64_t nknots);

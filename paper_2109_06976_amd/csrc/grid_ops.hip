@@ -125,7 +125,7 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
 {
     using S = typename I::S;
     constexpr int B = S::B;
-    constexpr int N = GRID_N;
+    constexpr int N = I::N;
     constexpr int P = op_problems<S, OP>();
     constexpr int Q = OP == kOpId ? 1
                       : OP == kOpIdGrad ? S::Q
@@ -138,7 +138,7 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
     const int wave = tid / 64;
     const int lane = tid % 64;
     const int c = lane & 3;
-    const Lane ln = lane_of(c == 3 ? 0 : c);
+    const Lane ln = lane_of(c == 3 ? 0 : c, I::a0());
     const int quad = (lane / 4) % Q;
     const int pslot = (wave / W) * (16 / Q) + (lane / 4) / Q;
     const int s = quad + Q * (wave % W);
@@ -266,6 +266,10 @@ __device__ __forceinline__ void run_op(const OpArgs& A, int block)
 
 }  // namespace gridq
 
+// kernels of a one-robot module (a module of several robots defines GRID_PIPE_ONLY and its
+// own entry point, grid_fdgrad_pipe_mixed)
+#ifndef GRID_PIPE_ONLY
+
 // defined by the generated epilogue: workgroup -> (branch, problem group)
 template <int OP>
 __device__ void grid_dispatch_op(const gridq::OpArgs& args, int block);
@@ -294,3 +298,5 @@ extern "C" __global__ void __launch_bounds__(64) grid_op_vjp(gridq::OpArgs args)
 {
     grid_dispatch_op<gridq::kOpVjp>(args, (int)blockIdx.x);
 }
+
+#endif  // GRID_PIPE_ONLY

@@ -418,26 +418,49 @@ static void reduce_fixed(const grid_model_desc* src, ReducedDesc* out)
     std::memcpy(d.gravity, src->gravity, sizeof d.gravity);
 }
 
-static grid_status prepare(const grid_model_desc* desc, uint32_t flags, Topology* topo,
-                           std::string* src)
+}  // extern "C"
+
+namespace grid_impl {
+
+// validated description -> topology of the model without its fixed joints, and its packed
+// constants; the status and *err on failure
+grid_status prepare_robot(const grid_model_desc* desc, Topology* topo,
+                          std::vector<float>* consts, std::string* err)
 {
-    std::string err;
-    grid_status s = validate_desc(desc, &err);
+    grid_status s = validate_desc(desc, err);
     if (s != GRID_OK)
-        return fail(s, err);
-    if (flags != 0)
-        return fail(GRID_EINVAL, "unknown flag bits");
+        return s;
     ReducedDesc red;
     reduce_fixed(desc, &red);
-    if (red.d.n < 1)
-        return fail(GRID_EINVAL, "the model has no movable joint");
-    if (!analyse_topology(red.d.parent, red.d.n, topo, &err))
-        return fail(GRID_EINVAL, err);
+    if (red.d.n < 1) {
+        *err = "the model has no movable joint";
+        return GRID_EINVAL;
+    }
+    if (!analyse_topology(red.d.parent, red.d.n, topo, err))
+        return GRID_EINVAL;
     for (BranchInst& inst : topo->insts)
         for (size_t k = 0; k < inst.body.size(); ++k)
             if (red.d.joint_type[inst.body[k]] == GRID_JOINT_PRISMATIC)
                 inst.prism |= 1ull << k;
-    *src = generate_source(*topo, pack_constants(&red.d, *topo), red.d.gravity, flags);
+    *consts = pack_constants(&red.d, *topo);
+    return GRID_OK;
+}
+
+}  // namespace grid_impl
+
+extern "C" {
+
+static grid_status prepare(const grid_model_desc* desc, uint32_t flags, Topology* topo,
+                           std::string* src)
+{
+    std::string err;
+    std::vector<float> consts;
+    grid_status s = prepare_robot(desc, topo, &consts, &err);
+    if (s != GRID_OK)
+        return fail(s, err);
+    if (flags != 0)
+        return fail(GRID_EINVAL, "unknown flag bits");
+    *src = generate_source(*topo, consts, desc->gravity, flags);
     return GRID_OK;
 }
 

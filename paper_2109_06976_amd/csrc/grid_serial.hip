@@ -105,7 +105,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 {
     using S = typename I::S;
     constexpr int B = S::B;
-    constexpr int N = GRID_N;
+    constexpr int N = I::N;
     const int lane = (int)threadIdx.x;
     const int kraw = block * 64 + lane;
     const bool valid = kraw < A.nknots;
@@ -143,7 +143,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
             R[i][k] = c[9 + k];
         }
     }
-    const float a0[6] = {0.0f, 0.0f, 0.0f, grid_a0[0], grid_a0[1], grid_a0[2]};   // -g
+    const float a0[6] = {0.0f, 0.0f, 0.0f, I::a0()[0], I::a0()[1], I::a0()[2]};   // -g
     const float zero6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 
     // ------------------------------------------------------------ 2. RNEA(q, qd, 0)
@@ -430,6 +430,10 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 
 }  // namespace grids
 
+// kernels of a one-robot module (a module of several robots defines GRID_PIPE_ONLY and its
+// own entry point, grid_fdgrad_pipe_mixed)
+#ifndef GRID_PIPE_ONLY
+
 // defined by the generated epilogue: workgroup -> (branch, 64 knots)
 __device__ void grid_dispatch_s(const grid::Args& args, int block);
 
@@ -437,3 +441,5 @@ extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_serial(grid::Args a
 {
     grid_dispatch_s(args, (int)blockIdx.x);
 }
+
+#endif  // GRID_PIPE_ONLY

@@ -73,6 +73,12 @@ class GridItem(C.Structure):
                 ("dqdd_dq", C.c_void_p), ("dqdd_dqd", C.c_void_p)]
 
 
+class GridMixedItem(C.Structure):
+    _fields_ = [("robot", C.c_int32), ("N", C.c_int32), ("q", C.c_void_p), ("qd", C.c_void_p),
+                ("tau", C.c_void_p), ("qdd", C.c_void_p), ("Minv", C.c_void_p),
+                ("dqdd_dq", C.c_void_p), ("dqdd_dqd", C.c_void_p)]
+
+
 class GridError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{status_string(status)}: {message}")
@@ -134,6 +140,14 @@ _SIGS = {
     "grid_codegen_source": (C.c_int32, [C.POINTER(GridDesc), C.c_uint32, C.c_char_p,
                                         C.POINTER(C.c_size_t)]),
     "grid_codegen_precompile": (C.c_int32, [C.POINTER(GridDesc), C.c_uint32]),
+    "grid_mixed_create": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_void_p)]),
+    "grid_mixed_launch": (C.c_int32, [C.c_void_p, C.POINTER(GridMixedItem), C.c_int32,
+                                      C.c_void_p]),
+    "grid_mixed_destroy": (C.c_int32, [C.c_void_p]),
+    "grid_mixed_source": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_char_p,
+                                      C.POINTER(C.c_size_t)]),
+    "grid_mixed_precompile": (C.c_int32, [C.POINTER(GridDesc), C.c_int32]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -419,6 +433,61 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def _desc_array(robots):
+    descs = [_Desc(r) for r in robots]
+    arr = (GridDesc * len(descs))(*[d.c for d in descs])
+    return descs, arr
+
+
+class Mixed:
+    """grid_mixed: one module for several robots; a table of items runs as one launch."""
+
+    def __init__(self, robots, device: int = 0):
+        self._h = None
+        _descs, arr = _desc_array(robots)
+        h = C.c_void_p()
+        _check(lib().grid_mixed_create(arr, len(robots), int(device), C.byref(h)))
+        self._h = h
+        self.count = len(robots)
+        self.device = device
+
+    def launch(self, items, stream=None):
+        """items: sequence of (robot index, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd) with
+        device tensors (N taken from q)."""
+        arr = (GridMixedItem * len(items))()
+        for k, (r, q, qd, tau, qdd, Mi, dq, dqd) in enumerate(items):
+            arr[k] = GridMixedItem(int(r), int(q.shape[0]), _addr(q), _addr(qd), _addr(tau),
+                                   _addr(qdd), _addr(Mi), _addr(dq), _addr(dqd))
+        _check(lib().grid_mixed_launch(self._h, arr, len(items), _stream_handle(stream)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().grid_mixed_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mixed_source(robots) -> str:
+    """Generated HIP source of a mixed module (no device needed)."""
+    _descs, arr = _desc_array(robots)
+    ln = C.c_size_t(0)
+    _check(lib().grid_mixed_source(arr, len(robots), None, C.byref(ln)))
+    buf = C.create_string_buffer(ln.value)
+    _check(lib().grid_mixed_source(arr, len(robots), buf, C.byref(ln)))
+    return buf.value.decode()
+
+
+def mixed_precompile(robots):
+    """Compile a mixed module into the on-disk cache (no device needed)."""
+    _descs, arr = _desc_array(robots)
+    _check(lib().grid_mixed_precompile(arr, len(robots)))
 
 
 def tune(model, Ns, table_path=None):

@@ -92,6 +92,7 @@ def _shapes_quad(src):
 def _insts(src):
     out = []
     for m in re.finditer(r"struct Inst<(\d+)> \{\s*using S = Shape<(\d+)>;\s*"
+                         r"static constexpr int N = \d+;\s*"
                          r"static constexpr int body\[S::B\] = \{([^}]*)\};", src):
         out.append((int(m.group(2)), [int(x) for x in m.group(3).split(",")]))
     return out
@@ -99,7 +100,7 @@ def _insts(src):
 
 def test_codegen_quadruped_has_four_identical_branches():
     src = grid.codegen_source(synth.quad12())
-    assert "#define GRID_N 12" in src
+    assert src.count("static constexpr int N = 12;") == 4   # one per branch
     shapes = _shapes(src)
     assert shapes == [(3, 8, [-1, 0, 1], [0, 0b1, 0b11])]
     insts = _insts(src)
@@ -196,3 +197,51 @@ def test_model_queries_reject_null_without_a_device():
     assert grid.lib().grid_model_code_hash(None, C.byref(h)) == grid.GRID_EINVAL
     n = C.c_int32()
     assert grid.lib().grid_model_info(None, C.byref(n), None, None) == grid.GRID_EINVAL
+
+
+def test_mixed_module_source_holds_every_branch_of_every_robot():
+    robots = [synth.chain7(), synth.quad12(), synth.humanoid30()]
+    src = grid.mixed_source(robots)
+    assert "#define GRID_PIPE_ONLY" in src
+    assert 'extern "C" __global__' in src and "grid_fdgrad_pipe_mixed" in src
+    # the robots' branches, numbered across the robots, one switch case each
+    per = [len(_insts(grid.codegen_source(r))) for r in robots]
+    assert per[:2] == [1, 4]
+    total = sum(per)
+    assert len(re.findall(r"^\s*case \d+: gridq::run_pipe<Inst<\d+>>", src, re.M)) == total - 1
+    assert len(re.findall(r"^\s*default: gridq::run_pipe<Inst<%d>>" % (total - 1), src,
+                          re.M)) == 1
+    assert [b for _, b in _insts(src)] == sum((
+        [b for _, b in _insts(grid.codegen_source(r))] for r in robots), [])
+    # each robot carries its own joint count and gravity
+    assert src.count("static constexpr int N = 7;") == per[0]
+    assert src.count("static constexpr int N = 12;") == per[1]
+    assert src.count("static constexpr int N = 30;") == per[2]
+    assert all(f"grid_a0_{r}[3]" in src for r in range(3))
+    # the one-robot kernels are compiled out of the module
+    tail = src.split('#line 1 "grid_fused.hip"')[-1]
+    assert tail.index("#ifndef GRID_PIPE_ONLY") < tail.index("grid_fdgrad_quad(")
+
+
+def test_mixed_rejects_bad_arguments_without_a_device():
+    import ctypes as C
+    lib = grid.lib()
+    h = C.c_void_p()
+    assert lib.grid_mixed_create(None, 1, 0, C.byref(h)) == grid.GRID_EINVAL
+    _d, arr = grid._desc_array([synth.chain7()])
+    assert lib.grid_mixed_create(arr, 0, 0, C.byref(h)) == grid.GRID_EINVAL
+    _d17, arr17 = grid._desc_array([synth.chain7()] * 17)
+    assert lib.grid_mixed_create(arr17, 17, 0, C.byref(h)) == grid.GRID_EINVAL
+    bad = synth.chain7()
+    bad.parent = bad.parent.copy()
+    bad.parent[3] = 5                                   # a parent after its child
+    _db, arrb = grid._desc_array([synth.chain7(), bad])
+    assert lib.grid_mixed_create(arrb, 2, 0, C.byref(h)) == grid.GRID_EINVAL
+    assert "model 1" in grid.last_error()
+    assert lib.grid_mixed_create(arr, 1, 0, None) == grid.GRID_EINVAL
+    item = grid.GridMixedItem()
+    assert lib.grid_mixed_launch(None, C.byref(item), 1, None) == grid.GRID_EINVAL
+    assert lib.grid_mixed_destroy(None) == grid.GRID_OK
+    ln = C.c_size_t(0)
+    assert lib.grid_mixed_source(arr, 1, None, None) == grid.GRID_EINVAL
+    assert lib.grid_mixed_source(arr, 1, None, C.byref(ln)) == grid.GRID_OK and ln.value > 1000

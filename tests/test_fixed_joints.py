@@ -17,6 +17,7 @@ def _consts(src):
     """Per generated branch: robot bodies and their 24 floats (E_T, r, Ibar, h, m)."""
     out = {}
     for m in re.finditer(r"struct Inst<(\d+)> \{\s*using S = Shape<\d+>;\s*"
+                         r"static constexpr int N = \d+;\s*"
                          r"static constexpr int body\[S::B\] = \{([^}]*)\};", src):
         k = int(m.group(1))
         bodies = [int(x) for x in m.group(2).split(",")]
@@ -53,7 +54,7 @@ def test_reduced_constants_match_oracle_compositions(orc, parent, fixed):
     n = robot.n
     movable = [i for i in range(n) if i not in fixed]
     src = grid.codegen_source(robot)
-    assert f"#define GRID_N {len(movable)}\n" in src
+    assert f"static constexpr int N = {len(movable)};\n" in src
     consts = _consts(src)
     assert sorted(consts) == list(range(len(movable)))
     X0 = [orc.joint_transform(robot, i, 0.0) for i in range(n)]   # X_T: fixed joints at 0

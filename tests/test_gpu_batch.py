@@ -125,3 +125,72 @@ def test_graph_rejects_bad_items():
         grid.Graph([(m, t, None, t, t, t, t, t)])
     assert e.value.status == grid.GRID_EINVAL
     m.close()
+
+
+def test_mixed_one_launch_equals_pipe_build_alone(orc):
+    """One kernel launch over items of six robots (a chain, four legs, a 30-body tree,
+    prismatic joints, fixed joints, 32 one-body branches), with a robot used twice, an empty
+    item and ragged N: every item equals the same robot's pipe build run alone and the oracle."""
+    import torch
+    from paper_2109_06976_amd import build
+    robots = build.mixed_sets()[1]
+    say("[gpu] mixed module: " + " + ".join(r.name for r in robots))
+    mx = grid.Mixed(robots)
+    models = []
+    for r in robots:
+        m = grid.Model(r)
+        grid.tune_apply(m, {1 << 22: grid.BUILD_PIPE})
+        models.append(m)
+    plan = [(0, 37), (1, 64), (2, 5), (0, 1), (3, 0), (4, 19), (5, 3), (2, 2)]
+    for launch in range(2):                      # a second launch reuses the module
+        items, knots = [], []
+        for j, (r, N) in enumerate(plan):
+            n = models[r].n                      # degrees of freedom (fixed joints removed)
+            kn = synth.random_knots(n, N, 700 + 10 * launch + j)
+            ins = [torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)]
+            outs = [torch.full((N, n), float("nan"), device="cuda")] + \
+                   [torch.full((N, n, n), float("nan"), device="cuda") for _ in range(3)]
+            items.append((models[r], *ins, *outs))
+            knots.append(kn)
+        say(f"[gpu] mixed launch {launch}: items {plan}")
+        mx.launch([(r, *it[1:]) for (r, _), it in zip(plan, items)])
+        torch.cuda.synchronize()
+        tol = {"qdd": 1e-4, "Minv": 1e-3, "dqdd_dq": 1e-3, "dqdd_dqd": 1e-3}
+        for (r, N), item, kn in zip(plan, items, knots):
+            if N == 0:
+                continue
+            got = [t.cpu().numpy() for t in item[4:]]
+            want = alone(torch, models[r], item)
+            for k, g, w in zip(OUTS, got, want):
+                scale = float(np.abs(w).max()) if w.size else 1.0
+                np.testing.assert_allclose(g, w, rtol=1e-5, atol=1e-6 * scale,
+                                           err_msg=f"{robots[r].name} N={N} {k}")
+            if getattr(robots[r], "joint_type", None) is not None and \
+                    (robots[r].joint_type == grid.JOINT_FIXED).any():
+                continue                         # the locked-joint oracle covers its pipe build
+            ref = orc.fd_grad_batch(robots[r], kn.q, kn.qd, kn.tau)
+            for k, g in zip(OUTS, got):
+                y = g.astype(np.float64).reshape(N, -1)
+                w = ref[k].reshape(N, -1)
+                err = (np.abs(y - w).max(1) / np.maximum(np.abs(w).max(1), 1e-30)).max()
+                assert err <= tol[k], (robots[r].name, N, k, err)
+        for (r, N), item in zip(plan, items):
+            if N:
+                got = [t.cpu().numpy() for t in item[4:]]
+                want = alone(torch, models[r], item)
+                same = all(np.array_equal(g, w) for g, w in zip(got, want))
+                say(f"  item {robots[r].name} N={N}: matches its pipe build alone "
+                    f"(bitwise: {same})")
+    # host-side rejections: robot index, too many (item, branch) segments
+    t = torch.zeros((4, 7), device="cuda")
+    with pytest.raises(grid.GridError) as e:
+        mx.launch([(6, t, t, t, t, t, t, t)])
+    assert e.value.status == grid.GRID_EINVAL
+    s32 = torch.zeros((1, 32), device="cuda")
+    s32m = torch.zeros((1, 32, 32), device="cuda")
+    with pytest.raises(grid.GridError) as e:
+        mx.launch([(5, s32, s32, s32, s32, s32m, s32m, s32m)] * 3)   # 96 segments
+    assert e.value.status == grid.GRID_EINVAL
+    mx.close()
+    for m in models:
+        m.close()
