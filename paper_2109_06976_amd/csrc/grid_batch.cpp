@@ -3,6 +3,7 @@
 #include "grid_internal.h"
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -208,6 +209,13 @@ grid_status grid_graph_destroy(grid_graph g)
 }  // extern "C"
 
 // ------------------------------------------------------------------ one launch, several robots
+
+// the block is passed by value as the kernel's only argument: its host layout must be the
+// device one (ints, then 8-byte aligned argument blocks of the same field order)
+static_assert(sizeof(KernelArgs) == 72, "Args: an int and eight pointers");
+static_assert(offsetof(MixedArgs, item) == 4 + 3 * 4 * kMixedSegs + 4 &&
+                  sizeof(MixedArgs) == offsetof(MixedArgs, item) + kMixedItems * sizeof(KernelArgs),
+              "MixedArgs layout");
 
 struct grid_mixed_s {
     int device = 0;
