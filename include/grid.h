@@ -196,8 +196,14 @@ grid_status grid_fd_grad_staged(grid_model m, grid_workspace ws, int32_t N, cons
  * topology as compile-time structures, its constants as float literals) into buf (len
  * in: capacity, out: bytes needed including the terminating NUL; buf may be NULL to
  * query), or compile it into the kernel cache. Used by the build step and by tests.
- * Errors: as grid_model_create's description checks; EINVAL if buf is too small.
+ * A model has two code objects: every kernel, and the role-split fused kernel (the build
+ * grid_fd_grad picks for small batches) alone, compiled with an instruction-level-
+ * parallelism schedule. grid_codegen_source returns the first, or with
+ * GRID_CODEGEN_PIPE_MODULE the second; grid_codegen_precompile (flags 0) compiles both.
+ * Errors: as grid_model_create's description checks; EINVAL if buf is too small or a flag
+ * bit is unknown.
  */
+#define GRID_CODEGEN_PIPE_MODULE (1u << 16)
 grid_status grid_codegen_source(const grid_model_desc* desc, uint32_t flags, char* buf,
                                 size_t* len);
 grid_status grid_codegen_precompile(const grid_model_desc* desc, uint32_t flags);

@@ -23,6 +23,8 @@ LIB = os.path.join(HERE, "libgrid.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # no packed FP32 instructions in any HIP code of this project
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# the pipe kernel module's scheduling strategy (the library passes the same to hiprtc)
+KERNEL_SCHED = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
 
 
 def _run(cmd, verbose):
@@ -136,17 +138,20 @@ def mixed_sets():
 
 
 def offline_compile_check(verbose=False):
-    """hipcc --genco of the generated source for the three workload robots."""
+    """hipcc --genco of the generated sources (both modules) for the three workload robots,
+    with the options the library gives hiprtc for each."""
     from paper_2109_06976_amd import grid, synth
     for robot in (synth.chain7(), synth.quad12(), synth.humanoid30()):
-        src = "#include <hip/hip_runtime.h>\n" + grid.codegen_source(robot)
         name = robot.name.split("-")[0]
-        path = os.path.join(BUILD, f"{name}.hip")
-        with open(path, "w") as f:
-            f.write(src)
-        out = os.path.join(BUILD, f"{name}.hsaco")
-        _run([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", *NO_PACKED_FP32, "--genco",
-              "-save-temps=obj", "-o", out, path], verbose)
+        for suffix, flags, extra in (("", 0, []),
+                                     ("_pipe", grid.GRID_CODEGEN_PIPE_MODULE, KERNEL_SCHED)):
+            src = "#include <hip/hip_runtime.h>\n" + grid.codegen_source(robot, flags)
+            path = os.path.join(BUILD, f"{name}{suffix}.hip")
+            with open(path, "w") as f:
+                f.write(src)
+            out = os.path.join(BUILD, f"{name}{suffix}.hsaco")
+            _run([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", *NO_PACKED_FP32, *extra,
+                  "--genco", "-save-temps=obj", "-o", out, path], verbose)
 
 
 def _precompile_one(robot):

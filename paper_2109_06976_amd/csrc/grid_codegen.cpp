@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cstring>
 #include <fstream>
+#include <iterator>
 #include <mutex>
 #include <sstream>
 
@@ -336,6 +337,35 @@ static void emit_prelude(std::ostringstream& os, const std::vector<RobotSource>&
     }
 }
 
+// A dispatcher walks the branches: workgroups [0, nb_0) run branch 0, the next nb_1 run
+// branch 1, and so on. The grid holds exactly sum nb_k workgroups, so the last branch takes
+// the rest without a bound check: with one branch nothing waits for nknots before the other
+// kernel arguments are loaded. (A workgroup past the end would still only recompute the last
+// knot and store nothing: every store checks its knot.) `@` in per_block and call stands for
+// the branch's Inst.
+static void emit_dispatch(std::ostringstream& os, const Topology& t, const char* sig,
+                          const std::string& per_block, const std::string& call)
+{
+    os << sig << "\n{\n    int b = block;\n";
+    for (size_t k = 0; k < t.insts.size(); ++k) {
+        const std::string K = "Inst<" + std::to_string(k) + ">";
+        auto sub = [&](std::string x) {
+            for (size_t at; (at = x.find("@")) != std::string::npos;)
+                x.replace(at, 1, K);
+            return x;
+        };
+        if (k + 1 == t.insts.size()) {
+            os << "    " << sub(call) << ";\n";
+            break;
+        }
+        os << "    {\n        const int P = " << sub(per_block) << ";\n"
+           << "        const int nb = (a.nknots + P - 1) / P;\n"
+           << "        if (b < nb) {\n            " << sub(call) << ";\n            return;\n"
+           << "        }\n        b -= nb;\n    }\n";
+    }
+    os << "}\n";
+}
+
 std::string generate_source(const Topology& t, const std::vector<float>& consts,
                             const double gravity[3], uint32_t flags)
 {
@@ -347,52 +377,49 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     emit_prelude(os, {rs}, &base);
     os << "#line 1 \"grid_device.hip\"\n";
     os << grid_device_src;
-    // A dispatcher walks the branches: workgroups [0, nb_0) run branch 0, the next nb_1 run
-    // branch 1, and so on. The grid holds exactly sum nb_k workgroups, so the last branch
-    // takes the rest without a bound check: with one branch nothing waits for nknots before
-    // the other kernel arguments are loaded. (A workgroup past the end would still only
-    // recompute the last knot and store nothing: every store checks its knot.)
-    auto dispatch = [&](const char* sig, const std::string& per_block,
-                        const std::string& call) {
-        os << sig << "\n{\n    int b = block;\n";
-        for (size_t k = 0; k < t.insts.size(); ++k) {
-            const std::string K = "Inst<" + std::to_string(k) + ">";
-            auto sub = [&](std::string x) {
-                for (size_t at; (at = x.find("@")) != std::string::npos;)
-                    x.replace(at, 1, K);
-                return x;
-            };
-            if (k + 1 == t.insts.size()) {
-                os << "    " << sub(call) << ";\n";
-                break;
-            }
-            os << "    {\n        const int P = " << sub(per_block) << ";\n"
-               << "        const int nb = (a.nknots + P - 1) / P;\n"
-               << "        if (b < nb) {\n            " << sub(call) << ";\n            return;\n"
-               << "        }\n        b -= nb;\n    }\n";
-        }
-        os << "}\n";
-    };
     os << "\n// generated: workgroup -> (branch, knot group)\n";
-    dispatch("template <int ST>\n__device__ void grid_dispatch(const grid::Args& a, int block)",
+    emit_dispatch(os, t, "template <int ST>\n__device__ void grid_dispatch(const grid::Args& a, int block)",
              "64 / @::S::L", "grid::run_branch<@, ST>(a, b)");
     os << "#line 1 \"grid_fused.hip\"\n";
     os << grid_fused_src;
     os << "\n// generated: workgroup -> (branch, problem group), quad layout\n";
-    dispatch("__device__ void grid_dispatch_q(const grid::Args& a, int block)",
+    emit_dispatch(os, t, "__device__ void grid_dispatch_q(const grid::Args& a, int block)",
              "(GRID_WAVES / @::S::W) * (16 / @::S::Q)", "gridq::run_fused<@>(a, b)");
     os << "#line 1 \"grid_serial.hip\"\n";
     os << grid_serial_src;
     os << "\n// generated: workgroup -> (branch, 64 knots), one lane per knot\n";
-    dispatch("__device__ void grid_dispatch_s(const grid::Args& a, int block)", "64",
+    emit_dispatch(os, t, "__device__ void grid_dispatch_s(const grid::Args& a, int block)", "64",
              "grids::run_serial<@>(a, b)");
-    dispatch("__device__ void grid_dispatch_p(const grid::Args& a, int block)", "@::S::PP",
+    emit_dispatch(os, t, "__device__ void grid_dispatch_p(const grid::Args& a, int block)", "@::S::PP",
              "gridq::run_pipe<@>(a, b)");
     os << "#line 1 \"grid_ops.hip\"\n";
     os << grid_ops_src;
     os << "\n// generated: workgroup -> (branch, problem group), standalone algorithms\n";
-    dispatch("template <int OP>\n__device__ void grid_dispatch_op(const gridq::OpArgs& a, int block)",
+    emit_dispatch(os, t, "template <int OP>\n__device__ void grid_dispatch_op(const gridq::OpArgs& a, int block)",
              "gridq::op_problems<@::S, OP>()", "gridq::run_op<@, OP>(a, b)");
+    return os.str();
+}
+
+// The pipe kernel (build 4) alone, for its own module compiled with the ILP schedule.
+std::string generate_pipe_source(const Topology& t, const std::vector<float>& consts,
+                                 const double gravity[3])
+{
+    std::ostringstream os;
+    os << "// generated: one robot as compile-time structures and constants, pipe kernel\n";
+    os << "#define GRID_PIPE_ONLY 1\n";
+    std::vector<int> base;
+    RobotSource rs{&t, &consts, {gravity[0], gravity[1], gravity[2]}};
+    emit_prelude(os, {rs}, &base);
+    os << "#line 1 \"grid_device.hip\"\n";
+    os << grid_device_src;
+    os << "#line 1 \"grid_fused.hip\"\n";
+    os << grid_fused_src;
+    os << "\n// generated: workgroup -> (branch, problem group), pipe kernel\n";
+    emit_dispatch(os, t, "__device__ void grid_dispatch_p(const grid::Args& a, int block)",
+                  "@::S::PP", "gridq::run_pipe<@>(a, b)");
+    os << "extern \"C\" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) "
+          "grid_fdgrad_pipe(grid::Args args)\n{\n"
+          "    grid_dispatch_p(args, (int)blockIdx.x);\n}\n";
     return os.str();
 }
 
@@ -442,6 +469,12 @@ static const char* const kCompileOptions[] = {
     // packed FP32 instructions are not generated (correctness of some packed forms)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 };
+
+// the pipe kernel's own module: each of its wavefronts has a SIMD to itself and runs one long
+// dependent chain, so it is scheduled for instruction-level parallelism rather than
+// occupancy (chain7, N = 128: 4.65 against 4.97 us per launch; quad12 and humanoid30
+// unchanged). The throughput builds keep the default (build 2 at N = 16384 lost 9% with it).
+static const char* const kIlpOptions[] = {"-mllvm", "-amdgpu-sched-strategy=max-ilp"};
 
 static uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull)
 {
@@ -496,10 +529,14 @@ static void write_file_atomic(const std::string& dir, const std::string& path,
 
 static std::mutex g_compile_mutex;
 
-grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err)
+grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err,
+                           bool ilp)
 {
+    std::vector<const char*> opts(std::begin(kCompileOptions), std::end(kCompileOptions));
+    if (ilp)
+        opts.insert(opts.end(), std::begin(kIlpOptions), std::end(kIlpOptions));
     std::string key_src = source;
-    for (const char* o : kCompileOptions)
+    for (const char* o : opts)
         key_src += std::string("\n//opt ") + o;
     char name[64];
     std::snprintf(name, sizeof name, "grid_%016llx.hsaco", (unsigned long long)fnv1a(key_src));
@@ -517,8 +554,7 @@ grid_status compile_cached(const std::string& source, std::vector<char>* code, s
         *err = "hiprtcCreateProgram failed";
         return GRID_ECOMPILE;
     }
-    const int nopt = sizeof(kCompileOptions) / sizeof(kCompileOptions[0]);
-    hiprtcResult rc = hiprtcCompileProgram(prog, nopt, kCompileOptions);
+    hiprtcResult rc = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
     if (rc != HIPRTC_SUCCESS) {
         size_t log_size = 0;
         hiprtcGetProgramLogSize(prog, &log_size);

@@ -115,6 +115,8 @@ bool analyse_topology(const int32_t* parent, int32_t n, Topology* out, std::stri
 std::vector<float> pack_constants(const grid_model_desc* d, const Topology& t);
 std::string generate_source(const Topology& t, const std::vector<float>& consts,
                             const double gravity[3], uint32_t flags);
+std::string generate_pipe_source(const Topology& t, const std::vector<float>& consts,
+                                 const double gravity[3]);
 std::string generate_mixed_source(const std::vector<RobotSource>& robots,
                                   std::vector<int>* inst_base);
 grid_status prepare_robot(const grid_model_desc* desc, Topology* topo,
@@ -129,7 +131,9 @@ int pipe_problems(int B);
 int pipe_waves(const Topology& t);
 int lanes_per_knot(const Topology& t);
 WorkspaceLayout workspace_layout(const Topology& t);
-grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err);
+// ilp: the instruction-level-parallelism schedule (the pipe kernel's module)
+grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err,
+                           bool ilp = false);
 uint64_t source_hash(const std::string& source);
 grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
                          const float* tau, float* qdd, float* Minv, float* dq, float* dqd,
@@ -161,6 +165,7 @@ struct grid_model_s {
     hipFunction_t op[grid_impl::kNumOps] = {};                    // see kOpId
     std::vector<std::pair<int32_t, int>> tuned;   // (largest N, variant), ascending N
     hipModule_t module = nullptr;
+    hipModule_t pipe_module = nullptr;  // build 4 alone, compiled with the ILP schedule
     hipFunction_t stage[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 

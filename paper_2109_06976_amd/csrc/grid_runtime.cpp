@@ -450,17 +450,20 @@ grid_status prepare_robot(const grid_model_desc* desc, Topology* topo,
 
 extern "C" {
 
-static grid_status prepare(const grid_model_desc* desc, uint32_t flags, Topology* topo,
-                           std::string* src)
+// the model's two module sources: every kernel, and the pipe kernel alone (compiled with the
+// ILP schedule); `allowed` are the flag bits the caller accepts
+static grid_status prepare(const grid_model_desc* desc, uint32_t flags, uint32_t allowed,
+                           Topology* topo, std::string* src, std::string* pipe_src)
 {
     std::string err;
     std::vector<float> consts;
     grid_status s = prepare_robot(desc, topo, &consts, &err);
     if (s != GRID_OK)
         return fail(s, err);
-    if (flags != 0)
+    if (flags & ~allowed)
         return fail(GRID_EINVAL, "unknown flag bits");
-    *src = generate_source(*topo, consts, desc->gravity, flags);
+    *src = generate_source(*topo, consts, desc->gravity, 0);
+    *pipe_src = generate_pipe_source(*topo, consts, desc->gravity);
     return GRID_OK;
 }
 
@@ -470,10 +473,11 @@ grid_status grid_codegen_source(const grid_model_desc* desc, uint32_t flags, cha
     if (!len)
         return fail(GRID_EINVAL, "len must not be NULL");
     Topology t;
-    std::string src;
-    grid_status s = prepare(desc, flags, &t, &src);
+    std::string main_src, pipe_src;
+    grid_status s = prepare(desc, flags, GRID_CODEGEN_PIPE_MODULE, &t, &main_src, &pipe_src);
     if (s != GRID_OK)
         return s;
+    const std::string& src = (flags & GRID_CODEGEN_PIPE_MODULE) ? pipe_src : main_src;
     const size_t need = src.size() + 1;
     const bool fits = buf && *len >= need;
     if (fits)
@@ -487,12 +491,14 @@ grid_status grid_codegen_source(const grid_model_desc* desc, uint32_t flags, cha
 grid_status grid_codegen_precompile(const grid_model_desc* desc, uint32_t flags)
 {
     Topology t;
-    std::string src, err;
-    grid_status s = prepare(desc, flags, &t, &src);
+    std::string src, pipe_src, err;
+    grid_status s = prepare(desc, flags, 0, &t, &src, &pipe_src);
     if (s != GRID_OK)
         return s;
     std::vector<char> code;
     s = compile_cached(src, &code, &err);
+    if (s == GRID_OK)
+        s = compile_cached(pipe_src, &code, &err, true);
     if (s != GRID_OK)
         return fail(s, err);
     return GRID_OK;
@@ -505,12 +511,14 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
         return fail(GRID_EINVAL, "out must not be NULL");
     *out = nullptr;
     Topology topo;
-    std::string src, err;
-    grid_status s = prepare(desc, flags, &topo, &src);
+    std::string src, pipe_src, err;
+    grid_status s = prepare(desc, flags, 0, &topo, &src, &pipe_src);
     if (s != GRID_OK)
         return s;
-    std::vector<char> code;
+    std::vector<char> code, pipe_code;
     s = compile_cached(src, &code, &err);
+    if (s == GRID_OK)
+        s = compile_cached(pipe_src, &pipe_code, &err, true);
     if (s != GRID_OK)
         return fail(s, err);
 
@@ -531,7 +539,8 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     m->device = device;
     m->flags = flags;
     m->topo = std::move(topo);
-    m->code_hash = source_hash(std::string(code.begin(), code.end()));
+    m->code_hash = source_hash(std::string(code.begin(), code.end()) +
+                               std::string(pipe_code.begin(), pipe_code.end()));
     static const char* const kStages[5] = {"grid_stage_rnea", "grid_stage_minv", "grid_stage_qdd",
                                            "grid_stage_drnea", "grid_stage_fdgrad"};
     static const char* const kVariants[kNumVariants] = {
@@ -548,6 +557,11 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
         e = hipModuleGetFunction(&m->op[k], m->module, kOps[k]);
     for (int k = 0; k < 5 && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->stage[k], m->module, kStages[k]);
+    if (e == hipSuccess)
+        e = hipModuleLoadData(&m->pipe_module, pipe_code.data());
+    if (e == hipSuccess)   // build 4 from its own module
+        e = hipModuleGetFunction(&m->fused_variant[kVariantPipe], m->pipe_module,
+                                 "grid_fdgrad_pipe");
     if (e != hipSuccess) {
         grid_model_destroy(m);
         return hip_fail(e, "module load");
@@ -564,6 +578,8 @@ grid_status grid_model_destroy(grid_model m)
     (void)hipSetDevice(m->device);
     if (m->module)
         (void)hipModuleUnload(m->module);
+    if (m->pipe_module)
+        (void)hipModuleUnload(m->pipe_module);
     delete m;
     return GRID_OK;
 }

@@ -26,6 +26,7 @@ GRID_EBUSY = -6
 GRID_ETIMEDOUT = -7
 GRID_ECANCELED = -8
 GRID_SERVER_PER_REQUEST = 1
+GRID_CODEGEN_PIPE_MODULE = 1 << 16
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)

@@ -245,3 +245,22 @@ def test_mixed_rejects_bad_arguments_without_a_device():
     ln = C.c_size_t(0)
     assert lib.grid_mixed_source(arr, 1, None, None) == grid.GRID_EINVAL
     assert lib.grid_mixed_source(arr, 1, None, C.byref(ln)) == grid.GRID_OK and ln.value > 1000
+
+
+def test_pipe_kernel_has_a_module_of_its_own():
+    robot = synth.chain7()
+    main = grid.codegen_source(robot)
+    pipe = grid.codegen_source(robot, grid.GRID_CODEGEN_PIPE_MODULE)
+    assert "#define GRID_PIPE_ONLY" in pipe and "#define GRID_PIPE_ONLY" not in main
+    assert 'grid_fdgrad_pipe(grid::Args args)' in pipe
+    assert "grid_dispatch_p(args, (int)blockIdx.x)" in pipe
+    # the same robot: identical branch structures and constants in both preludes
+    assert _insts(pipe) == _insts(main)
+    assert pipe.split('#line 1 "grid_device.hip"')[0].split("\n", 2)[2] == \
+        main.split('#line 1 "grid_device.hip"')[0].split("\n", 1)[1]
+    with pytest.raises(grid.GridError) as e:
+        grid.codegen_source(robot, 1 << 3)
+    assert e.value.status == grid.GRID_EINVAL
+    with pytest.raises(grid.GridError) as e:
+        grid.Model(robot, flags=grid.GRID_CODEGEN_PIPE_MODULE)   # a codegen flag only
+    assert e.value.status == grid.GRID_EINVAL
