@@ -129,10 +129,10 @@ grid_status grid_model_destroy(grid_model m);
 grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
                             int32_t* lanes);
 
-/* A 64-bit FNV-1a hash of the model's loaded code object (every kernel generated for the
- * robot), so that measurements taken on a kernel can be matched to the exact machine code
- * they ran; the same robot, sources and compiler give the same hash. Errors: EINVAL (NULL
- * argument). */
+/* A 64-bit FNV-1a hash of the model's two loaded code objects (every kernel generated for
+ * the robot, then the role-split kernel's own module), so that measurements taken on a
+ * kernel can be matched to the exact machine code they ran; the same robot, sources and
+ * compiler give the same hash. Errors: EINVAL (NULL argument). */
 grid_status grid_model_code_hash(grid_model m, uint64_t* hash);
 
 /*

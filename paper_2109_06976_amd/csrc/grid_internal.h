@@ -159,7 +159,7 @@ struct grid_model_s {
     uint32_t flags = 0;
     grid_impl::Topology topo;
     uint64_t source_hash = 0;           // of the generated source: keys tuning tables
-    uint64_t code_hash = 0;             // of the loaded code object (all of its kernels)
+    uint64_t code_hash = 0;             // of the two loaded code objects, in that order
     int compute_units = 256;
     hipFunction_t fused_variant[grid_impl::kNumVariants] = {};   // see kVariantQuad
     hipFunction_t op[grid_impl::kNumOps] = {};                    // see kOpId
