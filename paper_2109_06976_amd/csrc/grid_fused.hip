@@ -191,6 +191,20 @@ __device__ __forceinline__ constexpr bool is_anc(int a, int i)
     return (S::anc[i] >> a) & 1ull;
 }
 
+// Columns j >= JMIN only: body i carries a nonzero forward derivative only in the subtree of
+// j (local indices >= j), and a nonzero backward one only there or on j's ancestor path.
+// Known at compile time once the body loops are unrolled, so the dead bodies cost nothing.
+template <class S, int JMIN>
+__device__ __forceinline__ constexpr bool live_back(int i)
+{
+    if (i >= JMIN)
+        return true;
+    for (int k = JMIN; k < S::B; ++k)
+        if (is_anc<S>(i, k))
+            return true;
+    return false;
+}
+
 template <class I>
 __device__ __forceinline__ float mass(int i)
 {
@@ -338,8 +352,9 @@ __device__ __forceinline__ void rnea_at(const Lane& ln, const float (&qd)[I::S::
 }
 
 // column jm of M as ID(q, 0, e_jm) without gravity; M_i,jm = S^T f_i is s_half(f_i) on
-// lane 2 of the quad
-template <class I>
+// lane 2 of the quad. JMIN: jm >= JMIN is known (rows outside jm's subtree and ancestor path
+// come out zero)
+template <class I, int JMIN = 0>
 __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B],
                                          const LaneK (&K)[I::S::B], int jm, V (&fm)[I::S::B])
 {
@@ -350,7 +365,11 @@ __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B]
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         const int p = S::parent[i];
-        if (p >= 0)
+        if (i < JMIN) {                       // not in the subtree of jm
+            fm[i] = V{0.0f, 0.0f};
+            continue;
+        }
+        if (p >= JMIN)
             am[i] = xmv(E[i], K[i], am[p < 0 ? 0 : p], nam[p < 0 ? 0 : p]);
         else
             am[i] = V{0.0f, 0.0f};
@@ -362,7 +381,7 @@ __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B]
 #pragma unroll
     for (int i = B - 1; i >= 0; --i) {
         const int p = S::parent[i];
-        if (p >= 0)
+        if (p >= 0 && live_back<S, JMIN>(i))
             fm[p < 0 ? 0 : p] = add(fm[p < 0 ? 0 : p], xtfv(E[i], K[i], fm[i], gather(fm[i])));
     }
 }
@@ -447,7 +466,7 @@ __device__ __forceinline__ void delta_rnea(const Lane& ln, const Rot (&E)[I::S::
 // One dRNEA column (Algorithm 1 forward, then the backward pass) with sources src_v, src_a
 // entering at body j and src_f entering j's parent. kVel = false is the sweep with dv = 0
 // (da_i = X_i da_lambda + source, df_i = I_i da_i). Returns dtau (every lane of the quad).
-template <class I, bool kVel>
+template <class I, bool kVel, int JMIN = 0>
 __device__ __forceinline__ void drnea_column(const Lane& ln, const float (&qd)[I::S::B],
                                              const Rot (&E)[I::S::B], const LaneK (&K)[I::S::B],
                                              const V (&v)[I::S::B], const V (&gam)[I::S::B],
@@ -463,9 +482,13 @@ __device__ __forceinline__ void drnea_column(const Lane& ln, const float (&qd)[I
 #pragma unroll
         for (int i = 0; i < B; ++i) {
             const int p = S::parent[i];
+            if (i < JMIN) {                   // j >= JMIN: not in the subtree of j
+                df[i] = V{0.0f, 0.0f};
+                continue;
+            }
             const float sel = (i == j) ? 1.0f : 0.0f;
             V xdv{0.0f, 0.0f}, xda{0.0f, 0.0f};
-            if (p >= 0) {
+            if (p >= JMIN) {
                 if constexpr (kVel)
                     xdv = xmv(E[i], K[i], dv[p < 0 ? 0 : p], ndv[p < 0 ? 0 : p]);
                 xda = xmv(E[i], K[i], da[p < 0 ? 0 : p], nda[p < 0 ? 0 : p]);
@@ -490,6 +513,10 @@ __device__ __forceinline__ void drnea_column(const Lane& ln, const float (&qd)[I
     }
 #pragma unroll
     for (int i = B - 1; i >= 0; --i) {
+        if (!live_back<S, JMIN>(i)) {         // off j's subtree and ancestor path
+            dx[i] = 0.0f;
+            continue;
+        }
         dx[i] = qperm<kZ>(s_half(prismatic<I>(i), df[i]));
         const int p = S::parent[i];
         if (p >= 0) {
@@ -887,7 +914,10 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             V fm[B];
-            m_column<I>(ln, E, K, js[cb], fm);
+            if (cb == 0)
+                m_column<I>(ln, E, K, js[cb], fm);
+            else                              // columns 16.. only
+                m_column<I, 16>(ln, E, K, js[cb], fm);
             if (owns[cb] && c == 2) {
 #pragma unroll
                 for (int i = 0; i < B; ++i)
@@ -949,8 +979,12 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
             const V src_a = cross_s(ln, pj, pick<B>(xd, j));
             const V src_f = back_source(ln, pj, Ej, Kj, pick<B>(Df, j));
             float dxc[B];
-            drnea_column<I, false>(ln, qd, E, K, none, none, j, V{0.0f, 0.0f}, src_a, src_f,
-                                   dxc);
+            if (cb == 0)
+                drnea_column<I, false>(ln, qd, E, K, none, none, j, V{0.0f, 0.0f}, src_a,
+                                       src_f, dxc);
+            else                              // columns 16.. only
+                drnea_column<I, false, 16>(ln, qd, E, K, none, none, j, V{0.0f, 0.0f}, src_a,
+                                           src_f, dxc);
             if (owns[cb]) {
 #pragma unroll
                 for (int i = 0; i < B; ++i)
