@@ -424,3 +424,14 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* threads of later batch calls (timing control only; no effect on any result) */
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0)
+        omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}

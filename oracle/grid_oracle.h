@@ -82,6 +82,7 @@ int orc_fd_grad_batch(const orc_model *m, int N, const double *q, const double *
                       const double *tau, double *qdd, double *Minv, double *dqdd_dq,
                       double *dqdd_dqd);
 int orc_num_threads(void);
+void orc_set_num_threads(int k);
 
 /* complex-step instantiations (same source, scalar type double complex) */
 int orc_rnea_z(const orc_model *m, const double complex *q, const double complex *qd,

@@ -30,6 +30,17 @@ class OracleError(RuntimeError):
     pass
 
 
+def _load(path):
+    handle = C.CDLL(path)
+    for name in ("orc_rnea", "orc_crba", "orc_minv_cholesky", "orc_minv_direct", "orc_fd",
+                 "orc_rnea_grad", "orc_fd_grad", "orc_fd_grad_batch", "orc_rnea_z", "orc_fd_z",
+                 "orc_joint_transform", "orc_spatial_inertia", "orc_num_threads"):
+        getattr(handle, name).restype = C.c_int
+    handle.orc_set_num_threads.restype = None
+    handle.orc_set_num_threads.argtypes = [C.c_int]
+    return handle
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -39,12 +50,21 @@ def lib():
             mod = importlib.util.module_from_spec(spec)
             spec.loader.exec_module(mod)
             mod.build()
-        _lib = C.CDLL(_LIB_PATH)
-        for name in ("orc_rnea", "orc_crba", "orc_minv_cholesky", "orc_minv_direct", "orc_fd",
-                     "orc_rnea_grad", "orc_fd_grad", "orc_fd_grad_batch", "orc_rnea_z", "orc_fd_z",
-                     "orc_joint_transform", "orc_spatial_inertia", "orc_num_threads"):
-            getattr(_lib, name).restype = C.c_int
+        _lib = _load(_LIB_PATH)
     return _lib
+
+
+def use_library(path: str):
+    """Load another build of the same oracle source (the CPU-baseline timing build) for every
+    later call of this module."""
+    global _lib
+    _lib = _load(path)
+    return _lib
+
+
+def set_num_threads(k: int):
+    """OpenMP threads of later batch calls."""
+    lib().orc_set_num_threads(int(k))
 
 
 def _f64(x, shape=None):
