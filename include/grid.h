@@ -31,7 +31,8 @@
  *
  * Errors: every call returns a grid_status. Arguments are validated on the host
  * before any device work, so on error nothing has been enqueued. N = 0 is a no-op that
- * returns GRID_OK. NaN or Inf inputs are not checked and propagate to the outputs. A
+ * returns GRID_OK. A call takes at most GRID_MAX_KNOTS knots (2^24; a larger N is EINVAL).
+ * NaN or Inf inputs are not checked and propagate to the outputs. A
  * fault of an asynchronous launch surfaces as GRID_EDEVICE at the next call that
  * synchronises. grid_last_error() returns a thread-local description of the last
  * failure on the calling thread. No C++ exception crosses this interface.
@@ -61,6 +62,9 @@ typedef int32_t grid_status;
 #define GRID_EBUSY (-6)         /* a request larger than the server's admission budget */
 #define GRID_ETIMEDOUT (-7)     /* the wait ended before the request completed */
 #define GRID_ECANCELED (-8)     /* the server was destroyed before the request ran */
+
+/* The largest knot count N of one call (and max_knots of a workspace): 2^24. */
+#define GRID_MAX_KNOTS (1 << 24)
 
 #define GRID_JOINT_REVOLUTE 0
 #define GRID_JOINT_PRISMATIC 1
@@ -141,7 +145,7 @@ grid_status grid_model_code_hash(grid_model m, uint64_t* hash);
  * dRNEA forward/backward, -M^-1 dtau and M^-1). All pointers are device
  * pointers in the layouts above; `stream` is a hipStream_t (NULL = default stream).
  * Asynchronous: returns after the launch is enqueued. Errors: EINVAL (N < 0, a NULL
- * pointer with N > 0, N > 2^31/64), EDEVICE (launch failure).
+ * pointer with N > 0, N > GRID_MAX_KNOTS), EDEVICE (launch failure).
  */
 grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* qd,
                          const float* tau, float* qdd, float* Minv, float* dqdd_dq,
@@ -153,7 +157,7 @@ grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* q
  *   qbar = (dqdd/dq)^T gbar,  qdbar = (dqdd/dqd)^T gbar,  taubar = M^-1 gbar
  * (dqdd/dtau = M^-1 is symmetric; Sec. IV-B). Device pointers, [N][n] vectors and
  * [N][n][n] matrices as above; asynchronous on `stream`. Errors: EINVAL (N < 0, NULL
- * pointers), EDEVICE.
+ * pointers, N > GRID_MAX_KNOTS), EDEVICE.
  */
 grid_status grid_fd_vjp(grid_model m, int32_t N, const float* dqdd_dq, const float* dqdd_dqd,
                         const float* Minv, const float* gbar, float* qbar, float* qdbar,
@@ -178,6 +182,31 @@ grid_status grid_workspace_destroy(grid_workspace ws);
 grid_status grid_fd_grad_host(grid_model m, grid_workspace ws, int32_t N, const float* q,
                               const float* qd, const float* tau, float* qdd, float* Minv,
                               float* dqdd_dq, float* dqdd_dqd, grid_timing* timing);
+
+/*
+ * The workspace's pinned host buffers, for callers that write the inputs and read the outputs
+ * in place (no pageable staging; the I/O of Sec. V-B without host-side copies). For a call on
+ * N knots the arrays are packed one after the other in the layouts above:
+ *   in  = q [N][n] | qd [N][n] | tau [N][n]
+ *   out = qdd [N][n] | Minv [N][n][n] | dqdd_dq [N][n][n] | dqdd_dqd [N][n][n]
+ * Both are sized for max_knots and belong to the workspace (valid until it is destroyed).
+ * Errors: EINVAL (a NULL argument).
+ */
+grid_status grid_workspace_host_buffers(grid_workspace ws, float** in, float** out);
+
+/*
+ * The host call on the workspace's pinned buffers: copies the inputs of N knots from `in` to
+ * the device, runs grid_fd_grad's fused kernel, copies the outputs into `out` and waits.
+ * pieces = 1: one copy each way around one launch, timed per phase (timing as in
+ * grid_fd_grad_host). pieces > 1: the batch is split into that many contiguous ranges of knots
+ * whose copies and launches go to two streams in turn, so that one range's copies overlap
+ * another's kernel; only timing->total_ms (first copy start to last copy end) is set. Each
+ * launch runs the build grid_fd_grad picks for its own knot count, and its results equal
+ * grid_fd_grad's on those knots bit for bit. Errors: EINVAL (N > max_knots of the workspace, a
+ * workspace of another model, pieces outside 1..64), EDEVICE.
+ */
+grid_status grid_fd_grad_pinned(grid_model m, grid_workspace ws, int32_t N, int32_t pieces,
+                                grid_timing* timing);
 
 /*
  * The plain staged pipeline, for comparison with the fused launch: the same steps in
@@ -222,12 +251,13 @@ typedef struct grid_item {
 
 typedef struct grid_graph_s* grid_graph;
 
-/* Launch every item's fused kernel on `stream`, one after the other. */
+/* Launch every item's fused kernel on `stream`, one after the other. Errors: as
+ * grid_graph_create's item checks. */
 grid_status grid_fd_grad_batch(const grid_item* items, int32_t count, void* stream);
 
 /* Capture the items into one hipGraph (their kernels as a chain of kernel nodes, in item
  * order), instantiate it, and return it. All models must be on one device. Errors: EINVAL
- * (NULL, count < 1 or > 64, N < 0), EDEVICE. */
+ * (NULL, count < 1 or > 64, N < 0 or > GRID_MAX_KNOTS), EDEVICE. */
 grid_status grid_graph_create(const grid_item* items, int32_t count, grid_graph* out);
 
 /* Replay the graph on `stream` (one launch call for the whole mixed batch). */
@@ -261,19 +291,56 @@ typedef struct grid_mixed_item {
 } grid_mixed_item;
 
 /* Validate `count` (1..16) robot descriptions, generate and compile (or take from the kernel
- * cache) their common module, and load it on `device`. The descriptions are read during the
+ * cache) their common module, and load it on `device`, together with each robot's own modules
+ * (as grid_model_create; the per-robot mode below). The descriptions are read during the
  * call only. Errors: EINVAL (a description invalid, as grid_model_create), ECOMPILE, EDEVICE,
  * EUNSUPPORTED (not a gfx950 device). */
 grid_status grid_mixed_create(const grid_model_desc* descs, int32_t count, int32_t device,
                               grid_mixed* out);
 
-/* Launch the items (1..16, any robot of the module, in any order, a robot more than once) as
- * one kernel on `stream`. Items must not share output buffers. At most 64 (item, branch)
+/* Launch the items (1..16, any robot of the module, in any order, a robot more than once) on
+ * `stream`, in the mode grid_mixed_tune chose for a batch of this size (one kernel when
+ * untuned; see the modes below). Items must not share output buffers. At most 64 (item, branch)
  * segments per launch (an item has as many branches as its robot has bodies on the fixed
- * base). Errors: EINVAL (NULL, a robot index out of range, N < 0, a NULL data pointer of an
- * item with N > 0, too many segments), EDEVICE. Nothing is launched when every N is 0. */
+ * base). Errors: EINVAL (NULL, a robot index out of range, N < 0 or > GRID_MAX_KNOTS, a NULL
+ * data pointer of an item with N > 0, too many segments), EDEVICE. Nothing is launched when
+ * every N is 0. */
 grid_status grid_mixed_launch(grid_mixed mx, const grid_mixed_item* items, int32_t count,
                               void* stream);
+
+/*
+ * The three ways a mixed batch can run (the heterogeneous-batch choice the module's tuner
+ * makes with each measured):
+ *   GRID_MIXED_ONE_LAUNCH   one kernel, one workgroup per block of knots of a segment;
+ *   GRID_MIXED_PERSISTENT   one kernel whose workgroups (as many as the device holds at once)
+ *                           stride over the blocks, the segments of the largest branches
+ *                           first; each block's arithmetic is the one-launch form's;
+ *   GRID_MIXED_PER_ROBOT    one launch per item on its robot's own module, with the build
+ *                           grid_fd_grad picks for the item's N (robots whose kernels need
+ *                           fewer registers keep their own occupancy).
+ * The first two give bitwise the same outputs (the three-role build of grid_fd_grad run on
+ * each item alone); the third gives the outputs of the build the robot's tuning picks.
+ */
+#define GRID_MIXED_ONE_LAUNCH 0
+#define GRID_MIXED_PERSISTENT 1
+#define GRID_MIXED_PER_ROBOT 2
+
+/* grid_mixed_launch in a given mode. Errors: as grid_mixed_launch, EINVAL for an unknown
+ * mode. */
+grid_status grid_mixed_launch_mode(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                                   int32_t mode, void* stream);
+
+/*
+ * Time the three modes on these items (3 warm-up and 20 timed launches per trial, median of
+ * 5 trials, HIP events on a stream of the library's; the items' outputs are written) and keep
+ * the fastest for launches of this size: from then on grid_mixed_launch runs a batch of B
+ * blocks in the mode tuned for the smallest tuned size >= B (the largest beyond; one launch
+ * when nothing is tuned). *chosen (may be NULL) receives the mode; us (may be NULL) receives
+ * the three median times per launch in microseconds, indexed by mode. Errors: as
+ * grid_mixed_launch, EINVAL when the items hold no knots, EDEVICE.
+ */
+grid_status grid_mixed_tune(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                            int32_t* chosen, float* us);
 
 grid_status grid_mixed_destroy(grid_mixed mx);
 
@@ -291,7 +358,7 @@ grid_status grid_mixed_precompile(const grid_model_desc* descs, int32_t count);
  *   B[k] = d(q', qd')/dtau     = [[dt^2 M^-1], [dt M^-1]]
  * with Dq = dqdd/dq, Dqd = dqdd/dqd; A is [N][2n][2n] and B [N][2n][n], row-major, device
  * pointers, asynchronous on `stream`. Errors: EINVAL (N < 0, dt not positive and finite,
- * NULL pointers, 6 N n^2 >= 2^31), EDEVICE.
+ * NULL pointers, N > GRID_MAX_KNOTS, 6 N n^2 > 2^31 - 256), EDEVICE.
  */
 grid_status grid_dt_jacobians(grid_model m, int32_t N, float dt, const float* dqdd_dq,
                               const float* dqdd_dqd, const float* Minv, float* A, float* B,
@@ -303,7 +370,7 @@ grid_status grid_dt_jacobians(grid_model m, int32_t N, float dt, const float* dq
  * kernel launch each, per knot and per base branch; device pointers, `stream` a
  * hipStream_t, asynchronous. Arrays: q, qd, qdd, tau [N][n]; Minv, dtau_dq, dtau_dqd
  * [N][n][n] row-major (dtau_dq[k][i][j] = d tau_i / d q_j). Errors: EINVAL (N < 0, a
- * required pointer NULL with N > 0, N > 2^31/64), EDEVICE (launch failure).
+ * required pointer NULL with N > 0, N > GRID_MAX_KNOTS), EDEVICE (launch failure).
  */
 
 /* Inverse dynamics tau = ID(q, qd, qdd) by RNEA with gravity (Sec. IV-B, Eq. 1). */
@@ -352,7 +419,8 @@ grid_status grid_fd_vjp_adjoint(grid_model m, int32_t N, const float* q, const f
  * knots, the choice made for the smallest tuned count >= N (the largest otherwise).
  * chosen[i] (may be NULL) receives the build index (0..5) picked for Ns[i]. The
  * result is also appended to `table_path` (may be NULL) as one JSON line keyed by the
- * generated source's hash; grid_model_create reads the file named by GRID_TUNE_TABLE,
+ * hash of the model's code objects (grid_model_code_hash), so a table is applied only to
+ * the machine code it was tuned on; grid_model_create reads the file named by GRID_TUNE_TABLE,
  * if set, and applies the last matching line. Errors: EINVAL, ENOMEM, EDEVICE.
  */
 grid_status grid_tune(grid_model m, const int32_t* Ns, int32_t count, const char* table_path,
@@ -376,9 +444,13 @@ grid_status grid_build_for(grid_model m, int32_t N, int32_t* build);
  * one model into the next free batch context (up to max_batch_knots knots per launch), and
  * issues H2D copy, one fused launch and D2H copy on that context's stream. Several batch
  * contexts per model are in flight at once, so requests that arrive while others run are
- * packed into the next launch and their work overlaps on the device. Model constants live
- * in the models' code objects on the device. Each knot's arithmetic does not depend on the
- * other knots of its launch, so a request's results are the same alone and in a mix.
+ * packed into the next launch (the batching policy of the config decides how long a batch
+ * waits for company) and their work overlaps on the device. Each context has a thread that
+ * waits for its batch on the device and copies the outputs to the callers' buffers; no
+ * thread of the server spins while it waits (condition variables, and an event wait that
+ * polls only for the first tens of microseconds). Model constants live in the models' code
+ * objects on the device. Each knot's arithmetic does not depend on the other knots of its
+ * launch, so a request's results are the same alone and in a mix.
  */
 typedef struct grid_server_s* grid_server;
 
@@ -389,6 +461,13 @@ typedef struct grid_server_config {
     int32_t max_batch_knots;     /* knots per launch, >= the largest request */
     int32_t contexts_per_model;  /* batch contexts (streams) per model, >= 1 */
     uint32_t flags;              /* 0 or GRID_SERVER_PER_REQUEST */
+    /* Batching policy. While a model has no batch in flight, its admitted requests launch as
+     * soon as a context is free. While one is in flight, the next batch of that model waits
+     * until it holds min_batch_knots knots or its oldest request has waited batch_window_us
+     * microseconds, so that requests arriving meanwhile share a launch. 0 and 0: never wait.
+     * Ignored with GRID_SERVER_PER_REQUEST. */
+    int32_t batch_window_us;     /* 0 .. 1000000 */
+    int32_t min_batch_knots;     /* 0 .. max_batch_knots */
 } grid_server_config;
 
 typedef struct grid_server_stats {
@@ -438,11 +517,22 @@ typedef struct grid_loadgen_config {
     uint64_t seed;
 } grid_loadgen_config;
 
+/* Where a request's latency goes (microseconds): queue = scheduled arrival to the launch of
+ * its batch (admission, waiting for a context or the batch window); h2d, kernel, d2h = the
+ * batch's device phases (HIP events); complete = launch to the server seeing the batch done
+ * (device queueing, the three phases and the wake-up); copyout = copying its outputs from the
+ * pinned staging into the caller's buffers. */
+typedef struct grid_latency_split {
+    double queue_us, h2d_us, kernel_us, d2h_us, complete_us, copyout_us;
+} grid_latency_split;
+
 typedef struct grid_loadgen_result {
     uint64_t requests, knots;    /* completed in the measured window */
     double seconds;              /* measured window */
     double p50_us, p90_us, p99_us, max_us, mean_us;
     double offered_rate_per_s;
+    double requests_per_launch;  /* over the whole run */
+    grid_latency_split p50, p99; /* per phase, over the measured requests */
 } grid_loadgen_result;
 
 grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,

@@ -37,8 +37,9 @@ grid_status check_items(const grid_item* items, int32_t count)
         return fail(GRID_EINVAL, "items must hold 1..64 entries");
     for (int k = 0; k < count; ++k) {
         const grid_item& it = items[k];
-        if (!it.model || it.N < 0)
-            return fail(GRID_EINVAL, "item " + std::to_string(k) + ": NULL model or N < 0");
+        if (!it.model || it.N < 0 || it.N > GRID_MAX_KNOTS)
+            return fail(GRID_EINVAL, "item " + std::to_string(k) +
+                                         ": NULL model or N outside 0..GRID_MAX_KNOTS");
         if (it.model->device != items[0].model->device)
             return fail(GRID_EINVAL, "all items must be on one device");
         if (it.N > 0 && (!it.q || !it.qd || !it.tau || !it.qdd || !it.Minv || !it.dqdd_dq ||
@@ -213,7 +214,7 @@ grid_status grid_graph_destroy(grid_graph g)
 // the block is passed by value as the kernel's only argument: its host layout must be the
 // device one (ints, then 8-byte aligned argument blocks of the same field order)
 static_assert(sizeof(KernelArgs) == 72, "Args: an int and eight pointers");
-static_assert(offsetof(MixedArgs, item) == 4 + 3 * 4 * kMixedSegs + 4 &&
+static_assert(offsetof(MixedArgs, item) == 8 + 3 * 4 * kMixedSegs &&
                   sizeof(MixedArgs) == offsetof(MixedArgs, item) + kMixedItems * sizeof(KernelArgs),
               "MixedArgs layout");
 
@@ -223,7 +224,13 @@ struct grid_mixed_s {
     std::vector<int> inst_base;       // per robot: index of its first branch in the module
     int waves = 1;                    // wavefronts per workgroup (the largest robot's)
     hipModule_t module = nullptr;
-    hipFunction_t fn = nullptr;
+    hipFunction_t fn = nullptr;             // one workgroup per block
+    hipFunction_t fn_persistent = nullptr;  // resident workgroups striding over the blocks
+    int resident = 0;                       // workgroups of fn_persistent resident at once
+    std::vector<grid_model> models;         // per robot: its own modules (per-robot launches)
+    // (blocks of the largest tuned plan, mode): a launch of B blocks uses the mode tuned for
+    // the smallest entry >= B (the last one beyond); untuned: one workgroup per block
+    std::vector<std::pair<int64_t, int>> tuned;
 };
 
 namespace {
@@ -325,34 +332,64 @@ grid_status grid_mixed_create(const grid_model_desc* descs, int32_t count, int32
     hipError_t e = hipModuleLoadData(&mx->module, code.data());
     if (e == hipSuccess)
         e = hipModuleGetFunction(&mx->fn, mx->module, "grid_fdgrad_pipe_mixed");
+    if (e == hipSuccess)
+        e = hipModuleGetFunction(&mx->fn_persistent, mx->module,
+                                 "grid_fdgrad_pipe_mixed_persistent");
+    int per_cu = 0, cus = 0;
+    if (e == hipSuccess)
+        e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mx->fn_persistent,
+                                                               64 * mx->waves, 0);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) {
         grid_mixed_destroy(mx);
         return fail(GRID_EDEVICE, std::string("mixed module load: ") + hipGetErrorString(e));
+    }
+    mx->resident = std::max(1, per_cu) * std::max(1, cus);
+    for (int r = 0; r < count; ++r) {
+        grid_model m = nullptr;
+        st = grid_model_create(&descs[r], device, 0, &m);
+        if (st != GRID_OK) {
+            grid_mixed_destroy(mx);
+            return st;
+        }
+        mx->models.push_back(m);
     }
     *out = mx;
     return GRID_OK;
 }
 
-grid_status grid_mixed_launch(grid_mixed mx, const grid_mixed_item* items, int32_t count,
-                              void* stream)
+}  // extern "C"
+
+namespace {
+
+// Checks the items and builds the segment table of a launch: one segment per (item, branch)
+// with knots, each with its first block. In item order for one workgroup per block; for the
+// persistent form ordered by the branch's bodies, largest first, so that the longest blocks
+// start in the first wave of resident workgroups. *blocks: the blocks of the launch.
+grid_status mixed_args(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                       bool by_cost, MixedArgs* a, int64_t* blocks)
 {
     if (!mx)
         return fail(GRID_EINVAL, "mixed module is NULL");
     if (!items || count < 1 || count > kMixedItems)
         return fail(GRID_EINVAL, "items must hold 1.." + std::to_string(kMixedItems) + " entries");
-    MixedArgs a;
-    std::memset(&a, 0, sizeof a);
-    int64_t blocks = 0;
+    std::memset(a, 0, sizeof *a);
+    struct Seg {
+        int inst, item, B;
+        int64_t nb;
+    };
+    std::vector<Seg> segs;
     for (int j = 0; j < count; ++j) {
         const grid_mixed_item& it = items[j];
         if (it.robot < 0 || it.robot >= (int)mx->topo.size())
             return fail(GRID_EINVAL, "item " + std::to_string(j) + ": robot index out of range");
-        if (it.N < 0 || it.N > (1 << 30) / 64)
+        if (it.N < 0 || it.N > GRID_MAX_KNOTS)
             return fail(GRID_EINVAL, "item " + std::to_string(j) + ": N out of range");
         if (it.N > 0 && (!it.q || !it.qd || !it.tau || !it.qdd || !it.Minv || !it.dqdd_dq ||
                          !it.dqdd_dqd))
             return fail(GRID_EINVAL, "item " + std::to_string(j) + ": a data pointer is NULL");
-        KernelArgs& k = a.item[j];
+        KernelArgs& k = a->item[j];
         k.nknots = it.N;
         k.work = nullptr;
         k.q = it.q;
@@ -366,25 +403,175 @@ grid_status grid_mixed_launch(grid_mixed mx, const grid_mixed_item* items, int32
             continue;
         const Topology& t = mx->topo[it.robot];
         for (size_t b = 0; b < t.insts.size(); ++b) {
-            if (a.nseg == kMixedSegs)
+            if ((int)segs.size() == kMixedSegs)
                 return fail(GRID_EINVAL, "more than " + std::to_string(kMixedSegs) +
                                              " (item, branch) segments in one launch");
-            const int P = pipe_problems(t.shapes[t.insts[b].shape].B);
-            a.seg_start[a.nseg] = (int)blocks;
-            a.seg_inst[a.nseg] = mx->inst_base[it.robot] + (int)b;
-            a.seg_item[a.nseg] = j;
-            ++a.nseg;
-            blocks += (it.N + P - 1) / P;
+            const int B = t.shapes[t.insts[b].shape].B;
+            const int P = pipe_problems(B);
+            segs.push_back(Seg{mx->inst_base[it.robot] + (int)b, j, B, (it.N + P - 1) / P});
         }
     }
+    if (by_cost)
+        std::stable_sort(segs.begin(), segs.end(),
+                         [](const Seg& x, const Seg& y) { return x.B > y.B; });
+    int64_t total = 0;
+    for (const Seg& g : segs) {
+        a->seg_start[a->nseg] = (int)total;
+        a->seg_inst[a->nseg] = g.inst;
+        a->seg_item[a->nseg] = g.item;
+        ++a->nseg;
+        total += g.nb;
+    }
+    if (total > INT32_MAX)
+        return fail(GRID_EINVAL, "too many knots in one launch");
+    a->nblocks = (int)total;
+    *blocks = total;
+    return GRID_OK;
+}
+
+grid_status mixed_launch_mode(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                              int mode, hipStream_t stream)
+{
+    if (mode < GRID_MIXED_ONE_LAUNCH || mode > GRID_MIXED_PER_ROBOT)
+        return fail(GRID_EINVAL, "unknown mixed launch mode " + std::to_string(mode));
+    MixedArgs a;
+    int64_t blocks = 0;
+    grid_status st = mixed_args(mx, items, count, mode == GRID_MIXED_PERSISTENT, &a, &blocks);
+    if (st != GRID_OK)
+        return st;
     if (blocks == 0)
         return GRID_OK;
-    if (blocks > INT32_MAX)
-        return fail(GRID_EINVAL, "too many knots in one launch");
     HIP_TRY(hipSetDevice(mx->device));
+    if (mode == GRID_MIXED_PER_ROBOT) {
+        for (int j = 0; j < count; ++j) {
+            const grid_mixed_item& it = items[j];
+            if (it.N == 0)
+                continue;
+            st = launch_fused(mx->models[it.robot], it.N, it.q, it.qd, it.tau, it.qdd, it.Minv,
+                              it.dqdd_dq, it.dqdd_dqd, stream);
+            if (st != GRID_OK)
+                return st;
+        }
+        return GRID_OK;
+    }
+    const bool pers = mode == GRID_MIXED_PERSISTENT;
+    const unsigned grid = (unsigned)(pers ? std::min<int64_t>(blocks, mx->resident) : blocks);
     void* params[] = {&a};   // the kernel takes one argument: the MixedArgs block
-    HIP_TRY(hipModuleLaunchKernel(mx->fn, (unsigned)blocks, 1, 1, 64u * (unsigned)mx->waves, 1, 1,
-                                  0, (hipStream_t)stream, params, nullptr));
+    HIP_TRY(hipModuleLaunchKernel(pers ? mx->fn_persistent : mx->fn, grid, 1, 1,
+                                  64u * (unsigned)mx->waves, 1, 1, 0, stream, params, nullptr));
+    return GRID_OK;
+}
+
+// the mode tuned for a launch of `blocks` blocks
+int mixed_mode_for(grid_mixed mx, int64_t blocks)
+{
+    for (const auto& e : mx->tuned)
+        if (blocks <= e.first)
+            return e.second;
+    return mx->tuned.empty() ? GRID_MIXED_ONE_LAUNCH : mx->tuned.back().second;
+}
+
+}  // namespace
+
+extern "C" {
+
+grid_status grid_mixed_launch(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                              void* stream)
+{
+    MixedArgs a;
+    int64_t blocks = 0;
+    grid_status st = mixed_args(mx, items, count, false, &a, &blocks);
+    if (st != GRID_OK)
+        return st;
+    if (blocks == 0)
+        return GRID_OK;
+    return mixed_launch_mode(mx, items, count, mixed_mode_for(mx, blocks), (hipStream_t)stream);
+}
+
+grid_status grid_mixed_launch_mode(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                                   int32_t mode, void* stream)
+{
+    return mixed_launch_mode(mx, items, count, mode, (hipStream_t)stream);
+}
+
+grid_status grid_mixed_tune(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                            int32_t* chosen, float* us)
+{
+    MixedArgs a;
+    int64_t blocks = 0;
+    grid_status st = mixed_args(mx, items, count, false, &a, &blocks);
+    if (st != GRID_OK)
+        return st;
+    if (blocks == 0)
+        return fail(GRID_EINVAL, "the items hold no knots");
+    HIP_TRY(hipSetDevice(mx->device));
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    auto cleanup = [&]() {
+        if (s)
+            (void)hipStreamSynchronize(s);
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+        if (s)
+            (void)hipStreamDestroy(s);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(GRID_EDEVICE, std::string("mixed tuning: ") + hipGetErrorString(e));
+    }
+    int best = GRID_MIXED_ONE_LAUNCH;
+    float best_us = 1e30f;
+    for (int mode = GRID_MIXED_ONE_LAUNCH; mode <= GRID_MIXED_PER_ROBOT; ++mode) {
+        const int reps = 20;
+        float times[5];
+        for (int trial = 0; trial < 5; ++trial) {
+            for (int w = 0; w < 3 && st == GRID_OK; ++w)
+                st = mixed_launch_mode(mx, items, count, mode, s);
+            e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && st == GRID_OK; ++r)
+                st = mixed_launch_mode(mx, items, count, mode, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            if (st != GRID_OK || e != hipSuccess) {
+                cleanup();
+                return st != GRID_OK ? st
+                                     : fail(GRID_EDEVICE, std::string("mixed tuning: ") +
+                                                              hipGetErrorString(e));
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            times[trial] = 1e3f * ms / reps;
+        }
+        std::sort(times, times + 5);
+        if (us)
+            us[mode] = times[2];
+        if (times[2] < best_us) {
+            best_us = times[2];
+            best = mode;
+        }
+    }
+    cleanup();
+    bool replaced = false;
+    for (auto& t : mx->tuned)
+        if (t.first == blocks) {
+            t.second = best;
+            replaced = true;
+        }
+    if (!replaced) {
+        mx->tuned.emplace_back(blocks, best);
+        std::sort(mx->tuned.begin(), mx->tuned.end());
+    }
+    if (chosen)
+        *chosen = best;
     return GRID_OK;
 }
 
@@ -393,6 +580,8 @@ grid_status grid_mixed_destroy(grid_mixed mx)
     if (!mx)
         return GRID_OK;
     (void)hipSetDevice(mx->device);
+    for (grid_model m : mx->models)
+        grid_model_destroy(m);
     if (mx->module)
         (void)hipModuleUnload(mx->module);
     delete mx;
@@ -493,7 +682,7 @@ grid_status grid_tune(grid_model m, const int32_t* Ns, int32_t count, const char
         std::ofstream f(table_path, std::ios::app);
         if (!f)
             return fail(GRID_EINVAL, std::string("cannot write ") + table_path);
-        f << "{\"arch\": \"gfx950\", \"model\": \"" << std::hex << m->source_hash << std::dec
+        f << "{\"arch\": \"gfx950\", \"model\": \"" << std::hex << m->code_hash << std::dec
           << "\", \"buckets\": [";
         for (size_t i = 0; i < table.size(); ++i)
             f << (i ? ", " : "") << "[" << table[i].first << ", " << table[i].second << "]";
@@ -533,7 +722,8 @@ grid_status grid_build_for(grid_model m, int32_t N, int32_t* build)
 
 namespace grid_impl {
 
-// Apply the last line of $GRID_TUNE_TABLE whose model hash matches this model.
+// Apply the last line of $GRID_TUNE_TABLE whose model hash matches this model's code objects
+// (a table tuned on other machine code is not applied).
 void load_tuning(grid_model m)
 {
     const char* path = std::getenv("GRID_TUNE_TABLE");
@@ -543,7 +733,7 @@ void load_tuning(grid_model m)
     if (!f)
         return;
     char key[32];
-    std::snprintf(key, sizeof key, "\"model\": \"%llx\"", (unsigned long long)m->source_hash);
+    std::snprintf(key, sizeof key, "\"model\": \"%llx\"", (unsigned long long)m->code_hash);
     std::string line, last;
     while (std::getline(f, line))
         if (line.find(key) != std::string::npos)

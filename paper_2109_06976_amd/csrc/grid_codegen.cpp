@@ -390,8 +390,6 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << "\n// generated: workgroup -> (branch, 64 knots), one lane per knot\n";
     emit_dispatch(os, t, "__device__ void grid_dispatch_s(const grid::Args& a, int block)", "64",
              "grids::run_serial<@>(a, b)");
-    emit_dispatch(os, t, "__device__ void grid_dispatch_p(const grid::Args& a, int block)", "@::S::PP",
-             "gridq::run_pipe<@>(a, b)");
     os << "#line 1 \"grid_ops.hip\"\n";
     os << grid_ops_src;
     os << "\n// generated: workgroup -> (branch, problem group), standalone algorithms\n";
@@ -442,12 +440,12 @@ std::string generate_mixed_source(const std::vector<RobotSource>& robots,
     for (const RobotSource& r : robots)
         ninst += (int)r.topo->insts.size();
     os << "\n// generated: workgroup -> (segment: item, branch), fused pipe kernel\n";
-    os << "struct MixedArgs {\n    int nseg;\n    int seg_start[" << kMixedSegs
+    os << "struct MixedArgs {\n    int nseg;\n    int nblocks;\n    int seg_start[" << kMixedSegs
        << "];\n    int seg_inst[" << kMixedSegs << "];\n    int seg_item[" << kMixedSegs
        << "];\n    grid::Args item[" << kMixedItems << "];\n};\n";
-    os << "extern \"C\" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) "
-          "grid_fdgrad_pipe_mixed(MixedArgs args)\n{\n"
-          "    const int b = (int)blockIdx.x;\n"
+    // block b of the launch: its segment (uniform scan of the table), then that segment's
+    // branch on its item's buffers
+    os << "__device__ __forceinline__ void grid_mixed_block(const MixedArgs& args, int b)\n{\n"
           "    int s = 0;\n"
           "    while (s + 1 < args.nseg && b >= args.seg_start[s + 1])\n"
           "        ++s;\n"
@@ -461,6 +459,22 @@ std::string generate_mixed_source(const std::vector<RobotSource>& robots,
             os << "    case " << k << ": gridq::run_pipe<Inst<" << k << ">>(x, lb); break;\n";
     }
     os << "    }\n}\n";
+    // one workgroup per block
+    os << "extern \"C\" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) "
+          "grid_fdgrad_pipe_mixed(MixedArgs args)\n{\n"
+          "    grid_mixed_block(args, (int)blockIdx.x);\n}\n";
+    // persistent: a grid of resident workgroups strides over the blocks. b is uniform, so every
+    // wavefront of a workgroup runs the same blocks and takes each block's three barriers (lane
+    // table, bias forces, products). Consecutive blocks on one workgroup do not overlap in
+    // LDS: a block reads its lane table before its second barrier, and the next block writes
+    // its table after every wavefront has passed the third; the arrays read after the third
+    // barrier (M^-1 or the factor, the qdd parts) are written by the next block only after
+    // its first barrier, which a wavefront reaches only once it has finished the block before.
+    // (Blocks of different branches use different LDS arrays altogether.)
+    os << "extern \"C\" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) "
+          "grid_fdgrad_pipe_mixed_persistent(MixedArgs args)\n{\n"
+          "    for (int b = (int)blockIdx.x; b < args.nblocks; b += (int)gridDim.x)\n"
+          "        grid_mixed_block(args, b);\n}\n";
     return os.str();
 }
 

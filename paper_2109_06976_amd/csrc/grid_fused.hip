@@ -1036,12 +1036,7 @@ extern "C" __global__ void __launch_bounds__(64 * GRID_WAVES) grid_fdgrad_quad(g
     grid_dispatch_q(args, (int)blockIdx.x);
 }
 
-__device__ void grid_dispatch_p(const grid::Args& args, int block);
-
-// Fused kernel, quad layout in three roles: GRID_PIPE_WAVES wavefronts per workgroup.
-extern "C" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) grid_fdgrad_pipe(grid::Args args)
-{
-    grid_dispatch_p(args, (int)blockIdx.x);
-}
+// The three-role kernel (grid_fdgrad_pipe) has an entry point only in the module generated
+// for it alone, which is compiled with its own schedule.
 
 #endif  // GRID_PIPE_ONLY

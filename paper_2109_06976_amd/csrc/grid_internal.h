@@ -105,7 +105,8 @@ constexpr int kMixedSegs = 64;
 // Kernel argument block of the mixed kernel; must match MixedArgs of the generated source.
 struct MixedArgs {
     int nseg;
-    int seg_start[kMixedSegs];       // first workgroup of the segment, ascending
+    int nblocks;                     // blocks of the launch (the persistent form's bound)
+    int seg_start[kMixedSegs];       // first block of the segment, ascending
     int seg_inst[kMixedSegs];        // the branch the segment runs
     int seg_item[kMixedSegs];        // the item whose buffers it reads and writes
     KernelArgs item[kMixedItems];
@@ -158,8 +159,8 @@ struct grid_model_s {
     int device = 0;
     uint32_t flags = 0;
     grid_impl::Topology topo;
-    uint64_t source_hash = 0;           // of the generated source: keys tuning tables
-    uint64_t code_hash = 0;             // of the two loaded code objects, in that order
+    uint64_t code_hash = 0;             // of the two loaded code objects, in that order:
+                                        // keys tuning tables
     int compute_units = 256;
     hipFunction_t fused_variant[grid_impl::kNumVariants] = {};   // see kVariantQuad
     hipFunction_t op[grid_impl::kNumOps] = {};                    // see kOpId
@@ -173,6 +174,7 @@ struct grid_workspace_s {
     grid_model model = nullptr;
     int32_t max_knots = 0;
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;      // second stream of the pieces of a pinned call
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float* d_in = nullptr;              // q | qd | tau
     float* d_out = nullptr;             // qdd | Minv | dqdd_dq | dqdd_dqd

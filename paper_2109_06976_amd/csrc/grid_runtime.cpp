@@ -546,11 +546,11 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     static const char* const kVariants[kNumVariants] = {
         "grid_fdgrad_quad", "grid_fdgrad_fused", "grid_fdgrad_fused_w2", "grid_fdgrad_fused_w4",
         "grid_fdgrad_pipe", "grid_fdgrad_serial"};
-    m->source_hash = source_hash(src);
     m->compute_units = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     hipError_t e = hipModuleLoadData(&m->module, code.data());
     for (int k = 0; k < kNumVariants && e == hipSuccess; ++k)
-        e = hipModuleGetFunction(&m->fused_variant[k], m->module, kVariants[k]);
+        if (k != kVariantPipe)   // build 4 lives in the pipe module alone
+            e = hipModuleGetFunction(&m->fused_variant[k], m->module, kVariants[k]);
     static const char* const kOps[kNumOps] = {"grid_op_id", "grid_op_fd", "grid_op_minv",
                                               "grid_op_idgrad", "grid_op_vjp"};
     for (int k = 0; k < kNumOps && e == hipSuccess; ++k)
@@ -617,7 +617,7 @@ grid_status grid_fd_grad(grid_model m, int32_t N, const float* q, const float* q
         return fail(GRID_EINVAL, "N must be >= 0");
     if (N == 0)
         return GRID_OK;
-    if (N > (1 << 30) / 64)
+    if (N > GRID_MAX_KNOTS)
         return fail(GRID_EINVAL, "N too large");
     if (!q || !qd || !tau || !qdd || !Minv || !dqdd_dq || !dqdd_dqd)
         return fail(GRID_EINVAL, "a data pointer is NULL");
@@ -635,7 +635,7 @@ static grid_status launch_op(grid_model m, int op, int32_t N, const float* q, co
         return fail(GRID_EINVAL, "N must be >= 0");
     if (N == 0)
         return GRID_OK;
-    if (N > (1 << 30) / 64)
+    if (N > GRID_MAX_KNOTS)
         return fail(GRID_EINVAL, "N too large");
     const bool needs_qd = op != kOpMinv, needs_u = op != kOpMinv;
     const bool needs_out1 = op == kOpIdGrad || op == kOpVjp, vjp = op == kOpVjp;
@@ -690,6 +690,21 @@ grid_status grid_fd_vjp_adjoint(grid_model m, int32_t N, const float* q, const f
     return launch_op(m, kOpVjp, N, q, qd, qdd, qbar, qdbar, stream, gbar, taubar);
 }
 
+// the five stage kernels of the plain pipeline, intermediates in `work` (N x the model's
+// workspace stride floats; every stage writes what a later one reads, so it needs no clearing)
+static grid_status launch_staged(grid_model m, float* work, int32_t N, const float* q,
+                                 const float* qd, const float* tau, float* qdd, float* Minv,
+                                 float* dqdd_dq, float* dqdd_dqd, hipStream_t stream)
+{
+    for (int k = 0; k < 5; ++k) {
+        grid_status s = launch(m->stage[k], (unsigned)workgroups_for(m->topo, N), 64u, N, work,
+                               q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, stream);
+        if (s != GRID_OK)
+            return s;
+    }
+    return GRID_OK;
+}
+
 grid_status grid_fd_grad_staged(grid_model m, grid_workspace w, int32_t N, const float* q,
                                 const float* qd, const float* tau, float* qdd, float* Minv,
                                 float* dqdd_dq, float* dqdd_dqd, void* stream)
@@ -705,14 +720,8 @@ grid_status grid_fd_grad_staged(grid_model m, grid_workspace w, int32_t N, const
     if (!q || !qd || !tau || !qdd || !Minv || !dqdd_dq || !dqdd_dqd)
         return fail(GRID_EINVAL, "a data pointer is NULL");
     HIP_TRY(hipSetDevice(m->device));
-    for (int k = 0; k < 5; ++k) {
-        grid_status s = launch(m->stage[k], (unsigned)workgroups_for(m->topo, N), 64u, N,
-                               w->d_stage, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd,
-                               (hipStream_t)stream);
-        if (s != GRID_OK)
-            return s;
-    }
-    return GRID_OK;
+    return launch_staged(m, w->d_stage, N, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd,
+                         (hipStream_t)stream);
 }
 
 grid_status grid_fd_vjp(grid_model m, int32_t N, const float* dqdd_dq, const float* dqdd_dqd,
@@ -721,7 +730,7 @@ grid_status grid_fd_vjp(grid_model m, int32_t N, const float* dqdd_dq, const flo
 {
     if (!m)
         return fail(GRID_EINVAL, "model is NULL");
-    if (N < 0 || N > (1 << 30) / 64)
+    if (N < 0 || N > GRID_MAX_KNOTS)
         return fail(GRID_EINVAL, "N out of range");
     if (N == 0)
         return GRID_OK;
@@ -739,7 +748,7 @@ grid_status grid_dt_jacobians(grid_model m, int32_t N, float dt, const float* dq
 {
     if (!m)
         return fail(GRID_EINVAL, "model is NULL");
-    if (N < 0 || N > (1 << 30) / 64)
+    if (N < 0 || N > GRID_MAX_KNOTS)
         return fail(GRID_EINVAL, "N out of range");
     if (!(dt > 0.0f) || !std::isfinite(dt))
         return fail(GRID_EINVAL, "dt must be positive and finite");
@@ -759,7 +768,7 @@ grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspac
     if (!m || !out)
         return fail(GRID_EINVAL, "model and out must not be NULL");
     *out = nullptr;
-    if (max_knots < 1 || max_knots > (1 << 30) / 64)
+    if (max_knots < 1 || max_knots > GRID_MAX_KNOTS)
         return fail(GRID_EINVAL, "max_knots out of range");
     HIP_TRY(hipSetDevice(m->device));
     grid_workspace w = new (std::nothrow) grid_workspace_s;
@@ -771,6 +780,8 @@ grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspac
     const size_t in_f = (size_t)max_knots * 3 * n;
     const size_t out_f = (size_t)max_knots * (n + 3 * n * n);
     hipError_t e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&w->stream2, hipStreamNonBlocking);
     for (int k = 0; k < 4 && e == hipSuccess; ++k)
         e = hipEventCreate(&w->ev[k]);
     if (e == hipSuccess)
@@ -799,11 +810,15 @@ grid_status grid_workspace_destroy(grid_workspace w)
     (void)hipSetDevice(w->model->device);
     if (w->stream)
         (void)hipStreamSynchronize(w->stream);
+    if (w->stream2)
+        (void)hipStreamSynchronize(w->stream2);
     for (auto& ev : w->ev)
         if (ev)
             (void)hipEventDestroy(ev);
     if (w->stream)
         (void)hipStreamDestroy(w->stream);
+    if (w->stream2)
+        (void)hipStreamDestroy(w->stream2);
     (void)hipFree(w->d_in);
     (void)hipFree(w->d_out);
     (void)hipFree(w->d_stage);
@@ -813,6 +828,116 @@ grid_status grid_workspace_destroy(grid_workspace w)
         (void)hipHostFree(w->h_out);
     delete w;
     return GRID_OK;
+}
+
+// Knots [k0, k1) of a batch of N whose arrays sit packed in the workspace's pinned and device
+// buffers (q | qd | tau, qdd | Minv | dqdd_dq | dqdd_dqd, each for N knots): their rows' H2D
+// copies, one fused launch and the D2H copies of their outputs, on `s`.
+static grid_status issue_piece(grid_model m, grid_workspace w, int32_t N, int32_t k0, int32_t k1,
+                               hipStream_t s)
+{
+    const size_t n = (size_t)m->topo.n;
+    const size_t vec = (size_t)N * n, mat = vec * n;
+    const size_t ov = (size_t)k0 * n, om = ov * n;
+    const size_t rv = (size_t)(k1 - k0) * n, rm = rv * n;
+    for (int a = 0; a < 3; ++a)
+        HIP_TRY(hipMemcpyAsync(w->d_in + a * vec + ov, w->h_in + a * vec + ov, rv * sizeof(float),
+                               hipMemcpyHostToDevice, s));
+    float* d_q = w->d_in;
+    float* d_qdd = w->d_out;
+    grid_status st = launch_fused(m, k1 - k0, d_q + ov, d_q + vec + ov, d_q + 2 * vec + ov,
+                                  d_qdd + ov, d_qdd + vec + om, d_qdd + vec + mat + om,
+                                  d_qdd + vec + 2 * mat + om, s);
+    if (st != GRID_OK)
+        return st;
+    HIP_TRY(hipMemcpyAsync(w->h_out + ov, d_qdd + ov, rv * sizeof(float), hipMemcpyDeviceToHost,
+                           s));
+    for (int a = 0; a < 3; ++a)
+        HIP_TRY(hipMemcpyAsync(w->h_out + vec + a * mat + om, d_qdd + vec + a * mat + om,
+                               rm * sizeof(float), hipMemcpyDeviceToHost, s));
+    return GRID_OK;
+}
+
+// H2D of the pinned inputs, the fused kernel and D2H into the pinned outputs for N knots, then
+// a wait. One piece: one copy each way (the packed arrays are contiguous) on the workspace's
+// stream, the three phases timed by events. Several pieces: issued on the two streams in turn,
+// so that the copies of one overlap the kernel of another; only the total is timed.
+static grid_status run_pinned(grid_model m, grid_workspace w, int32_t N, int32_t pieces,
+                              grid_timing* timing)
+{
+    const size_t n = (size_t)m->topo.n;
+    const size_t vec = (size_t)N * n, mat = vec * n;
+    if (pieces <= 1) {
+        float* d_q = w->d_in;
+        float* d_qdd = w->d_out;
+        HIP_TRY(hipEventRecord(w->ev[0], w->stream));
+        HIP_TRY(hipMemcpyAsync(d_q, w->h_in, 3 * vec * sizeof(float), hipMemcpyHostToDevice,
+                               w->stream));
+        HIP_TRY(hipEventRecord(w->ev[1], w->stream));
+        grid_status s = launch_fused(m, N, d_q, d_q + vec, d_q + 2 * vec, d_qdd, d_qdd + vec,
+                                     d_qdd + vec + mat, d_qdd + vec + 2 * mat, w->stream);
+        if (s != GRID_OK)
+            return s;
+        HIP_TRY(hipEventRecord(w->ev[2], w->stream));
+        HIP_TRY(hipMemcpyAsync(w->h_out, d_qdd, (vec + 3 * mat) * sizeof(float),
+                               hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(hipEventRecord(w->ev[3], w->stream));
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        if (timing) {
+            HIP_TRY(hipEventElapsedTime(&timing->h2d_ms, w->ev[0], w->ev[1]));
+            HIP_TRY(hipEventElapsedTime(&timing->kernel_ms, w->ev[1], w->ev[2]));
+            HIP_TRY(hipEventElapsedTime(&timing->d2h_ms, w->ev[2], w->ev[3]));
+            HIP_TRY(hipEventElapsedTime(&timing->total_ms, w->ev[0], w->ev[3]));
+        }
+        return GRID_OK;
+    }
+    HIP_TRY(hipEventRecord(w->ev[0], w->stream));
+    HIP_TRY(hipStreamWaitEvent(w->stream2, w->ev[0], 0));
+    for (int32_t c = 0; c < pieces; ++c) {
+        const int32_t k0 = (int32_t)((int64_t)N * c / pieces);
+        const int32_t k1 = (int32_t)((int64_t)N * (c + 1) / pieces);
+        grid_status s = issue_piece(m, w, N, k0, k1, (c & 1) ? w->stream2 : w->stream);
+        if (s != GRID_OK) {
+            (void)hipStreamSynchronize(w->stream2);
+            (void)hipStreamSynchronize(w->stream);
+            return s;
+        }
+    }
+    HIP_TRY(hipEventRecord(w->ev[1], w->stream2));
+    HIP_TRY(hipStreamWaitEvent(w->stream, w->ev[1], 0));
+    HIP_TRY(hipEventRecord(w->ev[3], w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if (timing)
+        HIP_TRY(hipEventElapsedTime(&timing->total_ms, w->ev[0], w->ev[3]));
+    return GRID_OK;
+}
+
+grid_status grid_workspace_host_buffers(grid_workspace w, float** in, float** out)
+{
+    if (!w || !in || !out)
+        return fail(GRID_EINVAL, "workspace and both output pointers are required");
+    *in = w->h_in;
+    *out = w->h_out;
+    return GRID_OK;
+}
+
+grid_status grid_fd_grad_pinned(grid_model m, grid_workspace w, int32_t N, int32_t pieces,
+                                grid_timing* timing)
+{
+    if (!m || !w)
+        return fail(GRID_EINVAL, "model and workspace must not be NULL");
+    if (w->model != m)
+        return fail(GRID_EINVAL, "workspace was created for another model");
+    if (N < 0 || N > w->max_knots)
+        return fail(GRID_EINVAL, "N must be in 0..max_knots of the workspace");
+    if (pieces < 1 || pieces > 64)
+        return fail(GRID_EINVAL, "pieces must be in 1..64");
+    if (timing)
+        *timing = grid_timing{0, 0, 0, 0};
+    if (N == 0)
+        return GRID_OK;
+    HIP_TRY(hipSetDevice(m->device));
+    return run_pinned(m, w, N, std::min(pieces, N), timing);
 }
 
 grid_status grid_fd_grad_host(grid_model m, grid_workspace w, int32_t N, const float* q,
@@ -837,30 +962,13 @@ grid_status grid_fd_grad_host(grid_model m, grid_workspace w, int32_t N, const f
     std::memcpy(w->h_in, q, vec * sizeof(float));
     std::memcpy(w->h_in + vec, qd, vec * sizeof(float));
     std::memcpy(w->h_in + 2 * vec, tau, vec * sizeof(float));
-    float* d_q = w->d_in;
-    float* d_qdd = w->d_out;
-    HIP_TRY(hipEventRecord(w->ev[0], w->stream));
-    HIP_TRY(hipMemcpyAsync(d_q, w->h_in, 3 * vec * sizeof(float), hipMemcpyHostToDevice, w->stream));
-    HIP_TRY(hipEventRecord(w->ev[1], w->stream));
-    grid_status s = launch_fused(m, N, d_q, d_q + vec, d_q + 2 * vec, d_qdd, d_qdd + vec,
-                                 d_qdd + vec + mat, d_qdd + vec + 2 * mat, w->stream);
+    grid_status s = run_pinned(m, w, N, 1, timing);
     if (s != GRID_OK)
         return s;
-    HIP_TRY(hipEventRecord(w->ev[2], w->stream));
-    HIP_TRY(hipMemcpyAsync(w->h_out, d_qdd, (vec + 3 * mat) * sizeof(float),
-                           hipMemcpyDeviceToHost, w->stream));
-    HIP_TRY(hipEventRecord(w->ev[3], w->stream));
-    HIP_TRY(hipStreamSynchronize(w->stream));
     std::memcpy(qdd, w->h_out, vec * sizeof(float));
     std::memcpy(Minv, w->h_out + vec, mat * sizeof(float));
     std::memcpy(dqdd_dq, w->h_out + vec + mat, mat * sizeof(float));
     std::memcpy(dqdd_dqd, w->h_out + vec + 2 * mat, mat * sizeof(float));
-    if (timing) {
-        HIP_TRY(hipEventElapsedTime(&timing->h2d_ms, w->ev[0], w->ev[1]));
-        HIP_TRY(hipEventElapsedTime(&timing->kernel_ms, w->ev[1], w->ev[2]));
-        HIP_TRY(hipEventElapsedTime(&timing->d2h_ms, w->ev[2], w->ev[3]));
-        HIP_TRY(hipEventElapsedTime(&timing->total_ms, w->ev[0], w->ev[3]));
-    }
     return GRID_OK;
 }
 

@@ -1,14 +1,17 @@
 // Continuous-batching dFD server and its open-loop load generator (include/grid.h).
 //
 // Threads:
-//   clients   grid_server_submit pushes a request onto the pending queue;
+//   clients   grid_server_submit queues a request and wakes the scheduler; grid_server_wait
+//             sleeps on a condition variable until the request is final;
 //   scheduler admits pending requests while the in-flight bytes fit the budget, packs
 //             admitted requests of one model into a free batch context (pinned staging,
-//             device buffers, its own stream), enqueues H2D copy, one launch, D2H copy and
-//             an event, and polls the events of busy contexts;
-//   copiers   scatter a completed context's outputs from pinned staging into the
-//             requests' host buffers, mark the requests done, and free the context and
-//             its admission bytes.
+//             device buffers, its own stream) under the batching policy, and enqueues H2D
+//             copy, one launch and D2H copy with events around each phase; it sleeps until a
+//             request arrives, a context frees up or a batch window closes;
+//   workers   one per context: waits for its batch on the device (polling the last event for
+//             a short while, then a blocking wait), copies the outputs from pinned staging into
+//             the requests' host buffers, publishes them and frees the context and its
+//             admission bytes.
 #include "grid_internal.h"
 
 #include <algorithm>
@@ -33,6 +36,9 @@ using Clock = std::chrono::steady_clock;
 
 enum ReqState : int { kQueued = 0, kLaunched = 1, kDone = 2, kCanceled = 3 };
 
+// how long a worker polls its batch's last event before it blocks on it
+constexpr auto kPollBeforeBlock = std::chrono::microseconds(60);
+
 struct Request {
     uint64_t ticket = 0;
     int model = 0;
@@ -41,19 +47,25 @@ struct Request {
     float *qdd = nullptr, *Minv = nullptr, *dq = nullptr, *dqd = nullptr;
     size_t bytes = 0;
     std::atomic<int> state{kQueued};
-    Clock::time_point t_done;
+    // timeline (host clock) and the device phases of its batch (ms)
+    Clock::time_point t_admit, t_launch, t_seen, t_done;
+    float h2d_ms = 0, kernel_ms = 0, d2h_ms = 0;
 };
 
 struct BatchCtx {
     int model = 0;
     int n = 0;
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    hipEvent_t ev[4] = {};                     // before H2D, after H2D, after kernel, after D2H
     float *d_in = nullptr, *d_out = nullptr, *h_in = nullptr, *h_out = nullptr;
     grid_workspace ws = nullptr;               // staged (per-request) mode only
     std::vector<Request*> reqs;
     int knots = 0;
-    std::atomic<bool> busy{false};             // set by the scheduler, cleared by a copier
+    std::atomic<bool> busy{false};             // set by the scheduler, cleared by its worker
+    std::thread worker;
+    std::mutex mu;                             // launched, quit
+    std::condition_variable cv;
+    bool launched = false, quit = false;
 };
 
 size_t request_bytes(int n, int N) { return sizeof(float) * (size_t)N * (4 * n + 3 * n * n); }
@@ -66,22 +78,18 @@ struct grid_server_s {
     int device = 0;
     std::vector<std::unique_ptr<BatchCtx>> ctx;
 
-    std::mutex mu;                             // pending, tickets, next_ticket, accepting
+    std::mutex mu;                             // everything below up to `stop`
+    std::condition_variable sched_cv;          // a request arrived, a context freed, stop
+    std::condition_variable done_cv;           // a request reached a final state
     std::deque<Request*> pending;
     std::unordered_map<uint64_t, Request*> tickets;
     uint64_t next_ticket = 1;
+    uint64_t wake_seq = 0;                     // bumped with every scheduler wake-up
     bool accepting = true;
+    bool stop = false;                         // scheduler: drain and exit
 
-    std::mutex done_mu;                        // completed contexts for the copiers
-    std::condition_variable done_cv;
-    std::deque<BatchCtx*> completed;
-    std::atomic<int> free_events{0};           // contexts released by copiers (wake-up hint)
-
-    std::atomic<bool> stop{false};             // scheduler: drain and exit
-    std::atomic<bool> copiers_stop{false};     // copiers: exit once nothing is left
     std::atomic<size_t> inflight_bytes{0};
     std::thread scheduler;
-    std::vector<std::thread> copiers;
 
     std::atomic<uint64_t> submitted{0}, completed_n{0}, canceled{0}, knots_done{0}, launches{0};
     std::atomic<uint64_t> max_inflight{0};
@@ -94,6 +102,15 @@ grid_status fail(grid_status s, const std::string& msg)
 {
     set_error(msg);
     return s;
+}
+
+void wake_scheduler(grid_server s)
+{
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        ++s->wake_seq;
+    }
+    s->sched_cv.notify_one();
 }
 
 // Return a context and its requests' admission bytes. Requests are published (done or
@@ -109,25 +126,53 @@ void finish_ctx(grid_server s, BatchCtx* c, int final_state)
     c->knots = 0;
     s->inflight_bytes.fetch_sub(freed);
     c->busy.store(false, std::memory_order_release);
-    s->free_events.fetch_add(1);
     for (Request* r : reqs) {
         if (final_state == kCanceled)
             s->canceled.fetch_add(1);
         r->state.store(final_state, std::memory_order_release);
     }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);   // orders the stores before any waiter's check
+        ++s->wake_seq;
+    }
+    s->done_cv.notify_all();
+    s->sched_cv.notify_one();
 }
 
-void copier_loop(grid_server s)
+// wait for the batch's last event: poll for a short while (most batches finish within tens of
+// microseconds), then block in the runtime
+hipError_t wait_batch(BatchCtx* c)
 {
+    const auto t0 = Clock::now();
     for (;;) {
-        BatchCtx* c = nullptr;
+        const hipError_t q = hipEventQuery(c->ev[3]);
+        if (q != hipErrorNotReady)
+            return q;
+        if (Clock::now() - t0 > kPollBeforeBlock)
+            return hipEventSynchronize(c->ev[3]);
+        std::this_thread::yield();
+    }
+}
+
+void worker_loop(grid_server s, BatchCtx* c)
+{
+    (void)hipSetDevice(s->device);
+    for (;;) {
         {
-            std::unique_lock<std::mutex> lk(s->done_mu);
-            s->done_cv.wait(lk, [&] { return !s->completed.empty() || s->copiers_stop.load(); });
-            if (s->completed.empty())
+            std::unique_lock<std::mutex> lk(c->mu);
+            c->cv.wait(lk, [&] { return c->launched || c->quit; });
+            if (!c->launched)
                 return;
-            c = s->completed.front();
-            s->completed.pop_front();
+            c->launched = false;
+        }
+        const hipError_t e = wait_batch(c);
+        const auto t_seen = Clock::now();
+        float ph[3] = {0, 0, 0};
+        if (e != hipSuccess) {
+            s->device_error.store(true);
+        } else {
+            for (int k = 0; k < 3; ++k)
+                (void)hipEventElapsedTime(&ph[k], c->ev[k], c->ev[k + 1]);
         }
         const size_t n = (size_t)c->n, K = (size_t)c->knots;
         const float* oq = c->h_out;
@@ -137,6 +182,10 @@ void copier_loop(grid_server s)
         size_t off = 0;
         for (Request* r : c->reqs) {
             const size_t N = (size_t)r->N;
+            r->t_seen = t_seen;
+            r->h2d_ms = ph[0];
+            r->kernel_ms = ph[1];
+            r->d2h_ms = ph[2];
             std::memcpy(r->qdd, oq + off * n, N * n * sizeof(float));
             std::memcpy(r->Minv, oM + off * n * n, N * n * n * sizeof(float));
             std::memcpy(r->dq, oD + off * n * n, N * n * n * sizeof(float));
@@ -152,7 +201,7 @@ void copier_loop(grid_server s)
 
 bool ctx_busy(BatchCtx* c) { return c->busy.load(std::memory_order_acquire); }
 
-// stage inputs, enqueue copy-in, launch, copy-out and the completion event
+// stage inputs, enqueue copy-in, launch, copy-out and the events around them
 bool launch_ctx(grid_server s, BatchCtx* c)
 {
     grid_model m = s->models[c->model];
@@ -161,11 +210,13 @@ bool launch_ctx(grid_server s, BatchCtx* c)
     float* iqd = iq + K * n;
     float* itau = iqd + K * n;
     size_t off = 0;
+    const auto now = Clock::now();
     for (Request* r : c->reqs) {
         const size_t N = (size_t)r->N;
         std::memcpy(iq + off * n, r->q, N * n * sizeof(float));
         std::memcpy(iqd + off * n, r->qd, N * n * sizeof(float));
         std::memcpy(itau + off * n, r->tau, N * n * sizeof(float));
+        r->t_launch = now;
         r->state.store(kLaunched, std::memory_order_relaxed);
         off += N;
     }
@@ -176,8 +227,10 @@ bool launch_ctx(grid_server s, BatchCtx* c)
     float* oM = oq + K * n;
     float* oD = oM + K * n * n;
     float* oV = oD + K * n * n;
-    if (hipMemcpyAsync(dq, iq, 3 * K * n * sizeof(float), hipMemcpyHostToDevice, c->stream) !=
-        hipSuccess)
+    if (hipEventRecord(c->ev[0], c->stream) != hipSuccess ||
+        hipMemcpyAsync(dq, iq, 3 * K * n * sizeof(float), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipEventRecord(c->ev[1], c->stream) != hipSuccess)
         return false;
     grid_status st;
     if (s->cfg.flags & GRID_SERVER_PER_REQUEST)
@@ -186,12 +239,17 @@ bool launch_ctx(grid_server s, BatchCtx* c)
         st = grid_fd_grad(m, (int32_t)K, dq, dqd, dtau, oq, oM, oD, oV, c->stream);
     if (st != GRID_OK)
         return false;
-    if (hipMemcpyAsync(c->h_out, c->d_out, K * (n + 3 * n * n) * sizeof(float),
-                       hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-        return false;
-    if (hipEventRecord(c->done, c->stream) != hipSuccess)
+    if (hipEventRecord(c->ev[2], c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->h_out, c->d_out, K * (n + 3 * n * n) * sizeof(float),
+                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipEventRecord(c->ev[3], c->stream) != hipSuccess)
         return false;
     s->launches.fetch_add(1);
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->launched = true;
+    }
+    c->cv.notify_one();
     return true;
 }
 
@@ -199,91 +257,113 @@ void scheduler_loop(grid_server s)
 {
     (void)hipSetDevice(s->device);
     const int nm = (int)s->models.size();
+    const bool per_request = (s->cfg.flags & GRID_SERVER_PER_REQUEST) != 0;
+    const auto window = std::chrono::microseconds(per_request ? 0 : s->cfg.batch_window_us);
+    const int min_fill = per_request ? 0 : s->cfg.min_batch_knots;
     std::vector<std::deque<Request*>> admitted(nm);
-    std::vector<BatchCtx*> inflight;
+    std::vector<int> admitted_knots(nm, 0);
+    uint64_t seen = 0;
     for (;;) {
-        bool progress = false;
-        // completions: hand finished contexts to the copiers
-        for (size_t k = 0; k < inflight.size();) {
-            BatchCtx* c = inflight[k];
-            hipError_t q = hipEventQuery(c->done);
-            if (q == hipErrorNotReady) {
-                ++k;
-                continue;
-            }
-            if (q != hipSuccess)
-                s->device_error.store(true);
-            {
-                std::lock_guard<std::mutex> lk(s->done_mu);
-                s->completed.push_back(c);
-            }
-            s->done_cv.notify_one();
-            inflight[k] = inflight.back();
-            inflight.pop_back();
-            progress = true;
-        }
+        bool stopping = false;
         // admission: FIFO while the bytes fit
         {
             std::lock_guard<std::mutex> lk(s->mu);
+            seen = s->wake_seq;
+            stopping = s->stop;
+            const auto now = Clock::now();
             while (!s->pending.empty()) {
                 Request* r = s->pending.front();
                 const size_t cur = s->inflight_bytes.load();
                 if (cur + r->bytes > s->cfg.device_budget_bytes)
                     break;
                 s->inflight_bytes.fetch_add(r->bytes);
-                size_t now = cur + r->bytes, seen = s->max_inflight.load();
-                while (now > seen && !s->max_inflight.compare_exchange_weak(seen, now)) {
+                size_t now_b = cur + r->bytes, top = s->max_inflight.load();
+                while (now_b > top && !s->max_inflight.compare_exchange_weak(top, now_b)) {
                 }
                 s->pending.pop_front();
+                r->t_admit = now;
                 admitted[r->model].push_back(r);
-                progress = true;
+                admitted_knots[r->model] += r->N;
             }
         }
-        // packing: each free context of a model takes admitted requests up to the limit
-        for (auto& cp : s->ctx) {
-            BatchCtx* c = cp.get();
-            auto& q = admitted[c->model];
-            if (q.empty() || ctx_busy(c))
-                continue;
-            int knots = 0;
+        // packing under the batching policy
+        Clock::time_point deadline = Clock::time_point::max();
+        for (int k = 0; k < nm; ++k) {
+            auto& q = admitted[k];
             while (!q.empty()) {
-                Request* r = q.front();
-                if (knots > 0 && ((s->cfg.flags & GRID_SERVER_PER_REQUEST) ||
-                                  knots + r->N > s->cfg.max_batch_knots))
+                BatchCtx* free_ctx = nullptr;
+                int busy = 0;
+                for (auto& cp : s->ctx) {
+                    if (cp->model != k)
+                        continue;
+                    if (ctx_busy(cp.get()))
+                        ++busy;
+                    else if (!free_ctx)
+                        free_ctx = cp.get();
+                }
+                if (!free_ctx)
                     break;
-                c->reqs.push_back(r);
-                knots += r->N;
-                q.pop_front();
+                if (busy > 0 && !stopping && admitted_knots[k] < min_fill) {
+                    const auto due = q.front()->t_admit + window;
+                    if (Clock::now() < due) {
+                        deadline = std::min(deadline, due);
+                        break;
+                    }
+                }
+                BatchCtx* c = free_ctx;
+                int knots = 0;
+                while (!q.empty()) {
+                    Request* r = q.front();
+                    if (knots > 0 && (per_request || knots + r->N > s->cfg.max_batch_knots))
+                        break;
+                    c->reqs.push_back(r);
+                    knots += r->N;
+                    q.pop_front();
+                }
+                admitted_knots[k] -= knots;
+                c->knots = knots;
+                c->busy.store(true, std::memory_order_release);
+                if (!launch_ctx(s, c)) {
+                    s->device_error.store(true);
+                    (void)hipStreamSynchronize(c->stream);
+                    finish_ctx(s, c, kCanceled);
+                }
             }
-            c->knots = knots;
-            c->busy.store(true, std::memory_order_release);
-            if (!launch_ctx(s, c)) {
-                s->device_error.store(true);
-                (void)hipStreamSynchronize(c->stream);
-                finish_ctx(s, c, kCanceled);
-                continue;
-            }
-            inflight.push_back(c);
-            progress = true;
         }
-        if (s->stop.load()) {
-            bool idle = inflight.empty();
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->stop) {
+            bool idle = true;
             for (auto& q : admitted)
                 idle = idle && q.empty();
-            if (idle)
+            for (auto& cp : s->ctx)
+                idle = idle && !ctx_busy(cp.get());
+            if (idle && s->pending.empty())
                 break;
         }
-        if (!progress)
-            std::this_thread::yield();
+        // sleep until a request arrives, a context frees up or a batch window closes
+        auto woken = [&] { return s->wake_seq != seen; };
+        if (deadline == Clock::time_point::max())
+            s->sched_cv.wait(lk, woken);
+        else
+            s->sched_cv.wait_until(lk, deadline, woken);
     }
 }
 
 void destroy_ctx(BatchCtx* c)
 {
+    if (c->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            c->quit = true;
+        }
+        c->cv.notify_one();
+        c->worker.join();
+    }
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
-    if (c->done)
-        (void)hipEventDestroy(c->done);
+    for (hipEvent_t e : c->ev)
+        if (e)
+            (void)hipEventDestroy(e);
     if (c->stream)
         (void)hipStreamDestroy(c->stream);
     (void)hipFree(c->d_in);
@@ -309,7 +389,9 @@ grid_status grid_server_create(const grid_model* models, int32_t count,
     if (!models || count < 1 || !cfg)
         return fail(GRID_EINVAL, "models, count and config are required");
     if (cfg->max_batch_knots < 1 || cfg->max_batch_knots > (1 << 20) || cfg->contexts_per_model < 1 ||
-        cfg->contexts_per_model > 64 || (cfg->flags & ~(uint32_t)GRID_SERVER_PER_REQUEST))
+        cfg->contexts_per_model > 64 || (cfg->flags & ~(uint32_t)GRID_SERVER_PER_REQUEST) ||
+        cfg->batch_window_us < 0 || cfg->batch_window_us > 1000000 || cfg->min_batch_knots < 0 ||
+        cfg->min_batch_knots > cfg->max_batch_knots)
         return fail(GRID_EINVAL, "bad server configuration");
     for (int k = 0; k < count; ++k)
         if (!models[k] || models[k]->device != models[0]->device)
@@ -331,8 +413,9 @@ grid_status grid_server_create(const grid_model* models, int32_t count,
             b->n = models[k]->topo.n;
             const size_t n = (size_t)b->n, K = (size_t)cfg->max_batch_knots;
             hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-            if (e == hipSuccess)
-                e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+            for (int v = 0; v < 4 && e == hipSuccess; ++v)   // the last one is waited on
+                e = hipEventCreateWithFlags(&b->ev[v], v == 3 ? hipEventBlockingSync
+                                                              : hipEventDefault);
             if (e == hipSuccess)
                 e = hipMalloc(&b->d_in, 3 * K * n * sizeof(float));
             if (e == hipSuccess)
@@ -352,9 +435,8 @@ grid_status grid_server_create(const grid_model* models, int32_t count,
                 return fail(GRID_ENOMEM, "server buffer allocation failed");
             }
         }
-    const int ncopy = 4;
-    for (int k = 0; k < ncopy; ++k)
-        s->copiers.emplace_back(copier_loop, s);
+    for (auto& cp : s->ctx)
+        cp->worker = std::thread(worker_loop, s, cp.get());
     s->scheduler = std::thread(scheduler_loop, s);
     *out = s;
     return GRID_OK;
@@ -397,7 +479,9 @@ grid_status grid_server_submit(grid_server s, int32_t model_index, int32_t N, co
         r->ticket = s->next_ticket++;
         s->tickets[r->ticket] = r;
         s->pending.push_back(r);
+        ++s->wake_seq;
     }
+    s->sched_cv.notify_one();
     s->submitted.fetch_add(1);
     *ticket = r->ticket;
     return GRID_OK;
@@ -419,6 +503,19 @@ static void drop_ticket(grid_server s, Request* r)
     delete r;
 }
 
+// sleep until the request is final or the timeout passes (timeout_us < 0: no limit); true if
+// final
+static bool wait_final(grid_server s, Request* r, int64_t timeout_us)
+{
+    auto final_ = [&] { return r->state.load(std::memory_order_acquire) >= kDone; };
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (timeout_us < 0) {
+        s->done_cv.wait(lk, final_);
+        return true;
+    }
+    return s->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), final_);
+}
+
 grid_status grid_server_wait(grid_server s, uint64_t ticket, int64_t timeout_us)
 {
     if (!s)
@@ -426,23 +523,15 @@ grid_status grid_server_wait(grid_server s, uint64_t ticket, int64_t timeout_us)
     Request* r = find_request(s, ticket);
     if (!r)
         return fail(GRID_EINVAL, "unknown ticket");
-    const auto t0 = Clock::now();
-    for (;;) {
-        const int st = r->state.load(std::memory_order_acquire);
-        if (st == kDone || st == kCanceled) {
-            drop_ticket(s, r);
-            if (st == kCanceled)
-                return fail(GRID_ECANCELED, "request canceled");
-            if (s->device_error.load())
-                return fail(GRID_EDEVICE, "a device operation of the server failed");
-            return GRID_OK;
-        }
-        if (timeout_us >= 0 &&
-            std::chrono::duration_cast<std::chrono::microseconds>(Clock::now() - t0).count() >=
-                timeout_us)
-            return fail(GRID_ETIMEDOUT, "request still running");
-        std::this_thread::yield();
-    }
+    if (!wait_final(s, r, timeout_us))
+        return fail(GRID_ETIMEDOUT, "request still running");
+    const int st = r->state.load(std::memory_order_acquire);
+    drop_ticket(s, r);
+    if (st == kCanceled)
+        return fail(GRID_ECANCELED, "request canceled");
+    if (s->device_error.load())
+        return fail(GRID_EDEVICE, "a device operation of the server failed");
+    return GRID_OK;
 }
 
 grid_status grid_server_stats_get(grid_server s, grid_server_stats* out)
@@ -472,25 +561,16 @@ grid_status grid_server_destroy(grid_server s)
         s->canceled.fetch_add(1);
         r->state.store(kCanceled, std::memory_order_release);   // the waiter frees it
     }
-    s->stop.store(true);
-    if (s->scheduler.joinable())
-        s->scheduler.join();
-    // the scheduler has handed every launched context to the copiers; let them drain
-    for (;;) {
-        bool busy = false;
-        for (auto& c : s->ctx)
-            busy = busy || ctx_busy(c.get());
-        if (!busy)
-            break;
-        std::this_thread::yield();
-    }
     {
-        std::lock_guard<std::mutex> lk(s->done_mu);
-        s->copiers_stop.store(true);
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        ++s->wake_seq;
     }
     s->done_cv.notify_all();
-    for (auto& t : s->copiers)
-        t.join();
+    s->sched_cv.notify_one();
+    // the scheduler launches what it admitted and returns once every context is free
+    if (s->scheduler.joinable())
+        s->scheduler.join();
     for (auto& c : s->ctx)
         destroy_ctx(c.get());
     {
@@ -520,6 +600,7 @@ grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
     }
     if (std::fabs(acc - 1.0) > 1e-6)
         return fail(GRID_EINVAL, "model probabilities must sum to 1");
+    std::memset(out, 0, sizeof *out);
     std::mt19937_64 rng(cfg->seed);
     std::uniform_real_distribution<double> uni(0.0, 1.0);
     std::normal_distribution<float> gauss(0.0f, 1.0f);
@@ -564,25 +645,28 @@ grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
     const double total_s = cfg->warmup_s + cfg->duration_s;
     double t_arr = 0.0;
     std::vector<double> lat;
+    std::vector<double> split[6];   // queue, h2d, kernel, d2h, complete, copyout (us)
     uint64_t knots = 0;
+    const uint64_t launches0 = s->launches.load();
+    auto us = [](Clock::time_point a, Clock::time_point b) {
+        return std::chrono::duration<double, std::micro>(b - a).count();
+    };
     auto settle = [&](size_t idx) -> grid_status {
         Sent& e = sent[idx];
-        // the caller owns the request until wait reports completion
+        // the request's timeline is read once it is final and before wait releases it
         Request* r = find_request(s, e.ticket);
-        Clock::time_point t_done;
-        if (r) {
-            while (r->state.load(std::memory_order_acquire) < kDone)
-                std::this_thread::yield();
-            t_done = r->t_done;
-        }
-        grid_status st = grid_server_wait(s, e.ticket, -1);
-        if (st != GRID_OK)
-            return st;
-        if (e.counted) {
-            lat.push_back(std::chrono::duration<double, std::micro>(t_done - e.t_sched).count());
+        if (r && wait_final(s, r, -1) && e.counted &&
+            r->state.load(std::memory_order_acquire) == kDone) {
+            lat.push_back(us(e.t_sched, r->t_done));
+            split[0].push_back(us(e.t_sched, r->t_launch));
+            split[1].push_back(1e3 * r->h2d_ms);
+            split[2].push_back(1e3 * r->kernel_ms);
+            split[3].push_back(1e3 * r->d2h_ms);
+            split[4].push_back(us(r->t_launch, r->t_seen));
+            split[5].push_back(us(r->t_seen, r->t_done));
             knots += (uint64_t)e.N;
         }
-        return GRID_OK;
+        return grid_server_wait(s, e.ticket, -1);
     };
     size_t settled = 0;
     for (;;) {
@@ -612,6 +696,9 @@ grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
                 ++settled;
             }
         }
+        // sleep through most of the gap, then spin to the scheduled instant
+        if (t_sched - Clock::now() > std::chrono::microseconds(200))
+            std::this_thread::sleep_until(t_sched - std::chrono::microseconds(100));
         while (Clock::now() < t_sched) {
         }
         uint64_t ticket = 0;
@@ -631,13 +718,25 @@ grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
             return st;
         ++settled;
     }
+    const uint64_t nlaunch = s->launches.load() - launches0;
     std::sort(lat.begin(), lat.end());
-    auto pct = [&](double p) {
-        if (lat.empty())
+    auto pct_of = [](const std::vector<double>& v, double p) {
+        if (v.empty())
             return 0.0;
-        const size_t i = std::min(lat.size() - 1, (size_t)std::floor(p * (lat.size() - 1) + 0.5));
-        return lat[i];
+        const size_t i = std::min(v.size() - 1, (size_t)std::floor(p * (v.size() - 1) + 0.5));
+        return v[i];
     };
+    auto pct = [&](double p) { return pct_of(lat, p); };
+    double* p50f[6] = {&out->p50.queue_us, &out->p50.h2d_us, &out->p50.kernel_us,
+                       &out->p50.d2h_us, &out->p50.complete_us, &out->p50.copyout_us};
+    double* p99f[6] = {&out->p99.queue_us, &out->p99.h2d_us, &out->p99.kernel_us,
+                       &out->p99.d2h_us, &out->p99.complete_us, &out->p99.copyout_us};
+    for (int k = 0; k < 6; ++k) {
+        std::sort(split[k].begin(), split[k].end());
+        *p50f[k] = pct_of(split[k], 0.50);
+        *p99f[k] = pct_of(split[k], 0.99);
+    }
+    out->requests_per_launch = nlaunch ? (double)sent.size() / (double)nlaunch : 0.0;
     double mean = 0;
     for (double x : lat)
         mean += x;

@@ -25,6 +25,7 @@ GRID_ECOMPILE = -5
 GRID_EBUSY = -6
 GRID_ETIMEDOUT = -7
 GRID_ECANCELED = -8
+GRID_MAX_KNOTS = 1 << 24      # the largest N of one call
 GRID_SERVER_PER_REQUEST = 1
 GRID_CODEGEN_PIPE_MODULE = 1 << 16
 
@@ -46,7 +47,8 @@ class GridTiming(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("device_budget_bytes", C.c_size_t), ("max_batch_knots", C.c_int32),
-                ("contexts_per_model", C.c_int32), ("flags", C.c_uint32)]
+                ("contexts_per_model", C.c_int32), ("flags", C.c_uint32),
+                ("batch_window_us", C.c_int32), ("min_batch_knots", C.c_int32)]
 
 
 class ServerStats(C.Structure):
@@ -61,11 +63,17 @@ class LoadgenConfig(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class LatencySplit(C.Structure):
+    _fields_ = [("queue_us", C.c_double), ("h2d_us", C.c_double), ("kernel_us", C.c_double),
+                ("d2h_us", C.c_double), ("complete_us", C.c_double), ("copyout_us", C.c_double)]
+
+
 class LoadgenResult(C.Structure):
     _fields_ = [("requests", C.c_uint64), ("knots", C.c_uint64), ("seconds", C.c_double),
                 ("p50_us", C.c_double), ("p90_us", C.c_double), ("p99_us", C.c_double),
                 ("max_us", C.c_double), ("mean_us", C.c_double),
-                ("offered_rate_per_s", C.c_double)]
+                ("offered_rate_per_s", C.c_double), ("requests_per_launch", C.c_double),
+                ("p50", LatencySplit), ("p99", LatencySplit)]
 
 
 class GridItem(C.Structure):
@@ -146,6 +154,14 @@ _SIGS = {
     "grid_mixed_launch": (C.c_int32, [C.c_void_p, C.POINTER(GridMixedItem), C.c_int32,
                                       C.c_void_p]),
     "grid_mixed_destroy": (C.c_int32, [C.c_void_p]),
+    "grid_mixed_launch_mode": (C.c_int32, [C.c_void_p, C.POINTER(GridMixedItem), C.c_int32,
+                                           C.c_int32, C.c_void_p]),
+    "grid_mixed_tune": (C.c_int32, [C.c_void_p, C.POINTER(GridMixedItem), C.c_int32,
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "grid_workspace_host_buffers": (C.c_int32, [C.c_void_p, C.POINTER(C.POINTER(C.c_float)),
+                                                C.POINTER(C.POINTER(C.c_float))]),
+    "grid_fd_grad_pinned": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                        C.POINTER(GridTiming)]),
     "grid_mixed_source": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_char_p,
                                       C.POINTER(C.c_size_t)]),
     "grid_mixed_precompile": (C.c_int32, [C.POINTER(GridDesc), C.c_int32]),
@@ -182,13 +198,39 @@ def _check(status: int):
         raise GridError(status, last_error())
 
 
-def _addr(x) -> int | None:
-    """Device address of a torch tensor (or an int address)."""
-    if x is None:
-        return None
-    if isinstance(x, int):
+def _dev(x, numel: int, device: int, what: str) -> int | None:
+    """Device address of a float32 buffer that a kernel will read or write `numel` elements
+    of. A torch tensor must be a contiguous float32 tensor on GPU `device` holding at least
+    `numel` elements; anything else raises GridError(GRID_EINVAL) before the call, so that no
+    kernel is launched on a host pointer, a short buffer or data of another type. None and
+    int addresses are passed through (the library rejects NULL itself)."""
+    if x is None or isinstance(x, int):
         return x
+    if not getattr(x, "is_cuda", False):
+        raise GridError(GRID_EINVAL, f"{what}: not a GPU tensor")
+    if x.get_device() != device:
+        raise GridError(GRID_EINVAL, f"{what}: on GPU {x.get_device()}, the model is on {device}")
+    if str(x.dtype) != "torch.float32":
+        raise GridError(GRID_EINVAL, f"{what}: dtype {x.dtype}, float32 required")
+    if not x.is_contiguous():
+        raise GridError(GRID_EINVAL, f"{what}: not contiguous")
+    if x.numel() < numel:
+        raise GridError(GRID_EINVAL, f"{what}: {x.numel()} elements, {numel} required")
     return int(x.data_ptr())
+
+
+def _vec_mat(N: int, n: int):
+    """Elements of an [N][n] and an [N][n][n] array (0 when N <= 0: the library handles it)."""
+    N = max(int(N), 0)
+    return N * n, N * n * n
+
+
+def _fd_grad_ptrs(N, n, device, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd):
+    """The seven checked device addresses of a gradient-of-forward-dynamics call."""
+    v, m = _vec_mat(N, n)
+    return (_dev(q, v, device, "q"), _dev(qd, v, device, "qd"), _dev(tau, v, device, "tau"),
+            _dev(qdd, v, device, "qdd"), _dev(Minv, m, device, "Minv"),
+            _dev(dqdd_dq, m, device, "dqdd_dq"), _dev(dqdd_dqd, m, device, "dqdd_dqd"))
 
 
 def _stream_handle(stream) -> int | None:
@@ -264,9 +306,8 @@ class Model:
         """grid_fd_grad on device buffers (torch tensors or addresses), asynchronous."""
         if N is None:
             N = int(q.shape[0])
-        _check(lib().grid_fd_grad(self._h, int(N), _addr(q), _addr(qd), _addr(tau), _addr(qdd),
-                                  _addr(Minv), _addr(dqdd_dq), _addr(dqdd_dqd),
-                                  _stream_handle(stream)))
+        ptrs = _fd_grad_ptrs(N, self.n, self.device, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd)
+        _check(lib().grid_fd_grad(self._h, int(N), *ptrs, _stream_handle(stream)))
 
 
     def fd_grad_call(self, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, N=None, stream=None):
@@ -277,7 +318,8 @@ class Model:
         if N is None:
             N = int(q.shape[0])
         bufs = (q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd)
-        args = (self._h, C.c_int(int(N)), *(C.c_void_p(_addr(x)) for x in bufs),
+        ptrs = _fd_grad_ptrs(N, self.n, self.device, *bufs)
+        args = (self._h, C.c_int(int(N)), *(C.c_void_p(x) for x in ptrs),
                 C.c_void_p(_stream_handle(stream)))
         fn = lib().grid_fd_grad
 
@@ -293,33 +335,48 @@ class Model:
     def id(self, q, qd, qdd, tau, N=None, stream=None):
         """grid_id: tau = ID(q, qd, qdd)."""
         N = int(q.shape[0]) if N is None else N
-        _check(lib().grid_id(self._h, int(N), _addr(q), _addr(qd), _addr(qdd), _addr(tau),
+        v, _ = _vec_mat(N, self.n)
+        d = self.device
+        _check(lib().grid_id(self._h, int(N), _dev(q, v, d, "q"), _dev(qd, v, d, "qd"),
+                             _dev(qdd, v, d, "qdd"), _dev(tau, v, d, "tau"),
                              _stream_handle(stream)))
 
     def fd(self, q, qd, tau, qdd, N=None, stream=None):
         """grid_fd: qdd = FD(q, qd, tau)."""
         N = int(q.shape[0]) if N is None else N
-        _check(lib().grid_fd(self._h, int(N), _addr(q), _addr(qd), _addr(tau), _addr(qdd),
+        v, _ = _vec_mat(N, self.n)
+        d = self.device
+        _check(lib().grid_fd(self._h, int(N), _dev(q, v, d, "q"), _dev(qd, v, d, "qd"),
+                             _dev(tau, v, d, "tau"), _dev(qdd, v, d, "qdd"),
                              _stream_handle(stream)))
 
     def minv(self, q, Minv, N=None, stream=None):
         """grid_minv: M(q)^-1."""
         N = int(q.shape[0]) if N is None else N
-        _check(lib().grid_minv(self._h, int(N), _addr(q), _addr(Minv), _stream_handle(stream)))
+        v, m = _vec_mat(N, self.n)
+        _check(lib().grid_minv(self._h, int(N), _dev(q, v, self.device, "q"),
+                               _dev(Minv, m, self.device, "Minv"), _stream_handle(stream)))
 
     def id_grad(self, q, qd, qdd, dtau_dq, dtau_dqd, N=None, stream=None):
         """grid_id_grad: dtau/dq and dtau/dqd at the given qdd."""
         N = int(q.shape[0]) if N is None else N
-        _check(lib().grid_id_grad(self._h, int(N), _addr(q), _addr(qd), _addr(qdd),
-                                  _addr(dtau_dq), _addr(dtau_dqd), _stream_handle(stream)))
+        v, m = _vec_mat(N, self.n)
+        d = self.device
+        _check(lib().grid_id_grad(self._h, int(N), _dev(q, v, d, "q"), _dev(qd, v, d, "qd"),
+                                  _dev(qdd, v, d, "qdd"), _dev(dtau_dq, m, d, "dtau_dq"),
+                                  _dev(dtau_dqd, m, d, "dtau_dqd"), _stream_handle(stream)))
 
 
 def fd_vjp_adjoint(model, q, qd, qdd, gbar, qbar, qdbar, taubar, N=None, stream=None):
     """grid_fd_vjp_adjoint: the VJP of FD by one reverse sweep (no Jacobians needed)."""
     if N is None:
         N = int(gbar.shape[0])
-    _check(lib().grid_fd_vjp_adjoint(model.handle, int(N), _addr(q), _addr(qd), _addr(qdd),
-                                     _addr(gbar), _addr(qbar), _addr(qdbar), _addr(taubar),
+    v, _ = _vec_mat(N, model.n)
+    d = model.device
+    _check(lib().grid_fd_vjp_adjoint(model.handle, int(N), _dev(q, v, d, "q"),
+                                     _dev(qd, v, d, "qd"), _dev(qdd, v, d, "qdd"),
+                                     _dev(gbar, v, d, "gbar"), _dev(qbar, v, d, "qbar"),
+                                     _dev(qdbar, v, d, "qdbar"), _dev(taubar, v, d, "taubar"),
                                      _stream_handle(stream)))
 
 
@@ -327,8 +384,12 @@ def fd_vjp(model, dqdd_dq, dqdd_dqd, Minv, gbar, qbar, qdbar, taubar, N=None, st
     """grid_fd_vjp on device buffers (torch tensors or addresses), asynchronous."""
     if N is None:
         N = int(gbar.shape[0])
-    _check(lib().grid_fd_vjp(model.handle, int(N), _addr(dqdd_dq), _addr(dqdd_dqd), _addr(Minv),
-                             _addr(gbar), _addr(qbar), _addr(qdbar), _addr(taubar),
+    v, m = _vec_mat(N, model.n)
+    d = model.device
+    _check(lib().grid_fd_vjp(model.handle, int(N), _dev(dqdd_dq, m, d, "dqdd_dq"),
+                             _dev(dqdd_dqd, m, d, "dqdd_dqd"), _dev(Minv, m, d, "Minv"),
+                             _dev(gbar, v, d, "gbar"), _dev(qbar, v, d, "qbar"),
+                             _dev(qdbar, v, d, "qdbar"), _dev(taubar, v, d, "taubar"),
                              _stream_handle(stream)))
 
 
@@ -337,9 +398,12 @@ def dt_jacobians(model, dt, dqdd_dq, dqdd_dqd, Minv, A, B, N=None, stream=None):
     Euler step from the dFD outputs (device buffers, asynchronous)."""
     if N is None:
         N = int(dqdd_dq.shape[0])
-    _check(lib().grid_dt_jacobians(model.handle, int(N), float(dt), _addr(dqdd_dq),
-                                   _addr(dqdd_dqd), _addr(Minv), _addr(A), _addr(B),
-                                   _stream_handle(stream)))
+    _, m = _vec_mat(N, model.n)
+    d = model.device
+    _check(lib().grid_dt_jacobians(model.handle, int(N), float(dt),
+                                   _dev(dqdd_dq, m, d, "dqdd_dq"), _dev(dqdd_dqd, m, d, "dqdd_dqd"),
+                                   _dev(Minv, m, d, "Minv"), _dev(A, 4 * m, d, "A"),
+                                   _dev(B, 2 * m, d, "B"), _stream_handle(stream)))
 
 
 class Workspace:
@@ -368,9 +432,38 @@ class Workspace:
         """grid_fd_grad_staged: the five-launch pipeline on device buffers, asynchronous."""
         if N is None:
             N = int(q.shape[0])
-        _check(lib().grid_fd_grad_staged(self.model.handle, self._h, int(N), _addr(q), _addr(qd),
-                                         _addr(tau), _addr(qdd), _addr(Minv), _addr(dqdd_dq),
-                                         _addr(dqdd_dqd), _stream_handle(stream)))
+        ptrs = _fd_grad_ptrs(N, self.model.n, self.model.device, q, qd, tau, qdd, Minv,
+                             dqdd_dq, dqdd_dqd)
+        _check(lib().grid_fd_grad_staged(self.model.handle, self._h, int(N), *ptrs,
+                                         _stream_handle(stream)))
+
+    def host_buffers(self, N):
+        """The pinned buffers as numpy views for a call on N knots: (inputs dict q, qd, tau;
+        outputs dict qdd, Minv, dqdd_dq, dqdd_dqd), packed as grid_workspace_host_buffers
+        lays them out. Write the inputs in place, call fd_grad_pinned, read the outputs."""
+        if not 0 <= N <= self.max_knots:
+            raise GridError(GRID_EINVAL, "N must be in 0..max_knots of the workspace")
+        pin, pout = C.POINTER(C.c_float)(), C.POINTER(C.c_float)()
+        _check(lib().grid_workspace_host_buffers(self._h, C.byref(pin), C.byref(pout)))
+        n = self.model.n
+        vec, mat = N * n, N * n * n
+        fin = np.ctypeslib.as_array(pin, shape=(3 * vec,)) if N else np.zeros(0, np.float32)
+        fout = (np.ctypeslib.as_array(pout, shape=(vec + 3 * mat,)) if N
+                else np.zeros(0, np.float32))
+        ins = {k: fin[i * vec:(i + 1) * vec].reshape(N, n)
+               for i, k in enumerate(("q", "qd", "tau"))}
+        outs = {"qdd": fout[:vec].reshape(N, n)}
+        for i, k in enumerate(("Minv", "dqdd_dq", "dqdd_dqd")):
+            outs[k] = fout[vec + i * mat:vec + (i + 1) * mat].reshape(N, n, n)
+        return ins, outs
+
+    def fd_grad_pinned(self, N, pieces=1):
+        """grid_fd_grad_pinned on the inputs already in the pinned buffers; returns the timing
+        dict (with pieces > 1 only total_ms is measured)."""
+        t = GridTiming()
+        _check(lib().grid_fd_grad_pinned(self.model.handle, self._h, int(N), int(pieces),
+                                         C.byref(t)))
+        return {k: float(getattr(t, k)) for k in ("h2d_ms", "kernel_ms", "d2h_ms", "total_ms")}
 
     def fd_grad_host(self, q, qd, tau):
         """grid_fd_grad_host on numpy arrays; returns (outputs dict, timing dict)."""
@@ -396,8 +489,9 @@ def _items(items):
     tensors (N taken from q)."""
     arr = (GridItem * len(items))()
     for k, (m, q, qd, tau, qdd, Mi, dq, dqd) in enumerate(items):
-        arr[k] = GridItem(m.handle.value, int(q.shape[0]), _addr(q), _addr(qd), _addr(tau),
-                          _addr(qdd), _addr(Mi), _addr(dq), _addr(dqd))
+        N = int(q.shape[0])
+        arr[k] = GridItem(m.handle.value, N,
+                          *_fd_grad_ptrs(N, m.n, m.device, q, qd, tau, qdd, Mi, dq, dqd))
     return arr
 
 
@@ -453,15 +547,55 @@ class Mixed:
         self._h = h
         self.count = len(robots)
         self.device = device
+        # joints the arrays of each robot hold (fixed joints merged away)
+        self.dofs = [int(np.sum(np.asarray(r.joint_type) != JOINT_FIXED))
+                     if getattr(r, "joint_type", None) is not None else len(r.parent)
+                     for r in robots]
 
-    def launch(self, items, stream=None):
-        """items: sequence of (robot index, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd) with
-        device tensors (N taken from q)."""
+    def _items(self, items):
         arr = (GridMixedItem * len(items))()
         for k, (r, q, qd, tau, qdd, Mi, dq, dqd) in enumerate(items):
-            arr[k] = GridMixedItem(int(r), int(q.shape[0]), _addr(q), _addr(qd), _addr(tau),
-                                   _addr(qdd), _addr(Mi), _addr(dq), _addr(dqd))
-        _check(lib().grid_mixed_launch(self._h, arr, len(items), _stream_handle(stream)))
+            N = int(q.shape[0])
+            # an index out of range is the library's to reject; its buffers are not checked
+            n = self.dofs[r] if 0 <= int(r) < len(self.dofs) else 0
+            arr[k] = GridMixedItem(int(r), N,
+                                   *_fd_grad_ptrs(N if n else 0, n, self.device, q, qd, tau,
+                                                  qdd, Mi, dq, dqd))
+        return arr
+
+    def launch(self, items, stream=None, mode=None):
+        """items: sequence of (robot index, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd) with
+        device tensors (N taken from q). mode None: the tuned (or default) mode; else one of
+        MIXED_ONE_LAUNCH, MIXED_PERSISTENT, MIXED_PER_ROBOT."""
+        arr = self._items(items)
+        if mode is None:
+            _check(lib().grid_mixed_launch(self._h, arr, len(items), _stream_handle(stream)))
+        else:
+            _check(lib().grid_mixed_launch_mode(self._h, arr, len(items), int(mode),
+                                                _stream_handle(stream)))
+
+    def launch_call(self, items, stream=None, mode=None):
+        """The launch bound to fixed items (converted to C once) for timing loops."""
+        arr = self._items(items)
+        h, cnt, st = self._h, len(items), C.c_void_p(_stream_handle(stream))
+        fn = lib().grid_mixed_launch if mode is None else lib().grid_mixed_launch_mode
+        extra = () if mode is None else (int(mode),)
+
+        def call():
+            rc = fn(h, arr, cnt, *extra, st)
+            if rc != GRID_OK:
+                raise GridError(rc, last_error())
+
+        call.buffers = items
+        return call
+
+    def tune(self, items):
+        """grid_mixed_tune: (chosen mode, {mode: us per launch})."""
+        arr = self._items(items)
+        chosen = C.c_int32()
+        us = (C.c_float * 3)()
+        _check(lib().grid_mixed_tune(self._h, arr, len(items), C.byref(chosen), us))
+        return chosen.value, {m: float(us[m]) for m in range(3)}
 
     def close(self):
         if self._h is not None and self._h.value:
@@ -511,6 +645,8 @@ def tune_apply(model, table):
 
 
 BUILD_QUAD, BUILD_LANE, BUILD_LANE_W2, BUILD_LANE_W4, BUILD_PIPE, BUILD_SERIAL = range(6)
+MIXED_ONE_LAUNCH, MIXED_PERSISTENT, MIXED_PER_ROBOT = range(3)
+MIXED_MODES = ("one_launch", "persistent", "per_robot")
 JOINT_REVOLUTE, JOINT_PRISMATIC, JOINT_FIXED = 0, 1, 2
 BUILD_KERNELS = ("grid_fdgrad_quad", "grid_fdgrad_fused", "grid_fdgrad_fused_w2",
                  "grid_fdgrad_fused_w4", "grid_fdgrad_pipe", "grid_fdgrad_serial")
@@ -527,12 +663,12 @@ class Server:
     """grid_server: continuous batching of dFD requests over several models."""
 
     def __init__(self, models, budget_bytes=1 << 30, max_batch_knots=1024, contexts_per_model=3,
-                 flags=0):
+                 flags=0, batch_window_us=0, min_batch_knots=0):
         self._h = None
         self.models = list(models)
         handles = (C.c_void_p * len(self.models))(*[m.handle.value for m in self.models])
         cfg = ServerConfig(int(budget_bytes), int(max_batch_knots), int(contexts_per_model),
-                           int(flags))
+                           int(flags), int(batch_window_us), int(min_batch_knots))
         h = C.c_void_p()
         _check(lib().grid_server_create(handles, len(self.models), C.byref(cfg), C.byref(h)))
         self._h = h
@@ -574,8 +710,14 @@ class Server:
                             probs.ctypes.data_as(_f64p), int(n_min), int(n_max), int(seed))
         r = LoadgenResult()
         _check(lib().grid_server_loadgen(self._h, C.byref(cfg), C.byref(r)))
-        return {k: (float(getattr(r, k)) if t is C.c_double else int(getattr(r, k)))
-                for k, t in LoadgenResult._fields_}
+        out = {}
+        for k, t in LoadgenResult._fields_:
+            v = getattr(r, k)
+            if t is LatencySplit:
+                out[k + "_split"] = {f: float(getattr(v, f)) for f, _ in LatencySplit._fields_}
+            else:
+                out[k] = float(v) if t is C.c_double else int(v)
+        return out
 
     def close(self):
         if self._h is not None and self._h.value:
@@ -608,6 +750,7 @@ def codegen_precompile(robot, flags: int = 0):
 def fd_grad_torch(model: Model, q, qd, tau, stream=None):
     """Allocate outputs with torch on q's device and launch on the current stream."""
     import torch
+    q, qd, tau = (x.contiguous().float() for x in (q, qd, tau))
     N, n = q.shape
     dev = q.device
     out = {"qdd": torch.empty((N, n), device=dev, dtype=torch.float32),

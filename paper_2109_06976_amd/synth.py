@@ -36,6 +36,14 @@ SEED_CHAIN7 = 0
 SEED_QUAD12 = 1
 SEED_HUMANOID30 = 2
 
+# Batch sizes of the measured workloads (the tests run parity at each of them):
+# the paper's multiple-computation sweep (Sec. V-B, Fig. 4) on each of the three robots
+SWEEP_KNOTS = (32, 64, 128, 256, 1024)
+# larger batches of the 7-dof chain, where the throughput builds take over
+THROUGHPUT_KNOTS = (1024, 16384, 65536)
+# quadruped + 7-dof chain mixes at uneven knot counts in one step
+MIXED_PLANS = ((64, 37), (256, 181), (1024, 613))
+
 
 def _f32(x):
     return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)

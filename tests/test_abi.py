@@ -137,7 +137,10 @@ def test_codegen_quad_layout_shapes():
             qb = 16 // p
             assert qb * (1 if B <= 16 else 2) >= B and (qb == 16 or qb < 2 * B or qb == 1)
             assert pw >= max(2, (2 * B + 15) // 16) + 1 + (B <= 16)
-        assert "grid_dispatch_p(const grid::Args& a, int block)" in src
+        # the three-role kernel is generated into its own module only
+        assert "grid_dispatch_p(" not in src and "grid_fdgrad_pipe(" not in src
+        assert "grid_dispatch_p(const grid::Args& a, int block)" in \
+            grid.codegen_source(robot, grid.GRID_CODEGEN_PIPE_MODULE)
 
 
 def test_codegen_humanoid_branches():
@@ -203,7 +206,11 @@ def test_mixed_module_source_holds_every_branch_of_every_robot():
     robots = [synth.chain7(), synth.quad12(), synth.humanoid30()]
     src = grid.mixed_source(robots)
     assert "#define GRID_PIPE_ONLY" in src
-    assert 'extern "C" __global__' in src and "grid_fdgrad_pipe_mixed" in src
+    assert 'extern "C" __global__' in src and "grid_fdgrad_pipe_mixed(" in src
+    # the persistent form: resident workgroups stride over the same blocks, bounded by nblocks
+    assert "grid_fdgrad_pipe_mixed_persistent(MixedArgs args)" in src
+    assert "b < args.nblocks; b += (int)gridDim.x" in src
+    assert re.search(r"struct MixedArgs \{\s*int nseg;\s*int nblocks;", src)
     # the robots' branches, numbered across the robots, one switch case each
     per = [len(_insts(grid.codegen_source(r))) for r in robots]
     assert per[:2] == [1, 4]
@@ -264,3 +271,75 @@ def test_pipe_kernel_has_a_module_of_its_own():
     with pytest.raises(grid.GridError) as e:
         grid.Model(robot, flags=grid.GRID_CODEGEN_PIPE_MODULE)   # a codegen flag only
     assert e.value.status == grid.GRID_EINVAL
+
+
+class _FakeTensor:
+    """Just enough of a torch tensor's interface for the binding's checks (no GPU here)."""
+
+    def __init__(self, numel, dtype="torch.float32", is_cuda=True, device=0, contiguous=True):
+        self._n, self.dtype, self.is_cuda = numel, dtype, is_cuda
+        self._dev, self._contig = device, contiguous
+
+    def get_device(self):
+        return self._dev if self.is_cuda else -1
+
+    def is_contiguous(self):
+        return self._contig
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def test_binding_rejects_unusable_tensors_before_the_call():
+    """A kernel must never see a host pointer, a short buffer, another dtype, a strided view
+    or memory of another GPU: the binding raises GRID_EINVAL first."""
+    ok = _FakeTensor(4 * 7)
+    assert grid._dev(ok, 28, 0, "q") == 0x1000
+    assert grid._dev(None, 28, 0, "q") is None and grid._dev(0x2000, 28, 0, "q") == 0x2000
+    bad = {"host": _FakeTensor(28, is_cuda=False), "short": _FakeTensor(27),
+           "float64": _FakeTensor(28, dtype="torch.float64"),
+           "strided": _FakeTensor(28, contiguous=False), "other GPU": _FakeTensor(28, device=1)}
+    for what, t in bad.items():
+        with pytest.raises(grid.GridError) as e:
+            grid._dev(t, 28, 0, what)
+        assert e.value.status == grid.GRID_EINVAL, what
+    # the sizes a gradient-of-forward-dynamics call needs: [N][n] vectors, [N][n][n] matrices
+    v, m = grid._vec_mat(4, 7)
+    assert (v, m) == (28, 196) and grid._vec_mat(-1, 7) == (0, 0)
+    vecs = [_FakeTensor(28)] * 4
+    mats = [_FakeTensor(196)] * 3
+    assert len(grid._fd_grad_ptrs(4, 7, 0, *vecs[:3], vecs[3], *mats)) == 7
+    with pytest.raises(grid.GridError):
+        grid._fd_grad_ptrs(4, 7, 0, *vecs[:3], vecs[3], mats[0], mats[1], _FakeTensor(195))
+    import torch
+    with pytest.raises(grid.GridError):
+        grid._dev(torch.zeros(28), 28, 0, "q")          # a real host tensor
+
+
+def test_max_knots_constant_matches_the_header():
+    hdr = open(HEADER).read()
+    assert re.search(r"#define GRID_MAX_KNOTS \(1 << 24\)", hdr)
+    assert grid.GRID_MAX_KNOTS == 1 << 24
+
+
+def test_mixed_modes_reject_bad_arguments_without_a_device():
+    import ctypes as C
+    lib = grid.lib()
+    item = grid.GridMixedItem()
+    assert lib.grid_mixed_launch_mode(None, C.byref(item), 1, 0, None) == grid.GRID_EINVAL
+    assert lib.grid_mixed_tune(None, C.byref(item), 1, None, None) == grid.GRID_EINVAL
+    assert (grid.MIXED_ONE_LAUNCH, grid.MIXED_PERSISTENT, grid.MIXED_PER_ROBOT) == (0, 1, 2)
+    hdr = open(HEADER).read()
+    for name, v in (("ONE_LAUNCH", 0), ("PERSISTENT", 1), ("PER_ROBOT", 2)):
+        assert re.search(r"#define GRID_MIXED_%s %d" % (name, v), hdr)
+
+
+def test_pinned_path_rejects_bad_arguments_without_a_device():
+    import ctypes as C
+    lib = grid.lib()
+    pin, pout = C.POINTER(C.c_float)(), C.POINTER(C.c_float)()
+    assert lib.grid_workspace_host_buffers(None, C.byref(pin), C.byref(pout)) == grid.GRID_EINVAL
+    assert lib.grid_fd_grad_pinned(None, None, 4, 1, None) == grid.GRID_EINVAL

@@ -164,6 +164,41 @@ def test_host_pointer_path_matches_device_path(torch_cuda):
         ws2.fd_grad_host(kn.q, kn.qd, kn.tau)     # N > max_knots
 
 
+def test_pinned_path_matches_device_path(torch_cuda):
+    """The pinned-buffer call (inputs written in place, no pageable copies), in one piece and
+    split into overlapping pieces, gives bitwise the device path's outputs (each piece runs the
+    build picked for its own knot count, so the model is pinned to one build here)."""
+    robot, model = get_model("chain7")
+    N = 300
+    kn = synth.random_knots(robot.n, N, 35)
+    ws = grid.Workspace(model, 512)
+    try:
+        for build in (grid.BUILD_PIPE, grid.BUILD_LANE):
+            grid.tune_apply(model, {1 << 22: build})
+            dev = run_device(torch_cuda, model, kn)
+            for pieces in (1, 2, 3, 7):
+                say(f"[gpu] pinned path chain7 N={N} build {build} pieces={pieces}")
+                ins, outs = ws.host_buffers(N)
+                ins["q"][:], ins["qd"][:], ins["tau"][:] = kn.q, kn.qd, kn.tau
+                for o in outs.values():
+                    o.fill(np.nan)
+                t = ws.fd_grad_pinned(N, pieces)
+                assert t["total_ms"] > 0
+                if pieces == 1:
+                    assert t["kernel_ms"] > 0 and t["h2d_ms"] > 0 and t["d2h_ms"] > 0
+                for key in OUTS:
+                    np.testing.assert_array_equal(outs[key], dev[key])
+        with pytest.raises(grid.GridError) as e:
+            ws.fd_grad_pinned(N, 0)
+        assert e.value.status == grid.GRID_EINVAL
+        with pytest.raises(grid.GridError) as e:
+            ws.fd_grad_pinned(513, 1)
+        assert e.value.status == grid.GRID_EINVAL
+    finally:
+        grid.tune_apply(model, {})
+        ws.close()
+
+
 def test_invalid_launch_arguments(torch_cuda):
     robot, model = get_model("chain7")
     t = torch_cuda.zeros((4, 7), device="cuda")

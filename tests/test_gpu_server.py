@@ -185,4 +185,51 @@ def test_loadgen_short_run(models):
     r = srv.loadgen(5000, 0.5, [0.5, 0.3, 0.2], warmup_s=0.2)
     say(f"  {r}")
     assert r["requests"] > 1000 and 0 < r["p50_us"] <= r["p99_us"] <= r["max_us"]
+    # where the latency goes: every phase measured, each below the whole
+    assert r["requests_per_launch"] >= 1.0
+    for q in ("p50_split", "p99_split"):
+        sp = r[q]
+        assert sp["kernel_us"] > 0 and sp["h2d_us"] > 0 and sp["d2h_us"] > 0
+        assert all(0 <= v <= r["max_us"] for v in sp.values()), sp
     srv.close()
+
+
+def test_batch_window_policy(models, orc):
+    """With a batch window, requests that arrive while their model has a batch in flight wait
+    for company (up to the window or min_batch_knots) instead of taking a context each: a
+    stream from two client threads goes out in fewer launches than requests, every result
+    equals the direct launch on its knots within the parity tolerance, and a bad policy is
+    rejected."""
+    robots, ms = models
+    say("[gpu] server batch window 300 us, min fill 512 knots")
+    srv = grid.Server(ms[:2], budget_bytes=1 << 28, max_batch_knots=2048, contexts_per_model=3,
+                      batch_window_us=300, min_batch_knots=512)
+    got = []
+
+    def client(seed, count):
+        r = np.random.default_rng(seed)
+        for _ in range(count):
+            k = int(r.integers(0, 2))
+            kn = synth.random_knots(robots[k].n, int(r.integers(16, 129)), int(r.integers(1 << 30)))
+            got.append((k, kn, *srv.submit(k, kn.q, kn.qd, kn.tau)))
+
+    th = [threading.Thread(target=client, args=(s, 50)) for s in (21, 22)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    for k, kn, t, out in got:
+        srv.wait(t)
+    st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == 100 and st["launches"] < 100
+    for k, kn, t, out in got[::10]:
+        ref = orc.fd_grad_batch(robots[k], kn.q, kn.qd, kn.tau)
+        e = np.abs(out["dqdd_dq"] - ref["dqdd_dq"]).reshape(kn.N, -1).max(1) / \
+            np.abs(ref["dqdd_dq"]).reshape(kn.N, -1).max(1)
+        assert e.max() <= 1e-3
+    srv.close()
+    for bad in ({"batch_window_us": -1}, {"min_batch_knots": 4096}):
+        with pytest.raises(grid.GridError) as e:
+            grid.Server(ms[:1], budget_bytes=1 << 26, max_batch_knots=2048, **bad)
+        assert e.value.status == grid.GRID_EINVAL
