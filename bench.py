@@ -42,6 +42,15 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused.json")
 
 
+FLOPS_FILE = os.path.join(ROOT, "profiles", "flops_per_knot.json")
+
+
+def algorithmic_flops(robot: str) -> int:
+    """FLOPs per knot of the path, counted on the oracle's formulation by an instrumented
+    replay of its steps (the stored record; recomputed by the command it names)."""
+    return int(json.load(open(FLOPS_FILE))["robots"][robot]["total"])
+
+
 def measured_counters(workload: str, kernel: str, code_hash: str):
     """The committed rocprofv3 counter record (HBM bytes and VALU instructions per launch)
     for this kernel and workload, if it was taken on the same machine code (the hash of the
@@ -68,12 +77,23 @@ def parse():
                     help="bounded CPU sample for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-io", action="store_true")
-    ap.add_argument("--sweep", default="1024,16384",
+    ap.add_argument("--sweep", default="1024,16384,65536",
                     help="comma-separated extra knot counts to time (\"\" for none)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="measured seconds of the served load (0 disables serving)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
-    ap.add_argument("--serve-sweep", default="", help="extra request rates, comma-separated")
+    ap.add_argument("--serve-sweep", default="5000,10000,40000",
+                    help="extra request rates, comma-separated")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=3.0,
+                    help="measured seconds per extra rate")
+    ap.add_argument("--serve-contexts", type=int, default=2,
+                    help="batch contexts per model of the batched server")
+    ap.add_argument("--serve-window-us", type=int, default=60,
+                    help="batch window of the batched server (microseconds)")
+    ap.add_argument("--serve-min-knots", type=int, default=512,
+                    help="knots at which a waiting batch launches before its window closes")
+    ap.add_argument("--no-io-sweep", action="store_true",
+                    help="skip the per-robot batch-size sweep with host transfers")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-knot latency table (ID, Minv, FD, dID, dFD at N = 1)")
     ap.add_argument("--no-tune", action="store_true",
@@ -84,6 +104,11 @@ def parse():
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="also run a plain device copy of this size (for counter scaling)")
     return ap.parse_args()
+
+
+def progress(msg):
+    """One line per finished leg on stderr (the JSON result line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def time_steps(torch, launch, steps, warmup):
@@ -180,8 +205,10 @@ def mixed_batches(torch, grid, synth, chain_model, steps):
     quad = grid.Model(synth.quad12())
     mixed = grid.Mixed([synth.quad12(), synth.chain7()])
     out = {"workload": "quad12 + chain7 at uneven knot counts in one step (knot-evals/s over "
-                       "both robots)"}
-    for nq, nc in ((64, 37), (256, 181), (1024, 613)):
+                       "both robots)",
+           "resident_workgroups_note": "persistent: resident workgroups of the mixed kernel "
+                                       "stride over the blocks, largest branches first"}
+    for nq, nc in synth.MIXED_PLANS:
         items = []
         for m, n, NK, seed in ((quad, 12, nq, 300 + nq), (chain_model, 7, nc, 400 + nc)):
             k = synth.random_knots(n, NK, seed)
@@ -198,17 +225,87 @@ def mixed_batches(torch, grid, synth, chain_model, steps):
         graph = grid.Graph(items)
         table = [(r, *it[1:]) for r, it in enumerate(items)]   # robot 0: quad12, 1: chain7
         res = {}
-        for label, fn in (("two_calls", separate),
+        modes = [(grid.MIXED_MODES[m], mixed.launch_call(table, stream=stream, mode=m))
+                 for m in (grid.MIXED_ONE_LAUNCH, grid.MIXED_PERSISTENT, grid.MIXED_PER_ROBOT)]
+        for label, fn in [("two_calls", separate),
                           ("batch_call", lambda: grid.fd_grad_batch(items, stream=stream)),
-                          ("graph", lambda: graph.launch(stream=stream)),
-                          ("one_launch", lambda: mixed.launch(table, stream=stream))):
-            wall, _ = time_steps(torch, fn, steps, 50)
-            res[label] = {"us_per_step": round(wall * 1e6, 3),
+                          ("graph", lambda: graph.launch(stream=stream))] + modes:
+            wall, gpu = time_steps(torch, fn, steps, 50)
+            res[label] = {"us_per_step": round(wall * 1e6, 3), "gpu_us": round(gpu * 1e6, 3),
                           "knot_evals_per_s": round((nq + nc) / wall, 1)}
+        # the module's tuner times the three mixed modes and keeps one for this size
+        chosen, us = mixed.tune(table)
+        res["tuned"] = {"mode": grid.MIXED_MODES[chosen],
+                        "tuner_us": {grid.MIXED_MODES[m]: round(t, 3) for m, t in us.items()}}
         graph.close()
         out[f"{nq}+{nc}"] = res
     mixed.close()
     quad.close()
+    return out
+
+
+def io_sweep(torch, grid, synth, reps):
+    """The paper's multiple-computation sweep (Sec. V-B, Fig. 4) on each robot: per batch size,
+    the fused kernel with inputs resident in device memory (compute only), and the host call on
+    the workspace's pinned buffers split into H2D / kernel / D2H (HIP events), the same call
+    cut into overlapping pieces, and the call on pageable host arrays (staged through the
+    pinned buffers)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": "gradient of forward dynamics per robot and batch size; compute only "
+                       "(device-resident) and with host transfers"}
+    for name in ("chain7", "quad12", "humanoid30"):
+        robot = synth.model_by_name(name)
+        n = robot.n
+        m = grid.Model(robot)
+        tuned = grid.tune(m, list(synth.SWEEP_KNOTS))
+        ws = grid.Workspace(m, max(synth.SWEEP_KNOTS))
+        rows = {}
+        for N in synth.SWEEP_KNOTS:
+            kn = synth.random_knots(n, N, 500 + N)
+            ins = [torch.from_numpy(a).to(dev) for a in (kn.q, kn.qd, kn.tau)]
+            outs = [torch.empty((N, n), device=dev)] + \
+                [torch.empty((N, n, n), device=dev) for _ in range(3)]
+            call = m.fd_grad_call(*ins, *outs, stream=stream)
+            wall, gpu = time_steps(torch, call, reps, 50)
+            pin_in, _ = ws.host_buffers(N)
+            pin_in["q"][:], pin_in["qd"][:], pin_in["tau"][:] = kn.q, kn.qd, kn.tau
+            legs = {}
+            for pieces in (1, 2, 4):
+                for _ in range(10):
+                    ws.fd_grad_pinned(N, pieces)
+                acc = {"h2d_ms": 0.0, "kernel_ms": 0.0, "d2h_ms": 0.0, "total_ms": 0.0}
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    t = ws.fd_grad_pinned(N, pieces)
+                    for k in acc:
+                        acc[k] += t[k]
+                legs[pieces] = {"wall_us": (time.perf_counter() - t0) / reps * 1e6,
+                                **{k.replace("_ms", "_us"): v / reps * 1e3
+                                   for k, v in acc.items()}}
+            one = legs[1]
+            best = min(legs, key=lambda k: legs[k]["wall_us"])
+            for _ in range(10):
+                ws.fd_grad_host(kn.q, kn.qd, kn.tau)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ws.fd_grad_host(kn.q, kn.qd, kn.tau)
+            pageable = (time.perf_counter() - t0) / reps * 1e6
+            rows[str(N)] = {
+                "build": grid.BUILD_KERNELS[tuned[N]],
+                "compute_knot_evals_per_s": N / wall, "kernel_us": gpu * 1e6,
+                "alu_frac": algorithmic_flops(name) * N / gpu / 1e12 / PEAK_FP32_TFLOPS,
+                "step_us": wall * 1e6,
+                "pinned": {k: round(v, 2) for k, v in one.items()},
+                "io_share": (one["h2d_us"] + one["d2h_us"]) / one["total_us"],
+                "overlapped": {"pieces": best, "wall_us": round(legs[best]["wall_us"], 2),
+                               "device_us": round(legs[best]["total_us"], 2)},
+                "with_io_knot_evals_per_s": N / (legs[best]["wall_us"] * 1e-6),
+                "pageable_wall_us": round(pageable, 2),
+            }
+        ws.close()
+        m.close()
+        out[name] = rows
     return out
 
 
@@ -221,16 +318,31 @@ def serve(args, grid, synth, chain_model=None):
     out = {"workload": "Poisson arrivals, chain7/quad12/humanoid30 at 50/30/20 %, "
                        "N ~ U{16..256}, latency = outputs in host memory - scheduled arrival",
            "measured_s": args.serve_seconds, "warmup_s": 1.0}
-    rates = [args.serve_rate] + [float(x) for x in args.serve_sweep.split(",") if x]
+    rates = [args.serve_rate] + [float(x) for x in args.serve_sweep.split(",")
+                                 if x and float(x) != args.serve_rate]
+    out["policy"] = {"contexts_per_model": args.serve_contexts,
+                     "batch_window_us": args.serve_window_us,
+                     "min_batch_knots": args.serve_min_knots}
     for label, flags in (("batched", 0), ("per_request_plain", grid.GRID_SERVER_PER_REQUEST)):
+        batched = flags == 0
         srv = grid.Server(models, budget_bytes=1 << 30, max_batch_knots=2048,
-                          contexts_per_model=3, flags=flags)
+                          contexts_per_model=args.serve_contexts if batched else 3, flags=flags,
+                          batch_window_us=args.serve_window_us if batched else 0,
+                          min_batch_knots=args.serve_min_knots if batched else 0)
         res = {}
         for rate in rates:
-            r = srv.loadgen(rate, args.serve_seconds, probs, n_min=16, n_max=256, warmup_s=1.0,
-                            seed=7)
+            secs = args.serve_seconds if rate == args.serve_rate else args.serve_sweep_seconds
+            r = srv.loadgen(rate, secs, probs, n_min=16, n_max=256, warmup_s=1.0, seed=7)
+            progress(f"served {label} at {int(rate)} req/s: p50 {r['p50_us']:.0f} us, "
+                     f"p99 {r['p99_us']:.0f} us, {r['requests_per_launch']:.2f} requests/launch")
             res[str(int(rate))] = {"p50_us": r["p50_us"], "p90_us": r["p90_us"],
                                    "p99_us": r["p99_us"], "max_us": r["max_us"],
+                                   "requests_per_launch": round(r["requests_per_launch"], 3),
+                                   "p50_split_us": {k.replace("_us", ""): round(v, 2)
+                                                    for k, v in r["p50_split"].items()},
+                                   "p99_split_us": {k.replace("_us", ""): round(v, 2)
+                                                    for k, v in r["p99_split"].items()},
+                                   "measured_s": secs,
                                    "requests_per_s": r["requests"] / r["seconds"],
                                    "knot_evals_per_s": r["knots"] / r["seconds"]}
         res["launches"] = srv.stats()["launches"]
@@ -239,6 +351,87 @@ def serve(args, grid, synth, chain_model=None):
     for m in models[1:] + ([] if chain_model else models[:1]):
         m.close()
     return out
+
+
+def host_cpu():
+    """Host CPU model, physical cores (distinct (core, socket) pairs of lscpu) and the logical
+    CPUs this process may run on."""
+    import subprocess
+    model, phys = "", None
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True,
+                             check=True).stdout
+        phys = len({ln for ln in out.splitlines() if ln and not ln.startswith("#")})
+        info = subprocess.run(["lscpu"], capture_output=True, text=True, check=True).stdout
+        for ln in info.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.CalledProcessError):
+        pass
+    return model, phys, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(args, robot, kn, synth):
+    """The FP64 oracle (steps of the path: transforms, RNEA, CRBA, Cholesky M^-1, FD, the
+    analytic dRNEA, -M^-1 dtau) as the CPU baseline: built here with -O3 -march=native for
+    this host, OpenMP over the knots of a batch, timed with CLOCK_MONOTONIC per batch call at
+    one thread and at every CPU this job may use, on the benchmark's batch; then the same
+    multi-threaded timing for each robot at the sweep sizes."""
+    import tempfile
+    import numpy as np
+    from oracle import build as oracle_build
+    from oracle import oracle as orc
+    path = os.path.join(tempfile.mkdtemp(prefix="grid_oracle_timing_"), "liboracle_timing.so")
+    cmd = oracle_build.build_timing(path)
+    orc.use_library(path)
+    model_name, phys, avail = host_cpu()
+    threads = avail
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        threads = min(threads, int(env))
+
+    def timed(om, q, qd, tau, seconds, min_reps):
+        orc.fd_grad_batch(om, q, qd, tau)
+        times = []
+        t_end = time.monotonic() + seconds
+        while time.monotonic() < t_end or len(times) < min_reps:
+            t0 = time.monotonic()
+            orc.fd_grad_batch(om, q, qd, tau)
+            times.append(time.monotonic() - t0)
+        return float(np.mean(times)), float(np.median(times)), len(times)
+
+    om = orc.OracleModel(robot)
+    q, qd, tau = (a.astype(np.float64) for a in (kn.q, kn.qd, kn.tau))
+    N = q.shape[0]
+    legs = {}
+    for k in (1, threads):
+        orc.set_num_threads(k)
+        mean, med, reps = timed(om, q, qd, tau, args.cpu_seconds * (0.6 if k == 1 else 0.4),
+                                10)
+        legs[k] = {"knot_evals_per_s": N / mean, "mean_ms": mean * 1e3, "median_ms": med * 1e3,
+                   "batches": reps}
+    orc.set_num_threads(threads)
+    sweep = {}
+    for name in ("chain7", "quad12", "humanoid30"):
+        r = synth.model_by_name(name)
+        orm = orc.OracleModel(r)
+        for NK in synth.SWEEP_KNOTS:
+            k2 = synth.random_knots(r.n, NK, 500 + NK)
+            mean, med, reps = timed(orm, *(a.astype(np.float64) for a in (k2.q, k2.qd, k2.tau)),
+                                    0.4, 3)
+            sweep[f"{name}-N{NK}"] = {"knot_evals_per_s": NK / mean, "mean_us": mean * 1e6,
+                                      "median_us": med * 1e6}
+    return {
+        "value": legs[threads]["knot_evals_per_s"], "unit": "knot-evals/s", "cores": threads,
+        "kind": "oracle",
+        "sample": f"{legs[1]['batches']} + {legs[threads]['batches']} calls on the same "
+                  f"{N}-knot {args.robot} batch at 1 and {threads} threads, then 0.4 s per "
+                  "(robot, N) of the sweep; FP64 C oracle, OpenMP over knots",
+        "one_thread": legs[1], "all_threads": legs[threads], "sweep": sweep,
+        "host": {"cpu": model_name, "physical_cores": phys, "cpus_available": avail,
+                 "omp_num_threads_env": env or None},
+        "build": cmd.replace(path + ".tmp", "<timing build>"),
+        "timer": "CLOCK_MONOTONIC (time.monotonic) around each batch call; mean and median"}
 
 
 def main():
@@ -294,6 +487,7 @@ def main():
         if not args.no_tune:
             tuned = grid.tune(model, sorted(set([N] + sweep_ns)))
     build = grid.build_for(model, N)
+    progress(f"builds timed, tuned {tuned}")
 
     sec_per_step, kernel_s = time_steps(torch, launch, args.steps, args.warmup)
     avg_ms = kernel_s * 1e3
@@ -307,8 +501,10 @@ def main():
     plain = lambda: ws_plain.fd_grad_staged(*ins, *outs, N=N, stream=stream)
     plain_step, plain_gpu = time_steps(torch, plain, max(200, args.steps // 5), 50)
     ws_plain.close()
+    progress("headline and plain pipeline timed")
 
-    fl = flops.fdgrad_flops(robot.parent)
+    fl = {"total": algorithmic_flops(args.robot)}
+    kernel_tally = flops.fdgrad_flops(robot.parent)["total"]
     flop_launch = fl["total"] * N
     achieved_tflops = flop_launch / (avg_ms * 1e-3) / 1e12
     workload = f"{args.robot}-N{N}"
@@ -320,6 +516,9 @@ def main():
                 "traffic": traffic,
                 "kernel": grid.BUILD_KERNELS[build], "kernel_avg_us": round(avg_ms * 1e3, 3),
                 "flop_per_knot": fl["total"],
+                "flop_per_knot_source": "oracle formulation, instrumented "
+                                        "(profiles/flops_per_knot.json)",
+                "flop_per_knot_kernel_tally": kernel_tally,
                 "hbm_bytes_per_launch": flops.io_bytes_per_knot(n) * N,
                 "hbm_frac": flops.io_bytes_per_knot(n) * N / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                 "launch_floor_us": round(floor_gpu * 1e6, 3),
@@ -358,21 +557,36 @@ def main():
 
     if not args.no_io:
         ws = grid.Workspace(model, N)
+        reps = 500
+        pin_in, _ = ws.host_buffers(N)
+        pin_in["q"][:], pin_in["qd"][:], pin_in["tau"][:] = kn.q, kn.qd, kn.tau
         for _ in range(20):
-            ws.fd_grad_host(kn.q, kn.qd, kn.tau)
-        reps = 200
+            ws.fd_grad_pinned(N)
         tot = {"h2d_ms": 0.0, "kernel_ms": 0.0, "d2h_ms": 0.0, "total_ms": 0.0}
         t0 = time.perf_counter()
         for _ in range(reps):
-            _, t = ws.fd_grad_host(kn.q, kn.qd, kn.tau)
+            t = ws.fd_grad_pinned(N)
             for k in tot:
                 tot[k] += t[k]
         wall = (time.perf_counter() - t0) / reps
+        for _ in range(20):
+            ws.fd_grad_host(kn.q, kn.qd, kn.tau)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ws.fd_grad_host(kn.q, kn.qd, kn.tau)
+        wall_pageable = (time.perf_counter() - t0) / reps
         ws.close()
         result["io_inclusive"] = {
             "value": N / wall, "unit": "knot-evals/s", "wall_ms_per_call": wall * 1e3,
             **{k: v / reps for k, v in tot.items()},
-            "note": "host-pointer call: pageable->pinned staging, H2D, kernel, D2H, sync"}
+            "pageable": {"value": N / wall_pageable, "wall_ms_per_call": wall_pageable * 1e3},
+            "note": "host call on the workspace's pinned buffers: H2D, kernel, D2H, wait "
+                    "(pageable: the caller's arrays staged through them, Python binding "
+                    "included)"}
+
+    if not args.no_io_sweep:
+        result["io_sweep"] = io_sweep(torch, grid, synth, 200)
+        progress("batch-size sweep with host transfers done")
 
     if args.sweep:
         sweep = {}
@@ -386,17 +600,21 @@ def main():
                               "alu_frac": fl["total"] * NK / a / 1e12 / PEAK_FP32_TFLOPS}
             del i2, o2
         result["sweep"] = sweep
+        progress("throughput sweep done")
 
     if not args.no_single:
         if args.robot == "chain7":
             result["mixed"] = mixed_batches(torch, grid, synth, model, 1000)
+            progress("mixed batches done")
         result["autograd"] = autograd_steps(torch, grid, synth, 300)
+        progress("autograd done")
         result["single_knot_us"] = single_knot_table(torch, grid, synth, 1000)
         result["single_knot_us"]["paper_table1_gpu_us"] = PAPER_TABLE1_GPU_US
 
     # the served load runs last: timed after it, the autograd step took about 60 us longer
     if args.serve_seconds > 0:
         result["served"] = serve(args, grid, synth, model if args.robot == "chain7" else None)
+        progress("serving done")
 
     if args.copy_calibration_mb > 0:
         nbytes = int(args.copy_calibration_mb * 2**20)
@@ -408,20 +626,8 @@ def main():
         result["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}
 
     if not args.no_cpu_baseline:
-        from oracle import oracle as orc
-        om = orc.OracleModel(robot)
-        q, qd, tau = (a.astype(np.float64) for a in (kn.q, kn.qd, kn.tau))
-        orc.fd_grad_batch(om, q, qd, tau)
-        reps, t0 = 0, time.perf_counter()
-        while time.perf_counter() - t0 < args.cpu_seconds:
-            orc.fd_grad_batch(om, q, qd, tau)
-            reps += 1
-        el = time.perf_counter() - t0
-        result["cpu_baseline"] = {
-            "value": reps * N / el, "unit": "knot-evals/s", "cores": orc.num_threads(),
-            "kind": "oracle",
-            "sample": f"{reps} repetitions of the same {N}-knot {args.robot} batch "
-                      f"({el:.1f} s), FP64 C oracle, OpenMP over knots"}
+        result["cpu_baseline"] = cpu_baseline(args, robot, kn, synth)
+        progress("cpu baseline done")
 
     model.close()
     print(json.dumps(result), flush=True)
