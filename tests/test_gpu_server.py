@@ -196,33 +196,28 @@ def test_loadgen_short_run(models):
 
 def test_batch_window_policy(models, orc):
     """With a batch window, requests that arrive while their model has a batch in flight wait
-    for company (up to the window or min_batch_knots) instead of taking a context each: a
-    stream from two client threads goes out in fewer launches than requests, every result
-    equals the direct launch on its knots within the parity tolerance, and a bad policy is
-    rejected."""
+    for company (up to the window or min_batch_knots) instead of taking a free context each: a
+    burst submitted faster than batches complete goes out in far fewer launches than requests,
+    every result equals the direct launch on its knots within the parity tolerance, and a bad
+    policy is rejected."""
     robots, ms = models
-    say("[gpu] server batch window 300 us, min fill 512 knots")
-    srv = grid.Server(ms[:2], budget_bytes=1 << 28, max_batch_knots=2048, contexts_per_model=3,
+    say("[gpu] server batch window 300 us, min fill 512 knots, burst of 100 requests")
+    srv = grid.Server(ms[:2], budget_bytes=1 << 28, max_batch_knots=2048, contexts_per_model=2,
                       batch_window_us=300, min_batch_knots=512)
+    r = np.random.default_rng(21)
+    plan = []
+    for _ in range(100):
+        k = int(r.integers(0, 2))
+        plan.append((k, synth.random_knots(robots[k].n, int(r.integers(16, 129)),
+                                           int(r.integers(1 << 30)))))
     got = []
-
-    def client(seed, count):
-        r = np.random.default_rng(seed)
-        for _ in range(count):
-            k = int(r.integers(0, 2))
-            kn = synth.random_knots(robots[k].n, int(r.integers(16, 129)), int(r.integers(1 << 30)))
-            got.append((k, kn, *srv.submit(k, kn.q, kn.qd, kn.tau)))
-
-    th = [threading.Thread(target=client, args=(s, 50)) for s in (21, 22)]
-    for x in th:
-        x.start()
-    for x in th:
-        x.join()
+    for k, kn in plan:                       # inputs made beforehand: the submits come in a burst
+        got.append((k, kn, *srv.submit(k, kn.q, kn.qd, kn.tau)))
     for k, kn, t, out in got:
         srv.wait(t)
     st = srv.stats()
     say(f"  stats {st}")
-    assert st["completed"] == 100 and st["launches"] < 100
+    assert st["completed"] == 100 and st["launches"] <= 60, st
     for k, kn, t, out in got[::10]:
         ref = orc.fd_grad_batch(robots[k], kn.q, kn.qd, kn.tau)
         e = np.abs(out["dqdd_dq"] - ref["dqdd_dq"]).reshape(kn.N, -1).max(1) / \
