@@ -221,6 +221,25 @@ grid_status grid_fd_grad_staged(grid_model m, grid_workspace ws, int32_t N, cons
                                 float* dqdd_dq, float* dqdd_dqd, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): grid_fd_grad_staged without a workspace. The five
+ * stage kernels keep their intermediates in the library's own static device array of
+ * GRID_NOALLOC_SCRATCH_BYTES (one per device, held until the process ends; its address is
+ * taken when the first model on that device is created). The call allocates nothing. Same
+ * arguments, layouts and results as grid_fd_grad_staged (bit for bit), asynchronous on
+ * `stream`. The array is shared by every call on the device and keeps the last call's
+ * contents: calls that overlap in time on one device race and must be ordered by the caller
+ * (one stream, or events). Errors: EINVAL (NULL model, N < 0, a NULL data pointer with N > 0,
+ * N times the model's per-knot scratch above GRID_NOALLOC_SCRATCH_BYTES; the message states
+ * the limit in knots), EDEVICE.
+ */
+#define GRID_NOALLOC_SCRATCH_BYTES (16u << 20)
+grid_status grid_fd_grad_staged_noalloc(grid_model m, int32_t N, const float* q,
+                                        const float* qd, const float* tau, float* qdd,
+                                        float* Minv, float* dqdd_dq, float* dqdd_dqd,
+                                        void* stream);
+
+/*
  * Code generation without a device: write the generated HIP source for a model (its
  * topology as compile-time structures, its constants as float literals) into buf (len
  * in: capacity, out: bytes needed including the terminating NUL; buf may be NULL to

@@ -153,6 +153,11 @@ hipError_t launch_vjp(int nknots, int n, const float* dq, const float* dqd, cons
 hipError_t launch_dt(int nknots, int n, float dt, const float* dq, const float* dqd,
                      const float* Minv, float* A, float* B, hipStream_t stream);
 
+// the library's static scratch array (grid_noalloc.hip): its device address on `device`, taken
+// once with that device current; noalloc_scratch returns it (NULL before the setup)
+grid_status noalloc_setup(int device, std::string* err);
+float* noalloc_scratch(int device);
+
 }  // namespace grid_impl
 
 struct grid_model_s {

@@ -533,6 +533,10 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
         return fail(GRID_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName +
                                            ", kernels are built for gfx950");
 
+    s = noalloc_setup(device, &err);   // once per device: the scratch array's address
+    if (s != GRID_OK)
+        return fail(s, err);
+
     grid_model m = new (std::nothrow) grid_model_s;
     if (!m)
         return fail(GRID_ENOMEM, "host allocation failed");
@@ -721,6 +725,36 @@ grid_status grid_fd_grad_staged(grid_model m, grid_workspace w, int32_t N, const
         return fail(GRID_EINVAL, "a data pointer is NULL");
     HIP_TRY(hipSetDevice(m->device));
     return launch_staged(m, w->d_stage, N, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd,
+                         (hipStream_t)stream);
+}
+
+grid_status grid_fd_grad_staged_noalloc(grid_model m, int32_t N, const float* q,
+                                        const float* qd, const float* tau, float* qdd,
+                                        float* Minv, float* dqdd_dq, float* dqdd_dqd,
+                                        void* stream)
+{
+    if (!m)
+        return fail(GRID_EINVAL, "model is NULL");
+    if (N < 0)
+        return fail(GRID_EINVAL, "N must be >= 0");
+    const size_t per_knot = (size_t)workspace_layout(m->topo).stride * sizeof(float);
+    if ((size_t)N * per_knot > (size_t)GRID_NOALLOC_SCRATCH_BYTES)
+        return fail(GRID_EINVAL, "N = " + std::to_string(N) + " needs " +
+                                     std::to_string((size_t)N * per_knot) +
+                                     " bytes of scratch; the static array holds " +
+                                     std::to_string((size_t)GRID_NOALLOC_SCRATCH_BYTES) +
+                                     " (at most " +
+                                     std::to_string(GRID_NOALLOC_SCRATCH_BYTES / per_knot) +
+                                     " knots of this model)");
+    if (N == 0)
+        return GRID_OK;
+    if (!q || !qd || !tau || !qdd || !Minv || !dqdd_dq || !dqdd_dqd)
+        return fail(GRID_EINVAL, "a data pointer is NULL");
+    float* work = noalloc_scratch(m->device);
+    if (!work)
+        return fail(GRID_EDEVICE, "the scratch array of this device has no address");
+    HIP_TRY(hipSetDevice(m->device));
+    return launch_staged(m, work, N, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd,
                          (hipStream_t)stream);
 }
 

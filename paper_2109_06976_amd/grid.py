@@ -25,6 +25,7 @@ GRID_ECOMPILE = -5
 GRID_EBUSY = -6
 GRID_ETIMEDOUT = -7
 GRID_ECANCELED = -8
+GRID_NOALLOC_SCRATCH_BYTES = 16 << 20
 GRID_MAX_KNOTS = 1 << 24      # the largest N of one call
 GRID_SERVER_PER_REQUEST = 1
 GRID_CODEGEN_PIPE_MODULE = 1 << 16
@@ -110,6 +111,8 @@ _SIGS = {
     "grid_fd_vjp": (C.c_int32, [C.c_void_p, C.c_int32] + [C.c_void_p] * 7 + [C.c_void_p]),
     "grid_fd_grad_staged": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32] + [C.c_void_p] * 7 +
                             [C.c_void_p]),
+    "grid_fd_grad_staged_noalloc": (C.c_int32, [C.c_void_p, C.c_int32] + [C.c_void_p] * 7 +
+                                    [C.c_void_p]),
     "grid_workspace_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "grid_fd_grad_batch": (C.c_int32, [C.POINTER(GridItem), C.c_int32, C.c_void_p]),
     "grid_graph_create": (C.c_int32, [C.POINTER(GridItem), C.c_int32, C.POINTER(C.c_void_p)]),
@@ -309,6 +312,16 @@ class Model:
         ptrs = _fd_grad_ptrs(N, self.n, self.device, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd)
         _check(lib().grid_fd_grad(self._h, int(N), *ptrs, _stream_handle(stream)))
 
+
+    def fd_grad_staged_noalloc(self, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, N=None,
+                               stream=None):
+        """grid_fd_grad_staged_noalloc: the five-launch pipeline with its intermediates in the
+        library's static scratch array (no allocation; calls on one device must not overlap)."""
+        if N is None:
+            N = int(q.shape[0])
+        ptrs = _fd_grad_ptrs(N, self.n, self.device, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd)
+        _check(lib().grid_fd_grad_staged_noalloc(self._h, int(N), *ptrs,
+                                                 _stream_handle(stream)))
 
     def fd_grad_call(self, q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd, N=None, stream=None):
         """grid_fd_grad bound to fixed device buffers: returns a callable that makes the call.
