@@ -13,7 +13,8 @@ Also reported (extra fields of the same line):
                 from HIP-event kernel durations measured here;
   builds        each build of the fused kernel at this N, and the autotuner's choices
                 (the timed steps run the tuned build);
-  io_inclusive  the host-pointer call (pinned staging, H2D + kernel + D2H);
+  io_inclusive  the host call on pinned buffers (H2D + kernel + D2H by copy engines; the
+                mapped call with no copy engines; the pageable-array call);
   served        p50/p99 latency and throughput of an open-loop Poisson request stream
                 (20k req/s over the three robots) through the continuous-batching
                 server, and through one plain staged launch per request;
@@ -96,6 +97,10 @@ def parse():
                     help="skip the per-robot batch-size sweep with host transfers")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-knot latency table (ID, Minv, FD, dID, dFD at N = 1)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-batch leg (quad12 + chain7 in one step)")
+    ap.add_argument("--no-autograd", action="store_true",
+                    help="skip the autograd leg (humanoid forward + backward)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (untuned build choice)")
     ap.add_argument("--build", type=int, default=-1,
@@ -197,9 +202,11 @@ def autograd_steps(torch, grid, synth, steps):
 
 
 def mixed_batches(torch, grid, synth, chain_model, steps):
-    """Quad12 and chain7 batches at uneven knot counts in one step, issued four ways: two
-    fd_grad calls, one grid_fd_grad_batch call, the mixed batch captured as one hipGraph
-    and launched, and one kernel launch of a module holding both robots (grid_mixed)."""
+    """Quad12 and chain7 batches at uneven knot counts in one step, issued several ways: two
+    fd_grad calls, one grid_fd_grad_batch call, the items' kernels captured as one hipGraph,
+    the module holding both robots (grid_mixed) in each of its three modes (one launch,
+    persistent, per robot), and its one-launch and persistent launches captured in a
+    hipGraph; then the module's tuner's choice."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     quad = grid.Model(synth.quad12())
@@ -227,6 +234,11 @@ def mixed_batches(torch, grid, synth, chain_model, steps):
         res = {}
         modes = [(grid.MIXED_MODES[m], mixed.launch_call(table, stream=stream, mode=m))
                  for m in (grid.MIXED_ONE_LAUNCH, grid.MIXED_PERSISTENT, grid.MIXED_PER_ROBOT)]
+        # one mixed launch (one-launch and persistent forms) captured in a hipGraph
+        mgraphs = {m: mixed.graph(table, mode=m)
+                   for m in (grid.MIXED_ONE_LAUNCH, grid.MIXED_PERSISTENT)}
+        modes += [("graph_" + grid.MIXED_MODES[m], g.launch_call(stream=stream))
+                  for m, g in mgraphs.items()]
         for label, fn in [("two_calls", separate),
                           ("batch_call", lambda: grid.fd_grad_batch(items, stream=stream)),
                           ("graph", lambda: graph.launch(stream=stream))] + modes:
@@ -238,6 +250,8 @@ def mixed_batches(torch, grid, synth, chain_model, steps):
         res["tuned"] = {"mode": grid.MIXED_MODES[chosen],
                         "tuner_us": {grid.MIXED_MODES[m]: round(t, 3) for m, t in us.items()}}
         graph.close()
+        for g in mgraphs.values():
+            g.close()
         out[f"{nq}+{nc}"] = res
     mixed.close()
     quad.close()
@@ -248,8 +262,9 @@ def io_sweep(torch, grid, synth, reps):
     """The paper's multiple-computation sweep (Sec. V-B, Fig. 4) on each robot: per batch size,
     the fused kernel with inputs resident in device memory (compute only), and the host call on
     the workspace's pinned buffers split into H2D / kernel / D2H (HIP events), the same call
-    cut into overlapping pieces, and the call on pageable host arrays (staged through the
-    pinned buffers)."""
+    cut into overlapping pieces, the mapped call (no copy engines: the kernel reads the pinned
+    inputs, a copy kernel or the fused kernel itself writes the pinned outputs), and the call on
+    pageable host arrays (staged through the pinned buffers)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     out = {"workload": "gradient of forward dynamics per robot and batch size; compute only "
@@ -283,8 +298,28 @@ def io_sweep(torch, grid, synth, reps):
                 legs[pieces] = {"wall_us": (time.perf_counter() - t0) / reps * 1e6,
                                 **{k.replace("_ms", "_us"): v / reps * 1e3
                                    for k, v in acc.items()}}
+            # no copy engines: the kernel reads the pinned inputs through the device mapping,
+            # the outputs go out by a copy kernel or by the fused kernel's own stores
+            # (wall time of untimed calls; device phases from timed calls)
+            mapped = {}
+            for label, mode in (("copy_kernel", grid.IO_COPY_KERNEL), ("direct", grid.IO_DIRECT)):
+                for _ in range(10):
+                    ws.fd_grad_mapped(N, mode, timed=False)
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    ws.fd_grad_mapped(N, mode, timed=False)
+                w_m = (time.perf_counter() - t0) / reps
+                acc = {"kernel_ms": 0.0, "d2h_ms": 0.0, "total_ms": 0.0}
+                for _ in range(reps):
+                    t = ws.fd_grad_mapped(N, mode)
+                    for k in acc:
+                        acc[k] += t[k]
+                mapped[label] = {"wall_us": round(w_m * 1e6, 2),
+                                 **{k.replace("_ms", "_us").replace("d2h", "copy"):
+                                    round(v / reps * 1e3, 2) for k, v in acc.items()}}
             one = legs[1]
             best = min(legs, key=lambda k: legs[k]["wall_us"])
+            best_mapped = min(mapped, key=lambda k: mapped[k]["wall_us"])
             for _ in range(10):
                 ws.fd_grad_host(kn.q, kn.qd, kn.tau)
             t0 = time.perf_counter()
@@ -301,6 +336,8 @@ def io_sweep(torch, grid, synth, reps):
                 "overlapped": {"pieces": best, "wall_us": round(legs[best]["wall_us"], 2),
                                "device_us": round(legs[best]["total_us"], 2)},
                 "with_io_knot_evals_per_s": N / (legs[best]["wall_us"] * 1e-6),
+                "mapped": mapped,
+                "mapped_knot_evals_per_s": N / (mapped[best_mapped]["wall_us"] * 1e-6),
                 "pageable_wall_us": round(pageable, 2),
             }
         ws.close()
@@ -323,14 +360,20 @@ def serve(args, grid, synth, chain_model=None):
     out["policy"] = {"contexts_per_model": args.serve_contexts,
                      "batch_window_us": args.serve_window_us,
                      "min_batch_knots": args.serve_min_knots}
-    for label, flags in (("batched", 0), ("per_request_plain", grid.GRID_SERVER_PER_REQUEST)):
-        batched = flags == 0
+    # batched: fused launches reading and writing the pinned staging through the device mapping;
+    # batched_copy_engines: the same with H2D / D2H copies (at the headline rate only);
+    # per_request_plain: one staged launch per request with ordinary copies (the baseline)
+    for label, flags, lrates in (
+            ("batched", grid.GRID_SERVER_MAPPED_IO, rates),
+            ("batched_copy_engines", 0, rates[:1]),
+            ("per_request_plain", grid.GRID_SERVER_PER_REQUEST, rates)):
+        batched = not flags & grid.GRID_SERVER_PER_REQUEST
         srv = grid.Server(models, budget_bytes=1 << 30, max_batch_knots=2048,
                           contexts_per_model=args.serve_contexts if batched else 3, flags=flags,
                           batch_window_us=args.serve_window_us if batched else 0,
                           min_batch_knots=args.serve_min_knots if batched else 0)
         res = {}
-        for rate in rates:
+        for rate in lrates:
             secs = args.serve_seconds if rate == args.serve_rate else args.serve_sweep_seconds
             r = srv.loadgen(rate, secs, probs, n_min=16, n_max=256, warmup_s=1.0, seed=7)
             progress(f"served {label} at {int(rate)} req/s: p50 {r['p50_us']:.0f} us, "
@@ -569,6 +612,21 @@ def main():
             for k in tot:
                 tot[k] += t[k]
         wall = (time.perf_counter() - t0) / reps
+        mapped = {}
+        for label, mode in (("copy_kernel", grid.IO_COPY_KERNEL), ("direct", grid.IO_DIRECT)):
+            for _ in range(20):
+                ws.fd_grad_mapped(N, mode, timed=False)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ws.fd_grad_mapped(N, mode, timed=False)
+            w_m = (time.perf_counter() - t0) / reps      # untimed calls
+            acc = {"kernel_ms": 0.0, "d2h_ms": 0.0, "total_ms": 0.0}
+            for _ in range(reps):
+                t = ws.fd_grad_mapped(N, mode)
+                for k in acc:
+                    acc[k] += t[k]
+            mapped[label] = {"value": N / w_m, "wall_ms_per_call": w_m * 1e3,
+                             **{k.replace("d2h", "copy"): v / reps for k, v in acc.items()}}
         for _ in range(20):
             ws.fd_grad_host(kn.q, kn.qd, kn.tau)
         t0 = time.perf_counter()
@@ -579,6 +637,7 @@ def main():
         result["io_inclusive"] = {
             "value": N / wall, "unit": "knot-evals/s", "wall_ms_per_call": wall * 1e3,
             **{k: v / reps for k, v in tot.items()},
+            "mapped": mapped,
             "pageable": {"value": N / wall_pageable, "wall_ms_per_call": wall_pageable * 1e3},
             "note": "host call on the workspace's pinned buffers: H2D, kernel, D2H, wait "
                     "(pageable: the caller's arrays staged through them, Python binding "
@@ -603,11 +662,12 @@ def main():
         progress("throughput sweep done")
 
     if not args.no_single:
-        if args.robot == "chain7":
+        if args.robot == "chain7" and not args.no_mixed:
             result["mixed"] = mixed_batches(torch, grid, synth, model, 1000)
             progress("mixed batches done")
-        result["autograd"] = autograd_steps(torch, grid, synth, 300)
-        progress("autograd done")
+        if not args.no_autograd:
+            result["autograd"] = autograd_steps(torch, grid, synth, 300)
+            progress("autograd done")
         result["single_knot_us"] = single_knot_table(torch, grid, synth, 1000)
         result["single_knot_us"]["paper_table1_gpu_us"] = PAPER_TABLE1_GPU_US
 

@@ -209,6 +209,26 @@ grid_status grid_fd_grad_pinned(grid_model m, grid_workspace ws, int32_t N, int3
                                 grid_timing* timing);
 
 /*
+ * The host call on the workspace's pinned buffers without copy-engine transfers (the I/O of
+ * Sec. V-B as part of the device work): the fused kernel reads q, qd, tau of N knots from the
+ * pinned input buffer through the device's mapping of it, and the outputs reach the pinned
+ * output buffer (layouts as in grid_workspace_host_buffers) either
+ *   GRID_IO_COPY_KERNEL  through the workspace's device buffer and one copy kernel with 16-byte
+ *                        stores into the mapping, or
+ *   GRID_IO_DIRECT       straight from the fused kernel's own stores into the mapping.
+ * Waits for the results. timing (may be NULL: no events are then recorded): kernel_ms = the
+ * fused kernel with its input reads, d2h_ms = the copy kernel (0 for DIRECT), total_ms = both;
+ * h2d_ms = 0. Results equal
+ * grid_fd_grad's on the same inputs bit for bit. Errors: EINVAL (NULL, a workspace of another
+ * model, N > its max_knots, an unknown mode), EUNSUPPORTED (the runtime maps no pinned buffer
+ * into the device's address space), EDEVICE.
+ */
+#define GRID_IO_COPY_KERNEL 0
+#define GRID_IO_DIRECT 1
+grid_status grid_fd_grad_mapped(grid_model m, grid_workspace ws, int32_t N, int32_t out_mode,
+                                grid_timing* timing);
+
+/*
  * The plain staged pipeline, for comparison with the fused launch: the same steps in
  * five launches on `stream` (transforms + RNEA -> c; M and its factor -> M^-1;
  * qdd; RNEA at qdd + dRNEA -> dtau/du; -M^-1 dtau/du), each intermediate going through
@@ -350,6 +370,20 @@ grid_status grid_mixed_launch_mode(grid_mixed mx, const grid_mixed_item* items, 
                                    int32_t mode, void* stream);
 
 /*
+ * One mixed launch captured in a hipGraph (the uneven mix of robots and knot counts as one
+ * replayable launch): `mode` as above, or -1 for the mode grid_mixed_launch picks for this
+ * batch size at capture time. The result is a grid_graph: replay it with grid_graph_launch,
+ * free it with grid_graph_destroy (before the mixed module). grid_mixed_graph_update
+ * re-captures it for other items (any count 1..16; the executable is updated in place or
+ * re-instantiated). Outputs equal those of grid_mixed_launch_mode in the same mode. Errors: as
+ * grid_mixed_launch, EINVAL for an unknown mode, or for grid_mixed_graph_update on a graph
+ * that grid_graph_create made (and grid_graph_update on one made here), EDEVICE.
+ */
+grid_status grid_mixed_graph_create(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                                    int32_t mode, grid_graph* out);
+grid_status grid_mixed_graph_update(grid_graph g, const grid_mixed_item* items, int32_t count);
+
+/*
  * Time the three modes on these items (3 warm-up and 20 timed launches per trial, median of
  * 5 trials, HIP events on a stream of the library's; the items' outputs are written) and keep
  * the fastest for launches of this size: from then on grid_mixed_launch runs a batch of B
@@ -474,12 +508,16 @@ grid_status grid_build_for(grid_model m, int32_t N, int32_t* build);
 typedef struct grid_server_s* grid_server;
 
 #define GRID_SERVER_PER_REQUEST 1   /* baseline: one staged (plain) launch per request */
+/* Batches read their inputs from, and write their outputs to, the contexts' pinned staging
+ * through the device's mapping of it (no copy-engine H2D and D2H; as grid_fd_grad_mapped with
+ * GRID_IO_DIRECT). The loadgen's H2D and D2H phases are then empty. */
+#define GRID_SERVER_MAPPED_IO 2
 
 typedef struct grid_server_config {
     size_t device_budget_bytes;  /* admission budget of in-flight request bytes (inputs+outputs) */
     int32_t max_batch_knots;     /* knots per launch, >= the largest request */
     int32_t contexts_per_model;  /* batch contexts (streams) per model, >= 1 */
-    uint32_t flags;              /* 0 or GRID_SERVER_PER_REQUEST */
+    uint32_t flags;              /* 0, or GRID_SERVER_PER_REQUEST and/or GRID_SERVER_MAPPED_IO */
     /* Batching policy. While a model has no batch in flight, its admitted requests launch as
      * soon as a context is free. While one is in flight, the next batch of that model waits
      * until it holds min_batch_knots knots or its oldest request has waited batch_window_us

@@ -58,6 +58,7 @@ def build_library(verbose=False) -> str:
            os.path.join(CSRC, "grid_runtime.cpp"), os.path.join(CSRC, "grid_codegen.cpp"),
            os.path.join(CSRC, "grid_vjp.hip"), os.path.join(CSRC, "grid_server.cpp"),
            os.path.join(CSRC, "grid_batch.cpp"), os.path.join(CSRC, "grid_noalloc.hip"),
+           os.path.join(CSRC, "grid_io.hip"),
            "-lhiprtc", "-lpthread", "-o", LIB + ".tmp"]
     _run(cmd, verbose)
     os.replace(LIB + ".tmp", LIB)

@@ -54,6 +54,8 @@ grid_status check_items(const grid_item* items, int32_t count)
 struct grid_graph_s {
     int device = 0;
     int count = 0;
+    grid_mixed mx = nullptr;    // a graph of one mixed launch (grid_mixed_graph_create)
+    int mode = -1;              // its launch mode (-1: the tuned one at each capture)
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -61,18 +63,15 @@ struct grid_graph_s {
 
 namespace {
 
-// the items' kernels in sequence on the capture stream: a chain of kernel nodes. (A first
-// version forked every item onto a side stream so that the nodes had no edges between them;
-// on ROCm 7.2 launching that graph took 39 us of host time for two nodes, the chain 14 us.)
-grid_status capture(grid_graph g, const grid_item* items, int32_t count, hipGraph_t* out)
+// `issue` enqueues the graph's work on the capture stream. The items' kernels in sequence
+// make a chain of kernel nodes. (A first version forked every item onto a side stream so that
+// the nodes had no edges between them; on ROCm 7.2 launching that graph took 39 us of host
+// time for two nodes, the chain 14 us.)
+template <class Issue>
+grid_status capture_with(grid_graph g, Issue issue, hipGraph_t* out)
 {
     HIP_TRY(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
-    grid_status st = GRID_OK;
-    for (int k = 0; k < count && st == GRID_OK; ++k)
-        if (items[k].N > 0)
-            st = launch_fused(items[k].model, items[k].N, items[k].q, items[k].qd, items[k].tau,
-                              items[k].qdd, items[k].Minv, items[k].dqdd_dq, items[k].dqdd_dqd,
-                              g->capture);
+    grid_status st = issue(g->capture);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(g->capture, &graph);
     if (st != GRID_OK) {
@@ -86,6 +85,42 @@ grid_status capture(grid_graph g, const grid_item* items, int32_t count, hipGrap
         return fail(GRID_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
     }
     *out = graph;
+    return GRID_OK;
+}
+
+grid_status capture(grid_graph g, const grid_item* items, int32_t count, hipGraph_t* out)
+{
+    return capture_with(g, [&](hipStream_t s) {
+        grid_status st = GRID_OK;
+        for (int k = 0; k < count && st == GRID_OK; ++k)
+            if (items[k].N > 0)
+                st = launch_fused(items[k].model, items[k].N, items[k].q, items[k].qd,
+                                  items[k].tau, items[k].qdd, items[k].Minv, items[k].dqdd_dq,
+                                  items[k].dqdd_dqd, s);
+        return st;
+    }, out);
+}
+
+// replace the graph's executable by one of `fresh`: updated in place, or re-instantiated if
+// the update is refused; takes ownership of `fresh`
+grid_status swap_in(grid_graph g, hipGraph_t fresh)
+{
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res;
+    if (hipGraphExecUpdate(g->exec, fresh, &err_node, &res) != hipSuccess ||
+        res != hipGraphExecUpdateSuccess) {
+        (void)hipGetLastError();
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipGraphInstantiate(&exec, fresh, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(fresh);
+            return fail(GRID_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        (void)hipGraphExecDestroy(g->exec);
+        g->exec = exec;
+    }
+    (void)hipGraphDestroy(g->graph);
+    g->graph = fresh;
     return GRID_OK;
 }
 
@@ -171,6 +206,8 @@ grid_status grid_graph_update(grid_graph g, const grid_item* items, int32_t coun
     grid_status st = check_items(items, count);
     if (st != GRID_OK)
         return st;
+    if (g->mx)
+        return fail(GRID_EINVAL, "a graph of a mixed launch is updated by grid_mixed_graph_update");
     if (count != g->count || items[0].model->device != g->device)
         return fail(GRID_EINVAL, "an update keeps the item count and the device");
     HIP_TRY(hipSetDevice(g->device));
@@ -178,23 +215,7 @@ grid_status grid_graph_update(grid_graph g, const grid_item* items, int32_t coun
     st = capture(g, items, count, &fresh);
     if (st != GRID_OK)
         return st;
-    hipGraphNode_t err_node = nullptr;
-    hipGraphExecUpdateResult res;
-    if (hipGraphExecUpdate(g->exec, fresh, &err_node, &res) != hipSuccess ||
-        res != hipGraphExecUpdateSuccess) {
-        (void)hipGetLastError();
-        hipGraphExec_t exec = nullptr;
-        hipError_t e = hipGraphInstantiate(&exec, fresh, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(fresh);
-            return fail(GRID_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        }
-        (void)hipGraphExecDestroy(g->exec);
-        g->exec = exec;
-    }
-    (void)hipGraphDestroy(g->graph);
-    g->graph = fresh;
-    return GRID_OK;
+    return swap_in(g, fresh);
 }
 
 grid_status grid_graph_destroy(grid_graph g)
@@ -214,7 +235,7 @@ grid_status grid_graph_destroy(grid_graph g)
 // the block is passed by value as the kernel's only argument: its host layout must be the
 // device one (ints, then 8-byte aligned argument blocks of the same field order)
 static_assert(sizeof(KernelArgs) == 72, "Args: an int and eight pointers");
-static_assert(offsetof(MixedArgs, item) == 8 + 3 * 4 * kMixedSegs &&
+static_assert(offsetof(MixedArgs, item) == 8 + 5 * 4 * kMixedSegs &&
                   sizeof(MixedArgs) == offsetof(MixedArgs, item) + kMixedItems * sizeof(KernelArgs),
               "MixedArgs layout");
 
@@ -364,11 +385,13 @@ grid_status grid_mixed_create(const grid_model_desc* descs, int32_t count, int32
 namespace {
 
 // Checks the items and builds the segment table of a launch: one segment per (item, branch)
-// with knots, each with its first block. In item order for one workgroup per block; for the
-// persistent form ordered by the branch's bodies, largest first, so that the longest blocks
-// start in the first wave of resident workgroups. *blocks: the blocks of the launch.
+// with knots, each with its first workgroup, its blocks and its workgroups. One workgroup per
+// block: in item order. Persistent (`resident` > 0): ordered by the branch's bodies, largest
+// first, and the resident workgroups (at most one per block) shared among the segments in
+// proportion to their blocks times a per-block cost of (bodies + 4), at least one each.
+// *blocks: the blocks of the launch; *wgs: its workgroups.
 grid_status mixed_args(grid_mixed mx, const grid_mixed_item* items, int32_t count,
-                       bool by_cost, MixedArgs* a, int64_t* blocks)
+                       int64_t resident, MixedArgs* a, int64_t* blocks, int64_t* wgs = nullptr)
 {
     if (!mx)
         return fail(GRID_EINVAL, "mixed module is NULL");
@@ -411,21 +434,59 @@ grid_status mixed_args(grid_mixed mx, const grid_mixed_item* items, int32_t coun
             segs.push_back(Seg{mx->inst_base[it.robot] + (int)b, j, B, (it.N + P - 1) / P});
         }
     }
-    if (by_cost)
+    const bool pers = resident > 0;
+    if (pers)
         std::stable_sort(segs.begin(), segs.end(),
                          [](const Seg& x, const Seg& y) { return x.B > y.B; });
     int64_t total = 0;
-    for (const Seg& g : segs) {
-        a->seg_start[a->nseg] = (int)total;
-        a->seg_inst[a->nseg] = g.inst;
-        a->seg_item[a->nseg] = g.item;
-        ++a->nseg;
+    for (const Seg& g : segs)
         total += g.nb;
-    }
     if (total > INT32_MAX)
         return fail(GRID_EINVAL, "too many knots in one launch");
+    std::vector<int64_t> w(segs.size());
+    for (size_t k = 0; k < segs.size(); ++k)
+        w[k] = segs[k].nb;
+    if (pers && total > 0) {
+        const int64_t W = std::min<int64_t>(total, resident);
+        double cost = 0;
+        for (const Seg& g : segs)
+            cost += (double)g.nb * (g.B + 4);
+        int64_t used = 0;
+        for (size_t k = 0; k < segs.size(); ++k) {
+            const double share = (double)W * segs[k].nb * (segs[k].B + 4) / cost;
+            w[k] = std::max<int64_t>(1, std::min<int64_t>(segs[k].nb, (int64_t)share));
+            used += w[k];
+        }
+        // the rest of the resident workgroups to the segments with the most cost per workgroup
+        for (; used < W; ++used) {
+            size_t best = segs.size();
+            double most = 0;
+            for (size_t k = 0; k < segs.size(); ++k) {
+                const double per = (double)segs[k].nb * (segs[k].B + 4) / (double)w[k];
+                if (w[k] < segs[k].nb && per > most) {
+                    most = per;
+                    best = k;
+                }
+            }
+            if (best == segs.size())
+                break;
+            ++w[best];
+        }
+    }
+    int64_t start = 0;
+    for (size_t k = 0; k < segs.size(); ++k) {
+        a->seg_start[a->nseg] = (int)start;
+        a->seg_inst[a->nseg] = segs[k].inst;
+        a->seg_item[a->nseg] = segs[k].item;
+        a->seg_blocks[a->nseg] = (int)segs[k].nb;
+        a->seg_wgs[a->nseg] = (int)w[k];
+        ++a->nseg;
+        start += w[k];
+    }
     a->nblocks = (int)total;
     *blocks = total;
+    if (wgs)
+        *wgs = start;
     return GRID_OK;
 }
 
@@ -435,8 +496,9 @@ grid_status mixed_launch_mode(grid_mixed mx, const grid_mixed_item* items, int32
     if (mode < GRID_MIXED_ONE_LAUNCH || mode > GRID_MIXED_PER_ROBOT)
         return fail(GRID_EINVAL, "unknown mixed launch mode " + std::to_string(mode));
     MixedArgs a;
-    int64_t blocks = 0;
-    grid_status st = mixed_args(mx, items, count, mode == GRID_MIXED_PERSISTENT, &a, &blocks);
+    int64_t blocks = 0, wgs = 0;
+    const bool pers = mode == GRID_MIXED_PERSISTENT;
+    grid_status st = mixed_args(mx, items, count, pers ? mx->resident : 0, &a, &blocks, &wgs);
     if (st != GRID_OK)
         return st;
     if (blocks == 0)
@@ -454,8 +516,7 @@ grid_status mixed_launch_mode(grid_mixed mx, const grid_mixed_item* items, int32
         }
         return GRID_OK;
     }
-    const bool pers = mode == GRID_MIXED_PERSISTENT;
-    const unsigned grid = (unsigned)(pers ? std::min<int64_t>(blocks, mx->resident) : blocks);
+    const unsigned grid = (unsigned)wgs;
     void* params[] = {&a};   // the kernel takes one argument: the MixedArgs block
     HIP_TRY(hipModuleLaunchKernel(pers ? mx->fn_persistent : mx->fn, grid, 1, 1,
                                   64u * (unsigned)mx->waves, 1, 1, 0, stream, params, nullptr));
@@ -471,6 +532,16 @@ int mixed_mode_for(grid_mixed mx, int64_t blocks)
     return mx->tuned.empty() ? GRID_MIXED_ONE_LAUNCH : mx->tuned.back().second;
 }
 
+// the launch a mixed graph records: `mode`, or the tuned mode for this many blocks (-1); an
+// empty batch records nothing (the graph then has no nodes)
+grid_status mixed_capture_launch(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                                 int mode, int64_t blocks, hipStream_t s)
+{
+    if (blocks == 0)
+        return GRID_OK;
+    return mixed_launch_mode(mx, items, count, mode >= 0 ? mode : mixed_mode_for(mx, blocks), s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -480,7 +551,7 @@ grid_status grid_mixed_launch(grid_mixed mx, const grid_mixed_item* items, int32
 {
     MixedArgs a;
     int64_t blocks = 0;
-    grid_status st = mixed_args(mx, items, count, false, &a, &blocks);
+    grid_status st = mixed_args(mx, items, count, 0, &a, &blocks);
     if (st != GRID_OK)
         return st;
     if (blocks == 0)
@@ -494,12 +565,76 @@ grid_status grid_mixed_launch_mode(grid_mixed mx, const grid_mixed_item* items, 
     return mixed_launch_mode(mx, items, count, mode, (hipStream_t)stream);
 }
 
+grid_status grid_mixed_graph_create(grid_mixed mx, const grid_mixed_item* items, int32_t count,
+                                    int32_t mode, grid_graph* out)
+{
+    if (!out)
+        return fail(GRID_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (mode < -1 || mode > GRID_MIXED_PER_ROBOT)
+        return fail(GRID_EINVAL, "unknown mixed launch mode " + std::to_string(mode));
+    MixedArgs a;
+    int64_t blocks = 0;
+    grid_status st = mixed_args(mx, items, count, 0, &a, &blocks);
+    if (st != GRID_OK)
+        return st;
+    HIP_TRY(hipSetDevice(mx->device));
+    grid_graph g = new (std::nothrow) grid_graph_s;
+    if (!g)
+        return fail(GRID_ENOMEM, "host allocation failed");
+    g->device = mx->device;
+    g->count = count;
+    g->mx = mx;
+    g->mode = mode;
+    hipError_t e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        destroy_graph(g);
+        return fail(GRID_EDEVICE, std::string("graph stream: ") + hipGetErrorString(e));
+    }
+    st = capture_with(g, [&](hipStream_t s) {
+        return mixed_capture_launch(mx, items, count, g->mode, blocks, s);
+    }, &g->graph);
+    if (st == GRID_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess)
+            st = fail(GRID_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (st != GRID_OK) {
+        destroy_graph(g);
+        return st;
+    }
+    *out = g;
+    return GRID_OK;
+}
+
+grid_status grid_mixed_graph_update(grid_graph g, const grid_mixed_item* items, int32_t count)
+{
+    if (!g)
+        return fail(GRID_EINVAL, "graph is NULL");
+    if (!g->mx)
+        return fail(GRID_EINVAL, "not a graph of a mixed launch (grid_graph_update updates it)");
+    MixedArgs a;
+    int64_t blocks = 0;
+    grid_status st = mixed_args(g->mx, items, count, 0, &a, &blocks);
+    if (st != GRID_OK)
+        return st;
+    HIP_TRY(hipSetDevice(g->device));
+    hipGraph_t fresh = nullptr;
+    st = capture_with(g, [&](hipStream_t s) {
+        return mixed_capture_launch(g->mx, items, count, g->mode, blocks, s);
+    }, &fresh);
+    if (st != GRID_OK)
+        return st;
+    g->count = count;
+    return swap_in(g, fresh);
+}
+
 grid_status grid_mixed_tune(grid_mixed mx, const grid_mixed_item* items, int32_t count,
                             int32_t* chosen, float* us)
 {
     MixedArgs a;
     int64_t blocks = 0;
-    grid_status st = mixed_args(mx, items, count, false, &a, &blocks);
+    grid_status st = mixed_args(mx, items, count, 0, &a, &blocks);
     if (st != GRID_OK)
         return st;
     if (blocks == 0)

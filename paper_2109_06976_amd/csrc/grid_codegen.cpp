@@ -442,39 +442,50 @@ std::string generate_mixed_source(const std::vector<RobotSource>& robots,
     os << "\n// generated: workgroup -> (segment: item, branch), fused pipe kernel\n";
     os << "struct MixedArgs {\n    int nseg;\n    int nblocks;\n    int seg_start[" << kMixedSegs
        << "];\n    int seg_inst[" << kMixedSegs << "];\n    int seg_item[" << kMixedSegs
+       << "];\n    int seg_blocks[" << kMixedSegs << "];\n    int seg_wgs[" << kMixedSegs
        << "];\n    grid::Args item[" << kMixedItems << "];\n};\n";
-    // block b of the launch: its segment (uniform scan of the table), then that segment's
-    // branch on its item's buffers
-    os << "__device__ __forceinline__ void grid_mixed_block(const MixedArgs& args, int b)\n{\n"
+    // the segment of workgroup w: a uniform scan of the first workgroups of the segments
+    os << "__device__ __forceinline__ int grid_mixed_segment(const MixedArgs& args, int w)\n{\n"
           "    int s = 0;\n"
-          "    while (s + 1 < args.nseg && b >= args.seg_start[s + 1])\n"
+          "    while (s + 1 < args.nseg && w >= args.seg_start[s + 1])\n"
           "        ++s;\n"
-          "    const grid::Args& x = args.item[args.seg_item[s]];\n"
-          "    const int lb = b - args.seg_start[s];\n"
-          "    switch (args.seg_inst[s]) {\n";
-    for (int k = 0; k < ninst; ++k) {
-        if (k + 1 == ninst)
-            os << "    default: gridq::run_pipe<Inst<" << k << ">>(x, lb); break;\n";
-        else
-            os << "    case " << k << ": gridq::run_pipe<Inst<" << k << ">>(x, lb); break;\n";
-    }
-    os << "    }\n}\n";
-    // one workgroup per block
+          "    return s;\n}\n";
+    // one workgroup per block: workgroup w runs block w - seg_start of its segment's branch on
+    // its item's buffers
     os << "extern \"C\" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) "
           "grid_fdgrad_pipe_mixed(MixedArgs args)\n{\n"
-          "    grid_mixed_block(args, (int)blockIdx.x);\n}\n";
-    // persistent: a grid of resident workgroups strides over the blocks. b is uniform, so every
-    // wavefront of a workgroup runs the same blocks and takes each block's three barriers (lane
-    // table, bias forces, products). Consecutive blocks on one workgroup do not overlap in
-    // LDS: a block reads its lane table before its second barrier, and the next block writes
-    // its table after every wavefront has passed the third; the arrays read after the third
-    // barrier (M^-1 or the factor, the qdd parts) are written by the next block only after
-    // its first barrier, which a wavefront reaches only once it has finished the block before.
-    // (Blocks of different branches use different LDS arrays altogether.)
+          "    const int w = (int)blockIdx.x;\n"
+          "    const int s = grid_mixed_segment(args, w);\n"
+          "    const grid::Args& x = args.item[args.seg_item[s]];\n"
+          "    const int lb = w - args.seg_start[s];\n"
+          "    switch (args.seg_inst[s]) {\n";
+    for (int k = 0; k < ninst; ++k)
+        os << "    " << (k + 1 == ninst ? std::string("default") : "case " + std::to_string(k))
+           << ": gridq::run_pipe<Inst<" << k << ">>(x, lb); break;\n";
+    os << "    }\n}\n";
+    // persistent: each segment owns seg_wgs resident workgroups, and each of them strides over
+    // the segment's blocks. The loop sits inside the segment's case, so what the compiler keeps
+    // live across iterations belongs to that one branch (a loop around the whole switch keeps
+    // every branch's per-lane set-up live at once: 307 VGPRs against 168 for two robots). A
+    // workgroup's blocks are uniform, so every wavefront takes each block's three barriers
+    // (lane table T, bias forces C, products P). Reusing LDS for the next block is ordered by
+    // those barriers: s_tab is written after P (read before C); s_c, s_M, the factor and s_D
+    // after T or C of the next block (read before P, or just after P by a wavefront that then
+    // reaches T); s_Mi after C (read after P).
     os << "extern \"C\" __global__ void __launch_bounds__(64 * GRID_PIPE_WAVES) "
           "grid_fdgrad_pipe_mixed_persistent(MixedArgs args)\n{\n"
-          "    for (int b = (int)blockIdx.x; b < args.nblocks; b += (int)gridDim.x)\n"
-          "        grid_mixed_block(args, b);\n}\n";
+          "    const int w = (int)blockIdx.x;\n"
+          "    const int s = grid_mixed_segment(args, w);\n"
+          "    const grid::Args& x = args.item[args.seg_item[s]];\n"
+          "    const int lw = w - args.seg_start[s];\n"
+          "    const int nb = args.seg_blocks[s];\n"
+          "    const int nw = args.seg_wgs[s];\n"
+          "    switch (args.seg_inst[s]) {\n";
+    for (int k = 0; k < ninst; ++k)
+        os << "    " << (k + 1 == ninst ? std::string("default") : "case " + std::to_string(k))
+           << ":\n        for (int lb = lw; lb < nb; lb += nw)\n"
+              "            gridq::run_pipe<Inst<" << k << ">, true>(x, lb);\n        break;\n";
+    os << "    }\n}\n";
     return os.str();
 }
 

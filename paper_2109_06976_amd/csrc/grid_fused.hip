@@ -753,7 +753,11 @@ struct PipeShape {
     static_assert(WA == 1 || P == 1, "one problem per workgroup beyond 8 bodies");
 };
 
-template <class I>
+// kLoop: the call sits in a loop over blocks (the persistent mixed kernel). The thread index is
+// then passed through an empty asm statement, so that nothing derived from it counts as loop
+// invariant: hoisted out of the loop, the per-lane set-up would stay live across iterations
+// beside the block's own state. The wavefront index is made uniform again explicitly.
+template <class I, bool kLoop = false>
 __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
 {
     using S = typename I::S;
@@ -773,9 +777,11 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     __shared__ float s_D[P][B][B];            // qdd part of the q-columns, [column][row] (B -> A)
     __shared__ float4 s_tab[3 * B * 4];       // the model's lane table (roles A, B)
 
-    const int tid = (int)threadIdx.x;
-    const int wave = tid / 64;
-    const int lane = tid % 64;
+    int tid = (int)threadIdx.x;
+    if constexpr (kLoop)
+        asm volatile("" : "+v"(tid));
+    const int wave = kLoop ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid / 64;
+    const int lane = kLoop ? (tid & 63) : tid % 64;
     const int c = lane & 3;
     const Lane ln = lane_of(c == 3 ? 0 : c, I::a0());
     const float* tab = lane_table<I, 64 * GRID_PIPE_WAVES>(s_tab, tid, c);

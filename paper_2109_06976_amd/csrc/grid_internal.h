@@ -105,10 +105,13 @@ constexpr int kMixedSegs = 64;
 // Kernel argument block of the mixed kernel; must match MixedArgs of the generated source.
 struct MixedArgs {
     int nseg;
-    int nblocks;                     // blocks of the launch (the persistent form's bound)
-    int seg_start[kMixedSegs];       // first block of the segment, ascending
+    int nblocks;                     // blocks of the launch over all segments
+    int seg_start[kMixedSegs];       // first workgroup of the segment, ascending
     int seg_inst[kMixedSegs];        // the branch the segment runs
     int seg_item[kMixedSegs];        // the item whose buffers it reads and writes
+    int seg_blocks[kMixedSegs];      // blocks of the segment
+    int seg_wgs[kMixedSegs];         // workgroups of the segment (= seg_blocks for one
+                                     // workgroup per block; fewer in the persistent form)
     KernelArgs item[kMixedItems];
 };
 
@@ -153,6 +156,9 @@ hipError_t launch_vjp(int nknots, int n, const float* dq, const float* dqd, cons
 hipError_t launch_dt(int nknots, int n, float dt, const float* dq, const float* dqd,
                      const float* Minv, float* A, float* B, hipStream_t stream);
 
+// device -> pinned host copy of n floats by a kernel (16-byte stores; both 16-byte aligned)
+hipError_t launch_copy_out(const float* src, float* dst, size_t n, hipStream_t stream);
+
 // the library's static scratch array (grid_noalloc.hip): its device address on `device`, taken
 // once with that device current; noalloc_scratch returns it (NULL before the setup)
 grid_status noalloc_setup(int device, std::string* err);
@@ -186,4 +192,6 @@ struct grid_workspace_s {
     float* d_stage = nullptr;           // staged pipeline intermediates
     float* h_in = nullptr;              // pinned staging
     float* h_out = nullptr;
+    float* h_in_dev = nullptr;          // the device's mapping of h_in and h_out (NULL if the
+    float* h_out_dev = nullptr;         // runtime gives none: the mapped call is unsupported)
 };

@@ -833,6 +833,16 @@ grid_status grid_workspace_create(grid_model m, int32_t max_knots, grid_workspac
         grid_workspace_destroy(w);
         return fail(GRID_ENOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
     }
+    // the device's view of the pinned buffers, for the mapped call (optional)
+    void* pin_in = nullptr;
+    void* pin_out = nullptr;
+    if (hipHostGetDevicePointer(&pin_in, w->h_in, 0) == hipSuccess &&
+        hipHostGetDevicePointer(&pin_out, w->h_out, 0) == hipSuccess) {
+        w->h_in_dev = static_cast<float*>(pin_in);
+        w->h_out_dev = static_cast<float*>(pin_out);
+    } else {
+        (void)hipGetLastError();
+    }
     *out = w;
     return GRID_OK;
 }
@@ -972,6 +982,53 @@ grid_status grid_fd_grad_pinned(grid_model m, grid_workspace w, int32_t N, int32
         return GRID_OK;
     HIP_TRY(hipSetDevice(m->device));
     return run_pinned(m, w, N, std::min(pieces, N), timing);
+}
+
+grid_status grid_fd_grad_mapped(grid_model m, grid_workspace w, int32_t N, int32_t out_mode,
+                                grid_timing* timing)
+{
+    if (!m || !w)
+        return fail(GRID_EINVAL, "model and workspace must not be NULL");
+    if (w->model != m)
+        return fail(GRID_EINVAL, "workspace was created for another model");
+    if (N < 0 || N > w->max_knots)
+        return fail(GRID_EINVAL, "N must be in 0..max_knots of the workspace");
+    if (out_mode != GRID_IO_COPY_KERNEL && out_mode != GRID_IO_DIRECT)
+        return fail(GRID_EINVAL, "unknown output mode " + std::to_string(out_mode));
+    if (timing)
+        *timing = grid_timing{0, 0, 0, 0};
+    if (N == 0)
+        return GRID_OK;
+    if (!w->h_in_dev || !w->h_out_dev)
+        return fail(GRID_EUNSUPPORTED, "the runtime gave no device mapping of the pinned buffers");
+    HIP_TRY(hipSetDevice(m->device));
+    const size_t n = (size_t)m->topo.n;
+    const size_t vec = (size_t)N * n, mat = vec * n;
+    const float* q = w->h_in_dev;
+    float* out = out_mode == GRID_IO_DIRECT ? w->h_out_dev : w->d_out;
+    // events only where a phase boundary is timed (each record costs the stream microseconds)
+    const bool copy = out_mode == GRID_IO_COPY_KERNEL;
+    if (timing)
+        HIP_TRY(hipEventRecord(w->ev[0], w->stream));
+    grid_status s = launch_fused(m, N, q, q + vec, q + 2 * vec, out, out + vec, out + vec + mat,
+                                 out + vec + 2 * mat, w->stream);
+    if (s != GRID_OK)
+        return s;
+    if (timing)
+        HIP_TRY(hipEventRecord(w->ev[1], w->stream));
+    if (copy) {
+        HIP_TRY(launch_copy_out(w->d_out, w->h_out_dev, vec + 3 * mat, w->stream));
+        if (timing)
+            HIP_TRY(hipEventRecord(w->ev[2], w->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if (timing) {
+        HIP_TRY(hipEventElapsedTime(&timing->kernel_ms, w->ev[0], w->ev[1]));
+        if (copy)
+            HIP_TRY(hipEventElapsedTime(&timing->d2h_ms, w->ev[1], w->ev[2]));
+        HIP_TRY(hipEventElapsedTime(&timing->total_ms, w->ev[0], w->ev[copy ? 2 : 1]));
+    }
+    return GRID_OK;
 }
 
 grid_status grid_fd_grad_host(grid_model m, grid_workspace w, int32_t N, const float* q,

@@ -58,6 +58,7 @@ struct BatchCtx {
     hipStream_t stream = nullptr;
     hipEvent_t ev[4] = {};                     // before H2D, after H2D, after kernel, after D2H
     float *d_in = nullptr, *d_out = nullptr, *h_in = nullptr, *h_out = nullptr;
+    float *h_in_dev = nullptr, *h_out_dev = nullptr;   // device mapping (mapped I/O)
     grid_workspace ws = nullptr;               // staged (per-request) mode only
     std::vector<Request*> reqs;
     int knots = 0;
@@ -170,6 +171,8 @@ void worker_loop(grid_server s, BatchCtx* c)
         float ph[3] = {0, 0, 0};
         if (e != hipSuccess) {
             s->device_error.store(true);
+        } else if (s->cfg.flags & GRID_SERVER_MAPPED_IO) {
+            (void)hipEventElapsedTime(&ph[1], c->ev[0], c->ev[3]);   // the kernel alone
         } else {
             for (int k = 0; k < 3; ++k)
                 (void)hipEventElapsedTime(&ph[k], c->ev[k], c->ev[k + 1]);
@@ -220,17 +223,21 @@ bool launch_ctx(grid_server s, BatchCtx* c)
         r->state.store(kLaunched, std::memory_order_relaxed);
         off += N;
     }
-    float* dq = c->d_in;
+    // mapped I/O: the kernel reads the pinned inputs and writes the pinned outputs through the
+    // device's mapping (no copy-engine transfers; no H2D and D2H phases, and no events for
+    // them: an event record costs a few microseconds of the stream's time)
+    const bool mapped = (s->cfg.flags & GRID_SERVER_MAPPED_IO) != 0;
+    float* dq = mapped ? c->h_in_dev : c->d_in;
     float* dqd = dq + K * n;
     float* dtau = dqd + K * n;
-    float* oq = c->d_out;
+    float* oq = mapped ? c->h_out_dev : c->d_out;
     float* oM = oq + K * n;
     float* oD = oM + K * n * n;
     float* oV = oD + K * n * n;
     if (hipEventRecord(c->ev[0], c->stream) != hipSuccess ||
-        hipMemcpyAsync(dq, iq, 3 * K * n * sizeof(float), hipMemcpyHostToDevice, c->stream) !=
-            hipSuccess ||
-        hipEventRecord(c->ev[1], c->stream) != hipSuccess)
+        (!mapped && (hipMemcpyAsync(dq, iq, 3 * K * n * sizeof(float), hipMemcpyHostToDevice,
+                                    c->stream) != hipSuccess ||
+                     hipEventRecord(c->ev[1], c->stream) != hipSuccess)))
         return false;
     grid_status st;
     if (s->cfg.flags & GRID_SERVER_PER_REQUEST)
@@ -239,9 +246,9 @@ bool launch_ctx(grid_server s, BatchCtx* c)
         st = grid_fd_grad(m, (int32_t)K, dq, dqd, dtau, oq, oM, oD, oV, c->stream);
     if (st != GRID_OK)
         return false;
-    if (hipEventRecord(c->ev[2], c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->h_out, c->d_out, K * (n + 3 * n * n) * sizeof(float),
-                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+    if ((!mapped && (hipEventRecord(c->ev[2], c->stream) != hipSuccess ||
+                     hipMemcpyAsync(c->h_out, c->d_out, K * (n + 3 * n * n) * sizeof(float),
+                                    hipMemcpyDeviceToHost, c->stream) != hipSuccess)) ||
         hipEventRecord(c->ev[3], c->stream) != hipSuccess)
         return false;
     s->launches.fetch_add(1);
@@ -389,7 +396,8 @@ grid_status grid_server_create(const grid_model* models, int32_t count,
     if (!models || count < 1 || !cfg)
         return fail(GRID_EINVAL, "models, count and config are required");
     if (cfg->max_batch_knots < 1 || cfg->max_batch_knots > (1 << 20) || cfg->contexts_per_model < 1 ||
-        cfg->contexts_per_model > 64 || (cfg->flags & ~(uint32_t)GRID_SERVER_PER_REQUEST) ||
+        cfg->contexts_per_model > 64 ||
+        (cfg->flags & ~(uint32_t)(GRID_SERVER_PER_REQUEST | GRID_SERVER_MAPPED_IO)) ||
         cfg->batch_window_us < 0 || cfg->batch_window_us > 1000000 || cfg->min_batch_knots < 0 ||
         cfg->min_batch_knots > cfg->max_batch_knots)
         return fail(GRID_EINVAL, "bad server configuration");
@@ -424,6 +432,15 @@ grid_status grid_server_create(const grid_model* models, int32_t count,
                 e = hipHostMalloc(&b->h_in, 3 * K * n * sizeof(float), hipHostMallocDefault);
             if (e == hipSuccess)
                 e = hipHostMalloc(&b->h_out, K * (n + 3 * n * n) * sizeof(float), hipHostMallocDefault);
+            if (e == hipSuccess && (cfg->flags & GRID_SERVER_MAPPED_IO)) {
+                void* pi = nullptr;
+                void* po = nullptr;
+                e = hipHostGetDevicePointer(&pi, b->h_in, 0);
+                if (e == hipSuccess)
+                    e = hipHostGetDevicePointer(&po, b->h_out, 0);
+                b->h_in_dev = static_cast<float*>(pi);
+                b->h_out_dev = static_cast<float*>(po);
+            }
             grid_status st = GRID_OK;
             if (e == hipSuccess && (cfg->flags & GRID_SERVER_PER_REQUEST))
                 st = grid_workspace_create(models[k], cfg->max_batch_knots, &b->ws);

@@ -26,8 +26,11 @@ GRID_EBUSY = -6
 GRID_ETIMEDOUT = -7
 GRID_ECANCELED = -8
 GRID_NOALLOC_SCRATCH_BYTES = 16 << 20
+IO_COPY_KERNEL = 0           # grid_fd_grad_mapped output modes
+IO_DIRECT = 1
 GRID_MAX_KNOTS = 1 << 24      # the largest N of one call
 GRID_SERVER_PER_REQUEST = 1
+GRID_SERVER_MAPPED_IO = 2
 GRID_CODEGEN_PIPE_MODULE = 1 << 16
 
 _i32p = C.POINTER(C.c_int32)
@@ -159,11 +162,16 @@ _SIGS = {
     "grid_mixed_destroy": (C.c_int32, [C.c_void_p]),
     "grid_mixed_launch_mode": (C.c_int32, [C.c_void_p, C.POINTER(GridMixedItem), C.c_int32,
                                            C.c_int32, C.c_void_p]),
+    "grid_mixed_graph_create": (C.c_int32, [C.c_void_p, C.POINTER(GridMixedItem), C.c_int32,
+                                            C.c_int32, C.POINTER(C.c_void_p)]),
+    "grid_mixed_graph_update": (C.c_int32, [C.c_void_p, C.POINTER(GridMixedItem), C.c_int32]),
     "grid_mixed_tune": (C.c_int32, [C.c_void_p, C.POINTER(GridMixedItem), C.c_int32,
                                     C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "grid_workspace_host_buffers": (C.c_int32, [C.c_void_p, C.POINTER(C.POINTER(C.c_float)),
                                                 C.POINTER(C.POINTER(C.c_float))]),
     "grid_fd_grad_pinned": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                        C.POINTER(GridTiming)]),
+    "grid_fd_grad_mapped": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                         C.POINTER(GridTiming)]),
     "grid_mixed_source": (C.c_int32, [C.POINTER(GridDesc), C.c_int32, C.c_char_p,
                                       C.POINTER(C.c_size_t)]),
@@ -478,6 +486,19 @@ class Workspace:
                                          C.byref(t)))
         return {k: float(getattr(t, k)) for k in ("h2d_ms", "kernel_ms", "d2h_ms", "total_ms")}
 
+    def fd_grad_mapped(self, N, out_mode=0, timed=True):
+        """grid_fd_grad_mapped on the inputs already in the pinned buffers, no copy-engine
+        transfers (out_mode IO_COPY_KERNEL or IO_DIRECT); returns the timing dict (None when
+        timed is False: no events are recorded)."""
+        if not timed:
+            _check(lib().grid_fd_grad_mapped(self.model.handle, self._h, int(N), int(out_mode),
+                                             None))
+            return None
+        t = GridTiming()
+        _check(lib().grid_fd_grad_mapped(self.model.handle, self._h, int(N), int(out_mode),
+                                         C.byref(t)))
+        return {k: float(getattr(t, k)) for k in ("h2d_ms", "kernel_ms", "d2h_ms", "total_ms")}
+
     def fd_grad_host(self, q, qd, tau):
         """grid_fd_grad_host on numpy arrays; returns (outputs dict, timing dict)."""
         n = self.model.n
@@ -602,6 +623,12 @@ class Mixed:
         call.buffers = items
         return call
 
+    def graph(self, items, mode=None):
+        """grid_mixed_graph_create: one mixed launch of these items captured in a hipGraph
+        (mode None: the mode grid_mixed_launch picks for the batch size). Returns a MixedGraph;
+        close it before this module."""
+        return MixedGraph(self, items, -1 if mode is None else int(mode))
+
     def tune(self, items):
         """grid_mixed_tune: (chosen mode, {mode: us per launch})."""
         arr = self._items(items)
@@ -613,6 +640,50 @@ class Mixed:
     def close(self):
         if self._h is not None and self._h.value:
             lib().grid_mixed_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MixedGraph:
+    """grid_graph made by grid_mixed_graph_create: one mixed launch as a replayable graph."""
+
+    def __init__(self, mixed: Mixed, items, mode: int):
+        self._h = None
+        self.mixed = mixed
+        self._arr = mixed._items(items)
+        self.buffers = items
+        h = C.c_void_p()
+        _check(lib().grid_mixed_graph_create(mixed._h, self._arr, len(items), int(mode),
+                                             C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().grid_graph_launch(self._h, _stream_handle(stream)))
+
+    def launch_call(self, stream=None):
+        """The replay with its arguments converted to C once (timing loops)."""
+        h, st, fn = self._h, C.c_void_p(_stream_handle(stream)), lib().grid_graph_launch
+
+        def call():
+            rc = fn(h, st)
+            if rc != GRID_OK:
+                raise GridError(rc, last_error())
+
+        return call
+
+    def update(self, items):
+        self._arr = self.mixed._items(items)
+        self.buffers = items
+        _check(lib().grid_mixed_graph_update(self._h, self._arr, len(items)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().grid_graph_destroy(self._h)
         self._h = None
 
     def __del__(self):

@@ -207,17 +207,20 @@ def test_mixed_module_source_holds_every_branch_of_every_robot():
     src = grid.mixed_source(robots)
     assert "#define GRID_PIPE_ONLY" in src
     assert 'extern "C" __global__' in src and "grid_fdgrad_pipe_mixed(" in src
-    # the persistent form: resident workgroups stride over the same blocks, bounded by nblocks
+    # the persistent form: each segment's workgroups stride over that segment's blocks, the
+    # loop inside the segment's case
     assert "grid_fdgrad_pipe_mixed_persistent(MixedArgs args)" in src
-    assert "b < args.nblocks; b += (int)gridDim.x" in src
     assert re.search(r"struct MixedArgs \{\s*int nseg;\s*int nblocks;", src)
-    # the robots' branches, numbered across the robots, one switch case each
+    # the robots' branches, numbered across the robots, one switch case each in both kernels
     per = [len(_insts(grid.codegen_source(r))) for r in robots]
     assert per[:2] == [1, 4]
     total = sum(per)
     assert len(re.findall(r"^\s*case \d+: gridq::run_pipe<Inst<\d+>>", src, re.M)) == total - 1
     assert len(re.findall(r"^\s*default: gridq::run_pipe<Inst<%d>>" % (total - 1), src,
                           re.M)) == 1
+    loops = re.findall(r"^\s*(case \d+|default):\n\s*for \(int lb = lw; lb < nb; lb \+= nw\)\n"
+                       r"\s*gridq::run_pipe<Inst<(\d+)>, true>\(x, lb\);", src, re.M)
+    assert [int(k) for _, k in loops] == list(range(total))
     assert [b for _, b in _insts(src)] == sum((
         [b for _, b in _insts(grid.codegen_source(r))] for r in robots), [])
     # each robot carries its own joint count and gravity

@@ -256,3 +256,63 @@ def test_mixed_persistent_equals_one_launch(orc, plan_name):
         mx.close()
         for m in models:
             m.close()
+
+
+@pytest.mark.parametrize("mode", [None, grid.MIXED_ONE_LAUNCH, grid.MIXED_PERSISTENT,
+                                  grid.MIXED_PER_ROBOT])
+def test_mixed_launch_graph_replays_and_updates(mode):
+    """One mixed launch captured in a hipGraph (grid_mixed_graph_create): every replay, with
+    eager work and synchronisations between replays, equals the eager launch in the same mode
+    bit for bit; after grid_mixed_graph_update to other items (another count, other N) the
+    replays equal the eager launch of those items."""
+    import torch
+    from paper_2109_06976_amd import build
+    robots = build.mixed_sets()[0]                    # quad12, chain7
+    models = [grid.Model(r) for r in robots]
+    mx = grid.Mixed(robots)
+    label = "tuned" if mode is None else grid.MIXED_MODES[mode]
+    try:
+        for plan, plan2 in [([(0, 64), (1, 37)], [(1, 181), (0, 256), (1, 5)]),
+                            ([(0, 1024), (1, 613)], [(0, 3)])]:
+            say(f"[gpu] mixed graph ({label}): {plan} then {plan2}")
+            items, _ = _mixed_items(torch, models, plan, 1100)
+            mx.launch(items, mode=mode)
+            torch.cuda.synchronize()
+            eager = [[t.clone() for t in it[4:]] for it in items]
+            g = mx.graph(items, mode=mode)
+            try:
+                for rep in range(3):
+                    for it in items:
+                        for t in it[4:]:
+                            t.fill_(float("nan"))
+                    torch.cuda.synchronize()
+                    g.launch(torch.cuda.current_stream())
+                    torch.cuda.synchronize()
+                    for it, ref in zip(items, eager):
+                        for k, a, b in zip(OUTS, it[4:], ref):
+                            assert torch.equal(a, b), f"replay {rep} {k}"
+                    _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # eager work between
+                items2, _ = _mixed_items(torch, models, plan2, 1200)
+                mx.launch(items2, mode=mode)
+                torch.cuda.synchronize()
+                eager2 = [[t.clone() for t in it[4:]] for it in items2]
+                g.update(items2)
+                for rep in range(2):
+                    for it in items2:
+                        for t in it[4:]:
+                            t.fill_(float("nan"))
+                    g.launch(torch.cuda.current_stream())
+                    torch.cuda.synchronize()
+                    for it, ref in zip(items2, eager2):
+                        for k, a, b in zip(OUTS, it[4:], ref):
+                            assert torch.equal(a, b), f"updated replay {rep} {k}"
+            finally:
+                g.close()
+        # an unknown mode is rejected
+        with pytest.raises(grid.GridError) as e:
+            mx.graph(items, mode=7)
+        assert e.value.status == grid.GRID_EINVAL
+    finally:
+        mx.close()
+        for m in models:
+            m.close()

@@ -199,6 +199,37 @@ def test_pinned_path_matches_device_path(torch_cuda):
         ws.close()
 
 
+@pytest.mark.parametrize("name,N", [("chain7", 301), ("humanoid30", 37), ("quad12", 1)])
+def test_mapped_path_matches_device_path(torch_cuda, name, N):
+    """The mapped call (the fused kernel reads the pinned inputs through the device mapping;
+    the outputs reach the pinned buffer through a copy kernel or straight from the fused
+    kernel's stores) gives bitwise the device path's outputs, for a size whose packed outputs
+    leave a tail of floats after the 16-byte copies."""
+    robot, model = get_model(name)
+    kn = synth.random_knots(robot.n, N, 36)
+    dev = run_device(torch_cuda, model, kn)
+    ws = grid.Workspace(model, N + 3)
+    try:
+        for mode in (grid.IO_COPY_KERNEL, grid.IO_DIRECT):
+            say(f"[gpu] mapped path {name} N={N} mode {mode}")
+            ins, outs = ws.host_buffers(N)
+            ins["q"][:], ins["qd"][:], ins["tau"][:] = kn.q, kn.qd, kn.tau
+            for o in outs.values():
+                o.fill(np.nan)
+            t = ws.fd_grad_mapped(N, mode)
+            assert t["total_ms"] > 0 and t["kernel_ms"] > 0 and t["h2d_ms"] == 0
+            for key in OUTS:
+                np.testing.assert_array_equal(outs[key], dev[key], err_msg=f"{key} mode {mode}")
+        with pytest.raises(grid.GridError) as e:
+            ws.fd_grad_mapped(N, 2)
+        assert e.value.status == grid.GRID_EINVAL
+        with pytest.raises(grid.GridError) as e:
+            ws.fd_grad_mapped(N + 4, 0)
+        assert e.value.status == grid.GRID_EINVAL
+    finally:
+        ws.close()
+
+
 def test_invalid_launch_arguments(torch_cuda):
     robot, model = get_model("chain7")
     t = torch_cuda.zeros((4, 7), device="cuda")

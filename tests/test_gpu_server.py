@@ -28,10 +28,17 @@ def models():
         m.close()
 
 
-def test_request_alone_equals_request_in_mix(models, orc):
+_alone_by_flags = {}
+
+
+@pytest.mark.parametrize("flags", [0, grid.GRID_SERVER_MAPPED_IO])
+def test_request_alone_equals_request_in_mix(models, orc, flags):
+    """A request's outputs are the same alone and in the middle of a mixed stream (bit for
+    bit), with copy-engine transfers and with mapped I/O, and the two I/O modes agree."""
     robots, ms = models
-    say("[gpu] server identity: alone vs Poisson-like mix")
-    srv = grid.Server(ms, budget_bytes=1 << 28, max_batch_knots=1024, contexts_per_model=3)
+    say(f"[gpu] server identity (flags {flags}): alone vs Poisson-like mix")
+    srv = grid.Server(ms, budget_bytes=1 << 28, max_batch_knots=1024, contexts_per_model=3,
+                      flags=flags)
     probe = synth.random_knots(robots[2].n, 100, 55)
     t, alone = srv.submit(2, probe.q, probe.qd, probe.tau)
     srv.wait(t)
@@ -59,6 +66,11 @@ def test_request_alone_equals_request_in_mix(models, orc):
         srv.wait(t)
     for key in OUTS:
         np.testing.assert_array_equal(mixed[key], alone[key])
+    _alone_by_flags[flags] = alone
+    if len(_alone_by_flags) == 2:
+        for key in OUTS:
+            np.testing.assert_array_equal(_alone_by_flags[0][key],
+                                          _alone_by_flags[grid.GRID_SERVER_MAPPED_IO][key])
     st = srv.stats()
     say(f"  stats {st}")
     assert st["completed"] == st["submitted"] == 82 and st["launches"] <= 82
