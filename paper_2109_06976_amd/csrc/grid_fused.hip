@@ -233,6 +233,34 @@ __device__ __forceinline__ const float* lane_table(float4 (&s_tab)[3 * I::S::B *
 // (alpha, beta, gamma) = (cos, sin, 0), (-sin, cos, 0), (0, 0, 1) for c = 0, 1, 2 (rows of
 // E_z); the lane keeps its row in the order (E_cc, E_c,c+1, E_c,c+2), and the column entries
 // E_c+1,c and E_c+2,c are the neighbours' third and second row entries.
+template <class I>
+__device__ __forceinline__ void make_body(int i, float qi, const Lane& ln, const float* tab,
+                                          Rot& E, LaneK& K)
+{
+    const float4* t = reinterpret_cast<const float4*>(tab + i * 16);
+    const float4 t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3];
+    // t1.w, t2, t3: E_T[row][(c + col) % 3] at 3 row + col
+    const float pT[3][3] = {{t1.w, t2.x, t2.y}, {t2.z, t2.w, t3.x}, {t3.y, t3.z, t3.w}};
+    K = LaneK{t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z};
+    float sn = 0.0f, co = 1.0f;                      // prismatic: E = E_T
+    if (prismatic<I>(i)) {
+        // r = r_T + q E_T^T e_z: components c+1 and c+2 of the third row of E_T
+        K.rr1 += qi * pT[2][1];
+        K.rr2 += qi * pT[2][2];
+    } else {
+        const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
+        sn = __builtin_amdgcn_sinf(rev);
+        co = __builtin_amdgcn_cosf(rev);
+    }
+    const float al = ln.oh0 * co - ln.oh1 * sn;
+    const float be = ln.oh0 * sn + ln.oh1 * co;
+    E.e0 = al * pT[0][0] + be * pT[1][0] + ln.oh2 * pT[2][0];
+    E.e1 = al * pT[0][1] + be * pT[1][1] + ln.oh2 * pT[2][1];
+    E.e2 = al * pT[0][2] + be * pT[1][2] + ln.oh2 * pT[2][2];
+    E.f1 = qperm<kNb1>(E.e2);
+    E.f2 = qperm<kNb2>(E.e1);
+}
+
 template <class I, bool kQd = true>
 __device__ __forceinline__ void load_bodies(const float* q_in, const float* qd_in, long vbase,
                                                 const Lane& ln, const float* tab,
@@ -241,31 +269,10 @@ __device__ __forceinline__ void load_bodies(const float* q_in, const float* qd_i
 {
 #pragma unroll
     for (int i = 0; i < I::S::B; ++i) {
-        const float4* t = reinterpret_cast<const float4*>(tab + i * 16);
-        const float4 t0 = t[0], t1 = t[1], t2 = t[2], t3 = t[3];
-        // t1.w, t2, t3: E_T[row][(c + col) % 3] at 3 row + col
-        const float pT[3][3] = {{t1.w, t2.x, t2.y}, {t2.z, t2.w, t3.x}, {t3.y, t3.z, t3.w}};
         const long o = vbase + I::body[i];
         const float qi = q_in[o];
         qd[i] = kQd ? qd_in[o] : 0.0f;
-        K[i] = LaneK{t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z};
-        float sn = 0.0f, co = 1.0f;                      // prismatic: E = E_T
-        if (prismatic<I>(i)) {
-            // r = r_T + q E_T^T e_z: components c+1 and c+2 of the third row of E_T
-            K[i].rr1 += qi * pT[2][1];
-            K[i].rr2 += qi * pT[2][2];
-        } else {
-            const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
-            sn = __builtin_amdgcn_sinf(rev);
-            co = __builtin_amdgcn_cosf(rev);
-        }
-        const float al = ln.oh0 * co - ln.oh1 * sn;
-        const float be = ln.oh0 * sn + ln.oh1 * co;
-        E[i].e0 = al * pT[0][0] + be * pT[1][0] + ln.oh2 * pT[2][0];
-        E[i].e1 = al * pT[0][1] + be * pT[1][1] + ln.oh2 * pT[2][1];
-        E[i].e2 = al * pT[0][2] + be * pT[1][2] + ln.oh2 * pT[2][2];
-        E[i].f1 = qperm<kNb1>(E[i].e2);
-        E[i].f2 = qperm<kNb2>(E[i].e1);
+        make_body<I>(i, qi, ln, tab, E[i], K[i]);
     }
 }
 
@@ -356,17 +363,18 @@ __device__ __forceinline__ void rnea_at(const Lane& ln, const float (&qd)[I::S::
 // come out zero)
 template <class I, int JMIN = 0>
 __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B],
-                                         const LaneK (&K)[I::S::B], int jm, V (&fm)[I::S::B])
+                                         const LaneK (&K)[I::S::B], int jm, V (&fm)[I::S::B],
+                                         V (&am)[I::S::B])
 {
     using S = typename I::S;
     constexpr int B = S::B;
-    V am[B];
     Nb nam[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         const int p = S::parent[i];
         if (i < JMIN) {                       // not in the subtree of jm
             fm[i] = V{0.0f, 0.0f};
+            am[i] = V{0.0f, 0.0f};
             continue;
         }
         if (p >= JMIN)
@@ -384,6 +392,33 @@ __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B]
         if (p >= 0 && live_back<S, JMIN>(i))
             fm[p < 0 ? 0 : p] = add(fm[p < 0 ? 0 : p], xtfv(E[i], K[i], fm[i], gather(fm[i])));
     }
+}
+
+template <class I, int JMIN = 0>
+__device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B],
+                                         const LaneK (&K)[I::S::B], int jm, V (&fm)[I::S::B])
+{
+    V am[I::S::B];
+    m_column<I, JMIN>(ln, E, K, jm, fm, am);
+}
+
+// Sum of x over the QB quads of a problem (lanes with the same component c in an aligned group
+// of 4 QB lanes): two DPP row rotations inside each row of 16 lanes, then lane swaps of 16 and
+// 32 for groups that span rows.
+template <int QB>
+__device__ __forceinline__ float quad_group_sum(float x)
+{
+    if constexpr (QB >= 4) {
+        x += qperm<0x128>(x);                 // row_ror:8
+        x += qperm<0x124>(x);                 // row_ror:4
+    } else if constexpr (QB == 2) {
+        x += __shfl_xor(x, 4);
+    }
+    if constexpr (QB >= 8)
+        x += __shfl_xor(x, 16);
+    if constexpr (QB >= 16)
+        x += __shfl_xor(x, 32);
+    return x;
 }
 
 // M = L^T L in place (L lower triangular, nonzero on ancestor paths only): for k from the
@@ -917,17 +952,28 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         Rot E[B];
         LaneK K[B];
         load_bodies<I>(A.q, A.qd, vbase, ln, tab, qd, E, K);
+        // the unit-acceleration responses of this quad's columns of M, kept for the increments
+        // (up to 16 bodies: see below)
+        constexpr bool kLinear = B <= 16;
+        V amk[kLinear ? CB : 1][B], fmk[kLinear ? CB : 1][B];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            V fm[B];
+            V fm[B], am[B];
             if (cb == 0)
-                m_column<I>(ln, E, K, js[cb], fm);
+                m_column<I>(ln, E, K, js[cb], fm, am);
             else                              // columns 16.. only
-                m_column<I, 16>(ln, E, K, js[cb], fm);
+                m_column<I, 16>(ln, E, K, js[cb], fm, am);
             if (owns[cb] && c == 2) {
 #pragma unroll
                 for (int i = 0; i < B; ++i)
                     s_M[pslot][i][js[cb]] = s_half(prismatic<I>(i), fm[i]);
+            }
+            if constexpr (kLinear) {
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    amk[cb][i] = am[i];
+                    fmk[cb][i] = fm[i];
+                }
             }
         }
         // the exchange stays inside this wavefront: order its LDS traffic only
@@ -970,7 +1016,37 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                     A.qdd[vbase + I::body[i]] = x[i];
         }
         V xd[B], Df[B];
-        delta_rnea<I>(ln, E, K, x, xd, Df);
+        if constexpr (kLinear) {
+            // RNEA is linear in qdd: Da_i = sum_k qdd_k a_i^(k) and Df_i = sum_k qdd_k f_i^(k)
+            // over the unit-acceleration responses of the columns k of M (quad k holds column
+            // k's), so the increments are a sum over the problem's quads instead of another
+            // sweep down and up the tree; xd_i = X_i Da_lambda(i) = Da_i - S_i qdd_i
+            // qdd_k of the quad's column k as a sum of x_k times a 0/1 mask (a chain of
+            // selects of the array's elements folds into one indexed load, and the array then
+            // moves to memory)
+            float wk[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                wk[cb] = 0.0f;
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    wk[cb] += (owns[cb] && js[cb] == k ? 1.0f : 0.0f) * x[k];
+            }
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                V da{0.0f, 0.0f}, df{0.0f, 0.0f};
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    da = V{da.a + wk[cb] * amk[cb][i].a, da.l + wk[cb] * amk[cb][i].l};
+                    df = V{df.a + wk[cb] * fmk[cb][i].a, df.l + wk[cb] * fmk[cb][i].l};
+                }
+                da = V{quad_group_sum<QB>(da.a), quad_group_sum<QB>(da.l)};
+                Df[i] = V{quad_group_sum<QB>(df.a), quad_group_sum<QB>(df.l)};
+                xd[i] = add_s(ln, prismatic<I>(i), da, -x[i]);
+            }
+        } else {
+            delta_rnea<I>(ln, E, K, x, xd, Df);
+        }
         V none[B];                            // velocities do not enter the dv = 0 sweep
 #pragma unroll
         for (int i = 0; i < B; ++i)

@@ -100,12 +100,48 @@ __device__ __forceinline__ void pick6(const float (&arr)[B][6], int j, float (&o
             out[k] = (i == j) ? arr[i][k] : out[k];
 }
 
+// The 64 knots of a wavefront own one contiguous block of each output array when their branch
+// is the whole robot (N == B). Lane-per-knot stores of one element each hit 64 addresses
+// N^2 floats apart, so for small robots the outputs are staged in LDS (two [64][N][N] arrays)
+// and written out by the wavefront as contiguous 16-byte stores.
+template <int B, int N>
+struct SerialStage {
+    static constexpr bool on = N == B && 2 * 64 * N * N * 4 <= 32 * 1024;
+    static constexpr int floats = on ? 64 * N * N : 4;
+};
+
+// the workgroup is one wavefront: ordering its own LDS traffic needs no workgroup barrier
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// copy `cnt` floats from LDS to global memory: 16 bytes per lane and step when the destination
+// is 16-byte aligned (the staging array is; a wavefront's block starts at a multiple of 64 N
+// floats, so only the caller's base address decides), else one float per lane and step
+__device__ __forceinline__ void flush_stage(float* dst, const float* src, int cnt, int lane)
+{
+    int done = 0;
+    if ((reinterpret_cast<unsigned long>(dst) & 15ul) == 0) {
+        const int n4 = cnt / 4;
+        for (int e = lane; e < n4; e += 64)
+            reinterpret_cast<float4*>(dst)[e] = reinterpret_cast<const float4*>(src)[e];
+        done = 4 * n4;
+    }
+    for (int e = done + lane; e < cnt; e += 64)
+        dst[e] = src[e];
+}
+
 template <class I>
 __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 {
     using S = typename I::S;
     constexpr int B = S::B;
     constexpr int N = I::N;
+    using ST = SerialStage<B, N>;
+    __shared__ __align__(16) float s_stage[2][ST::floats];
     const int lane = (int)threadIdx.x;
     const int kraw = block * 64 + lane;
     const bool valid = kraw < A.nknots;
@@ -243,8 +279,13 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
             // entries (i, jm), i <= jm, written to both mirrored positions: exactly symmetric
 #pragma unroll
             for (int i = 0; i <= jm; ++i) {
-                A.Minv[mbase + (long)I::body[i] * N + I::body[jm]] = mc[i];
-                A.Minv[mbase + (long)I::body[jm] * N + I::body[i]] = mc[i];
+                if constexpr (ST::on) {
+                    s_stage[0][lane * N * N + I::body[i] * N + I::body[jm]] = mc[i];
+                    s_stage[0][lane * N * N + I::body[jm] * N + I::body[i]] = mc[i];
+                } else {
+                    A.Minv[mbase + (long)I::body[i] * N + I::body[jm]] = mc[i];
+                    A.Minv[mbase + (long)I::body[jm] * N + I::body[i]] = mc[i];
+                }
             }
         }
     }
@@ -253,7 +294,20 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
     for (int i = 0; i < B; ++i)
         x[i] = A.tau[vbase + I::body[i]] - F[i][s_index(prismatic<I>(i))];
     gridq::ltl_solve<S>(Lf, dinv, x);
-    if (valid) {
+    // the wavefront's valid knots (its first knot is block * 64) and their output blocks
+    const int nv = min(64, A.nknots - block * 64);
+    const long kb = (long)block * 64;
+    if constexpr (ST::on) {
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                s_stage[1][lane * N + I::body[i]] = x[i];
+        }
+        wave_lds_sync();                      // M^-1 and qdd staged
+        flush_stage(A.Minv + kb * N * N, s_stage[0], nv * N * N, lane);
+        flush_stage(A.qdd + kb * N, s_stage[1], nv * N, lane);
+        wave_lds_sync();                      // staging free for the derivative columns
+    } else if (valid) {
 #pragma unroll
         for (int i = 0; i < B; ++i)
             A.qdd[vbase + I::body[i]] = x[i];
@@ -409,10 +463,20 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
             const int gj = I::body_of(j);
 #pragma unroll
             for (int i = 0; i < B; ++i) {
-                A.dqdd_dq[mbase + (long)I::body[i] * N + gj] = -dx[0][i];
-                A.dqdd_dqd[mbase + (long)I::body[i] * N + gj] = -dx[1][i];
+                if constexpr (ST::on) {
+                    s_stage[0][lane * N * N + I::body[i] * N + gj] = -dx[0][i];
+                    s_stage[1][lane * N * N + I::body[i] * N + gj] = -dx[1][i];
+                } else {
+                    A.dqdd_dq[mbase + (long)I::body[i] * N + gj] = -dx[0][i];
+                    A.dqdd_dqd[mbase + (long)I::body[i] * N + gj] = -dx[1][i];
+                }
             }
         }
+    }
+    if constexpr (ST::on) {
+        wave_lds_sync();                      // every column staged
+        flush_stage(A.dqdd_dq + kb * N * N, s_stage[0], nv * N * N, lane);
+        flush_stage(A.dqdd_dqd + kb * N * N, s_stage[1], nv * N * N, lane);
     }
     if (valid && N > B) {
         // this branch's rows hold zeros in the other branches' columns

@@ -96,3 +96,39 @@ def test_tune_apply_rejects_bad_tables():
         grid.tune_apply(m, {})
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("name", ["chain7", "chain2", "chain7-prism"])
+def test_serial_build_unaligned_outputs(name):
+    """Build 5 stages the outputs of single-branch robots in LDS and writes them with 16-byte
+    stores when the output arrays are 16-byte aligned, else one float at a time: outputs at an
+    offset of one float from an aligned base equal the aligned run bit for bit (N = 100: one
+    full and one partial wavefront)."""
+    import torch
+    robot = ROBOTS[name]()
+    m = grid.Model(robot)
+    try:
+        grid.tune_apply(m, {1 << 22: grid.BUILD_SERIAL})
+        n, N = robot.n, 100
+        kn = synth.random_knots(n, N, 808)
+        ins = [torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)]
+        say(f"[gpu] build 5 aligned vs unaligned outputs: {name} N={N}")
+        sizes = (N * n, N * n * n, N * n * n, N * n * n)
+        runs = []
+        for off in (0, 1):
+            bufs = [torch.full((s + 4,), float("nan"), device="cuda") for s in sizes]
+            outs = [b[off:off + s] for b, s in zip(bufs, sizes)]
+            m.fd_grad(*ins, *outs, N=N)
+            torch.cuda.synchronize()
+            runs.append([o.cpu().numpy() for o in outs])
+            # nothing written outside the arrays
+            for b, s in zip(bufs, sizes):
+                head = b[:off].cpu().numpy()
+                tail = b[off + s:].cpu().numpy()
+                assert np.all(np.isnan(head)) and np.all(np.isnan(tail))
+        for a, b in zip(*runs):
+            assert np.all(np.isfinite(a))
+            np.testing.assert_array_equal(b, a)
+    finally:
+        grid.tune_apply(m, {})
+        m.close()
