@@ -385,6 +385,12 @@ def serve(args, grid, synth, chain_model=None):
                                                     for k, v in r["p50_split"].items()},
                                    "p99_split_us": {k.replace("_us", ""): round(v, 2)
                                                     for k, v in r["p99_split"].items()},
+                                   "per_model": {
+                                       rb.name.split("-")[0]: {
+                                           "requests": r["model_requests"][k],
+                                           "p50_us": round(r["model_p50_us"][k], 1),
+                                           "p99_us": round(r["model_p99_us"][k], 1)}
+                                       for k, rb in enumerate(robots)},
                                    "measured_s": secs,
                                    "requests_per_s": r["requests"] / r["seconds"],
                                    "knot_evals_per_s": r["knots"] / r["seconds"]}

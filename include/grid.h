@@ -583,6 +583,8 @@ typedef struct grid_latency_split {
     double queue_us, h2d_us, kernel_us, d2h_us, complete_us, copyout_us;
 } grid_latency_split;
 
+#define GRID_LOADGEN_MODELS 8       /* models with their own latency percentiles below */
+
 typedef struct grid_loadgen_result {
     uint64_t requests, knots;    /* completed in the measured window */
     double seconds;              /* measured window */
@@ -590,6 +592,9 @@ typedef struct grid_loadgen_result {
     double offered_rate_per_s;
     double requests_per_launch;  /* over the whole run */
     grid_latency_split p50, p99; /* per phase, over the measured requests */
+    /* per model (index < GRID_LOADGEN_MODELS; 0 for a model without requests) */
+    uint64_t model_requests[GRID_LOADGEN_MODELS];
+    double model_p50_us[GRID_LOADGEN_MODELS], model_p99_us[GRID_LOADGEN_MODELS];
 } grid_loadgen_result;
 
 grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,

@@ -662,6 +662,7 @@ grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
     const double total_s = cfg->warmup_s + cfg->duration_s;
     double t_arr = 0.0;
     std::vector<double> lat;
+    std::vector<std::vector<double>> lat_model(std::min(nm, GRID_LOADGEN_MODELS));
     std::vector<double> split[6];   // queue, h2d, kernel, d2h, complete, copyout (us)
     uint64_t knots = 0;
     const uint64_t launches0 = s->launches.load();
@@ -675,6 +676,8 @@ grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
         if (r && wait_final(s, r, -1) && e.counted &&
             r->state.load(std::memory_order_acquire) == kDone) {
             lat.push_back(us(e.t_sched, r->t_done));
+            if (e.model < GRID_LOADGEN_MODELS)
+                lat_model[e.model].push_back(lat.back());
             split[0].push_back(us(e.t_sched, r->t_launch));
             split[1].push_back(1e3 * r->h2d_ms);
             split[2].push_back(1e3 * r->kernel_ms);
@@ -754,6 +757,12 @@ grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
         *p99f[k] = pct_of(split[k], 0.99);
     }
     out->requests_per_launch = nlaunch ? (double)sent.size() / (double)nlaunch : 0.0;
+    for (size_t k = 0; k < lat_model.size(); ++k) {
+        std::sort(lat_model[k].begin(), lat_model[k].end());
+        out->model_requests[k] = lat_model[k].size();
+        out->model_p50_us[k] = pct_of(lat_model[k], 0.50);
+        out->model_p99_us[k] = pct_of(lat_model[k], 0.99);
+    }
     double mean = 0;
     for (double x : lat)
         mean += x;

@@ -77,7 +77,9 @@ class LoadgenResult(C.Structure):
                 ("p50_us", C.c_double), ("p90_us", C.c_double), ("p99_us", C.c_double),
                 ("max_us", C.c_double), ("mean_us", C.c_double),
                 ("offered_rate_per_s", C.c_double), ("requests_per_launch", C.c_double),
-                ("p50", LatencySplit), ("p99", LatencySplit)]
+                ("p50", LatencySplit), ("p99", LatencySplit),
+                ("model_requests", C.c_uint64 * 8), ("model_p50_us", C.c_double * 8),
+                ("model_p99_us", C.c_double * 8)]
 
 
 class GridItem(C.Structure):
@@ -797,6 +799,9 @@ class Server:
         out = {}
         for k, t in LoadgenResult._fields_:
             v = getattr(r, k)
+            if k.startswith("model_"):
+                out[k] = [v[i] for i in range(len(self.models))][:8]
+                continue
             if t is LatencySplit:
                 out[k + "_split"] = {f: float(getattr(v, f)) for f, _ in LatencySplit._fields_}
             else:

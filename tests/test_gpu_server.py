@@ -203,6 +203,18 @@ def test_loadgen_short_run(models):
         sp = r[q]
         assert sp["kernel_us"] > 0 and sp["h2d_us"] > 0 and sp["d2h_us"] > 0
         assert all(0 <= v <= r["max_us"] for v in sp.values()), sp
+    # per model: every model served, the counts add up, each model's percentiles ordered
+    assert sum(r["model_requests"]) == r["requests"] and all(n > 0 for n in r["model_requests"])
+    for k in range(3):
+        assert 0 < r["model_p50_us"][k] <= r["model_p99_us"][k] <= r["max_us"]
+    srv.close()
+    # mapped I/O: no copy-engine phases
+    srv = grid.Server(ms, budget_bytes=1 << 30, max_batch_knots=1024,
+                      flags=grid.GRID_SERVER_MAPPED_IO)
+    r = srv.loadgen(5000, 0.3, [0.5, 0.3, 0.2], warmup_s=0.1)
+    say(f"  mapped: p50 {r['p50_us']:.0f} us, p99 {r['p99_us']:.0f} us")
+    assert r["requests"] > 500 and r["p50_split"]["h2d_us"] == 0 and r["p99_split"]["d2h_us"] == 0
+    assert r["p50_split"]["kernel_us"] > 0
     srv.close()
 
 
