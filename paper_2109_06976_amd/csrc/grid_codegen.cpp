@@ -146,9 +146,9 @@ int64_t workgroups_pipe(const Topology& t, int64_t nknots)
     return total;
 }
 
-int64_t workgroups_serial(const Topology& t, int64_t nknots)
+int64_t workgroups_serial(const Topology& t, int64_t nknots, int knots_per_wave)
 {
-    return (int64_t)t.insts.size() * ((nknots + 63) / 64);
+    return (int64_t)t.insts.size() * ((nknots + knots_per_wave - 1) / knots_per_wave);
 }
 
 // standalone algorithms (ID, FD, M^-1, dID, VJP): problems per workgroup, as in grid_ops.hip
@@ -390,6 +390,9 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << "\n// generated: workgroup -> (branch, 64 knots), one lane per knot\n";
     emit_dispatch(os, t, "__device__ void grid_dispatch_s(const grid::Args& a, int block)", "64",
              "grids::run_serial<@>(a, b)");
+    os << "\n// generated: workgroup -> (branch, 16 knots), four lanes per knot\n";
+    emit_dispatch(os, t, "__device__ void grid_dispatch_s4(const grid::Args& a, int block)", "16",
+             "grids::run_serial<@, 4>(a, b)");
     os << "#line 1 \"grid_ops.hip\"\n";
     os << grid_ops_src;
     os << "\n// generated: workgroup -> (branch, problem group), standalone algorithms\n";

@@ -810,6 +810,9 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                                               // bodies the factor L instead (B -> A)
     __shared__ float s_dinv[P][B];            // 1 / L_kk beyond 16 bodies (B -> A)
     __shared__ float s_D[P][B][B];            // qdd part of the q-columns, [column][row] (B -> A)
+    // role B's weighted unit-acceleration responses, [problem][quad][body][component]: the
+    // increments at qdd summed over the quads (branches of up to 16 bodies)
+    __shared__ float4 s_red[B <= 16 ? P : 1][B <= 16 ? PS::QB : 1][B <= 16 ? B : 1][3];
     __shared__ float4 s_tab[3 * B * 4];       // the model's lane table (roles A, B)
 
     int tid = (int)threadIdx.x;
@@ -1015,15 +1018,17 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 if ((i & 3) == c)
                     A.qdd[vbase + I::body[i]] = x[i];
         }
-        V xd[B], Df[B];
+        // per column of this quad: xd_j = X_j Da_lambda(j) and Df_j, the sources of its sweep
+        V xdj[CB], Dfj[CB];
         if constexpr (kLinear) {
             // RNEA is linear in qdd: Da_i = sum_k qdd_k a_i^(k) and Df_i = sum_k qdd_k f_i^(k)
             // over the unit-acceleration responses of the columns k of M (quad k holds column
             // k's), so the increments are a sum over the problem's quads instead of another
-            // sweep down and up the tree; xd_i = X_i Da_lambda(i) = Da_i - S_i qdd_i
-            // qdd_k of the quad's column k as a sum of x_k times a 0/1 mask (a chain of
-            // selects of the array's elements folds into one indexed load, and the array then
-            // moves to memory)
+            // sweep down and up the tree; xd_j = Da_j - S_j qdd_j. Each quad writes its weighted
+            // responses of every body to LDS and sums the ones of its own bodies j over the
+            // quads. qdd_k of the quad's column k comes as a sum of x_k times a 0/1 mask (a
+            // chain of selects of the array's elements folds into one indexed load, and the
+            // array then moves to memory).
             float wk[CB];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
@@ -1032,20 +1037,42 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 for (int k = 0; k < B; ++k)
                     wk[cb] += (owns[cb] && js[cb] == k ? 1.0f : 0.0f) * x[k];
             }
+            const int cc = c == 3 ? 0 : c;
+            if (c != 3) {
 #pragma unroll
-            for (int i = 0; i < B; ++i) {
-                V da{0.0f, 0.0f}, df{0.0f, 0.0f};
+                for (int i = 0; i < B; ++i) {
+                    V da{0.0f, 0.0f}, df{0.0f, 0.0f};
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    da = V{da.a + wk[cb] * amk[cb][i].a, da.l + wk[cb] * amk[cb][i].l};
-                    df = V{df.a + wk[cb] * fmk[cb][i].a, df.l + wk[cb] * fmk[cb][i].l};
+                    for (int cb = 0; cb < CB; ++cb) {
+                        da = V{da.a + wk[cb] * amk[cb][i].a, da.l + wk[cb] * amk[cb][i].l};
+                        df = V{df.a + wk[cb] * fmk[cb][i].a, df.l + wk[cb] * fmk[cb][i].l};
+                    }
+                    s_red[pslot][s][i][cc] = float4{da.a, da.l, df.a, df.l};
                 }
-                da = V{quad_group_sum<QB>(da.a), quad_group_sum<QB>(da.l)};
-                Df[i] = V{quad_group_sum<QB>(df.a), quad_group_sum<QB>(df.l)};
-                xd[i] = add_s(ln, prismatic<I>(i), da, -x[i]);
+            }
+            // the exchange stays inside this wavefront: order its LDS traffic only
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                float4 t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int q = 0; q < QB; ++q) {
+                    const float4 u = s_red[pslot][q][js[cb]][cc];
+                    t = float4{t.x + u.x, t.y + u.y, t.z + u.z, t.w + u.w};
+                }
+                xdj[cb] = add_s(ln, prismatic<I>(js[cb]), V{t.x, t.y}, -wk[cb]);
+                Dfj[cb] = V{t.z, t.w};
             }
         } else {
+            V xd[B], Df[B];
             delta_rnea<I>(ln, E, K, x, xd, Df);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                xdj[cb] = pick<B>(xd, js[cb]);
+                Dfj[cb] = pick<B>(Df, js[cb]);
+            }
         }
         V none[B];                            // velocities do not enter the dv = 0 sweep
 #pragma unroll
@@ -1058,8 +1085,8 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
             LaneK Kj;
             pick_joint<I>(E, K, j, Ej, Kj);
             const bool pj = prismatic<I>(j);
-            const V src_a = cross_s(ln, pj, pick<B>(xd, j));
-            const V src_f = back_source(ln, pj, Ej, Kj, pick<B>(Df, j));
+            const V src_a = cross_s(ln, pj, xdj[cb]);
+            const V src_f = back_source(ln, pj, Ej, Kj, Dfj[cb]);
             float dxc[B];
             if (cb == 0)
                 drnea_column<I, false>(ln, qd, E, K, none, none, j, V{0.0f, 0.0f}, src_a,

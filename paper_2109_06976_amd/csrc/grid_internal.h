@@ -21,7 +21,8 @@ constexpr int kVariantQuad = 0;
 constexpr int kVariantLane1 = 1;
 constexpr int kVariantPipe = 4;
 constexpr int kVariantSerial = 5;
-constexpr int kNumVariants = 6;
+constexpr int kVariantSerial4 = 6;
+constexpr int kNumVariants = 7;
 
 // standalone algorithms (grid_ops.hip)
 constexpr int kOpId = 0;
@@ -129,7 +130,7 @@ grid_status validate_desc(const grid_model_desc* d, std::string* err);
 int64_t workgroups_for(const Topology& t, int64_t nknots);
 int64_t workgroups_quad(const Topology& t, int64_t nknots);
 int64_t workgroups_pipe(const Topology& t, int64_t nknots);
-int64_t workgroups_serial(const Topology& t, int64_t nknots);
+int64_t workgroups_serial(const Topology& t, int64_t nknots, int knots_per_wave = 64);
 int64_t workgroups_op(const Topology& t, int64_t nknots, int op);
 int pipe_problems(int B);
 int pipe_waves(const Topology& t);

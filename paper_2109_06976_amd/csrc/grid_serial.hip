@@ -100,14 +100,14 @@ __device__ __forceinline__ void pick6(const float (&arr)[B][6], int j, float (&o
             out[k] = (i == j) ? arr[i][k] : out[k];
 }
 
-// The 64 knots of a wavefront own one contiguous block of each output array when their branch
+// The K knots of a wavefront own one contiguous block of each output array when their branch
 // is the whole robot (N == B). Lane-per-knot stores of one element each hit 64 addresses
-// N^2 floats apart, so for small robots the outputs are staged in LDS (two [64][N][N] arrays)
+// N^2 floats apart, so for small robots the outputs are staged in LDS (two [K][N][N] arrays)
 // and written out by the wavefront as contiguous 16-byte stores.
-template <int B, int N>
+template <int B, int N, int K>
 struct SerialStage {
-    static constexpr bool on = N == B && 2 * 64 * N * N * 4 <= 32 * 1024;
-    static constexpr int floats = on ? 64 * N * N : 4;
+    static constexpr bool on = N == B && 2 * K * N * N * 4 <= 32 * 1024;
+    static constexpr int floats = on ? K * N * N : 4;
 };
 
 // the workgroup is one wavefront: ordering its own LDS traffic needs no workgroup barrier
@@ -134,16 +134,23 @@ __device__ __forceinline__ void flush_stage(float* dst, const float* src, int cn
         dst[e] = src[e];
 }
 
-template <class I>
+// L lanes per knot (1: build 5; 4: build 6). Every lane of a knot runs steps 1-5; the columns
+// of M^-1 and the joints j of step 6 are dealt out among them (lane h takes h, h + L, ...), so
+// a wavefront holds 64 / L knots: L times the wavefronts of build 5 for the same batch, at the
+// cost of repeating steps 1-5 L times. The lanes of a knot are adjacent.
+template <class I, int L = 1>
 __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 {
     using S = typename I::S;
     constexpr int B = S::B;
     constexpr int N = I::N;
-    using ST = SerialStage<B, N>;
+    constexpr int K = 64 / L;                        // knots per wavefront
+    using ST = SerialStage<B, N, K>;
     __shared__ __align__(16) float s_stage[2][ST::floats];
     const int lane = (int)threadIdx.x;
-    const int kraw = block * 64 + lane;
+    const int h = lane % L;                          // this lane's share of the columns
+    const int kl = lane / L;                         // the knot within the wavefront
+    const int kraw = block * K + kl;
     const bool valid = kraw < A.nknots;
     const int knot = valid ? kraw : A.nknots - 1;   // tail lanes recompute the last knot
     const float* C = I::consts();                   // literals: folded into the code
@@ -268,7 +275,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
     gridq::ltl_factor<S>(Lf, dinv);
 
     // ------------------------------------------------------------ 4. M^-1 and qdd
-    if (valid) {
+    if (valid && L == 1) {
 #pragma unroll
         for (int jm = 0; jm < B; ++jm) {
             float mc[B];
@@ -280,11 +287,34 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 #pragma unroll
             for (int i = 0; i <= jm; ++i) {
                 if constexpr (ST::on) {
-                    s_stage[0][lane * N * N + I::body[i] * N + I::body[jm]] = mc[i];
-                    s_stage[0][lane * N * N + I::body[jm] * N + I::body[i]] = mc[i];
+                    s_stage[0][kl * N * N + I::body[i] * N + I::body[jm]] = mc[i];
+                    s_stage[0][kl * N * N + I::body[jm] * N + I::body[i]] = mc[i];
                 } else {
                     A.Minv[mbase + (long)I::body[i] * N + I::body[jm]] = mc[i];
                     A.Minv[mbase + (long)I::body[jm] * N + I::body[i]] = mc[i];
+                }
+            }
+        }
+    } else if (valid) {
+        // the knot's lanes share the columns of M^-1
+#pragma unroll 1
+        for (int jm = h; jm < B; jm += L) {
+            float mc[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                mc[i] = (i == jm) ? 1.0f : 0.0f;
+            gridq::ltl_solve<S>(Lf, dinv, mc);
+            const int gm = I::body_of(jm);
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                if (i > jm)
+                    continue;
+                if constexpr (ST::on) {
+                    s_stage[0][kl * N * N + I::body[i] * N + gm] = mc[i];
+                    s_stage[0][kl * N * N + gm * N + I::body[i]] = mc[i];
+                } else {
+                    A.Minv[mbase + (long)I::body[i] * N + gm] = mc[i];
+                    A.Minv[mbase + (long)gm * N + I::body[i]] = mc[i];
                 }
             }
         }
@@ -294,20 +324,20 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
     for (int i = 0; i < B; ++i)
         x[i] = A.tau[vbase + I::body[i]] - F[i][s_index(prismatic<I>(i))];
     gridq::ltl_solve<S>(Lf, dinv, x);
-    // the wavefront's valid knots (its first knot is block * 64) and their output blocks
-    const int nv = min(64, A.nknots - block * 64);
-    const long kb = (long)block * 64;
+    // the wavefront's valid knots (its first knot is block * K) and their output blocks
+    const int nv = min(K, A.nknots - block * K);
+    const long kb = (long)block * K;
     if constexpr (ST::on) {
-        if (valid) {
+        if (valid && h == 0) {
 #pragma unroll
             for (int i = 0; i < B; ++i)
-                s_stage[1][lane * N + I::body[i]] = x[i];
+                s_stage[1][kl * N + I::body[i]] = x[i];
         }
         wave_lds_sync();                      // M^-1 and qdd staged
         flush_stage(A.Minv + kb * N * N, s_stage[0], nv * N * N, lane);
         flush_stage(A.qdd + kb * N, s_stage[1], nv * N, lane);
         wave_lds_sync();                      // staging free for the derivative columns
-    } else if (valid) {
+    } else if (valid && h == 0) {
 #pragma unroll
         for (int i = 0; i < B; ++i)
             A.qdd[vbase + I::body[i]] = x[i];
@@ -351,7 +381,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 
     // ------------------------------------------------------------ 6. dRNEA and dFD columns
 #pragma unroll 1
-    for (int j = 0; j < B; ++j) {
+    for (int j = h; j < B; j += L) {
         // sources of joint j: u = q: dv += v_j x S, da += (X_j a_lambda(j)) x S,
         // backward += X_j^T (S x* f_j); u = qd: dv += S, da += v_j x S
         float vj[6], xaj[6], Fj[6], Ej[9], rj[3];
@@ -464,8 +494,8 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 #pragma unroll
             for (int i = 0; i < B; ++i) {
                 if constexpr (ST::on) {
-                    s_stage[0][lane * N * N + I::body[i] * N + gj] = -dx[0][i];
-                    s_stage[1][lane * N * N + I::body[i] * N + gj] = -dx[1][i];
+                    s_stage[0][kl * N * N + I::body[i] * N + gj] = -dx[0][i];
+                    s_stage[1][kl * N * N + I::body[i] * N + gj] = -dx[1][i];
                 } else {
                     A.dqdd_dq[mbase + (long)I::body[i] * N + gj] = -dx[0][i];
                     A.dqdd_dqd[mbase + (long)I::body[i] * N + gj] = -dx[1][i];
@@ -480,7 +510,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
     }
     if (valid && N > B) {
         // this branch's rows hold zeros in the other branches' columns
-        for (int e = 0; e < B * N; ++e) {
+        for (int e = h; e < B * N; e += L) {
             const int i = e / N, c2 = e % N;
             if (!I::contains(c2)) {
                 const long o = mbase + (long)I::body_of(i) * N + c2;
@@ -504,6 +534,14 @@ __device__ void grid_dispatch_s(const grid::Args& args, int block);
 extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_serial(grid::Args args)
 {
     grid_dispatch_s(args, (int)blockIdx.x);
+}
+
+// defined by the generated epilogue: workgroup -> (branch, 16 knots), four lanes per knot
+__device__ void grid_dispatch_s4(const grid::Args& args, int block);
+
+extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_serial4(grid::Args args)
+{
+    grid_dispatch_s4(args, (int)blockIdx.x);
 }
 
 #endif  // GRID_PIPE_ONLY

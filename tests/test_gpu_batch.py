@@ -69,7 +69,7 @@ def test_mixed_graph_equals_alone_and_updates():
 
 
 @pytest.mark.parametrize("robot_name,variant",
-                         [(r, v) for r in ("chain7", "quad12", "humanoid30") for v in range(6)])
+                         [(r, v) for r in ("chain7", "quad12", "humanoid30") for v in range(len(grid.BUILD_KERNELS))])
 def test_every_tuned_build_matches_oracle(orc, tmp_path, variant, robot_name):
     import torch
     robot = synth.model_by_name(robot_name)
@@ -80,7 +80,7 @@ def test_every_tuned_build_matches_oracle(orc, tmp_path, variant, robot_name):
     # every N and apply it at model creation
     m = grid.Model(robot)
     tuned = grid.tune(m, [64], table_path=str(table))
-    assert set(tuned.values()) <= set(range(6))
+    assert set(tuned.values()) <= set(range(len(grid.BUILD_KERNELS)))
     line = table.read_text().strip().splitlines()[-1]
     forced = line.split('"buckets"')[0] + f'"buckets": [[4194304, {variant}]]}}\n'
     table.write_text(forced)

@@ -1,7 +1,7 @@
 """Every build of the fused kernel against the FP64 oracle, through the C ABI, on an MI355X.
 
 Builds (grid_tune_apply pins one): 0 quad layout, 1-3 lane layout at 1, 2, 4 wavefronts per
-SIMD, 4 quad layout in two roles, 5 one lane per knot. Knot counts 1 and 37 leave ragged workgroups for every
+SIMD, 4 quad layout in three roles, 5 one lane per knot, 6 four lanes per knot. Knot counts 1 and 37 leave ragged workgroups for every
 packing; the tolerances are those of the parity tests (normwise per knot: qdd 1e-4, the
 matrices 1e-3), and M^-1 must come out exactly symmetric.
 """
@@ -54,7 +54,7 @@ def test_every_build_matches_oracle(orc, name):
     robot = ROBOTS[name]()
     m = grid.Model(robot)
     try:
-        for build in range(6):
+        for build in range(len(grid.BUILD_KERNELS)):
             grid.tune_apply(m, {1 << 22: build})
             assert grid.build_for(m, 5) == build
             for N in (1, 37, 130):
@@ -86,7 +86,7 @@ def test_tune_apply_rejects_bad_tables():
     try:
         for Ns, builds, status in (([64, 32], [0, 0], grid.GRID_EINVAL),
                                    ([0], [0], grid.GRID_EINVAL),
-                                   ([64], [6], grid.GRID_EUNSUPPORTED),
+                                   ([64], [len(grid.BUILD_KERNELS)], grid.GRID_EUNSUPPORTED),
                                    ([64], [-1], grid.GRID_EUNSUPPORTED)):
             n = np.array(Ns, np.int32)
             b = np.array(builds, np.int32)
@@ -98,21 +98,22 @@ def test_tune_apply_rejects_bad_tables():
         m.close()
 
 
+@pytest.mark.parametrize("build", [grid.BUILD_SERIAL, grid.BUILD_SERIAL4])
 @pytest.mark.parametrize("name", ["chain7", "chain2", "chain7-prism"])
-def test_serial_build_unaligned_outputs(name):
-    """Build 5 stages the outputs of single-branch robots in LDS and writes them with 16-byte
-    stores when the output arrays are 16-byte aligned, else one float at a time: outputs at an
-    offset of one float from an aligned base equal the aligned run bit for bit (N = 100: one
-    full and one partial wavefront)."""
+def test_serial_build_unaligned_outputs(name, build):
+    """Builds 5 and 6 stage the outputs of single-branch robots in LDS and write them with
+    16-byte stores when the output arrays are 16-byte aligned, else one float at a time: outputs
+    at an offset of one float from an aligned base equal the aligned run bit for bit (N = 100:
+    full and partial wavefronts)."""
     import torch
     robot = ROBOTS[name]()
     m = grid.Model(robot)
     try:
-        grid.tune_apply(m, {1 << 22: grid.BUILD_SERIAL})
+        grid.tune_apply(m, {1 << 22: build})
         n, N = robot.n, 100
         kn = synth.random_knots(n, N, 808)
         ins = [torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)]
-        say(f"[gpu] build 5 aligned vs unaligned outputs: {name} N={N}")
+        say(f"[gpu] build {build} aligned vs unaligned outputs: {name} N={N}")
         sizes = (N * n, N * n * n, N * n * n, N * n * n)
         runs = []
         for off in (0, 1):

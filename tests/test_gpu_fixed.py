@@ -64,7 +64,7 @@ def test_fixed_joint_robots_match_locked_oracle(orc, name):
         kn = synth.random_knots(nd, N, 610)
         ref = locked_reference(orc, robot, kn.q.astype(float), kn.qd.astype(float),
                                kn.tau.astype(float))
-        for build in range(6):
+        for build in range(len(grid.BUILD_KERNELS)):
             grid.tune_apply(m, {1 << 22: build})
             say(f"[gpu] {name} (n_dof={nd}): build {build}, N={N}")
             out = grid.fd_grad_torch(m, *(torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)))
