@@ -361,12 +361,16 @@ def serve(args, grid, synth, chain_model=None):
                      "batch_window_us": args.serve_window_us,
                      "min_batch_knots": args.serve_min_knots}
     # batched: fused launches reading and writing the pinned staging through the device mapping;
-    # batched_copy_engines: the same with H2D / D2H copies (at the headline rate only);
+    # batched_in_place: the clients' arrays are pinned and registered, and a batch of one request
+    # runs on them directly (no staging copy, no copy-out);
+    # batched_copy_engines: the staged form with H2D / D2H copies (at the headline rate only);
     # per_request_plain: one staged launch per request with ordinary copies (the baseline)
-    for label, flags, lrates in (
-            ("batched", grid.GRID_SERVER_MAPPED_IO, rates),
-            ("batched_copy_engines", 0, rates[:1]),
-            ("per_request_plain", grid.GRID_SERVER_PER_REQUEST, rates)):
+    mapped, direct = grid.GRID_SERVER_MAPPED_IO, grid.GRID_SERVER_DIRECT_PINNED
+    for label, flags, lrates, pinned in (
+            ("batched", mapped, rates, False),
+            ("batched_in_place", mapped | direct, rates, True),
+            ("batched_copy_engines", 0, rates[:1], False),
+            ("per_request_plain", grid.GRID_SERVER_PER_REQUEST, rates, False)):
         batched = not flags & grid.GRID_SERVER_PER_REQUEST
         srv = grid.Server(models, budget_bytes=1 << 30, max_batch_knots=2048,
                           contexts_per_model=args.serve_contexts if batched else 3, flags=flags,
@@ -375,7 +379,8 @@ def serve(args, grid, synth, chain_model=None):
         res = {}
         for rate in lrates:
             secs = args.serve_seconds if rate == args.serve_rate else args.serve_sweep_seconds
-            r = srv.loadgen(rate, secs, probs, n_min=16, n_max=256, warmup_s=1.0, seed=7)
+            r = srv.loadgen(rate, secs, probs, n_min=16, n_max=256, warmup_s=1.0, seed=7,
+                            pinned=pinned)
             progress(f"served {label} at {int(rate)} req/s: p50 {r['p50_us']:.0f} us, "
                      f"p99 {r['p99_us']:.0f} us, {r['requests_per_launch']:.2f} requests/launch")
             res[str(int(rate))] = {"p50_us": r["p50_us"], "p90_us": r["p90_us"],
@@ -394,7 +399,10 @@ def serve(args, grid, synth, chain_model=None):
                                    "measured_s": secs,
                                    "requests_per_s": r["requests"] / r["seconds"],
                                    "knot_evals_per_s": r["knots"] / r["seconds"]}
-        res["launches"] = srv.stats()["launches"]
+        st = srv.stats()
+        res["launches"] = st["launches"]
+        if pinned:
+            res["in_place_launches"] = st["inplace_launches"]
         srv.close()
         out[label] = res
     for m in models[1:] + ([] if chain_model else models[:1]):

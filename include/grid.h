@@ -514,12 +514,19 @@ typedef struct grid_server_s* grid_server;
  * through the device's mapping of it (no copy-engine H2D and D2H; as grid_fd_grad_mapped with
  * GRID_IO_DIRECT). The loadgen's H2D and D2H phases are then empty. */
 #define GRID_SERVER_MAPPED_IO 2
+/* A request whose seven arrays all lie inside pinned host ranges registered with
+ * grid_server_pin_range and that forms a batch alone is computed in place: the kernel reads
+ * the caller's inputs and writes the caller's outputs through the device's mapping, with no
+ * staging copy in and no copy-out (the loadgen's copy-out phase is then empty). Requests
+ * packed with others, and other arrays, take the staged path. */
+#define GRID_SERVER_DIRECT_PINNED 4
 
 typedef struct grid_server_config {
     size_t device_budget_bytes;  /* admission budget of in-flight request bytes (inputs+outputs) */
     int32_t max_batch_knots;     /* knots per launch, >= the largest request */
     int32_t contexts_per_model;  /* batch contexts (streams) per model, >= 1 */
-    uint32_t flags;              /* 0, or GRID_SERVER_PER_REQUEST and/or GRID_SERVER_MAPPED_IO */
+    uint32_t flags;              /* 0, or any of GRID_SERVER_PER_REQUEST, GRID_SERVER_MAPPED_IO,
+                                    GRID_SERVER_DIRECT_PINNED */
     /* Batching policy. While a model has no batch in flight, its admitted requests launch as
      * soon as a context is free. While one is in flight, the next batch of that model waits
      * until it holds min_batch_knots knots or its oldest request has waited batch_window_us
@@ -534,6 +541,7 @@ typedef struct grid_server_stats {
     uint64_t knots_completed;
     uint64_t launches;           /* device launches issued (fused, or staged pipelines) */
     uint64_t max_inflight_bytes;
+    uint64_t inplace_launches;   /* launches run in place on a request's own pinned arrays */
 } grid_server_stats;
 
 /* Create a server over `count` models (all on one device; the models must outlive the
@@ -563,6 +571,18 @@ grid_status grid_server_stats_get(grid_server s, grid_server_stats* out);
  * after this returns. */
 grid_status grid_server_destroy(grid_server s);
 
+/*
+ * Register (unregister) a range of pinned host memory for in-place requests on a
+ * GRID_SERVER_DIRECT_PINNED server: a request runs in place when each of its seven arrays lies
+ * inside a registered range and its batch holds it alone. The range must lie inside one
+ * allocation of pinned host memory mapped into the device (checked with the runtime's pointer
+ * queries when registering; EINVAL otherwise). The caller keeps the memory allocated until it
+ * unregisters the range and no request using it is in flight. At most 64 ranges per server;
+ * grid_server_unpin_range takes the pointer the range was registered with. Errors: EINVAL.
+ */
+grid_status grid_server_pin_range(grid_server s, const void* p, size_t bytes);
+grid_status grid_server_unpin_range(grid_server s, const void* p);
+
 /* Open-loop load generator for measurement: Poisson arrivals at `rate_per_s` for
  * `warmup_s + duration_s` seconds; each request picks model k with probability
  * model_prob[k] and N uniformly in [n_min, n_max]; inputs are drawn once per model
@@ -574,6 +594,8 @@ typedef struct grid_loadgen_config {
     const double* model_prob;    /* [count of server models], sums to 1 */
     int32_t n_min, n_max;
     uint64_t seed;
+    int32_t pinned;              /* nonzero: the clients' arrays are pinned host memory mapped
+                                    into the device (hipHostMalloc) rather than ordinary memory */
 } grid_loadgen_config;
 
 /* Where a request's latency goes (microseconds): queue = scheduled arrival to the launch of

@@ -46,6 +46,10 @@ struct Request {
     const float *q = nullptr, *qd = nullptr, *tau = nullptr;
     float *qdd = nullptr, *Minv = nullptr, *dq = nullptr, *dqd = nullptr;
     size_t bytes = 0;
+    // with GRID_SERVER_DIRECT_PINNED: the seven arrays as the device sees them, when all of them
+    // lie inside pinned host allocations mapped into the device (else direct = false)
+    bool direct = false;
+    float* dev[7] = {};
     std::atomic<int> state{kQueued};
     // timeline (host clock) and the device phases of its batch (ms)
     Clock::time_point t_admit, t_launch, t_seen, t_done;
@@ -62,6 +66,8 @@ struct BatchCtx {
     grid_workspace ws = nullptr;               // staged (per-request) mode only
     std::vector<Request*> reqs;
     int knots = 0;
+    bool inplace = false;                      // this batch runs on its request's own arrays
+    bool mapped = false;                       // and without copy-engine phases
     std::atomic<bool> busy{false};             // set by the scheduler, cleared by its worker
     std::thread worker;
     std::mutex mu;                             // launched, quit
@@ -70,6 +76,66 @@ struct BatchCtx {
 };
 
 size_t request_bytes(int n, int N) { return sizeof(float) * (size_t)N * (4 * n + 3 * n * n); }
+
+// The device address of host array [p, p + bytes) when the whole range lies inside one pinned
+// host allocation mapped into the device; NULL otherwise (pageable memory, a range that runs
+// past its allocation, or a failed query).
+// Host array for the load generator: ordinary memory, or pinned and mapped into the device.
+struct HostArray {
+    float* ptr = nullptr;
+    size_t len = 0;
+    bool pinned = false;
+    HostArray() = default;
+    HostArray(const HostArray&) = delete;
+    HostArray& operator=(const HostArray&) = delete;
+    ~HostArray()
+    {
+        if (pinned)
+            (void)hipHostFree(ptr);
+        else
+            delete[] ptr;
+    }
+    bool alloc(size_t n, bool pin)
+    {
+        len = n;
+        pinned = pin;
+        if (pin) {
+            void* p = nullptr;
+            if (hipHostMalloc(&p, n * sizeof(float), hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                pinned = false;
+                return false;
+            }
+            ptr = static_cast<float*>(p);
+        } else {
+            ptr = new (std::nothrow) float[n]();
+        }
+        return ptr != nullptr;
+    }
+    float* data() { return ptr; }
+    size_t size() const { return len; }
+    float& operator[](size_t i) { return ptr[i]; }
+};
+
+float* mapped_range(const void* p, size_t bytes)
+{
+    hipDeviceptr_t start = nullptr;
+    size_t size = 0;
+    hipPointerAttribute_t at{};
+    const hipDeviceptr_t hp = const_cast<void*>(p);
+    if (hipPointerGetAttribute(&start, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, hp) != hipSuccess ||
+        hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, hp) != hipSuccess ||
+        hipPointerGetAttributes(&at, start) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const char* s0 = static_cast<const char*>(start);
+    const char* c = static_cast<const char*>(p);
+    if (at.type != hipMemoryTypeHost || !at.devicePointer || c < s0 ||
+        (size_t)(c - s0) + bytes > size)
+        return nullptr;
+    return reinterpret_cast<float*>(static_cast<char*>(at.devicePointer) + (c - s0));
+}
 
 }  // namespace
 
@@ -93,8 +159,18 @@ struct grid_server_s {
     std::thread scheduler;
 
     std::atomic<uint64_t> submitted{0}, completed_n{0}, canceled{0}, knots_done{0}, launches{0};
-    std::atomic<uint64_t> max_inflight{0};
+    std::atomic<uint64_t> max_inflight{0}, inplace_launches{0};
     std::atomic<bool> device_error{false};
+
+    // pinned host ranges the caller registered for in-place requests: host start, length,
+    // the device's address of the start
+    struct PinRange {
+        const char* start;
+        size_t len;
+        char* dev;
+    };
+    std::mutex pin_mu;
+    std::vector<PinRange> pins;
 };
 
 namespace {
@@ -171,7 +247,7 @@ void worker_loop(grid_server s, BatchCtx* c)
         float ph[3] = {0, 0, 0};
         if (e != hipSuccess) {
             s->device_error.store(true);
-        } else if (s->cfg.flags & GRID_SERVER_MAPPED_IO) {
+        } else if (c->mapped) {
             (void)hipEventElapsedTime(&ph[1], c->ev[0], c->ev[3]);   // the kernel alone
         } else {
             for (int k = 0; k < 3; ++k)
@@ -189,10 +265,12 @@ void worker_loop(grid_server s, BatchCtx* c)
             r->h2d_ms = ph[0];
             r->kernel_ms = ph[1];
             r->d2h_ms = ph[2];
-            std::memcpy(r->qdd, oq + off * n, N * n * sizeof(float));
-            std::memcpy(r->Minv, oM + off * n * n, N * n * n * sizeof(float));
-            std::memcpy(r->dq, oD + off * n * n, N * n * n * sizeof(float));
-            std::memcpy(r->dqd, oV + off * n * n, N * n * n * sizeof(float));
+            if (!c->inplace) {                 // in place, the kernel wrote the caller's arrays
+                std::memcpy(r->qdd, oq + off * n, N * n * sizeof(float));
+                std::memcpy(r->Minv, oM + off * n * n, N * n * n * sizeof(float));
+                std::memcpy(r->dq, oD + off * n * n, N * n * n * sizeof(float));
+                std::memcpy(r->dqd, oV + off * n * n, N * n * n * sizeof(float));
+            }
             off += N;
             r->t_done = Clock::now();
             s->knots_done.fetch_add(N);
@@ -214,26 +292,32 @@ bool launch_ctx(grid_server s, BatchCtx* c)
     float* itau = iqd + K * n;
     size_t off = 0;
     const auto now = Clock::now();
+    c->inplace = c->reqs.size() == 1 && c->reqs[0]->direct;
     for (Request* r : c->reqs) {
         const size_t N = (size_t)r->N;
-        std::memcpy(iq + off * n, r->q, N * n * sizeof(float));
-        std::memcpy(iqd + off * n, r->qd, N * n * sizeof(float));
-        std::memcpy(itau + off * n, r->tau, N * n * sizeof(float));
+        if (!c->inplace) {
+            std::memcpy(iq + off * n, r->q, N * n * sizeof(float));
+            std::memcpy(iqd + off * n, r->qd, N * n * sizeof(float));
+            std::memcpy(itau + off * n, r->tau, N * n * sizeof(float));
+        }
         r->t_launch = now;
         r->state.store(kLaunched, std::memory_order_relaxed);
         off += N;
     }
     // mapped I/O: the kernel reads the pinned inputs and writes the pinned outputs through the
     // device's mapping (no copy-engine transfers; no H2D and D2H phases, and no events for
-    // them: an event record costs a few microseconds of the stream's time)
-    const bool mapped = (s->cfg.flags & GRID_SERVER_MAPPED_IO) != 0;
-    float* dq = mapped ? c->h_in_dev : c->d_in;
-    float* dqd = dq + K * n;
-    float* dtau = dqd + K * n;
-    float* oq = mapped ? c->h_out_dev : c->d_out;
-    float* oM = oq + K * n;
-    float* oD = oM + K * n * n;
-    float* oV = oD + K * n * n;
+    // them: an event record costs a few microseconds of the stream's time). In place: a batch
+    // of one request whose arrays are all pinned and mapped runs on them directly.
+    const bool mapped = c->inplace || (s->cfg.flags & GRID_SERVER_MAPPED_IO) != 0;
+    c->mapped = mapped;
+    float* const* rd = c->reqs[0]->dev;
+    float* dq = c->inplace ? rd[0] : mapped ? c->h_in_dev : c->d_in;
+    float* dqd = c->inplace ? rd[1] : dq + K * n;
+    float* dtau = c->inplace ? rd[2] : dqd + K * n;
+    float* oq = c->inplace ? rd[3] : mapped ? c->h_out_dev : c->d_out;
+    float* oM = c->inplace ? rd[4] : oq + K * n;
+    float* oD = c->inplace ? rd[5] : oM + K * n * n;
+    float* oV = c->inplace ? rd[6] : oD + K * n * n;
     if (hipEventRecord(c->ev[0], c->stream) != hipSuccess ||
         (!mapped && (hipMemcpyAsync(dq, iq, 3 * K * n * sizeof(float), hipMemcpyHostToDevice,
                                     c->stream) != hipSuccess ||
@@ -252,6 +336,8 @@ bool launch_ctx(grid_server s, BatchCtx* c)
         hipEventRecord(c->ev[3], c->stream) != hipSuccess)
         return false;
     s->launches.fetch_add(1);
+    if (c->inplace)
+        s->inplace_launches.fetch_add(1);
     {
         std::lock_guard<std::mutex> lk(c->mu);
         c->launched = true;
@@ -397,7 +483,8 @@ grid_status grid_server_create(const grid_model* models, int32_t count,
         return fail(GRID_EINVAL, "models, count and config are required");
     if (cfg->max_batch_knots < 1 || cfg->max_batch_knots > (1 << 20) || cfg->contexts_per_model < 1 ||
         cfg->contexts_per_model > 64 ||
-        (cfg->flags & ~(uint32_t)(GRID_SERVER_PER_REQUEST | GRID_SERVER_MAPPED_IO)) ||
+        (cfg->flags & ~(uint32_t)(GRID_SERVER_PER_REQUEST | GRID_SERVER_MAPPED_IO |
+                                  GRID_SERVER_DIRECT_PINNED)) ||
         cfg->batch_window_us < 0 || cfg->batch_window_us > 1000000 || cfg->min_batch_knots < 0 ||
         cfg->min_batch_knots > cfg->max_batch_knots)
         return fail(GRID_EINVAL, "bad server configuration");
@@ -487,6 +574,24 @@ grid_status grid_server_submit(grid_server s, int32_t model_index, int32_t N, co
     r->dq = dqdd_dq;
     r->dqd = dqdd_dqd;
     r->bytes = bytes;
+    if (s->cfg.flags & GRID_SERVER_DIRECT_PINNED) {
+        // every array inside a registered pinned range: the request can run in place
+        const size_t n = (size_t)s->models[model_index]->topo.n, v = N * n * sizeof(float);
+        const void* a[7] = {q, qd, tau, qdd, Minv, dqdd_dq, dqdd_dqd};
+        const size_t len[7] = {v, v, v, v, v * n, v * n, v * n};
+        std::lock_guard<std::mutex> lk(s->pin_mu);
+        r->direct = !s->pins.empty();
+        for (int k = 0; k < 7 && r->direct; ++k) {
+            const char* c = static_cast<const char*>(a[k]);
+            r->dev[k] = nullptr;
+            for (const auto& pr : s->pins)
+                if (c >= pr.start && (size_t)(c - pr.start) + len[k] <= pr.len) {
+                    r->dev[k] = reinterpret_cast<float*>(pr.dev + (c - pr.start));
+                    break;
+                }
+            r->direct = r->dev[k] != nullptr;
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (!s->accepting) {
@@ -502,6 +607,34 @@ grid_status grid_server_submit(grid_server s, int32_t model_index, int32_t N, co
     s->submitted.fetch_add(1);
     *ticket = r->ticket;
     return GRID_OK;
+}
+
+grid_status grid_server_pin_range(grid_server s, const void* p, size_t bytes)
+{
+    if (!s || !p || bytes == 0)
+        return fail(GRID_EINVAL, "server, pointer and a nonzero length are required");
+    float* dev = mapped_range(p, bytes);
+    if (!dev)
+        return fail(GRID_EINVAL, "the range is not inside one pinned host allocation mapped "
+                                 "into the device");
+    std::lock_guard<std::mutex> lk(s->pin_mu);
+    if (s->pins.size() >= 64)
+        return fail(GRID_EINVAL, "at most 64 pinned ranges per server");
+    s->pins.push_back({static_cast<const char*>(p), bytes, reinterpret_cast<char*>(dev)});
+    return GRID_OK;
+}
+
+grid_status grid_server_unpin_range(grid_server s, const void* p)
+{
+    if (!s || !p)
+        return fail(GRID_EINVAL, "server and pointer are required");
+    std::lock_guard<std::mutex> lk(s->pin_mu);
+    for (size_t k = 0; k < s->pins.size(); ++k)
+        if (s->pins[k].start == static_cast<const char*>(p)) {
+            s->pins.erase(s->pins.begin() + (long)k);
+            return GRID_OK;
+        }
+    return fail(GRID_EINVAL, "no registered range starts at this pointer");
 }
 
 static Request* find_request(grid_server s, uint64_t ticket)
@@ -561,6 +694,7 @@ grid_status grid_server_stats_get(grid_server s, grid_server_stats* out)
     out->knots_completed = s->knots_done.load();
     out->launches = s->launches.load();
     out->max_inflight_bytes = s->max_inflight.load();
+    out->inplace_launches = s->inplace_launches.load();
     return GRID_OK;
 }
 
@@ -621,31 +755,53 @@ grid_status grid_server_loadgen(grid_server s, const grid_loadgen_config* cfg,
     std::mt19937_64 rng(cfg->seed);
     std::uniform_real_distribution<double> uni(0.0, 1.0);
     std::normal_distribution<float> gauss(0.0f, 1.0f);
-    // input pools and output rings per model
-    const int pool_knots = 8192, ring = 256;
+    // input pools and output rings per model: ordinary host memory, or pinned host memory
+    // mapped into the device (cfg->pinned: the clients' arrays then qualify for in-place
+    // batches on a GRID_SERVER_DIRECT_PINNED server; a smaller ring keeps the pinned total
+    // modest)
+    const int pool_knots = 8192, ring = cfg->pinned ? 64 : 256;
     struct Pool {
         int n;
-        std::vector<float> q, qd, tau;
-        std::vector<float> qdd, M, D, V;       // ring of output slots
+        HostArray q, qd, tau;
+        HostArray qdd, M, D, V;                // ring of output slots
     };
     std::vector<Pool> pools(nm);
     for (int k = 0; k < nm; ++k) {
         Pool& p = pools[k];
         p.n = s->models[k]->topo.n;
-        const size_t n = (size_t)p.n;
-        p.q.resize(pool_knots * n);
-        p.qd.resize(pool_knots * n);
-        p.tau.resize(pool_knots * n);
+        const size_t n = (size_t)p.n, slot = (size_t)cfg->n_max;
+        const bool pin = cfg->pinned != 0;
+        if (!p.q.alloc(pool_knots * n, pin) || !p.qd.alloc(pool_knots * n, pin) ||
+            !p.tau.alloc(pool_knots * n, pin) || !p.qdd.alloc(ring * slot * n, pin) ||
+            !p.M.alloc(ring * slot * n * n, pin) || !p.D.alloc(ring * slot * n * n, pin) ||
+            !p.V.alloc(ring * slot * n * n, pin))
+            return fail(GRID_ENOMEM, "load generator buffers");
         for (size_t i = 0; i < p.q.size(); ++i) {
             p.q[i] = (float)(M_PI * (2.0 * uni(rng) - 1.0));
             p.qd[i] = gauss(rng);
             p.tau[i] = 5.0f * gauss(rng);
         }
-        const size_t slot = (size_t)cfg->n_max;
-        p.qdd.resize(ring * slot * n);
-        p.M.resize(ring * slot * n * n);
-        p.D.resize(ring * slot * n * n);
-        p.V.resize(ring * slot * n * n);
+    }
+    // pinned client arrays are registered with the server for the run (in-place requests on a
+    // GRID_SERVER_DIRECT_PINNED server) and unregistered on every way out
+    std::vector<const void*> pinned_ranges;
+    struct Unpin {
+        grid_server s;
+        std::vector<const void*>* r;
+        ~Unpin()
+        {
+            for (const void* p : *r)
+                (void)grid_server_unpin_range(s, p);
+        }
+    } unpin{s, &pinned_ranges};
+    if (cfg->pinned && (s->cfg.flags & GRID_SERVER_DIRECT_PINNED)) {
+        for (Pool& p : pools)
+            for (HostArray* a : {&p.q, &p.qd, &p.tau, &p.qdd, &p.M, &p.D, &p.V}) {
+                const grid_status st = grid_server_pin_range(s, a->data(), a->size() * sizeof(float));
+                if (st != GRID_OK)
+                    return st;
+                pinned_ranges.push_back(a->data());
+            }
     }
     struct Sent {
         uint64_t ticket;

@@ -31,6 +31,7 @@ IO_DIRECT = 1
 GRID_MAX_KNOTS = 1 << 24      # the largest N of one call
 GRID_SERVER_PER_REQUEST = 1
 GRID_SERVER_MAPPED_IO = 2
+GRID_SERVER_DIRECT_PINNED = 4
 GRID_CODEGEN_PIPE_MODULE = 1 << 16
 
 _i32p = C.POINTER(C.c_int32)
@@ -58,13 +59,13 @@ class ServerConfig(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("canceled", C.c_uint64),
                 ("knots_completed", C.c_uint64), ("launches", C.c_uint64),
-                ("max_inflight_bytes", C.c_uint64)]
+                ("max_inflight_bytes", C.c_uint64), ("inplace_launches", C.c_uint64)]
 
 
 class LoadgenConfig(C.Structure):
     _fields_ = [("rate_per_s", C.c_double), ("duration_s", C.c_double), ("warmup_s", C.c_double),
                 ("model_prob", _f64p), ("n_min", C.c_int32), ("n_max", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("pinned", C.c_int32)]
 
 
 class LatencySplit(C.Structure):
@@ -149,6 +150,8 @@ _SIGS = {
     "grid_server_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64]),
     "grid_server_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(ServerStats)]),
     "grid_server_destroy": (C.c_int32, [C.c_void_p]),
+    "grid_server_pin_range": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "grid_server_unpin_range": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "grid_server_loadgen": (C.c_int32, [C.c_void_p, C.POINTER(LoadgenConfig),
                                         C.POINTER(LoadgenResult)]),
     "grid_workspace_destroy": (C.c_int32, [C.c_void_p]),
@@ -229,6 +232,15 @@ def _dev(x, numel: int, device: int, what: str) -> int | None:
         raise GridError(GRID_EINVAL, f"{what}: not contiguous")
     if x.numel() < numel:
         raise GridError(GRID_EINVAL, f"{what}: {x.numel()} elements, {numel} required")
+    return int(x.data_ptr())
+
+
+def _host_addr(x) -> int:
+    """Address of a host buffer: an int, a numpy array, or a (pinned) CPU torch tensor."""
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
     return int(x.data_ptr())
 
 
@@ -762,16 +774,26 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, model_index, q, qd, tau):
-        """Queue one request on host arrays; returns (ticket, outputs dict being filled)."""
+    def submit(self, model_index, q, qd, tau, out=None):
+        """Queue one request on host arrays; returns (ticket, outputs dict being filled).
+        out: the caller's own output arrays (dict qdd, Minv, dqdd_dq, dqdd_dqd; contiguous
+        float32 of the right shapes), e.g. views of pinned memory for in-place requests."""
         n = self.models[model_index].n
         q = np.ascontiguousarray(q, dtype=np.float32).reshape(-1, n)
         N = q.shape[0]
         qd = np.ascontiguousarray(qd, dtype=np.float32).reshape(N, n)
         tau = np.ascontiguousarray(tau, dtype=np.float32).reshape(N, n)
-        out = {"qdd": np.empty((N, n), np.float32), "Minv": np.empty((N, n, n), np.float32),
-               "dqdd_dq": np.empty((N, n, n), np.float32),
-               "dqdd_dqd": np.empty((N, n, n), np.float32)}
+        if out is None:
+            out = {"qdd": np.empty((N, n), np.float32), "Minv": np.empty((N, n, n), np.float32),
+                   "dqdd_dq": np.empty((N, n, n), np.float32),
+                   "dqdd_dqd": np.empty((N, n, n), np.float32)}
+        else:
+            shapes = {"qdd": (N, n), "Minv": (N, n, n), "dqdd_dq": (N, n, n),
+                      "dqdd_dqd": (N, n, n)}
+            for k, sh in shapes.items():
+                a = out[k]
+                if a.dtype != np.float32 or a.shape != sh or not a.flags.c_contiguous:
+                    raise GridError(GRID_EINVAL, f"out[{k}]: contiguous float32 {sh} required")
         t = C.c_uint64()
         ptr = lambda a: a.ctypes.data
         _check(lib().grid_server_submit(self._h, int(model_index), N, ptr(q), ptr(qd), ptr(tau),
@@ -779,6 +801,14 @@ class Server:
                                         ptr(out["dqdd_dqd"]), C.byref(t)))
         self._keep[t.value] = (q, qd, tau, out)      # buffers must live until wait returns
         return t.value, out
+
+    def pin_range(self, ptr, nbytes):
+        """grid_server_pin_range: register a pinned host range (an address, or an array or
+        tensor whose data pointer is taken) for in-place requests."""
+        _check(lib().grid_server_pin_range(self._h, _host_addr(ptr), int(nbytes)))
+
+    def unpin_range(self, ptr):
+        _check(lib().grid_server_unpin_range(self._h, _host_addr(ptr)))
 
     def wait(self, ticket, timeout_us=-1):
         st = lib().grid_server_wait(self._h, C.c_uint64(ticket), C.c_int64(int(timeout_us)))
@@ -792,10 +822,11 @@ class Server:
         return {k: int(getattr(s, k)) for k, _ in ServerStats._fields_}
 
     def loadgen(self, rate_per_s, duration_s, model_prob, n_min=16, n_max=256, warmup_s=1.0,
-                seed=7):
+                seed=7, pinned=False):
         probs = np.ascontiguousarray(model_prob, dtype=np.float64)
         cfg = LoadgenConfig(float(rate_per_s), float(duration_s), float(warmup_s),
-                            probs.ctypes.data_as(_f64p), int(n_min), int(n_max), int(seed))
+                            probs.ctypes.data_as(_f64p), int(n_min), int(n_max), int(seed),
+                            int(bool(pinned)))
         r = LoadgenResult()
         _check(lib().grid_server_loadgen(self._h, C.byref(cfg), C.byref(r)))
         out = {}

@@ -252,3 +252,62 @@ def test_batch_window_policy(models, orc):
         with pytest.raises(grid.GridError) as e:
             grid.Server(ms[:1], budget_bytes=1 << 26, max_batch_knots=2048, **bad)
         assert e.value.status == grid.GRID_EINVAL
+
+
+def test_inplace_requests_on_pinned_arrays(models, orc):
+    """On a GRID_SERVER_DIRECT_PINNED server, a request whose arrays all lie in registered
+    pinned ranges and that forms a batch alone runs in place (no staging copy, no copy-out):
+    its outputs equal, bit for bit, the same request on ordinary arrays, and the oracle within
+    the parity tolerance; an unregistered or pageable range is refused; a pinned loadgen run
+    goes in place."""
+    import torch
+    robots, ms = models
+    say("[gpu] server in place on pinned arrays")
+    srv = grid.Server(ms, budget_bytes=1 << 28, max_batch_knots=1024, contexts_per_model=2,
+                      flags=grid.GRID_SERVER_MAPPED_IO | grid.GRID_SERVER_DIRECT_PINNED)
+    pinned = []
+
+    def pin(shape):
+        t = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+        srv.pin_range(t, t.numel() * 4)
+        pinned.append(t)
+        return t.numpy()
+
+    try:
+        with pytest.raises(grid.GridError) as e:
+            srv.pin_range(np.zeros(16, np.float32), 64)          # pageable memory
+        assert e.value.status == grid.GRID_EINVAL
+        with pytest.raises(grid.GridError) as e:
+            srv.unpin_range(np.zeros(16, np.float32))
+        assert e.value.status == grid.GRID_EINVAL
+        for k, N, seed in ((0, 37, 61), (2, 100, 62), (1, 256, 63)):
+            n = robots[k].n
+            kn = synth.random_knots(n, N, seed)
+            ins = [pin((N, n)) for _ in range(3)]
+            for a, b in zip(ins, (kn.q, kn.qd, kn.tau)):
+                a[:] = b
+            out = {"qdd": pin((N, n)), "Minv": pin((N, n, n)), "dqdd_dq": pin((N, n, n)),
+                   "dqdd_dqd": pin((N, n, n))}
+            for a in out.values():
+                a[:] = np.nan
+            before = srv.stats()["inplace_launches"]
+            t, got = srv.submit(k, *ins, out=out)
+            srv.wait(t)
+            assert srv.stats()["inplace_launches"] == before + 1
+            t2, ref_srv = srv.submit(k, kn.q.copy(), kn.qd.copy(), kn.tau.copy())
+            srv.wait(t2)
+            for key in OUTS:
+                np.testing.assert_array_equal(got[key], ref_srv[key], err_msg=f"{k} {key}")
+            ref = orc.fd_grad_batch(robots[k], kn.q, kn.qd, kn.tau)
+            e = np.abs(got["dqdd_dq"] - ref["dqdd_dq"]).reshape(N, -1).max(1) / \
+                np.abs(ref["dqdd_dq"]).reshape(N, -1).max(1)
+            assert e.max() <= 1e-3
+        for t in pinned:
+            srv.unpin_range(t)
+        r = srv.loadgen(5000, 0.3, [0.5, 0.3, 0.2], warmup_s=0.1, pinned=True)
+        st = srv.stats()
+        say(f"  pinned loadgen: p50 {r['p50_us']:.0f} us, p99 {r['p99_us']:.0f} us, "
+            f"in place {st['inplace_launches']} of {st['launches']} launches")
+        assert r["requests"] > 500 and st["inplace_launches"] > st["launches"] // 2
+    finally:
+        srv.close()
