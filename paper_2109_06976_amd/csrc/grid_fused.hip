@@ -769,6 +769,47 @@ __device__ __forceinline__ void minv_columns(float* Minv, const float (&Lf)[I::S
         zero_fill<I>(Minv, nullptr, mbase, lp, lanes);
 }
 
+// x[r4 + c] for the lane's c (0..3) in an unrolled loop over r4 = 0, 4, ..; 0 past the end.
+// The pick is a sum of the four candidates times the lane's 0/1 masks mk[k] = (c == k): a chain
+// of selects folds into one indexed load, and the array then moves to scratch memory.
+template <int B>
+__device__ __forceinline__ float row_of_four(const float (&x)[B], int r4, const float (&mk)[4])
+{
+    float v = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (r4 + k < B)
+            v += mk[k] * x[r4 + k];
+    return v;
+}
+
+// Beyond 16 bodies (one problem per workgroup) the problem's rows of M^-1, dqdd/dq and
+// dqdd/dqd are staged in LDS in local coordinates and the workgroup writes the B rows of N
+// floats of each matrix, zeros outside the branch's columns included: consecutive threads take
+// consecutive elements of a row, and no other pass writes those rows.
+template <class I>
+__device__ __forceinline__ void write_rows(const grid::Args& A, long mbase,
+                                           const float (&tile)[3][I::S::B][I::S::B],
+                                           const int* rowg, const int* locc, int t, int threads)
+{
+    constexpr int B = I::S::B;
+    constexpr int N = I::N;
+    for (int e = t; e < B * N; e += threads) {
+        const int r = e / N, c2 = e - (e / N) * N;
+        const int l = locc[c2];
+        const long o = mbase + (long)rowg[r] * N + c2;
+        float m = 0.0f, d = 0.0f, w = 0.0f;
+        if (l >= 0) {
+            m = tile[0][r][l];
+            d = tile[1][r][l];
+            w = tile[2][r][l];
+        }
+        A.Minv[o] = m;
+        A.dqdd_dq[o] = d;
+        A.dqdd_dqd[o] = w;
+    }
+}
+
 template <int B>
 struct PipeShape {
     static_assert(B >= 1 && B <= 32, "branches have at most 32 bodies");
@@ -813,7 +854,16 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     // role B's weighted unit-acceleration responses, [problem][quad][body][component]: the
     // increments at qdd summed over the quads (branches of up to 16 bodies)
     __shared__ float4 s_red[B <= 16 ? P : 1][B <= 16 ? PS::QB : 1][B <= 16 ? B : 1][3];
+    // beyond 16 bodies (one problem per workgroup, columns in two passes): role B's unweighted
+    // unit-acceleration responses, [column k][body][component] = (a.a, a.l, f.a, f.l)
+    __shared__ float4 s_resp[B > 16 ? B : 1][B > 16 ? B : 1][3];
     __shared__ float4 s_tab[3 * B * 4];       // the model's lane table (roles A, B)
+    // beyond 16 bodies: the staged output rows (M^-1, dqdd/dq, dqdd/dqd in local coordinates),
+    // local row -> global row, global column -> local column (-1: not in the branch)
+    constexpr bool kStage = !PS::HASC;
+    __shared__ float s_out[3][kStage ? B : 1][kStage ? B : 1];
+    __shared__ int s_rowg[kStage ? B : 1];
+    __shared__ int s_locc[kStage ? N : 1];
 
     int tid = (int)threadIdx.x;
     if constexpr (kLoop)
@@ -822,7 +872,27 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     const int lane = kLoop ? (tid & 63) : tid % 64;
     const int c = lane & 3;
     const Lane ln = lane_of(c == 3 ? 0 : c, I::a0());
+    if constexpr (kStage) {                   // ordered by the lane table's barrier
+        if (tid < B)
+            s_rowg[tid] = I::body_of(tid);
+        if (tid < N) {
+            int l = -1;
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                l = I::body[k] == tid ? k : l;
+            s_locc[tid] = l;
+        }
+    }
     const float* tab = lane_table<I, 64 * GRID_PIPE_WAVES>(s_tab, tid, c);
+    // the staged rows go out once the last tile is written (one problem per workgroup)
+    const auto stage_out = [&]() {
+        if constexpr (kStage) {
+            __syncthreads();                  // the output tiles are complete
+            if (block * P < A.nknots)
+                write_rows<I>(A, (long)(block * P) * N * N, s_out, s_rowg, s_locc, tid,
+                              64 * GRID_PIPE_WAVES);
+        }
+    };
 
     if (wave < PS::AW) {
         // -------------------------------------------------------- role A
@@ -864,6 +934,10 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         drnea_column<I, true>(ln, qd, E, K, v, gam, j, src_v, src_a, src_f, dx);
         const int lp = PS::WA == 1 ? lane % (4 * QA) : lane + 64 * wave;
         float Lf[B][B], dinv[B];              // beyond 16 bodies: role B's factor
+        float mk[4];                          // this lane's c as 0/1 masks (staged rows)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            mk[k] = c == k ? 1.0f : 0.0f;
         if constexpr (!PS::HASC) {
             // the factor has been in LDS since the first barrier: the quad of column (qd, j)
             // solves for column j of M^-1 while role B is still on the qdd parts (entries
@@ -879,17 +953,18 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                         Lf[i][b] = s_Mi[pslot][i][b];
             }
             ltl_solve<S>(Lf, dinv, mc);
-            if (valid) {
-                const int gj = I::body_of(j);
+            if (owns_col && u == 1) {
+                // lane c of the quad takes rows c, c + 4, ..; entries (i, j), i <= j, to both
+                // mirrored positions of the staged M^-1 (exactly symmetric)
 #pragma unroll
-                for (int i = 0; i < B; ++i) {
-                    if ((i & 3) != c || !owns_col || u != 1 || i > j)
-                        continue;
-                    const int gi = I::body[i];
-                    A.Minv[mbase + (long)gi * N + gj] = mc[i];
-                    A.Minv[mbase + (long)gj * N + gi] = mc[i];
+                for (int r = 0; r < (B + 3) / 4; ++r) {
+                    const int i = c + 4 * r;
+                    const float m = row_of_four<B>(mc, 4 * r, mk);
+                    if (i < B && i <= j) {
+                        s_out[0][i][j] = m;
+                        s_out[0][j][i] = m;
+                    }
                 }
-                zero_fill<I>(A.Minv, nullptr, mbase, lp, 64 * PS::WA);
             }
         }
         __syncthreads();                      // M^-1 and the qdd parts published
@@ -901,17 +976,16 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         if constexpr (!PS::HASC) {
             // beyond 16 bodies: dqdd/du_j = -(L^T L)^-1 dtau/du_j by the two triangular solves
             ltl_solve<S>(Lf, dinv, dx);
-            if (!valid)
-                return;
-            const int gj = I::body_of(j);
-            float* out = u == 0 ? A.dqdd_dq : A.dqdd_dqd;
+            if (owns_col) {
 #pragma unroll
-            for (int i = 0; i < B; ++i) {
-                if ((i & 3) != c || !owns_col)
-                    continue;
-                out[mbase + (long)I::body[i] * N + gj] = -dx[i];
+                for (int r = 0; r < (B + 3) / 4; ++r) {
+                    const int i = c + 4 * r;
+                    const float d = row_of_four<B>(dx, 4 * r, mk);
+                    if (i < B)
+                        s_out[1 + u][i][j] = -d;
+                }
             }
-            zero_fill<I>(A.dqdd_dq, A.dqdd_dqd, mbase, lp, 64 * PS::WA);
+            stage_out();
             return;
         }
         if (!valid)
@@ -976,6 +1050,14 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 for (int i = 0; i < B; ++i) {
                     amk[cb][i] = am[i];
                     fmk[cb][i] = fm[i];
+                }
+            } else {
+                // beyond 16 bodies the responses go to LDS as they come (two passes would
+                // hold twice the registers across the barrier)
+                if (owns[cb] && c != 3) {
+#pragma unroll
+                    for (int i = 0; i < B; ++i)
+                        s_resp[js[cb]][i][c] = float4{am[i].a, am[i].l, fm[i].a, fm[i].l};
                 }
             }
         }
@@ -1066,12 +1148,23 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 Dfj[cb] = V{t.z, t.w};
             }
         } else {
-            V xd[B], Df[B];
-            delta_rnea<I>(ln, E, K, x, xd, Df);
+            // the same sum beyond 16 bodies, from the responses role B left in LDS before the
+            // first barrier: Da_j = sum_k qdd_k a_j^(k), Df_j = sum_k qdd_k f_j^(k) for the
+            // quad's own bodies j (one problem per workgroup)
+            const int cc = c == 3 ? 0 : c;
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                xdj[cb] = pick<B>(xd, js[cb]);
-                Dfj[cb] = pick<B>(Df, js[cb]);
+                float4 t{0.0f, 0.0f, 0.0f, 0.0f};
+                float w = 0.0f;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    const float4 u = s_resp[k][js[cb]][cc];
+                    t = float4{t.x + x[k] * u.x, t.y + x[k] * u.y, t.z + x[k] * u.z,
+                               t.w + x[k] * u.w};
+                    w += (js[cb] == k ? 1.0f : 0.0f) * x[k];
+                }
+                xdj[cb] = add_s(ln, prismatic<I>(js[cb]), V{t.x, t.y}, -w);
+                Dfj[cb] = V{t.z, t.w};
             }
         }
         V none[B];                            // velocities do not enter the dv = 0 sweep
@@ -1102,6 +1195,7 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
             }
         }
         __syncthreads();                      // M^-1 and the qdd parts published
+        stage_out();
     } else if (wave == CWAVE) {
         // -------------------------------------------------------- role C
         constexpr int QB = PS::QB;
@@ -1124,9 +1218,10 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         minv_columns<I, CB>(A.Minv, Lf, dinv, pslot, s, c, valid, mbase, lane % (4 * QB), 4 * QB, s_Mi);
         __syncthreads();                      // M^-1 published
     } else {
-        // a wavefront this shape does not use still takes part in both barriers
+        // a wavefront this shape does not use still takes part in the barriers
         __syncthreads();
         __syncthreads();
+        stage_out();
     }
 }
 
