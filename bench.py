@@ -24,6 +24,8 @@ Also reported (extra fields of the same line):
                 stored-Jacobian and the reverse-sweep backward, eager and graph-replayed;
   single_knot_us  one knot (N = 1) of ID, M^-1, FD, dID and dFD on each robot, as the
                 paper's single-computation table, with the paper's GPU numbers as context;
+  minv_routes_us  M^-1 alone by the factorisation (quad layout, one lane per knot) and by
+                the paper's direct inverse (one lane per knot), per robot and knot count;
   cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
@@ -167,6 +169,34 @@ def single_knot_table(torch, grid, synth, steps):
                        for op, f in ops.items()}
         m.close()
     return table
+
+
+def minv_routes(torch, grid, synth):
+    """M^-1 alone by its three routes (grid_minv_route): the quad layout's factorisation, and
+    one lane per knot with composite bodies + L^T L or with the paper's direct articulated-body
+    inverse; HIP-event time per launch over back-to-back launches, per robot and knot count."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    names = {grid.MINV_QUAD: "quad_ltl", grid.MINV_LANE_LTL: "lane_ltl",
+             grid.MINV_LANE_DIRECT: "lane_direct"}
+    out = {"workload": "M^-1 only, us per launch (HIP events, back to back)"}
+    for name in ("chain7", "quad12", "humanoid30"):
+        robot = synth.model_by_name(name)
+        m = grid.Model(robot)
+        res = {}
+        for N in (1, 128, 16384, 65536):
+            q = torch.from_numpy(synth.random_knots(robot.n, N, 11).q).to(dev)
+            mi = torch.empty((N, robot.n, robot.n), device=dev)
+            steps = 1000 if N <= 128 else 100
+            res[str(N)] = {
+                label: round(time_steps(torch, lambda r=route: m.minv_route(q, mi, r, N=N,
+                                                                           stream=stream),
+                                        steps, 20)[1] * 1e6, 3)
+                for route, label in names.items()}
+            del q, mi
+        out[name] = res
+        m.close()
+    return out
 
 
 def autograd_steps(torch, grid, synth, steps):
@@ -684,6 +714,8 @@ def main():
             progress("autograd done")
         result["single_knot_us"] = single_knot_table(torch, grid, synth, 1000)
         result["single_knot_us"]["paper_table1_gpu_us"] = PAPER_TABLE1_GPU_US
+        result["minv_routes_us"] = minv_routes(torch, grid, synth)
+        progress("M^-1 routes timed")
 
     # the served load runs last: timed after it, the autograd step took about 60 us longer
     if args.serve_seconds > 0:

@@ -437,6 +437,23 @@ grid_status grid_fd(grid_model m, int32_t N, const float* q, const float* qd, co
 /* The mass-matrix inverse M(q)^-1 (Sec. IV-B), exactly symmetric. */
 grid_status grid_minv(grid_model m, int32_t N, const float* q, float* Minv, void* stream);
 
+/* M(q)^-1 by a chosen route, to compare the paper's direct inverse with the factorisation
+ * the fused kernels use (Sec. IV-B lists the direct inverse of Carpentier and Mansard):
+ *   GRID_MINV_QUAD         grid_minv itself (quad layout: columns of M, L^T L, solves);
+ *   GRID_MINV_LANE_LTL     one lane per knot and branch: M by composite rigid bodies,
+ *                          M = L^T L along ancestor paths, B triangular solve pairs;
+ *   GRID_MINV_LANE_DIRECT  one lane per knot and branch: the direct articulated-body
+ *                          recursion (zero velocity and gravity, the identity as its right-hand
+ *                          sides; inward articulated inertias, outward rows of M^-1).
+ * All three write Minv [N][n][n] row-major, exactly symmetric (upper triangle mirrored),
+ * device pointers, asynchronous on `stream`. Errors: EINVAL (unknown route, N < 0, NULL
+ * pointer with N > 0, N > GRID_MAX_KNOTS), EDEVICE. */
+#define GRID_MINV_QUAD 0
+#define GRID_MINV_LANE_LTL 1
+#define GRID_MINV_LANE_DIRECT 2
+grid_status grid_minv_route(grid_model m, int32_t N, const float* q, float* Minv, int32_t route,
+                            void* stream);
+
 /* The gradient of inverse dynamics at the given qdd: dtau/dq and dtau/dqd (Sec. IV-B,
  * Algorithm 1 and its backward pass). */
 grid_status grid_id_grad(grid_model m, int32_t N, const float* q, const float* qd,

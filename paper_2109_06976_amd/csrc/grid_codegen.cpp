@@ -393,6 +393,9 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << "\n// generated: workgroup -> (branch, 16 knots), four lanes per knot\n";
     emit_dispatch(os, t, "__device__ void grid_dispatch_s4(const grid::Args& a, int block)", "16",
              "grids::run_serial<@, 4>(a, b)");
+    os << "\n// generated: workgroup -> (branch, 64 knots), M^-1 alone by either route\n";
+    emit_dispatch(os, t, "template <bool D>\n__device__ void grid_dispatch_minv(const grid::Args& a, int block)",
+             "64", "grids::run_minv<@, D>(a, b)");
     os << "#line 1 \"grid_ops.hip\"\n";
     os << grid_ops_src;
     os << "\n// generated: workgroup -> (branch, problem group), standalone algorithms\n";

@@ -176,6 +176,7 @@ struct grid_model_s {
     int compute_units = 256;
     hipFunction_t fused_variant[grid_impl::kNumVariants] = {};   // see kVariantQuad
     hipFunction_t op[grid_impl::kNumOps] = {};                    // see kOpId
+    hipFunction_t minv_route[2] = {};   // M^-1 one lane per knot: L^T L, direct
     std::vector<std::pair<int32_t, int>> tuned;   // (largest N, variant), ascending N
     hipModule_t module = nullptr;
     hipModule_t pipe_module = nullptr;  // build 4 alone, compiled with the ILP schedule

@@ -562,6 +562,9 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
         e = hipModuleGetFunction(&m->op[k], m->module, kOps[k]);
     for (int k = 0; k < 5 && e == hipSuccess; ++k)
         e = hipModuleGetFunction(&m->stage[k], m->module, kStages[k]);
+    static const char* const kMinvRoutes[2] = {"grid_minv_serial", "grid_minv_direct"};
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipModuleGetFunction(&m->minv_route[k], m->module, kMinvRoutes[k]);
     if (e == hipSuccess)
         e = hipModuleLoadData(&m->pipe_module, pipe_code.data());
     if (e == hipSuccess)   // build 4 from its own module
@@ -680,6 +683,29 @@ grid_status grid_fd(grid_model m, int32_t N, const float* q, const float* qd, co
 grid_status grid_minv(grid_model m, int32_t N, const float* q, float* Minv, void* stream)
 {
     return launch_op(m, kOpMinv, N, q, nullptr, nullptr, Minv, nullptr, stream);
+}
+
+grid_status grid_minv_route(grid_model m, int32_t N, const float* q, float* Minv, int32_t route,
+                            void* stream)
+{
+    if (route == GRID_MINV_QUAD)
+        return grid_minv(m, N, q, Minv, stream);
+    if (route != GRID_MINV_LANE_LTL && route != GRID_MINV_LANE_DIRECT)
+        return fail(GRID_EINVAL, "unknown M^-1 route");
+    if (!m)
+        return fail(GRID_EINVAL, "model is NULL");
+    if (N < 0)
+        return fail(GRID_EINVAL, "N must be >= 0");
+    if (N == 0)
+        return GRID_OK;
+    if (N > GRID_MAX_KNOTS)
+        return fail(GRID_EINVAL, "N too large");
+    if (!q || !Minv)
+        return fail(GRID_EINVAL, "a data pointer is NULL");
+    HIP_TRY(hipSetDevice(m->device));
+    return launch(m->minv_route[route == GRID_MINV_LANE_DIRECT ? 1 : 0],
+                  (unsigned)workgroups_serial(m->topo, N, 64), 64u, N, nullptr, q, nullptr,
+                  nullptr, nullptr, Minv, nullptr, nullptr, (hipStream_t)stream);
 }
 
 grid_status grid_id_grad(grid_model m, int32_t N, const float* q, const float* qd,

@@ -87,6 +87,91 @@ __device__ __forceinline__ void rb_add(RB& x, const RB& y)
         x.I[e] += y.I[e];
 }
 
+// X_i = (E_i, r_i) of one body at joint position qi: E = E_z(q) E_T (hardware sin and cos,
+// argument in revolutions reduced to [0, 1)), r = r_T; prismatic: E = E_T, r = r_T + q E_T^T e_z
+template <class I>
+__device__ __forceinline__ void serial_transform(int i, float qi, float (&E)[9], float (&R)[3])
+{
+    const float* c = I::consts() + i * kConstStride;
+    if (prismatic<I>(i)) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            E[k] = c[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            R[k] = c[9 + k] + qi * c[6 + k];
+        return;
+    }
+    const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
+    const float s = __builtin_amdgcn_sinf(rev);
+    const float co = __builtin_amdgcn_cosf(rev);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        E[k] = co * c[k] + s * c[3 + k];
+        E[3 + k] = co * c[3 + k] - s * c[k];
+        E[6 + k] = c[6 + k];
+        R[k] = c[9 + k];
+    }
+}
+
+// M by composite rigid bodies, factored: I^c_i = I_i + sum over children of X^T I^c X as
+// (mass, first moment, rotational inertia); M_ii = S^T I^c_i S and M_ki = S^T (X^T ... I^c_i S)
+// up the ancestor path of i; then M = L^T L in place (Lf, dinv = 1 / L_kk)
+template <class I>
+__device__ __forceinline__ void serial_mass_factor(const float (&E)[I::S::B][9],
+                                                   const float (&R)[I::S::B][3],
+                                                   float (&Lf)[I::S::B][I::S::B],
+                                                   float (&dinv)[I::S::B])
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    const float* C = I::consts();
+    RB Ic[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const float* c = C + i * kConstStride;
+        Ic[i].m = c[21];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            Ic[i].h[k] = c[18 + k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            Ic[i].I[k] = c[12 + k];
+    }
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        // I^c_i S: [Ibar e_z; -(h x e_z)] for S = (e_z, 0), [h x e_z; m e_z] for (0, e_z)
+        float f[6] = {Ic[i].I[4], Ic[i].I[5], Ic[i].I[2], -Ic[i].h[1], Ic[i].h[0], 0.0f};
+        if (prismatic<I>(i)) {
+            f[0] = Ic[i].h[1];
+            f[1] = -Ic[i].h[0];
+            f[2] = 0.0f;
+            f[3] = 0.0f;
+            f[4] = 0.0f;
+            f[5] = Ic[i].m;
+        }
+        Lf[i][i] = f[s_index(prismatic<I>(i))];
+        // up the ancestor path (ancestors have smaller indices): f into the parent
+        // frame of k, M_{lambda(k), i} = S^T f
+#pragma unroll
+        for (int k = B - 1; k >= 0; --k) {
+            if (k <= i && (k == i || gridq::is_anc<S>(k, i)) && S::parent[k] >= 0) {
+                float y[6];
+                xt_fv(E[k], R[k], f, y);
+#pragma unroll
+                for (int e = 0; e < 6; ++e)
+                    f[e] = y[e];
+                const int pk = S::parent[k] < 0 ? 0 : S::parent[k];
+                Lf[i][pk] = f[s_index(prismatic<I>(pk))];
+            }
+        }
+        const int p = S::parent[i];
+        if (p >= 0)
+            rb_add(Ic[p], rb_to_parent(E[i], R[i], Ic[i]));
+    }
+    gridq::ltl_factor<S>(Lf, dinv);
+}
+
 template <int B>
 __device__ __forceinline__ void pick6(const float (&arr)[B][6], int j, float (&out)[6])
 {
@@ -162,29 +247,8 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         const long o = vbase + I::body[i];
-        const float* c = C + i * kConstStride;
-        const float qi = A.q[o];
         qd[i] = A.qd[o];
-        if (prismatic<I>(i)) {
-            // translation along the joint z axis: E = E_T, r = r_T + q E_T^T e_z
-#pragma unroll
-            for (int k = 0; k < 9; ++k)
-                E[i][k] = c[k];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                R[i][k] = c[9 + k] + qi * c[6 + k];
-            continue;
-        }
-        const float rev = __builtin_amdgcn_fractf(qi * 0.159154943091895336f);
-        const float s = __builtin_amdgcn_sinf(rev);
-        const float co = __builtin_amdgcn_cosf(rev);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            E[i][k] = co * c[k] + s * c[3 + k];
-            E[i][3 + k] = co * c[3 + k] - s * c[k];
-            E[i][6 + k] = c[6 + k];
-            R[i][k] = c[9 + k];
-        }
+        serial_transform<I>(i, A.q[o], E[i], R[i]);
     }
     const float a0[6] = {0.0f, 0.0f, 0.0f, I::a0()[0], I::a0()[1], I::a0()[2]};   // -g
     const float zero6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
@@ -227,52 +291,7 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
 
     // ------------------------------------------------------------ 3. M by composite bodies
     float Lf[B][B], dinv[B];
-    {
-        RB Ic[B];
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            const float* c = C + i * kConstStride;
-            Ic[i].m = c[21];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                Ic[i].h[k] = c[18 + k];
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                Ic[i].I[k] = c[12 + k];
-        }
-#pragma unroll
-        for (int i = B - 1; i >= 0; --i) {
-            // I^c_i S: [Ibar e_z; -(h x e_z)] for S = (e_z, 0), [h x e_z; m e_z] for (0, e_z)
-            float f[6] = {Ic[i].I[4], Ic[i].I[5], Ic[i].I[2], -Ic[i].h[1], Ic[i].h[0], 0.0f};
-            if (prismatic<I>(i)) {
-                f[0] = Ic[i].h[1];
-                f[1] = -Ic[i].h[0];
-                f[2] = 0.0f;
-                f[3] = 0.0f;
-                f[4] = 0.0f;
-                f[5] = Ic[i].m;
-            }
-            Lf[i][i] = f[s_index(prismatic<I>(i))];
-            // up the ancestor path (ancestors have smaller indices): f into the parent
-            // frame of k, M_{lambda(k), i} = S^T f
-#pragma unroll
-            for (int k = B - 1; k >= 0; --k) {
-                if (k <= i && (k == i || gridq::is_anc<S>(k, i)) && S::parent[k] >= 0) {
-                    float y[6];
-                    xt_fv(E[k], R[k], f, y);
-#pragma unroll
-                    for (int e = 0; e < 6; ++e)
-                        f[e] = y[e];
-                    const int pk = S::parent[k] < 0 ? 0 : S::parent[k];
-                    Lf[i][pk] = f[s_index(prismatic<I>(pk))];
-                }
-            }
-            const int p = S::parent[i];
-            if (p >= 0)
-                rb_add(Ic[p], rb_to_parent(E[i], R[i], Ic[i]));
-        }
-    }
-    gridq::ltl_factor<S>(Lf, dinv);
+    serial_mass_factor<I>(E, R, Lf, dinv);
 
     // ------------------------------------------------------------ 4. M^-1 and qdd
     if (valid && L == 1) {
@@ -522,6 +541,248 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
     }
 }
 
+// ------------------------------------------------------------------ M^-1 alone, two routes
+//
+// One lane per (knot, branch) problem, as build 5, computing only M^-1, by either route:
+//   kDirect = false: M by composite rigid bodies, M = L^T L along ancestor paths, and the B
+//     columns of M^-1 by two triangular solves each (the route every fused build takes);
+//   kDirect = true: the paper's direct inverse (Sec. IV-B): the articulated-body recursion
+//     with zero velocity and gravity and the identity as its B right-hand sides. Inward,
+//     U_i = IA_i S_i, D_i = S_i^T U_i, row_i = (e_i^T - S_i^T F_i) / D_i over the columns
+//     of the subtree of i, IA_lambda += X^T (IA_i - U_i U_i^T / D_i) X and
+//     F_lambda += X^T (F_i + U_i row_i); outward, per column c, A = X_i P_lambda,
+//     row_i -= U_i^T A / D_i and P_i = A + S_i row_i; M^-1 = [row_i]. The articulated
+//     inertias do not depend on the right-hand sides, so they come first, and then each
+//     column runs its inward and outward steps (the same arithmetic, fewer live values).
+// Both write the upper triangle of the branch's block to both mirrored positions (exactly
+// symmetric) and zeros in the other branches' columns, one float per store.
+
+// articulated-body inertia [[A, B], [B^T, C]] in a body frame: A, C symmetric (xx yy zz xy xz
+// yz), B row-major
+struct AB {
+    float A[6], B[9], C[6];
+};
+
+__device__ __forceinline__ constexpr int sym3(int a, int b)
+{
+    return a == b ? a : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5));
+}
+
+// X^T Ia X for X = [E 0; -E r~ E]: with A' = E^T A E, B' = E^T B E, C' = E^T C E,
+//   C'' = C', B'' = B' + r~ C', A'' = A' + G + G^T - r~ C' r~, G = r~ B'^T
+// (X = diag(E, E) [1 0; -r~ 1]; for a rigid body this is the transform rb_to_parent writes out)
+__device__ __forceinline__ AB ab_to_parent(const float* E, const float* r, const AB& x)
+{
+    float A1[6], C1[6], B1[3][3];
+    {
+        float Ta[3][3], Tb[3][3], Tc[3][3];    // A E, B E, C E
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                Ta[a][b] = x.A[sym3(a, 0)] * E[b] + x.A[sym3(a, 1)] * E[3 + b] +
+                           x.A[sym3(a, 2)] * E[6 + b];
+                Tb[a][b] = x.B[3 * a] * E[b] + x.B[3 * a + 1] * E[3 + b] + x.B[3 * a + 2] * E[6 + b];
+                Tc[a][b] = x.C[sym3(a, 0)] * E[b] + x.C[sym3(a, 1)] * E[3 + b] +
+                           x.C[sym3(a, 2)] * E[6 + b];
+            }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                B1[a][b] = E[a] * Tb[0][b] + E[3 + a] * Tb[1][b] + E[6 + a] * Tb[2][b];
+                if (a <= b) {
+                    A1[sym3(a, b)] = E[a] * Ta[0][b] + E[3 + a] * Ta[1][b] + E[6 + a] * Ta[2][b];
+                    C1[sym3(a, b)] = E[a] * Tc[0][b] + E[3 + a] * Tc[1][b] + E[6 + a] * Tc[2][b];
+                }
+            }
+    }
+    const float rt[3][3] = {{0.0f, -r[2], r[1]}, {r[2], 0.0f, -r[0]}, {-r[1], r[0], 0.0f}};
+    float W[3][3], G[3][3];                    // r~ C', r~ B'^T
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            W[a][b] = rt[a][0] * C1[sym3(0, b)] + rt[a][1] * C1[sym3(1, b)] +
+                      rt[a][2] * C1[sym3(2, b)];
+            G[a][b] = rt[a][0] * B1[b][0] + rt[a][1] * B1[b][1] + rt[a][2] * B1[b][2];
+        }
+    AB o;
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+        o.C[e] = C1[e];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            o.B[3 * a + b] = B1[a][b] + W[a][b];
+            if (a <= b) {
+                const float wr = W[a][0] * rt[0][b] + W[a][1] * rt[1][b] + W[a][2] * rt[2][b];
+                o.A[sym3(a, b)] = A1[sym3(a, b)] + G[a][b] + G[b][a] - wr;
+            }
+        }
+    return o;
+}
+
+template <class I, bool kDirect>
+__device__ __forceinline__ void run_minv(const grid::Args& A, int block)
+{
+    using S = typename I::S;
+    constexpr int B = S::B;
+    constexpr int N = I::N;
+    const int lane = (int)threadIdx.x;
+    const int kraw = block * 64 + lane;
+    const bool valid = kraw < A.nknots;
+    const int knot = valid ? kraw : A.nknots - 1;
+    const long mbase = (long)knot * N * N;
+    float E[B][9], R[B][3];
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+        serial_transform<I>(i, A.q[(long)knot * N + I::body[i]], E[i], R[i]);
+    const auto put = [&](int i, int c, float x) {   // entry (i, c), i <= c, and its mirror
+        if (valid) {
+            A.Minv[mbase + (long)I::body[i] * N + I::body[c]] = x;
+            A.Minv[mbase + (long)I::body[c] * N + I::body[i]] = x;
+        }
+    };
+    if constexpr (!kDirect) {
+        float Lf[B][B], dinv[B];
+        serial_mass_factor<I>(E, R, Lf, dinv);
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            float mc[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                mc[i] = (i == c) ? 1.0f : 0.0f;
+            gridq::ltl_solve<S>(Lf, dinv, mc);
+#pragma unroll
+            for (int i = 0; i <= c; ++i)
+                put(i, c, mc[i]);
+        }
+    } else {
+        const float* C = I::consts();
+        float U[B][6], dv[B];
+        {
+            // inward: the articulated inertias, U_i = IA_i S_i and 1 / D_i (no right-hand side
+            // enters them)
+            AB Ia[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {   // I_i = [[Ibar, h~], [-h~, m 1]]
+                const float* c = C + i * kConstStride;
+                const float h0 = c[18], h1 = c[19], h2 = c[20], m = c[21];
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    Ia[i].A[k] = c[12 + k];
+                const float hb[9] = {0.0f, -h2, h1, h2, 0.0f, -h0, -h1, h0, 0.0f};
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    Ia[i].B[k] = hb[k];
+                const float cm[6] = {m, m, m, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    Ia[i].C[k] = cm[k];
+            }
+#pragma unroll
+            for (int i = B - 1; i >= 0; --i) {
+                const AB& x = Ia[i];
+                if (prismatic<I>(i)) {        // IA_i e_6 = [B[:, 2]; C[:, 2]]
+                    const float u[6] = {x.B[2], x.B[5], x.B[8], x.C[4], x.C[5], x.C[2]};
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        U[i][k] = u[k];
+                } else {                      // IA_i e_3 = [A[:, 2]; B[2, :]]
+                    const float u[6] = {x.A[4], x.A[5], x.A[2], x.B[6], x.B[7], x.B[8]};
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        U[i][k] = u[k];
+                }
+                dv[i] = 1.0f / U[i][s_index(prismatic<I>(i))];
+                const int p = S::parent[i];
+                if (p < 0)
+                    continue;
+                AB y = x;                     // IA_i - U_i U_i^T / D_i
+                const float* Ua = U[i];
+                const float* Ul = U[i] + 3;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        y.B[3 * a + b] -= Ua[a] * Ul[b] * dv[i];
+                        if (a <= b) {
+                            y.A[sym3(a, b)] -= Ua[a] * Ua[b] * dv[i];
+                            y.C[sym3(a, b)] -= Ul[a] * Ul[b] * dv[i];
+                        }
+                    }
+                const AB z = ab_to_parent(E[i], R[i], y);
+                const int pp = p < 0 ? 0 : p;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    Ia[pp].A[k] += z.A[k];
+                    Ia[pp].C[k] += z.C[k];
+                }
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    Ia[pp].B[k] += z.B[k];
+            }
+        }
+        // the right-hand sides one column c at a time (the recursion is linear in them): F_i
+        // of column c is nonzero only on the ancestor path of c, so inward it is one 6-vector
+        // carried from c to the root; outward every body takes its row entry
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            float row[B];
+            {
+                float f[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int i = B - 1; i >= 0; --i) {
+                    if (!in_subtree<S>(c, i)) {
+                        row[i] = 0.0f;
+                        continue;
+                    }
+                    row[i] = ((c == i ? 1.0f : 0.0f) - f[s_index(prismatic<I>(i))]) * dv[i];
+                    if (S::parent[i] >= 0) {
+                        float col[6];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            col[k] = f[k] + U[i][k] * row[i];
+                        xt_fv(E[i], R[i], col, f);
+                    }
+                }
+            }
+            float P[B][6];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const int p = S::parent[i];
+                float Av[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                float x = row[i];
+                if (p >= 0) {
+                    x_mv(E[i], R[i], P[p < 0 ? 0 : p], Av);
+                    float ua = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        ua += U[i][k] * Av[k];
+                    x -= ua * dv[i];
+                }
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    P[i][k] = Av[k];
+                P[i][s_index(prismatic<I>(i))] += x;
+                if (i <= c)
+                    put(i, c, x);
+            }
+        }
+    }
+    if (valid && N > B) {
+        // this branch's rows hold zeros in the other branches' columns
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+            for (int c2 = 0; c2 < N; ++c2)
+                if (!I::contains(c2))
+                    A.Minv[mbase + (long)I::body[i] * N + c2] = 0.0f;
+    }
+}
+
 }  // namespace grids
 
 // kernels of a one-robot module (a module of several robots defines GRID_PIPE_ONLY and its
@@ -542,6 +803,22 @@ __device__ void grid_dispatch_s4(const grid::Args& args, int block);
 extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_serial4(grid::Args args)
 {
     grid_dispatch_s4(args, (int)blockIdx.x);
+}
+
+// defined by the generated epilogue: workgroup -> (branch, 64 knots), M^-1 by either route
+template <bool kDirect>
+__device__ void grid_dispatch_minv(const grid::Args& args, int block);
+
+// M^-1 alone, one lane per knot: composite bodies and the L^T L factor
+extern "C" __global__ void __launch_bounds__(64) grid_minv_serial(grid::Args args)
+{
+    grid_dispatch_minv<false>(args, (int)blockIdx.x);
+}
+
+// M^-1 alone, one lane per knot: the direct articulated-body inverse (Sec. IV-B)
+extern "C" __global__ void __launch_bounds__(64) grid_minv_direct(grid::Args args)
+{
+    grid_dispatch_minv<true>(args, (int)blockIdx.x);
 }
 
 #endif  // GRID_PIPE_ONLY

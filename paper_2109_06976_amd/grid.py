@@ -32,6 +32,8 @@ GRID_MAX_KNOTS = 1 << 24      # the largest N of one call
 GRID_SERVER_PER_REQUEST = 1
 GRID_SERVER_MAPPED_IO = 2
 GRID_SERVER_DIRECT_PINNED = 4
+# M^-1 routes of grid_minv_route
+MINV_QUAD, MINV_LANE_LTL, MINV_LANE_DIRECT = 0, 1, 2
 GRID_CODEGEN_PIPE_MODULE = 1 << 16
 
 _i32p = C.POINTER(C.c_int32)
@@ -135,6 +137,8 @@ _SIGS = {
     "grid_fd": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_void_p]),
     "grid_minv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "grid_minv_route": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                    C.c_void_p]),
     "grid_id_grad": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
     "grid_dt_jacobians": (C.c_int32, [C.c_void_p, C.c_int32, C.c_float, C.c_void_p,
@@ -391,6 +395,14 @@ class Model:
         v, m = _vec_mat(N, self.n)
         _check(lib().grid_minv(self._h, int(N), _dev(q, v, self.device, "q"),
                                _dev(Minv, m, self.device, "Minv"), _stream_handle(stream)))
+
+    def minv_route(self, q, Minv, route, N=None, stream=None):
+        """grid_minv_route: M(q)^-1 by MINV_QUAD, MINV_LANE_LTL or MINV_LANE_DIRECT."""
+        N = int(q.shape[0]) if N is None else N
+        v, m = _vec_mat(N, self.n)
+        _check(lib().grid_minv_route(self._h, int(N), _dev(q, v, self.device, "q"),
+                                     _dev(Minv, m, self.device, "Minv"), int(route),
+                                     _stream_handle(stream)))
 
     def id_grad(self, q, qd, qdd, dtau_dq, dtau_dqd, N=None, stream=None):
         """grid_id_grad: dtau/dq and dtau/dqd at the given qdd."""

@@ -106,6 +106,49 @@ def test_ops_match_oracle(orc, name):
         m.close()
 
 
+@pytest.mark.parametrize("name", list(ROBOTS))
+def test_minv_routes_match_oracle(orc, name):
+    """grid_minv_route: the one-lane-per-knot routes (composite bodies with the L^T L factor,
+    and the paper's direct articulated-body inverse) against the oracle's Cholesky M^-1 and
+    its direct recursion, at knot counts that leave ragged 64-knot workgroups; the quad route
+    is grid_minv itself (bit for bit); all three exactly symmetric with exact zeros between
+    base branches."""
+    import torch
+    robot = ROBOTS[name]()
+    n = robot.n
+    m = grid.Model(robot)
+    root = _roots(robot.parent)
+    cross = root[:, None] != root[None, :]
+    try:
+        for N in (1, 65, 130):
+            kn = synth.random_knots(n, N, 900 + N)
+            q = torch.from_numpy(kn.q).cuda()
+            r_chol = np.stack([orc.minv_cholesky(robot, kn.q[k]) for k in range(N)])
+            r_dir = np.stack([orc.minv_direct(robot, kn.q[k]) for k in range(N)])
+            say(f"[gpu] {name}: M^-1 routes at N={N}")
+            plain = torch.full((N, n, n), float("nan"), device="cuda")
+            m.minv(q, plain)
+            for route in (grid.MINV_QUAD, grid.MINV_LANE_LTL, grid.MINV_LANE_DIRECT):
+                out = torch.full((N, n, n), float("nan"), device="cuda")
+                m.minv_route(q, out, route)
+                torch.cuda.synchronize()
+                got = out.cpu().numpy()
+                e1 = normwise(got, r_chol).max()
+                e2 = normwise(got, r_dir).max()
+                say(f"  route {route}: vs Cholesky {e1:.1e}, vs direct {e2:.1e}")
+                assert e1 <= 1e-3 and e2 <= 1e-3, (name, N, route)
+                np.testing.assert_array_equal(got, np.swapaxes(got, 1, 2))
+                assert np.all(got[:, cross] == 0.0)
+                if route == grid.MINV_QUAD:
+                    np.testing.assert_array_equal(got, plain.cpu().numpy())
+        with pytest.raises(grid.GridError) as e:
+            m.minv_route(q, plain, 3)
+        assert e.value.status == grid.GRID_EINVAL
+        m.minv_route(q, plain, grid.MINV_LANE_DIRECT, N=0)   # N = 0 is a no-op
+    finally:
+        m.close()
+
+
 def test_ops_reject_bad_arguments():
     import torch
     m = grid.Model(synth.chain7())
