@@ -921,6 +921,8 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         }
         __syncthreads();                      // c published
 
+        // (computed before the barrier, where this wavefront waits, these sources made every
+        // launch 20-25% slower: after it they interleave with the start of the column sweep)
         Rot Ej;
         LaneK Kj;
         pick_joint<I>(E, K, j, Ej, Kj);
@@ -1073,6 +1075,20 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                 if (b == i || is_anc<S>(b, i))
                     Lf[i][b] = s_M[pslot][i][b];
         ltl_factor<S>(Lf, dinv);
+        // up to 16 bodies the factor is used only after the barrier, and the scheduler would
+        // sink it there, onto the chain that follows the barrier; taking its values as operands
+        // of an empty statement keeps it before, where this wavefront waits anyway (chain7:
+        // 4.46 -> 4.37 us per launch; beyond 16 bodies the factor's LDS copy keeps it there)
+        if constexpr (PS::HASC) {
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                asm volatile("" : "+v"(dinv[i]));
+#pragma unroll
+                for (int b = 0; b < i; ++b)
+                    if (is_anc<S>(b, i))
+                        asm volatile("" : "+v"(Lf[i][b]));
+            }
+        }
         if constexpr (!PS::HASC) {
             // no role C beyond 16 bodies: the factor goes to role A, which finishes with
             // triangular solves (and the columns of M^-1) after the second barrier
