@@ -864,6 +864,9 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     __shared__ float s_out[3][kStage ? B : 1][kStage ? B : 1];
     __shared__ int s_rowg[kStage ? B : 1];
     __shared__ int s_locc[kStage ? N : 1];
+    // beyond 16 bodies role B publishes its factor after the first barrier and raises this
+    // flag; role A needs the factor only after its dRNEA column and waits for the flag there
+    __shared__ int s_lflag;
 
     int tid = (int)threadIdx.x;
     if constexpr (kLoop)
@@ -873,6 +876,8 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
     const int c = lane & 3;
     const Lane ln = lane_of(c == 3 ? 0 : c, I::a0());
     if constexpr (kStage) {                   // ordered by the lane table's barrier
+        if (tid == 0)
+            s_lflag = 0;
         if (tid < B)
             s_rowg[tid] = I::body_of(tid);
         if (tid < N) {
@@ -941,9 +946,15 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
         for (int k = 0; k < 4; ++k)
             mk[k] = c == k ? 1.0f : 0.0f;
         if constexpr (!PS::HASC) {
-            // the factor has been in LDS since the first barrier: the quad of column (qd, j)
-            // solves for column j of M^-1 while role B is still on the qdd parts (entries
-            // (i, j), i <= j, to both mirrored positions: exactly symmetric)
+            // role B published the factor right after the first barrier (thousands of cycles
+            // before this point); the wait is bounded so that it ends in any case. The quad
+            // of column (qd, j) solves for column j of M^-1 while role B is still on the qdd
+            // parts (entries (i, j), i <= j, to both mirrored positions: exactly symmetric)
+            for (int spin = 0; spin < (1 << 20); ++spin) {
+                if (__hip_atomic_load(&s_lflag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP))
+                    break;
+                __builtin_amdgcn_s_sleep(1);
+            }
             float mc[B];
 #pragma unroll
             for (int i = 0; i < B; ++i) {
@@ -1089,9 +1100,11 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                         asm volatile("" : "+v"(Lf[i][b]));
             }
         }
+        __syncthreads();                      // c published
         if constexpr (!PS::HASC) {
             // no role C beyond 16 bodies: the factor goes to role A, which finishes with
-            // triangular solves (and the columns of M^-1) after the second barrier
+            // triangular solves (and the columns of M^-1); published after the barrier, so
+            // that the barrier does not wait for it, and released through the flag
             if (lane == 0) {
 #pragma unroll
                 for (int i = 0; i < B; ++i) {
@@ -1101,9 +1114,9 @@ __device__ __forceinline__ void run_pipe(const grid::Args& A, int block)
                         if (is_anc<S>(b, i))
                             s_Mi[pslot][i][b] = Lf[i][b];
                 }
+                __hip_atomic_store(&s_lflag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
-        __syncthreads();                      // c published
 
         float x[B];
 #pragma unroll
