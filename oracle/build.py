@@ -32,6 +32,14 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(path: str, verbose: bool = False) -> str:
+    """The same source with AddressSanitizer and UndefinedBehaviorSanitizer, at `path` (for the
+    CPU tests under the sanitizers)."""
+    return " ".join(_compile(["-O1", "-g", "-fsanitize=address,undefined",
+                              "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"],
+                             path, verbose))
+
+
 def build_timing(path: str, verbose: bool = False) -> str:
     """The timing build at `path`; returns the gcc command line it used."""
     return " ".join(_compile(TIMING_FLAGS, path, verbose))

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libgrid_oracle.so")
+# GRID_ORACLE_LIB names another build of the same source (the sanitized build of the tests)
+_LIB_PATH = os.environ.get("GRID_ORACLE_LIB") or os.path.join(_HERE, "libgrid_oracle.so")
 _lib = None
 
 _dp = C.POINTER(C.c_double)

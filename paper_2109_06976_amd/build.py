@@ -50,19 +50,29 @@ def embed_device_source() -> None:
                 f.write(text)
 
 
-def build_library(verbose=False) -> str:
+# AddressSanitizer and UndefinedBehaviorSanitizer on the host code only (each -fsanitize=
+# behind -Xarch_host: the device code is built as usual)
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def build_library(verbose=False, out=None, sanitize=False) -> str:
+    """libgrid.so in-tree; with sanitize=True a build of the same sources whose host code
+    carries ASan and UBSan, at `out` (for the CPU tests under the sanitizers)."""
     embed_device_source()
-    cmd = [HIPCC, "-std=c++17", "-O2", "-fPIC", "-shared", "-Wall", "-Wextra",
+    target = out or LIB
+    opt = ["-O1", "-g", *HOST_SANITIZE] if sanitize else ["-O2"]
+    cmd = [HIPCC, "-std=c++17", *opt, "-fPIC", "-shared", "-Wall", "-Wextra",
            "--offload-arch=gfx950", *NO_PACKED_FP32,
            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", BUILD,
            os.path.join(CSRC, "grid_runtime.cpp"), os.path.join(CSRC, "grid_codegen.cpp"),
            os.path.join(CSRC, "grid_vjp.hip"), os.path.join(CSRC, "grid_server.cpp"),
            os.path.join(CSRC, "grid_batch.cpp"), os.path.join(CSRC, "grid_noalloc.hip"),
            os.path.join(CSRC, "grid_io.hip"),
-           "-lhiprtc", "-lpthread", "-o", LIB + ".tmp"]
+           "-lhiprtc", "-lpthread", "-o", target + ".tmp"]
     _run(cmd, verbose)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(target + ".tmp", target)
+    return target
 
 
 def standard_models():

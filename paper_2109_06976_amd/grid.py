@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgrid.so")
+# GRID_LIB names another build of the same library (the sanitized host build of the tests)
+LIB_PATH = os.environ.get("GRID_LIB") or os.path.join(_HERE, "libgrid.so")
 
 GRID_OK = 0
 GRID_EINVAL = -1
