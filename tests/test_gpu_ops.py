@@ -149,6 +149,34 @@ def test_minv_routes_match_oracle(orc, name):
         m.close()
 
 
+@pytest.mark.parametrize("name", ["chain7", "quad12", "humanoid30"])
+def test_minv_routes_at_bench_sizes(orc, name):
+    """The M^-1 routes at the largest knot count the benchmark times them at (65536): a seeded
+    sample of knots, the first and last included, against the oracle's Cholesky inverse; every
+    knot exactly symmetric."""
+    import torch
+    robot = ROBOTS[name]()
+    n = robot.n
+    N = 65536
+    m = grid.Model(robot)
+    try:
+        kn = synth.random_knots(n, N, 950)
+        q = torch.from_numpy(kn.q).cuda()
+        pick = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(951).integers(0, N, 62)]))
+        ref = np.stack([orc.minv_cholesky(robot, kn.q[k]) for k in pick])
+        for route in (grid.MINV_QUAD, grid.MINV_LANE_LTL, grid.MINV_LANE_DIRECT):
+            say(f"[gpu] {name}: M^-1 route {route} at N={N}")
+            out = torch.full((N, n, n), float("nan"), device="cuda")
+            m.minv_route(q, out, route)
+            torch.cuda.synchronize()
+            assert bool(torch.equal(out, out.transpose(1, 2)))
+            got = out[torch.from_numpy(pick).cuda()].cpu().numpy()
+            assert normwise(got, ref).max() <= 1e-3, (name, route)
+            del out
+    finally:
+        m.close()
+
+
 def test_ops_reject_bad_arguments():
     import torch
     m = grid.Model(synth.chain7())
