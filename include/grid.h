@@ -133,10 +133,12 @@ grid_status grid_model_destroy(grid_model m);
 grid_status grid_model_info(grid_model m, int32_t* n, size_t* io_bytes_per_knot,
                             int32_t* lanes);
 
-/* A 64-bit FNV-1a hash of the model's two loaded code objects (every kernel generated for
- * the robot, then the role-split kernel's own module), so that measurements taken on a
- * kernel can be matched to the exact machine code they ran; the same robot, sources and
- * compiler give the same hash. Errors: EINVAL (NULL argument). */
+/* A 64-bit FNV-1a hash of the machine code of the model's two loaded code objects (every
+ * kernel generated for the robot, then the role-split kernel's own module: their .text,
+ * .rodata and .note sections), so that measurements taken on a kernel can be matched to the
+ * exact machine code they ran; the same robot, sources and compiler give the same hash, and
+ * an edit that leaves the machine code alone (a comment) does not change it.
+ * Errors: EINVAL (NULL argument). */
 grid_status grid_model_code_hash(grid_model m, uint64_t* hash);
 
 /*

@@ -518,6 +518,57 @@ static uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull)
 
 uint64_t source_hash(const std::string& source) { return fnv1a(source); }
 
+// The machine code and constant data of an ELF64 code object: the .text, .rodata and .note
+// sections (instructions, kernel descriptors and constant tables, kernel metadata), in that
+// order, each behind its name. The symbol tables are left out: they carry an identifier of
+// the compilation that changes with any edit of the source text, comments included, while the
+// machine code stays the same. An object that does not parse as ELF64 is taken whole.
+std::string machine_code(const std::vector<char>& elf)
+{
+    const std::string whole(elf.begin(), elf.end());
+    auto rd = [&](size_t off, size_t n, uint64_t* v) {
+        if (off + n > elf.size())
+            return false;
+        uint64_t x = 0;
+        for (size_t k = 0; k < n; ++k)   // little endian
+            x |= (uint64_t)(unsigned char)elf[off + k] << (8 * k);
+        *v = x;
+        return true;
+    };
+    if (elf.size() < 64 || elf[0] != 0x7f || elf[1] != 'E' || elf[2] != 'L' || elf[3] != 'F' ||
+        elf[4] != 2)
+        return whole;
+    uint64_t shoff, shentsize, shnum, shstrndx;
+    if (!rd(0x28, 8, &shoff) || !rd(0x3a, 2, &shentsize) || !rd(0x3c, 2, &shnum) ||
+        !rd(0x3e, 2, &shstrndx) || shentsize < 64 || shstrndx >= shnum)
+        return whole;
+    auto sec = [&](uint64_t k, uint64_t* name, uint64_t* type, uint64_t* off, uint64_t* size) {
+        const size_t h = (size_t)(shoff + k * shentsize);
+        return rd(h, 4, name) && rd(h + 4, 4, type) && rd(h + 24, 8, off) && rd(h + 32, 8, size);
+    };
+    uint64_t sn, st, soff, ssize;
+    if (!sec(shstrndx, &sn, &st, &soff, &ssize) || soff + ssize > elf.size())
+        return whole;
+    std::string out;
+    for (const char* want : {".text", ".rodata", ".note"}) {
+        for (uint64_t k = 0; k < shnum; ++k) {
+            uint64_t name, type, off, size;
+            if (!sec(k, &name, &type, &off, &size) || name >= ssize)
+                return whole;
+            const char* nm = elf.data() + soff + name;
+            if (std::strncmp(nm, want, ssize - name) != 0)
+                continue;
+            if (type == 8)                    // SHT_NOBITS: nothing in the file
+                continue;
+            if (off + size > elf.size())
+                return whole;
+            out += want;
+            out.append(elf.data() + off, (size_t)size);
+        }
+    }
+    return out.empty() ? whole : out;
+}
+
 std::string cache_dir()
 {
     if (const char* env = std::getenv("GRID_KERNEL_CACHE"))

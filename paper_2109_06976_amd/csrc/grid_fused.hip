@@ -402,25 +402,6 @@ __device__ __forceinline__ void m_column(const Lane& ln, const Rot (&E)[I::S::B]
     m_column<I, JMIN>(ln, E, K, jm, fm, am);
 }
 
-// Sum of x over the QB quads of a problem (lanes with the same component c in an aligned group
-// of 4 QB lanes): two DPP row rotations inside each row of 16 lanes, then lane swaps of 16 and
-// 32 for groups that span rows.
-template <int QB>
-__device__ __forceinline__ float quad_group_sum(float x)
-{
-    if constexpr (QB >= 4) {
-        x += qperm<0x128>(x);                 // row_ror:8
-        x += qperm<0x124>(x);                 // row_ror:4
-    } else if constexpr (QB == 2) {
-        x += __shfl_xor(x, 4);
-    }
-    if constexpr (QB >= 8)
-        x += __shfl_xor(x, 16);
-    if constexpr (QB >= 16)
-        x += __shfl_xor(x, 32);
-    return x;
-}
-
 // M = L^T L in place (L lower triangular, nonzero on ancestor paths only): for k from the
 // leaves, L_kk = sqrt(M_kk), L_ka = M_ka / L_kk, M_ab -= L_ka L_kb (a, b ancestors of k)
 template <class S>

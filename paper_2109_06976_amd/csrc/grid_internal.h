@@ -140,6 +140,7 @@ WorkspaceLayout workspace_layout(const Topology& t);
 grid_status compile_cached(const std::string& source, std::vector<char>* code, std::string* err,
                            bool ilp = false);
 uint64_t source_hash(const std::string& source);
+std::string machine_code(const std::vector<char>& elf);
 grid_status launch_fused(grid_model m, int32_t N, const float* q, const float* qd,
                          const float* tau, float* qdd, float* Minv, float* dq, float* dqd,
                          hipStream_t stream);

@@ -544,8 +544,7 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
     m->device = device;
     m->flags = flags;
     m->topo = std::move(topo);
-    m->code_hash = source_hash(std::string(code.begin(), code.end()) +
-                               std::string(pipe_code.begin(), pipe_code.end()));
+    m->code_hash = source_hash(machine_code(code) + machine_code(pipe_code));
     static const char* const kStages[5] = {"grid_stage_rnea", "grid_stage_minv", "grid_stage_qdd",
                                            "grid_stage_drnea", "grid_stage_fdgrad"};
     static const char* const kVariants[kNumVariants] = {
