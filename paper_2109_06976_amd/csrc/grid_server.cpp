@@ -77,9 +77,6 @@ struct BatchCtx {
 
 size_t request_bytes(int n, int N) { return sizeof(float) * (size_t)N * (4 * n + 3 * n * n); }
 
-// The device address of host array [p, p + bytes) when the whole range lies inside one pinned
-// host allocation mapped into the device; NULL otherwise (pageable memory, a range that runs
-// past its allocation, or a failed query).
 // Host array for the load generator: ordinary memory, or pinned and mapped into the device.
 struct HostArray {
     float* ptr = nullptr;
@@ -117,6 +114,9 @@ struct HostArray {
     float& operator[](size_t i) { return ptr[i]; }
 };
 
+// The device address of host array [p, p + bytes) when the whole range lies inside one pinned
+// host allocation mapped into the device; NULL otherwise (pageable memory, a range that runs
+// past its allocation, or a failed query).
 float* mapped_range(const void* p, size_t bytes)
 {
     hipDeviceptr_t start = nullptr;
