@@ -26,16 +26,18 @@
 //                        part of each q-column that depends on qdd
 //   role C (B columns, one wavefront; branches of up to 16 bodies): once role B has
 //                        published M, its factor and M^-1. Beyond 16 bodies role B publishes
-//                        its factor instead: role A's qd-columns solve for the columns of
-//                        M^-1 before the second barrier, and every column ends with two
-//                        triangular solves
+//                        its factor instead (after the first barrier, behind an LDS flag):
+//                        role A's qd-columns solve for the columns of M^-1 before the second
+//                        barrier, every column ends with two triangular solves, and the
+//                        outputs are staged in LDS and written as whole rows
 // dtau/dqd does not depend on qdd, and dtau/dq is affine in the two source terms that do:
 // the parent acceleration (X_j a_lambda(j)) x S enters the forward sweep and the term
 // X_j^T (S x* f_j) the backward sweep, each linearly, so the qdd part of a q-column is the
 // same sweep with the increments X_j Da_lambda(j) and Df_j as sources and dv = 0
 // (da_i = X_i da_lambda + source, df_i = I_i da_i). Role A adds role B's parts and
 // multiplies by role C's M^-1, both read from LDS. Two workgroup barriers: after RNEA and
-// the columns of M, and before the final products.
+// the columns of M, and before the final products (beyond 16 bodies a third before the staged
+// rows go out).
 
 namespace gridq {
 
