@@ -399,7 +399,11 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
     }
 
     // ------------------------------------------------------------ 6. dRNEA and dFD columns
-#pragma unroll 1
+    // One lane per knot and a branch of up to 8 bodies: the loop is unrolled, so that j is a
+    // constant in each copy (no selects of the joint's quantities, the subtree tests folded;
+    // chain7 at 65536 knots 44.6 -> 37.1 us); otherwise one copy of the body, j at run time.
+    constexpr int kUnrollJ = (L == 1 && B <= 8) ? B : 1;
+#pragma unroll kUnrollJ
     for (int j = h; j < B; j += L) {
         // sources of joint j: u = q: dv += v_j x S, da += (X_j a_lambda(j)) x S,
         // backward += X_j^T (S x* f_j); u = qd: dv += S, da += v_j x S
