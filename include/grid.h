@@ -386,8 +386,10 @@ grid_status grid_mixed_graph_create(grid_mixed mx, const grid_mixed_item* items,
 grid_status grid_mixed_graph_update(grid_graph g, const grid_mixed_item* items, int32_t count);
 
 /*
- * Time the three modes on these items (3 warm-up and 20 timed launches per trial, median of
- * 5 trials, HIP events on a stream of the library's; the items' outputs are written) and keep
+ * Tune each robot's own model for the knot counts it has among the items (grid_tune, so that
+ * the per-robot mode runs the builds that tuning picks), then time the three modes on these
+ * items (3 warm-up and 20 timed launches per trial, median of 5 trials, HIP events on a
+ * stream of the library's; the items' outputs are written) and keep
  * the fastest for launches of this size: from then on grid_mixed_launch runs a batch of B
  * blocks in the mode tuned for the smallest tuned size >= B (the largest beyond; one launch
  * when nothing is tuned). *chosen (may be NULL) receives the mode; us (may be NULL) receives

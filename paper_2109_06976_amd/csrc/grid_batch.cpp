@@ -661,6 +661,21 @@ grid_status grid_mixed_tune(grid_mixed mx, const grid_mixed_item* items, int32_t
         cleanup();
         return fail(GRID_EDEVICE, std::string("mixed tuning: ") + hipGetErrorString(e));
     }
+    // per-robot mode runs each robot's own build for the item's N: tune every robot's model
+    // for the knot counts it has here first, so that the modes are compared at their best
+    for (size_t r = 0; r < mx->models.size() && st == GRID_OK; ++r) {
+        std::vector<int32_t> Ns;
+        for (int j = 0; j < count; ++j)
+            if (items[j].robot == (int)r && items[j].N > 0 &&
+                std::find(Ns.begin(), Ns.end(), items[j].N) == Ns.end())
+                Ns.push_back(items[j].N);
+        if (!Ns.empty())
+            st = grid_tune(mx->models[r], Ns.data(), (int32_t)Ns.size(), nullptr, nullptr);
+    }
+    if (st != GRID_OK) {
+        cleanup();
+        return st;
+    }
     int best = GRID_MIXED_ONE_LAUNCH;
     float best_us = 1e30f;
     for (int mode = GRID_MIXED_ONE_LAUNCH; mode <= GRID_MIXED_PER_ROBOT; ++mode) {
