@@ -382,11 +382,19 @@ def serve(args, grid, synth, chain_model=None):
     robots = [synth.chain7(), synth.quad12(), synth.humanoid30()]
     models = [chain_model or grid.Model(robots[0]), grid.Model(robots[1]), grid.Model(robots[2])]
     probs = [0.5, 0.3, 0.2]
+    # the server's launches run the build each model's tuning picks for the batch's knot
+    # count: tune at the batch sizes it can launch (requests of 16-256 knots, batches up to
+    # 2048); untuned, a batch beyond one wavefront per SIMD would take the lane layout
+    batch_ns = [16, 32, 64, 128, 256, 512, 1024, 2048]
+    tuned_builds = {rb.name.split("-")[0]: {str(k): grid.BUILD_KERNELS[v]
+                                            for k, v in grid.tune(m, batch_ns).items()}
+                    for rb, m in zip(robots, models)}
     out = {"workload": "Poisson arrivals, chain7/quad12/humanoid30 at 50/30/20 %, "
                        "N ~ U{16..256}, latency = outputs in host memory - scheduled arrival",
            "measured_s": args.serve_seconds, "warmup_s": 1.0}
     rates = [args.serve_rate] + [float(x) for x in args.serve_sweep.split(",")
                                  if x and float(x) != args.serve_rate]
+    out["tuned_builds"] = tuned_builds
     out["policy"] = {"contexts_per_model": args.serve_contexts,
                      "batch_window_us": args.serve_window_us,
                      "min_batch_knots": args.serve_min_knots}
