@@ -2,6 +2,7 @@
 #include "grid_internal.h"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -238,10 +239,20 @@ int fused_variant_for(grid_model m, int32_t N)
             return e.second;
     if (!m->tuned.empty())
         return m->tuned.back().second;
-    // untuned: the two-role quad layout while its wavefronts fit one per SIMD of the device
-    // (the lowest-latency form), the lane layout beyond (fewer instructions per knot)
+    // untuned: the three-role kernel while its wavefronts fit one per SIMD of the device (the
+    // lowest-latency form), the lane layout beyond (fewer instructions per knot). A branch of
+    // more than 8 bodies makes the lane layout's repeated sweeps expensive, and the tuner keeps
+    // the three-role kernel far beyond one wavefront per SIMD there (humanoid30: up to 4096
+    // knots, then build 6)
     const int64_t waves = workgroups_pipe(m->topo, N) * pipe_waves(m->topo);
-    return waves <= 4 * (int64_t)m->compute_units ? kVariantPipe : kVariantLane1;
+    if (waves <= 4 * (int64_t)m->compute_units)
+        return kVariantPipe;
+    int largest = 0;
+    for (const BranchShape& sh : m->topo.shapes)
+        largest = std::max(largest, sh.B);
+    if (largest > 8)
+        return N <= 4096 ? kVariantPipe : kVariantSerial4;
+    return kVariantLane1;
 }
 
 grid_status launch_fused_variant(grid_model m, int variant, int32_t N, const float* q,

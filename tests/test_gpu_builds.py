@@ -133,3 +133,22 @@ def test_serial_build_unaligned_outputs(name, build):
     finally:
         grid.tune_apply(m, {})
         m.close()
+
+
+def test_untuned_build_choice():
+    """The build an untuned model runs per batch size: the three-role kernel while its
+    wavefronts fit one per SIMD, then the lane layout; a robot with a branch of more than 8
+    bodies keeps the three-role kernel up to 4096 knots and takes build 6 beyond (the choices
+    the tuner makes for these robots on an MI355X)."""
+    import torch
+    assert torch.cuda.is_available()
+    cases = {"chain7": {128: grid.BUILD_PIPE, 512: grid.BUILD_PIPE, 4096: grid.BUILD_LANE},
+             "humanoid30": {128: grid.BUILD_PIPE, 1024: grid.BUILD_PIPE, 4096: grid.BUILD_PIPE,
+                            8192: grid.BUILD_SERIAL4}}
+    for name, want in cases.items():
+        m = grid.Model(synth.model_by_name(name))
+        try:
+            for N, build in want.items():
+                assert grid.build_for(m, N) == build, (name, N, grid.build_for(m, N))
+        finally:
+            m.close()
