@@ -488,9 +488,10 @@ grid_status grid_fd_vjp_adjoint(grid_model m, int32_t N, const float* q, const f
  * one lane (no repeated work: the fewest instructions per knot, the longest latency). Build 6
  * is build 5 with four lanes per problem that share the columns of M^-1 and the derivative
  * columns (each repeats the rest): four times the wavefronts of build 5 for the same batch.
- * Untuned, a batch runs build 4 while its wavefronts fit one per SIMD of the device and
- * build 1 beyond, except for a robot with a base branch of more than 8 bodies: build 4 up to
- * 4096 knots, build 6 beyond. grid_tune times each build on the model's
+ * Untuned, a batch runs build 4 while its wavefronts fit one per SIMD of the device, build 1
+ * beyond, build 6 from 64 knots per compute unit and build 5 from 128, except for a robot
+ * with a base branch of more than 8 bodies: build 4 up to 4096 knots, build 6 beyond.
+ * grid_tune times each build on the model's
  * device for every knot count in Ns (synthetic inputs, HIP events, median of repeats),
  * keeps the fastest per count, and from then on grid_fd_grad uses, for a batch of N
  * knots, the choice made for the smallest tuned count >= N (the largest otherwise).

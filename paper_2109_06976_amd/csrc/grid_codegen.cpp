@@ -343,17 +343,27 @@ static void emit_prelude(std::ostringstream& os, const std::vector<RobotSource>&
 // kernel arguments are loaded. (A workgroup past the end would still only recompute the last
 // knot and store nothing: every store checks its knot.) `@` in per_block and call stands for
 // the branch's Inst.
+// `pool`, when given, is an expression in @ for the LDS floats one branch needs: the dispatch
+// then holds one array of the largest such size, `pool`, that every branch's call shares
 static void emit_dispatch(std::ostringstream& os, const Topology& t, const char* sig,
-                          const std::string& per_block, const std::string& call)
+                          const std::string& per_block, const std::string& call,
+                          const std::string& pool = "")
 {
-    os << sig << "\n{\n    int b = block;\n";
-    for (size_t k = 0; k < t.insts.size(); ++k) {
+    auto inst = [](size_t k, std::string x) {
         const std::string K = "Inst<" + std::to_string(k) + ">";
-        auto sub = [&](std::string x) {
-            for (size_t at; (at = x.find("@")) != std::string::npos;)
-                x.replace(at, 1, K);
-            return x;
-        };
+        for (size_t at; (at = x.find("@")) != std::string::npos;)
+            x.replace(at, 1, K);
+        return x;
+    };
+    os << sig << "\n{\n    int b = block;\n";
+    if (!pool.empty()) {
+        os << "    __shared__ __align__(16) float pool[grids::cmax(";
+        for (size_t k = 0; k < t.insts.size(); ++k)
+            os << (k ? ", " : "") << inst(k, pool);
+        os << ")];\n";
+    }
+    for (size_t k = 0; k < t.insts.size(); ++k) {
+        auto sub = [&](const std::string& x) { return inst(k, x); };
         if (k + 1 == t.insts.size()) {
             os << "    " << sub(call) << ";\n";
             break;
@@ -389,10 +399,10 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << grid_serial_src;
     os << "\n// generated: workgroup -> (branch, 64 knots), one lane per knot\n";
     emit_dispatch(os, t, "__device__ void grid_dispatch_s(const grid::Args& a, int block)", "64",
-             "grids::run_serial<@>(a, b)");
+             "grids::run_serial<@>(a, b, pool)", "grids::serial_stage_floats<@, 1>()");
     os << "\n// generated: workgroup -> (branch, 16 knots), four lanes per knot\n";
     emit_dispatch(os, t, "__device__ void grid_dispatch_s4(const grid::Args& a, int block)", "16",
-             "grids::run_serial<@, 4>(a, b)");
+             "grids::run_serial<@, 4>(a, b, pool)", "grids::serial_stage_floats<@, 4>()");
     os << "\n// generated: workgroup -> (branch, 64 knots), M^-1 alone by either route\n";
     emit_dispatch(os, t, "template <bool D>\n__device__ void grid_dispatch_minv(const grid::Args& a, int block)",
              "64", "grids::run_minv<@, D>(a, b)");

@@ -240,10 +240,12 @@ int fused_variant_for(grid_model m, int32_t N)
     if (!m->tuned.empty())
         return m->tuned.back().second;
     // untuned: the three-role kernel while its wavefronts fit one per SIMD of the device (the
-    // lowest-latency form), the lane layout beyond (fewer instructions per knot). A branch of
-    // more than 8 bodies makes the lane layout's repeated sweeps expensive, and the tuner keeps
-    // the three-role kernel far beyond one wavefront per SIMD there (humanoid30: up to 4096
-    // knots, then build 6)
+    // lowest-latency form), the lane layout beyond (fewer instructions per knot), and from 64
+    // knots per compute unit the forms with one problem per lane or four lanes (no repeated
+    // sweeps; build 5 once it has 128 knots per compute unit, half a wavefront per SIMD at
+    // least). A branch of more than 8 bodies makes the lane layout's repeated sweeps expensive,
+    // and the tuner keeps the three-role kernel far beyond one wavefront per SIMD there
+    // (humanoid30: up to 4096 knots, then build 6)
     const int64_t waves = workgroups_pipe(m->topo, N) * pipe_waves(m->topo);
     if (waves <= 4 * (int64_t)m->compute_units)
         return kVariantPipe;
@@ -252,6 +254,10 @@ int fused_variant_for(grid_model m, int32_t N)
         largest = std::max(largest, sh.B);
     if (largest > 8)
         return N <= 4096 ? kVariantPipe : kVariantSerial4;
+    if (N >= 128 * (int64_t)m->compute_units)
+        return kVariantSerial;
+    if (N >= 64 * (int64_t)m->compute_units)
+        return kVariantSerial4;
     return kVariantLane1;
 }
 

@@ -195,6 +195,49 @@ struct SerialStage {
     static constexpr int floats = on ? K * N * N : 4;
 };
 
+// A branch that is not the whole robot (N > B) owns B rows of each knot's blocks, scattered
+// over the robot's numbering: lane-per-knot stores of one element each would again hit 64
+// addresses N^2 floats apart. With one lane per knot its rows are staged instead ([K][B][N],
+// local row i, robot column) while two such tiles fit 32 KB, and the wavefront writes each
+// row's N floats with consecutive lanes on consecutive elements, zeros in the other branches'
+// columns included. (Four lanes per knot already store four columns side by side; staging
+// there gained 8% on 3-body legs but cost 8% on a robot whose other branch is too large to
+// stage, so it stays off.)
+template <int B, int N, int K>
+struct SerialRows {
+    static constexpr bool on = K == 64 && N > B && 2 * K * B * N * 4 <= 32 * 1024;
+    static constexpr int floats = on ? K * B * N : 4;
+};
+
+// floats of LDS one branch's staging takes (its two tiles); the dispatch of a robot allocates
+// the largest over its branches once, so that the branches of one kernel share it
+template <class I, int L>
+constexpr int serial_stage_floats()
+{
+    using ST = SerialStage<I::S::B, I::N, 64 / L>;
+    using SR = SerialRows<I::S::B, I::N, 64 / L>;
+    return 2 * (ST::on ? ST::floats : SR::floats);
+}
+
+constexpr int cmax(int a) { return a; }
+template <class... T>
+constexpr int cmax(int a, int b, T... rest) { return cmax(a > b ? a : b, rest...); }
+
+// write the staged rows of the wavefront's nv valid knots: element (knot, local row i, column c)
+// goes to row body(i) of that knot's block; `dst` is the block of the wavefront's first knot
+template <class I>
+__device__ __forceinline__ void flush_rows(float* dst, const float* tile, int nv, int lane)
+{
+    constexpr int B = I::S::B;
+    constexpr int N = I::N;
+    for (int e = lane; e < nv * B * N; e += 64) {
+        const int kl = e / (B * N), rem = e - kl * (B * N);
+        const int i = rem / N, c2 = rem - i * N;
+        const float v = I::contains(c2) ? tile[e] : 0.0f;
+        dst[(long)kl * N * N + (long)I::body_of(i) * N + c2] = v;
+    }
+}
+
 // the workgroup is one wavefront: ordering its own LDS traffic needs no workgroup barrier
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -223,15 +266,17 @@ __device__ __forceinline__ void flush_stage(float* dst, const float* src, int cn
 // of M^-1 and the joints j of step 6 are dealt out among them (lane h takes h, h + L, ...), so
 // a wavefront holds 64 / L knots: L times the wavefronts of build 5 for the same batch, at the
 // cost of repeating steps 1-5 L times. The lanes of a knot are adjacent.
+// `pool` is the dispatch's LDS array of at least serial_stage_floats<I, L>() floats.
 template <class I, int L = 1>
-__device__ __forceinline__ void run_serial(const grid::Args& A, int block)
+__device__ __forceinline__ void run_serial(const grid::Args& A, int block, float* pool)
 {
     using S = typename I::S;
     constexpr int B = S::B;
     constexpr int N = I::N;
     constexpr int K = 64 / L;                        // knots per wavefront
     using ST = SerialStage<B, N, K>;
-    __shared__ __align__(16) float s_stage[2][ST::floats];
+    using SR = SerialRows<B, N, K>;
+    float* const s_stage[2] = {pool, pool + serial_stage_floats<I, L>() / 2};
     const int lane = (int)threadIdx.x;
     const int h = lane % L;                          // this lane's share of the columns
     const int kl = lane / L;                         // the knot within the wavefront
@@ -308,6 +353,9 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
                 if constexpr (ST::on) {
                     s_stage[0][kl * N * N + I::body[i] * N + I::body[jm]] = mc[i];
                     s_stage[0][kl * N * N + I::body[jm] * N + I::body[i]] = mc[i];
+                } else if constexpr (SR::on) {
+                    s_stage[0][kl * B * N + i * N + I::body[jm]] = mc[i];
+                    s_stage[0][kl * B * N + jm * N + I::body[i]] = mc[i];
                 } else {
                     A.Minv[mbase + (long)I::body[i] * N + I::body[jm]] = mc[i];
                     A.Minv[mbase + (long)I::body[jm] * N + I::body[i]] = mc[i];
@@ -331,6 +379,9 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
                 if constexpr (ST::on) {
                     s_stage[0][kl * N * N + I::body[i] * N + gm] = mc[i];
                     s_stage[0][kl * N * N + gm * N + I::body[i]] = mc[i];
+                } else if constexpr (SR::on) {
+                    s_stage[0][kl * B * N + i * N + gm] = mc[i];
+                    s_stage[0][kl * B * N + jm * N + I::body[i]] = mc[i];
                 } else {
                     A.Minv[mbase + (long)I::body[i] * N + gm] = mc[i];
                     A.Minv[mbase + (long)gm * N + I::body[i]] = mc[i];
@@ -356,10 +407,17 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
         flush_stage(A.Minv + kb * N * N, s_stage[0], nv * N * N, lane);
         flush_stage(A.qdd + kb * N, s_stage[1], nv * N, lane);
         wave_lds_sync();                      // staging free for the derivative columns
-    } else if (valid && h == 0) {
+    } else {
+        if (valid && h == 0) {
 #pragma unroll
-        for (int i = 0; i < B; ++i)
-            A.qdd[vbase + I::body[i]] = x[i];
+            for (int i = 0; i < B; ++i)
+                A.qdd[vbase + I::body[i]] = x[i];
+        }
+        if constexpr (SR::on) {
+            wave_lds_sync();                  // the rows of M^-1 staged
+            flush_rows<I>(A.Minv + kb * N * N, s_stage[0], nv, lane);
+            wave_lds_sync();                  // staging free for the derivative columns
+        }
     }
 
     // ------------------------------------------------------------ 5. RNEA at qdd
@@ -519,6 +577,9 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
                 if constexpr (ST::on) {
                     s_stage[0][kl * N * N + I::body[i] * N + gj] = -dx[0][i];
                     s_stage[1][kl * N * N + I::body[i] * N + gj] = -dx[1][i];
+                } else if constexpr (SR::on) {
+                    s_stage[0][kl * B * N + i * N + gj] = -dx[0][i];
+                    s_stage[1][kl * B * N + i * N + gj] = -dx[1][i];
                 } else {
                     A.dqdd_dq[mbase + (long)I::body[i] * N + gj] = -dx[0][i];
                     A.dqdd_dqd[mbase + (long)I::body[i] * N + gj] = -dx[1][i];
@@ -531,7 +592,12 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block)
         flush_stage(A.dqdd_dq + kb * N * N, s_stage[0], nv * N * N, lane);
         flush_stage(A.dqdd_dqd + kb * N * N, s_stage[1], nv * N * N, lane);
     }
-    if (valid && N > B) {
+    if constexpr (SR::on) {
+        wave_lds_sync();                      // every column staged
+        flush_rows<I>(A.dqdd_dq + kb * N * N, s_stage[0], nv, lane);
+        flush_rows<I>(A.dqdd_dqd + kb * N * N, s_stage[1], nv, lane);
+    }
+    if (valid && N > B && !SR::on) {
         // this branch's rows hold zeros in the other branches' columns
         for (int e = h; e < B * N; e += L) {
             const int i = e / N, c2 = e % N;

@@ -99,12 +99,15 @@ def test_tune_apply_rejects_bad_tables():
 
 
 @pytest.mark.parametrize("build", [grid.BUILD_SERIAL, grid.BUILD_SERIAL4])
-@pytest.mark.parametrize("name", ["chain7", "chain2", "chain7-prism"])
+@pytest.mark.parametrize("name", ["chain7", "chain2", "chain7-prism", "quad12", "tree3", "star32"])
 def test_serial_build_unaligned_outputs(name, build):
     """Builds 5 and 6 stage the outputs of single-branch robots in LDS and write them with
     16-byte stores when the output arrays are 16-byte aligned, else one float at a time: outputs
     at an offset of one float from an aligned base equal the aligned run bit for bit (N = 100:
-    full and partial wavefronts)."""
+    full and partial wavefronts). Build 5 stages a smaller branch's rows of a branched robot
+    and writes them row by row, zeros in the other branches' columns included: on arrays
+    filled with NaN beforehand every element comes out finite, and nothing outside them is
+    written."""
     import torch
     robot = ROBOTS[name]()
     m = grid.Model(robot)
@@ -137,14 +140,20 @@ def test_serial_build_unaligned_outputs(name, build):
 
 def test_untuned_build_choice():
     """The build an untuned model runs per batch size: the three-role kernel while its
-    wavefronts fit one per SIMD, then the lane layout; a robot with a branch of more than 8
-    bodies keeps the three-role kernel up to 4096 knots and takes build 6 beyond (the choices
-    the tuner makes for these robots on an MI355X)."""
+    wavefronts fit one per SIMD, then the lane layout, build 6 from 64 knots per compute unit
+    and build 5 from 128 (16384 and 32768 knots on the MI355X's 256); a robot with a branch of
+    more than 8 bodies keeps the three-role kernel up to 4096 knots and takes build 6 beyond
+    (the choices the tuner makes for these robots on an MI355X)."""
     import torch
     assert torch.cuda.is_available()
-    cases = {"chain7": {128: grid.BUILD_PIPE, 512: grid.BUILD_PIPE, 4096: grid.BUILD_LANE},
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    cases = {"chain7": {128: grid.BUILD_PIPE, 512: grid.BUILD_PIPE, 4096: grid.BUILD_LANE,
+                        64 * cu - 1: grid.BUILD_LANE, 64 * cu: grid.BUILD_SERIAL4,
+                        128 * cu - 1: grid.BUILD_SERIAL4, 128 * cu: grid.BUILD_SERIAL,
+                        65536: grid.BUILD_SERIAL},
+             "quad12": {64 * cu: grid.BUILD_SERIAL4, 128 * cu: grid.BUILD_SERIAL},
              "humanoid30": {128: grid.BUILD_PIPE, 1024: grid.BUILD_PIPE, 4096: grid.BUILD_PIPE,
-                            8192: grid.BUILD_SERIAL4}}
+                            8192: grid.BUILD_SERIAL4, 65536: grid.BUILD_SERIAL4}}
     for name, want in cases.items():
         m = grid.Model(synth.model_by_name(name))
         try:
