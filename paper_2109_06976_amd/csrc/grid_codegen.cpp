@@ -399,10 +399,17 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     os << grid_serial_src;
     os << "\n// generated: workgroup -> (branch, 64 knots), one lane per knot\n";
     emit_dispatch(os, t, "__device__ void grid_dispatch_s(const grid::Args& a, int block)", "64",
-             "grids::run_serial<@>(a, b, pool)", "grids::serial_stage_floats<@, 1>()");
-    os << "\n// generated: workgroup -> (branch, 16 knots), four lanes per knot\n";
+             "grids::run_serial<@, 1, true>(a, b, pool)",
+             "grids::serial_stage_floats<@, 1, true>()");
+    os << "\n// generated: workgroup -> (branch, 16 knots), four lanes per knot; rows staged only\n"
+          "// when every branch's fit\n";
+    os << "constexpr bool grid_rows4 = true";
+    for (size_t k = 0; k < t.insts.size(); ++k)
+        os << " && grids::serial_rows_fit<Inst<" << k << ">, 4>()";
+    os << ";\n";
     emit_dispatch(os, t, "__device__ void grid_dispatch_s4(const grid::Args& a, int block)", "16",
-             "grids::run_serial<@, 4>(a, b, pool)", "grids::serial_stage_floats<@, 4>()");
+             "grids::run_serial<@, 4, grid_rows4>(a, b, pool)",
+             "grids::serial_stage_floats<@, 4, grid_rows4>()");
     os << "\n// generated: workgroup -> (branch, 64 knots), M^-1 alone by either route\n";
     emit_dispatch(os, t, "template <bool D>\n__device__ void grid_dispatch_minv(const grid::Args& a, int block)",
              "64", "grids::run_minv<@, D>(a, b)");

@@ -197,25 +197,32 @@ struct SerialStage {
 
 // A branch that is not the whole robot (N > B) owns B rows of each knot's blocks, scattered
 // over the robot's numbering: lane-per-knot stores of one element each would again hit 64
-// addresses N^2 floats apart. With one lane per knot its rows are staged instead ([K][B][N],
-// local row i, robot column) while two such tiles fit 32 KB, and the wavefront writes each
-// row's N floats with consecutive lanes on consecutive elements, zeros in the other branches'
-// columns included. (Four lanes per knot already store four columns side by side; staging
-// there gained 8% on 3-body legs but cost 8% on a robot whose other branch is too large to
-// stage, so it stays off.)
-template <int B, int N, int K>
+// addresses N^2 floats apart. Its rows are staged instead ([K][B][N], local row i, robot
+// column) while two such tiles fit 32 KB, and the wavefront writes each row's N floats with
+// consecutive lanes on consecutive elements, zeros in the other branches' columns included.
+// With four lanes per knot (whose stores already put four columns side by side) the dispatch
+// stages only when every branch of the robot fits: on a robot whose long branch does not,
+// staging its short ones made the launch slower.
+template <int B, int N, int K, bool kAllowed = true>
 struct SerialRows {
-    static constexpr bool on = K == 64 && N > B && 2 * K * B * N * 4 <= 32 * 1024;
+    static constexpr bool fits = N > B && 2 * K * B * N * 4 <= 32 * 1024;
+    static constexpr bool on = kAllowed && fits;
     static constexpr int floats = on ? K * B * N : 4;
 };
 
+template <class I, int L>
+constexpr bool serial_rows_fit()
+{
+    return SerialRows<I::S::B, I::N, 64 / L>::fits;
+}
+
 // floats of LDS one branch's staging takes (its two tiles); the dispatch of a robot allocates
 // the largest over its branches once, so that the branches of one kernel share it
-template <class I, int L>
+template <class I, int L, bool kRows>
 constexpr int serial_stage_floats()
 {
     using ST = SerialStage<I::S::B, I::N, 64 / L>;
-    using SR = SerialRows<I::S::B, I::N, 64 / L>;
+    using SR = SerialRows<I::S::B, I::N, 64 / L, kRows>;
     return 2 * (ST::on ? ST::floats : SR::floats);
 }
 
@@ -266,8 +273,9 @@ __device__ __forceinline__ void flush_stage(float* dst, const float* src, int cn
 // of M^-1 and the joints j of step 6 are dealt out among them (lane h takes h, h + L, ...), so
 // a wavefront holds 64 / L knots: L times the wavefronts of build 5 for the same batch, at the
 // cost of repeating steps 1-5 L times. The lanes of a knot are adjacent.
-// `pool` is the dispatch's LDS array of at least serial_stage_floats<I, L>() floats.
-template <class I, int L = 1>
+// `pool` is the dispatch's LDS array of at least serial_stage_floats<I, L, kRows>() floats;
+// kRows allows the row staging of a branch smaller than the robot.
+template <class I, int L, bool kRows>
 __device__ __forceinline__ void run_serial(const grid::Args& A, int block, float* pool)
 {
     using S = typename I::S;
@@ -275,8 +283,8 @@ __device__ __forceinline__ void run_serial(const grid::Args& A, int block, float
     constexpr int N = I::N;
     constexpr int K = 64 / L;                        // knots per wavefront
     using ST = SerialStage<B, N, K>;
-    using SR = SerialRows<B, N, K>;
-    float* const s_stage[2] = {pool, pool + serial_stage_floats<I, L>() / 2};
+    using SR = SerialRows<B, N, K, kRows>;
+    float* const s_stage[2] = {pool, pool + serial_stage_floats<I, L, kRows>() / 2};
     const int lane = (int)threadIdx.x;
     const int h = lane % L;                          // this lane's share of the columns
     const int kl = lane / L;                         // the knot within the wavefront

@@ -104,8 +104,9 @@ def test_serial_build_unaligned_outputs(name, build):
     """Builds 5 and 6 stage the outputs of single-branch robots in LDS and write them with
     16-byte stores when the output arrays are 16-byte aligned, else one float at a time: outputs
     at an offset of one float from an aligned base equal the aligned run bit for bit (N = 100:
-    full and partial wavefronts). Build 5 stages a smaller branch's rows of a branched robot
-    and writes them row by row, zeros in the other branches' columns included: on arrays
+    full and partial wavefronts). A branched robot's smaller branches have their rows staged
+    and written row by row, zeros in the other branches' columns included (build 6 only when
+    every branch fits, as on quad12, tree3 and star32): on arrays
     filled with NaN beforehand every element comes out finite, and nothing outside them is
     written."""
     import torch
