@@ -26,6 +26,8 @@ Also reported (extra fields of the same line):
                 paper's single-computation table, with the paper's GPU numbers as context;
   minv_routes_us  M^-1 alone by the factorisation (quad layout, one lane per knot) and by
                 the paper's direct inverse (one lane per knot), per robot and knot count;
+  sweep         the headline robot at larger batches (tuned build per size);
+  sweep_robots  quad12 and humanoid30 at large batches, each model tuned at those sizes;
   cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
@@ -82,6 +84,9 @@ def parse():
     ap.add_argument("--no-io", action="store_true")
     ap.add_argument("--sweep", default="1024,16384,65536",
                     help="comma-separated extra knot counts to time (\"\" for none)")
+    ap.add_argument("--sweep-robots", default="quad12:16384,65536;humanoid30:4096,16384",
+                    help="robot:knot counts;... timed like the sweep on their own models, "
+                         "with the sweep (none when --sweep is \"\")")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="measured seconds of the served load (0 disables serving)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
@@ -196,6 +201,37 @@ def minv_routes(torch, grid, synth):
             del q, mi
         out[name] = res
         m.close()
+    return out
+
+
+def robot_sweeps(torch, grid, synth, args):
+    """Other robots at large batches: each model tuned over its sizes, then every size timed
+    on the tuned build like the headline sweep (HIP events, back-to-back launches)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for spec in args.sweep_robots.split(";"):
+        name, ns = spec.split(":")
+        ns = [int(x) for x in ns.split(",") if x]
+        robot = synth.model_by_name(name)
+        n = robot.n
+        model = grid.Model(robot, device=0)
+        grid.tune(model, ns)
+        res = {}
+        for NK in ns:
+            k = synth.random_knots(n, NK, args.seed + NK)
+            ins = [torch.from_numpy(a).to(dev) for a in (k.q, k.qd, k.tau)]
+            outs = [torch.empty((NK, n), device=dev)] + \
+                [torch.empty((NK, n, n), device=dev) for _ in range(3)]
+            call = model.fd_grad_call(*ins, *outs, N=NK, stream=stream)
+            s, a = time_steps(torch, call, max(200, args.steps // 5), 50)
+            res[str(NK)] = {"knot_evals_per_s": NK / s, "ms_per_step": s * 1e3,
+                            "kernel_avg_us": a * 1e6,
+                            "kernel": grid.BUILD_KERNELS[grid.build_for(model, NK)],
+                            "alu_frac": algorithmic_flops(name) * NK / a / 1e12 / PEAK_FP32_TFLOPS}
+            del ins, outs, call
+        model.close()
+        out[name] = res
     return out
 
 
@@ -712,6 +748,10 @@ def main():
             del i2, o2
         result["sweep"] = sweep
         progress("throughput sweep done")
+
+    if args.sweep and args.sweep_robots:
+        result["sweep_robots"] = robot_sweeps(torch, grid, synth, args)
+        progress("robot sweeps done")
 
     if not args.no_single:
         if args.robot == "chain7" and not args.no_mixed:
