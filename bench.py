@@ -84,7 +84,9 @@ def parse():
     ap.add_argument("--no-io", action="store_true")
     ap.add_argument("--sweep", default="1024,16384,65536",
                     help="comma-separated extra knot counts to time (\"\" for none)")
-    ap.add_argument("--sweep-robots", default="quad12:16384,65536;humanoid30:4096,16384",
+    ap.add_argument("--sweep-robots",
+                    default=";".join(f"{r}:{','.join(map(str, ns))}"
+                                     for r, ns in synth_robot_sweep().items()),
                     help="robot:knot counts;... timed like the sweep on their own models, "
                          "with the sweep (none when --sweep is \"\")")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -202,6 +204,11 @@ def minv_routes(torch, grid, synth):
         out[name] = res
         m.close()
     return out
+
+
+def synth_robot_sweep():
+    from paper_2109_06976_amd import synth
+    return synth.ROBOT_THROUGHPUT_KNOTS
 
 
 def robot_sweeps(torch, grid, synth, args):

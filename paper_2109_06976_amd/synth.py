@@ -41,6 +41,8 @@ SEED_HUMANOID30 = 2
 SWEEP_KNOTS = (32, 64, 128, 256, 1024)
 # larger batches of the 7-dof chain, where the throughput builds take over
 THROUGHPUT_KNOTS = (1024, 16384, 65536)
+# larger batches of the quadruped and the humanoid, each on its own tuned build
+ROBOT_THROUGHPUT_KNOTS = {"quad12": (16384, 65536), "humanoid30": (4096, 16384)}
 # quadruped + 7-dof chain mixes at uneven knot counts in one step
 MIXED_PLANS = ((64, 37), (256, 181), (1024, 613))
 

@@ -3,6 +3,8 @@
 * every build of the fused kernel (the tuner may pick any of them) at every batch size the
   benchmark runs: the multiple-computation sweep N = 32 .. 1024 on the three robots, and the
   7-dof chain's throughput sizes up to 65536 knots;
+* every build at the quadruped's and the humanoid's large batches (16384 and 65536 knots;
+  4096 and 16384), on sampled knots, every output element written;
 * the one-launch mixed module at the benchmark's quadruped + chain plans, each item bitwise
   equal to its robot's three-role build run alone;
 * the largest batch one call accepts (GRID_MAX_KNOTS), on sampled knots.
@@ -76,6 +78,42 @@ def test_every_build_at_every_benchmark_size(orc, name):
                 check(ref, device_run(torch, m, kn), f"{name} build {build} N={N}")
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("name", list(synth.ROBOT_THROUGHPUT_KNOTS))
+def test_every_build_at_robot_throughput_sizes(orc, name):
+    """The large batches the benchmark times on the quadruped and the humanoid: every build
+    runs the whole batch into arrays filled with NaN beforehand (every element must come out
+    finite), and 64 sampled knots, the first and the last included, are checked against the
+    oracle."""
+    import torch
+    robot = synth.model_by_name(name)
+    n = robot.n
+    m = grid.Model(robot)
+    try:
+        for N in synth.ROBOT_THROUGHPUT_KNOTS[name]:
+            kn = synth.random_knots(n, N, 520 + N)
+            rng = np.random.default_rng(521 + N)
+            idx = np.unique(np.concatenate([[0, N - 1], rng.integers(0, N, 62)]))
+            ref = orc.fd_grad_batch(robot, kn.q[idx], kn.qd[idx], kn.tau[idx])
+            ins = [torch.from_numpy(a).cuda() for a in (kn.q, kn.qd, kn.tau)]
+            it = torch.from_numpy(idx).cuda()
+            for build in range(len(grid.BUILD_KERNELS)):
+                grid.tune_apply(m, {1 << 22: build})
+                say(f"[gpu] {name}: build {build} ({grid.BUILD_KERNELS[build]}), N={N}, sampled")
+                outs = [torch.full((N, n), float("nan"), device="cuda")] + \
+                    [torch.full((N, n, n), float("nan"), device="cuda") for _ in range(3)]
+                m.fd_grad(*ins, *outs, N=N)
+                torch.cuda.synchronize()
+                for k, o in zip(OUTS, outs):
+                    assert bool(torch.isfinite(o).all()), (name, build, N, k)
+                got = {k: o[it].cpu().numpy() for k, o in zip(OUTS, outs)}
+                check(ref, got, f"{name} build {build} N={N}, {len(idx)} sampled knots")
+                del outs
+    finally:
+        grid.tune_apply(m, {})
+        m.close()
+        torch.cuda.empty_cache()
 
 
 def test_mixed_one_launch_at_benchmark_plans(orc):
