@@ -477,7 +477,7 @@ grid_status grid_fd_vjp_adjoint(grid_model m, int32_t N, const float* q, const f
 
 /* ------------------------------------------------------------------ autotuning
  *
- * The fused kernel exists in seven builds. Build 0 spreads each spatial vector over the
+ * The fused kernel exists in eight builds. Build 0 spreads each spatial vector over the
  * four lanes of a quad and gives every derivative column its own quad (few instructions per
  * lane: low latency). Builds 1, 2, 3 give every column one lane that runs the shared
  * sweeps itself (fewest instructions per knot: the highest throughput), allowed 1, 2 or 4
@@ -488,6 +488,7 @@ grid_status grid_fd_vjp_adjoint(grid_model m, int32_t N, const float* q, const f
  * one lane (no repeated work: the fewest instructions per knot, the longest latency). Build 6
  * is build 5 with four lanes per problem that share the columns of M^-1 and the derivative
  * columns (each repeats the rest): four times the wavefronts of build 5 for the same batch.
+ * Build 7 is the same with two lanes per problem (twice the wavefronts of build 5).
  * Untuned, a batch runs build 4 while its wavefronts fit one per SIMD of the device, build 1
  * beyond, build 6 from 64 knots per compute unit and build 5 from 128, except for a robot
  * with a base branch of more than 8 bodies: build 4 up to 4096 knots, build 6 beyond.
@@ -495,7 +496,7 @@ grid_status grid_fd_vjp_adjoint(grid_model m, int32_t N, const float* q, const f
  * device for every knot count in Ns (synthetic inputs, HIP events, median of repeats),
  * keeps the fastest per count, and from then on grid_fd_grad uses, for a batch of N
  * knots, the choice made for the smallest tuned count >= N (the largest otherwise).
- * chosen[i] (may be NULL) receives the build index (0..6) picked for Ns[i]. The
+ * chosen[i] (may be NULL) receives the build index (0..7) picked for Ns[i]. The
  * result is also appended to `table_path` (may be NULL) as one JSON line keyed by the
  * hash of the model's code objects (grid_model_code_hash), so a table is applied only to
  * the machine code it was tuned on; grid_model_create reads the file named by GRID_TUNE_TABLE,
@@ -507,11 +508,11 @@ grid_status grid_tune(grid_model m, const int32_t* Ns, int32_t count, const char
 /* Apply a tuning table from memory: a batch of N knots runs build builds[i] for the
  * smallest Ns[i] >= N (builds[count - 1] beyond the largest). Ns must be ascending
  * (1..2^22, 1 <= count <= 64); count = 0 returns the model to the untuned choice.
- * EUNSUPPORTED if a build index is outside 0..6, EINVAL otherwise. */
+ * EUNSUPPORTED if a build index is outside 0..7, EINVAL otherwise. */
 grid_status grid_tune_apply(grid_model m, const int32_t* Ns, const int32_t* builds,
                             int32_t count);
 
-/* The build (0..6) a batch of N >= 1 knots runs with the model's current tuning. */
+/* The build (0..7) a batch of N >= 1 knots runs with the model's current tuning. */
 grid_status grid_build_for(grid_model m, int32_t N, int32_t* build);
 
 /* ------------------------------------------------------------------ serving

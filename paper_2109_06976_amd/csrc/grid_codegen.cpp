@@ -401,15 +401,20 @@ std::string generate_source(const Topology& t, const std::vector<float>& consts,
     emit_dispatch(os, t, "__device__ void grid_dispatch_s(const grid::Args& a, int block)", "64",
              "grids::run_serial<@, 1, true>(a, b, pool)",
              "grids::serial_stage_floats<@, 1, true>()");
-    os << "\n// generated: workgroup -> (branch, 16 knots), four lanes per knot; rows staged only\n"
-          "// when every branch's fit\n";
-    os << "constexpr bool grid_rows4 = true";
-    for (size_t k = 0; k < t.insts.size(); ++k)
-        os << " && grids::serial_rows_fit<Inst<" << k << ">, 4>()";
-    os << ";\n";
+    os << "\n// generated: workgroup -> (branch, 16 or 32 knots), four or two lanes per knot; rows\n"
+          "// staged only when every branch's fit\n";
+    for (int L : {4, 2}) {
+        os << "constexpr bool grid_rows" << L << " = true";
+        for (size_t k = 0; k < t.insts.size(); ++k)
+            os << " && grids::serial_rows_fit<Inst<" << k << ">, " << L << ">()";
+        os << ";\n";
+    }
     emit_dispatch(os, t, "__device__ void grid_dispatch_s4(const grid::Args& a, int block)", "16",
              "grids::run_serial<@, 4, grid_rows4>(a, b, pool)",
              "grids::serial_stage_floats<@, 4, grid_rows4>()");
+    emit_dispatch(os, t, "__device__ void grid_dispatch_s2(const grid::Args& a, int block)", "32",
+             "grids::run_serial<@, 2, grid_rows2>(a, b, pool)",
+             "grids::serial_stage_floats<@, 2, grid_rows2>()");
     os << "\n// generated: workgroup -> (branch, 64 knots), M^-1 alone by either route\n";
     emit_dispatch(os, t, "template <bool D>\n__device__ void grid_dispatch_minv(const grid::Args& a, int block)",
              "64", "grids::run_minv<@, D>(a, b)");

@@ -16,13 +16,14 @@ constexpr int kMaxBodies = 32;      // the 2B derivative columns of a branch fit
 constexpr int kConstStride = 24;    // floats of device constants per body
 
 // builds of the fused kernel: quad layout, lane layout at 1, 2, 4 wavefronts per SIMD,
-// quad layout in two roles, one lane per knot
+// quad layout in three roles, one lane per knot, four lanes per knot, two lanes per knot
 constexpr int kVariantQuad = 0;
 constexpr int kVariantLane1 = 1;
 constexpr int kVariantPipe = 4;
 constexpr int kVariantSerial = 5;
 constexpr int kVariantSerial4 = 6;
-constexpr int kNumVariants = 7;
+constexpr int kVariantSerial2 = 7;
+constexpr int kNumVariants = 8;
 
 // standalone algorithms (grid_ops.hip)
 constexpr int kOpId = 0;

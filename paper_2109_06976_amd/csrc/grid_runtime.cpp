@@ -275,9 +275,10 @@ grid_status launch_fused_variant(grid_model m, int variant, int32_t N, const flo
         return launch(m->fused_variant[variant], (unsigned)workgroups_pipe(m->topo, N),
                       64u * (unsigned)pipe_waves(m->topo), N, nullptr, q, qd, tau, qdd, Minv, dq,
                       dqd, stream);
-    if (variant == kVariantSerial || variant == kVariantSerial4)
+    if (variant == kVariantSerial || variant == kVariantSerial4 || variant == kVariantSerial2)
         return launch(m->fused_variant[variant],
-                      (unsigned)workgroups_serial(m->topo, N, variant == kVariantSerial ? 64 : 16),
+                      (unsigned)workgroups_serial(m->topo, N, variant == kVariantSerial ? 64
+                                                          : variant == kVariantSerial2 ? 32 : 16),
                       64u, N, nullptr, q, qd, tau, qdd, Minv, dq, dqd, stream);
     return launch(m->fused_variant[variant], (unsigned)workgroups_for(m->topo, N), 64u, N,
                   nullptr, q, qd, tau, qdd, Minv, dq, dqd, stream);
@@ -566,7 +567,7 @@ grid_status grid_model_create(const grid_model_desc* desc, int32_t device, uint3
                                            "grid_stage_drnea", "grid_stage_fdgrad"};
     static const char* const kVariants[kNumVariants] = {
         "grid_fdgrad_quad", "grid_fdgrad_fused", "grid_fdgrad_fused_w2", "grid_fdgrad_fused_w4",
-        "grid_fdgrad_pipe", "grid_fdgrad_serial", "grid_fdgrad_serial4"};
+        "grid_fdgrad_pipe", "grid_fdgrad_serial", "grid_fdgrad_serial4", "grid_fdgrad_serial2"};
     m->compute_units = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     hipError_t e = hipModuleLoadData(&m->module, code.data());
     for (int k = 0; k < kNumVariants && e == hipSuccess; ++k)

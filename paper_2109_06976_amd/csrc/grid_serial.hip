@@ -269,7 +269,7 @@ __device__ __forceinline__ void flush_stage(float* dst, const float* src, int cn
         dst[e] = src[e];
 }
 
-// L lanes per knot (1: build 5; 4: build 6). Every lane of a knot runs steps 1-5; the columns
+// L lanes per knot (1: build 5; 4: build 6; 2: build 7). Every lane of a knot runs steps 1-5; the columns
 // of M^-1 and the joints j of step 6 are dealt out among them (lane h takes h, h + L, ...), so
 // a wavefront holds 64 / L knots: L times the wavefronts of build 5 for the same batch, at the
 // cost of repeating steps 1-5 L times. The lanes of a knot are adjacent.
@@ -881,6 +881,14 @@ __device__ void grid_dispatch_s4(const grid::Args& args, int block);
 extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_serial4(grid::Args args)
 {
     grid_dispatch_s4(args, (int)blockIdx.x);
+}
+
+// defined by the generated epilogue: workgroup -> (branch, 32 knots), two lanes per knot
+__device__ void grid_dispatch_s2(const grid::Args& args, int block);
+
+extern "C" __global__ void __launch_bounds__(64) grid_fdgrad_serial2(grid::Args args)
+{
+    grid_dispatch_s2(args, (int)blockIdx.x);
 }
 
 // defined by the generated epilogue: workgroup -> (branch, 64 knots), M^-1 by either route

@@ -755,14 +755,14 @@ def tune_apply(model, table):
                                  builds.ctypes.data_as(_i32p), len(items)))
 
 
-BUILD_QUAD, BUILD_LANE, BUILD_LANE_W2, BUILD_LANE_W4, BUILD_PIPE, BUILD_SERIAL, BUILD_SERIAL4 = \
-    range(7)
+BUILD_QUAD, BUILD_LANE, BUILD_LANE_W2, BUILD_LANE_W4, BUILD_PIPE, BUILD_SERIAL, BUILD_SERIAL4, \
+    BUILD_SERIAL2 = range(8)
 MIXED_ONE_LAUNCH, MIXED_PERSISTENT, MIXED_PER_ROBOT = range(3)
 MIXED_MODES = ("one_launch", "persistent", "per_robot")
 JOINT_REVOLUTE, JOINT_PRISMATIC, JOINT_FIXED = 0, 1, 2
 BUILD_KERNELS = ("grid_fdgrad_quad", "grid_fdgrad_fused", "grid_fdgrad_fused_w2",
                  "grid_fdgrad_fused_w4", "grid_fdgrad_pipe", "grid_fdgrad_serial",
-                 "grid_fdgrad_serial4")
+                 "grid_fdgrad_serial4", "grid_fdgrad_serial2")
 
 
 def build_for(model, N):

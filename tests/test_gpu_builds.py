@@ -98,15 +98,15 @@ def test_tune_apply_rejects_bad_tables():
         m.close()
 
 
-@pytest.mark.parametrize("build", [grid.BUILD_SERIAL, grid.BUILD_SERIAL4])
+@pytest.mark.parametrize("build", [grid.BUILD_SERIAL, grid.BUILD_SERIAL4, grid.BUILD_SERIAL2])
 @pytest.mark.parametrize("name", ["chain7", "chain2", "chain7-prism", "quad12", "tree3", "star32"])
 def test_serial_build_unaligned_outputs(name, build):
-    """Builds 5 and 6 stage the outputs of single-branch robots in LDS and write them with
+    """Builds 5, 6 and 7 stage the outputs of single-branch robots in LDS and write them with
     16-byte stores when the output arrays are 16-byte aligned, else one float at a time: outputs
     at an offset of one float from an aligned base equal the aligned run bit for bit (N = 100:
     full and partial wavefronts). A branched robot's smaller branches have their rows staged
-    and written row by row, zeros in the other branches' columns included (build 6 only when
-    every branch fits, as on quad12, tree3 and star32): on arrays
+    and written row by row, zeros in the other branches' columns included (builds 6 and 7 only
+    when every branch fits, as on quad12, tree3 and star32): on arrays
     filled with NaN beforehand every element comes out finite, and nothing outside them is
     written."""
     import torch
