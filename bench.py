@@ -82,7 +82,7 @@ def parse():
                     help="bounded CPU sample for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-io", action="store_true")
-    ap.add_argument("--sweep", default="1024,16384,65536",
+    ap.add_argument("--sweep", default=",".join(map(str, synth_throughput_knots())),
                     help="comma-separated extra knot counts to time (\"\" for none)")
     ap.add_argument("--sweep-robots",
                     default=";".join(f"{r}:{','.join(map(str, ns))}"
@@ -204,6 +204,11 @@ def minv_routes(torch, grid, synth):
         out[name] = res
         m.close()
     return out
+
+
+def synth_throughput_knots():
+    from paper_2109_06976_amd import synth
+    return synth.THROUGHPUT_KNOTS
 
 
 def synth_robot_sweep():

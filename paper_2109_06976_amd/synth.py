@@ -40,7 +40,7 @@ SEED_HUMANOID30 = 2
 # the paper's multiple-computation sweep (Sec. V-B, Fig. 4) on each of the three robots
 SWEEP_KNOTS = (32, 64, 128, 256, 1024)
 # larger batches of the 7-dof chain, where the throughput builds take over
-THROUGHPUT_KNOTS = (1024, 16384, 65536)
+THROUGHPUT_KNOTS = (1024, 16384, 32768, 65536)
 # larger batches of the quadruped and the humanoid, each on its own tuned build
 ROBOT_THROUGHPUT_KNOTS = {"quad12": (16384, 65536), "humanoid30": (4096, 16384)}
 # quadruped + 7-dof chain mixes at uneven knot counts in one step
